@@ -1,0 +1,113 @@
+"""Pins for oracle.su3, oracle.lattice and the seeded inputs (CPU)."""
+import itertools
+import os
+
+import numpy as np
+import pytest
+
+from oracle import lattice, su3
+from paper_2112_04556_amd import inputs
+
+
+def test_basis_normalisation():
+    T = su3.T
+    g = np.einsum("aij,bji->ab", T, T)
+    assert np.allclose(g, 0.5 * np.eye(8), atol=1e-15)
+    assert np.allclose(np.einsum("aii->a", T), 0, atol=1e-15)
+    assert np.allclose(T, su3.dagger(T), atol=0)
+
+
+def test_component_round_trip():
+    rng = np.random.default_rng(0)
+    phi = rng.normal(size=(5, 8))
+    assert np.allclose(su3.from_matrix(su3.to_matrix(phi)), phi, atol=1e-15)
+    # a random Hermitian traceless matrix is reproduced from its components
+    A = rng.normal(size=(3, 3)) + 1j * rng.normal(size=(3, 3))
+    H = A + A.conj().T
+    H -= np.trace(H) / 3 * np.eye(3)
+    assert np.allclose(su3.to_matrix(su3.from_matrix(H)), H, atol=1e-14)
+
+
+def test_structure_constants_textbook(golden_dir):
+    f = su3.structure_constants()
+    ref = np.zeros((8, 8, 8))
+    with open(os.path.join(golden_dir, "su3_structure_constants.txt")) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            a, b, c, v = line.split()
+            a, b, c, v = int(a) - 1, int(b) - 1, int(c) - 1, float(v)
+            for perm, sign in ((((a, b, c)), 1), ((b, c, a), 1), ((c, a, b), 1),
+                               ((b, a, c), -1), ((a, c, b), -1), ((c, b, a), -1)):
+                ref[perm] = sign * v
+    assert np.count_nonzero(ref) == 54
+    assert np.allclose(f, ref, atol=1e-14)
+
+
+def test_structure_constants_jacobi():
+    f = su3.structure_constants()
+    # f^{abe} f^{ecd} + f^{bce} f^{ead} + f^{cae} f^{ebd} = 0
+    j = (np.einsum("abe,ecd->abcd", f, f) + np.einsum("bce,ead->abcd", f, f)
+         + np.einsum("cae,ebd->abcd", f, f))
+    assert np.abs(j).max() < 1e-14
+
+
+def test_adjoint_matrix_properties():
+    U = inputs.haar_su3((20,), inputs.make_generator(5, 3)).numpy()
+    W = inputs.haar_su3((20,), inputs.make_generator(6, 3)).numpy()
+    R = su3.adjoint_matrix(U)
+    assert np.allclose(np.einsum("nab,ncb->nac", R, R), np.eye(8), atol=1e-14)
+    assert np.allclose(np.linalg.det(R), 1.0, atol=1e-13)
+    assert np.allclose(su3.adjoint_matrix(su3.dagger(U)), np.swapaxes(R, -1, -2), atol=1e-14)
+    assert np.allclose(su3.adjoint_matrix(U @ W), R @ su3.adjoint_matrix(W), atol=1e-14)
+    phi = np.random.default_rng(1).normal(size=(20, 8))
+    lhs = su3.from_matrix(U @ su3.to_matrix(phi) @ su3.dagger(U))
+    assert np.allclose(lhs, np.einsum("nab,nb->na", R, phi), atol=1e-14)
+
+
+@pytest.mark.parametrize("L", [(2, 2, 2, 2), (3, 4, 2, 5), (4, 1, 3, 2)])
+def test_neighbour_table_brute_force(L):
+    tab = lattice.neighbour_table(L)
+    V = lattice.volume(L)
+    # pure-Python loops over coordinates
+    for x3, x2, x1, x0 in itertools.product(*(range(n) for n in (L[3], L[2], L[1], L[0]))):
+        x = [x0, x1, x2, x3]
+        s = x0 + L[0] * (x1 + L[1] * (x2 + L[2] * x3))
+        for mu in range(4):
+            for k, sign in enumerate((1, -1)):
+                y = list(x)
+                y[mu] = (y[mu] + sign) % L[mu]
+                t = y[0] + L[0] * (y[1] + L[1] * (y[2] + L[2] * y[3]))
+                assert tab[s, 2 * mu + k] == t
+    # the roll-based shift agrees with the table
+    a = np.arange(V).reshape(lattice.lattice_shape(L))
+    for mu in range(4):
+        assert np.array_equal(lattice.shift(a, mu, +1, 0).ravel(), tab[:, 2 * mu])
+        assert np.array_equal(lattice.shift(a, mu, -1, 0).ravel(), tab[:, 2 * mu + 1])
+
+
+@pytest.mark.parametrize("kind", ["eps", "haar", "unit"])
+def test_links_are_su3(kind):
+    L = (4, 4, 2, 2)
+    U = inputs.random_links(L, kind, 0.5, seed=3).numpy()
+    I = np.eye(3)
+    assert np.abs(U @ su3.dagger(U) - I).max() < 1e-14
+    assert np.abs(np.linalg.det(U) - 1).max() < 1e-14
+
+
+def test_haar_and_eps_statistics():
+    U = inputs.random_links((8, 8, 8, 8), "haar", seed=4).numpy()
+    tr2 = np.abs(np.einsum("...ii", U)) ** 2
+    assert abs(tr2.mean() - 1.0) < 0.02          # Haar: E|Tr U|^2 = 1
+    Ue = inputs.random_links((8, 8, 8, 8), "eps", 0.3, seed=4).numpy()
+    # U = exp(i eps H) with <Tr H^2> = 8/2: 1 - Re Tr U / 3 = eps^2 <Tr H^2>/6 + O(eps^4) = 2 eps^2/3
+    d = 1 - np.einsum("...ii", Ue).real.mean() / 3
+    assert abs(d / (2 * 0.3 ** 2 / 3) - 1) < 0.05
+
+
+def test_field_moments():
+    P = inputs.gaussian_fields((8, 8, 8, 8), 2, seed=7).numpy()
+    assert abs(P.mean()) < 0.01 and abs(P.var() - 1) < 0.01
+    # determinism
+    Q = inputs.gaussian_fields((8, 8, 8, 8), 2, seed=7).numpy()
+    assert np.array_equal(P, Q)
