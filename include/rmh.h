@@ -1,0 +1,277 @@
+/*
+ * rmh.h -- C ABI of the MI355X (gfx950) adjoint-Laplacian library.
+ *
+ * The hot path of Riemannian-manifold HMC tooling for lattice QCD: the SU(3)
+ * gauge-covariant Laplacian in the adjoint representation (section 2, Eq. 3),
+ * applied to su(3)-valued link fields inside
+ *   - a Chebyshev bandpass recursion giving power spectra per mode (section 2, Eq. 4),
+ *   - a multi-shift conjugate-gradient solve applying the rational kinetic mass
+ *     term M^{-1} = R(Delta)^2 (section 3, Eq. 5 and Eq. 6),
+ * and the derivatives of both with respect to the links (section 3, the mass-term
+ * force F_M, with the left-multiplication derivative of section 2).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Lattice      periodic L[0] x L[1] x L[2] x L[3], every L[mu] >= 2, V = product.
+ *              Site index s = x0 + L0*(x1 + L1*(x2 + L2*x3)) (x0 fastest).
+ * Operator     Delta = -nabla^2_G >= 0 with spectrum in [0, 16]:
+ *              (Delta phi)(x) = 8 phi(x) - sum_mu [ U_mu(x) phi(x+mu) U_mu(x)^dag
+ *                                          + U_mu(x-mu)^dag phi(x-mu) U_mu(x-mu) ],
+ *              acting on each direction nu of a link field separately.  All spectral
+ *              quantities (window edges, shifts sigma) are in Delta units; the paper's
+ *              normalised operator -nabla^2_G/16 is Delta/16.
+ * su(3) basis  T^a = lambda^a/2 (Gell-Mann), component a = 0..7 is Gell-Mann a+1,
+ *              phi = sum_a phi^a T^a, <phi, psi> = sum_a phi^a psi^a.
+ * Links        "SoA" U[mu][18][V]: component 2*(3i+j) = Re U_ij, 2*(3i+j)+1 = Im U_ij.
+ *              "AoS" U[mu][V][3][3] complex interleaved (re, im) doubles.
+ * Link fields  "SoA" F[n][nu][a][V] = F[n][4][8][V] (n counts independent fields).
+ *              "AoS" F[n][V][4][8].
+ * dtype        RMH_F64 (double) or RMH_F32 (float) for links and fields where a call
+ *              takes a dtype; the computation runs in that precision, every dot product
+ *              and moment is accumulated in FP64.
+ * Pointers     "device" pointers are HIP device memory on the current device, 256-byte
+ *              aligned; "host" pointers are ordinary host memory.  The caller owns
+ *              every buffer.  The library never allocates device memory; scratch comes
+ *              from a caller-provided workspace sized by rmh_workspace_bytes().
+ *              Outputs must not overlap inputs (checked by address range: RMH_E_ARG).
+ * Streams      rmh_stream is a hipStream_t (NULL = the default stream).  Work is
+ *              ordered on that stream.  Calls that return host scalars (moments,
+ *              power, K, stats) synchronize the stream before returning; the others
+ *              return after enqueueing.
+ * Errors       every call returns an rmh_status; nothing is thrown.  rmh_last_error()
+ *              gives a thread-local message for the last failing call.
+ *              Reductions are deterministic (fixed order): repeated calls give
+ *              bitwise-identical results.
+ */
+#ifndef RMH_H
+#define RMH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void* rmh_stream; /* a hipStream_t */
+
+typedef enum {
+  RMH_OK = 0,
+  RMH_E_ARG = 1,           /* bad pointer, size, aliasing or option */
+  RMH_E_SHAPE = 2,         /* lattice extent < 2 or too large */
+  RMH_E_WORKSPACE = 3,     /* workspace smaller than rmh_workspace_bytes() */
+  RMH_E_POLES = 4,         /* shift sigma_j <= 0, complex or repeated roots */
+  RMH_E_NOCONV = 5,        /* solver hit maxiter; outputs hold the last iterate */
+  RMH_E_BREAKDOWN = 6,     /* non-finite or non-positive CG scalar (e.g. NaN source) */
+  RMH_E_HIP = 7,           /* a HIP runtime call failed */
+  RMH_E_UNIMPLEMENTED = 8
+} rmh_status;
+
+typedef enum { RMH_F64 = 0, RMH_F32 = 1 } rmh_dtype;
+
+/* Chebyshev bandpass windows (section 2): B_w(Delta) = sum_{k=0}^{degree} g_k c^w_k T_k(Delta/8 - 1),
+ * c^w_k the Chebyshev coefficients of the indicator of window w, g_k the Jackson kernel
+ * (kernel = 1) or 1 (kernel = 0).  edges: host, n_windows + 1 ascending values in [0, 16],
+ * or NULL for n_windows equal windows. */
+typedef struct {
+  int32_t degree;
+  int32_t n_windows;
+  const double* edges;
+  int32_t kernel;
+} rmh_cheb;
+
+/* R(Delta) = c + sum_j r_j (Delta + sigma_j)^{-1} (section 3, Eq. 6 in partial fractions,
+ * Delta units).  r, sigma: host arrays of n_poles values, sigma_j > 0. */
+typedef struct {
+  double c;
+  int32_t n_poles;
+  const double* r;
+  const double* sigma;
+} rmh_rational;
+
+/* Shifted-solve controls.  tol: per-shift FP64 true relative residual
+ * ||x - (Delta + sigma_j) x_j|| / ||x|| that every shift must reach.  mode 0: FP64 multi-shift
+ * CG; mode 1: FP32 stencil and vectors with FP64 reliable updates of the residual and of
+ * the shift solutions (delta = reliable-update threshold, e.g. 0.1).  check_every:
+ * iterations between host convergence checks (0 = default 8). */
+typedef struct {
+  double tol;
+  int32_t maxiter;
+  int32_t mode;
+  double delta;
+  int32_t check_every;
+} rmh_solver;
+
+/* Per-call solver statistics (host). */
+typedef struct {
+  int32_t iters;            /* multi-shift iterations (max over fields) */
+  int32_t reliable_updates; /* FP64 reliable updates (sum over fields) */
+  int32_t refine_iters;     /* iterations spent in per-shift refinement */
+  int32_t refine_rounds;
+  double true_relres_max;   /* max over fields and shifts of the final FP64 true residual */
+  double seconds;           /* wall time of the call */
+} rmh_stats;
+
+/* Operations for rmh_workspace_bytes(). */
+typedef enum {
+  RMH_OP_LAPLACIAN = 0,
+  RMH_OP_LAPLACIAN_BWD = 1,
+  RMH_OP_POWER_SPECTRUM = 2,
+  RMH_OP_CHEB_FILTER = 3,
+  RMH_OP_RATIONAL_APPLY = 4,
+  RMH_OP_RATIONAL_APPLY_BWD = 5,
+  RMH_OP_KINETIC_FORCE = 6
+} rmh_op;
+
+/* ---------------------------------------------------------------------------------------- */
+/* library */
+
+/* Thread-local description of the last error (never NULL). */
+const char* rmh_last_error(void);
+/* ABI version (major * 100 + minor). */
+int32_t rmh_version(void);
+/* Workspace bytes for op at this shape.  aux = n_windows (POWER_SPECTRUM, CHEB_FILTER) or
+ * n_poles (RATIONAL_*, KINETIC_FORCE), degree = Chebyshev degree (else 0), mode = solver
+ * mode (else 0).  Returns 0 on a bad argument (and sets the error string). */
+size_t rmh_workspace_bytes(int32_t op, const int32_t L[4], int32_t dtype, int32_t n_rhs, int32_t aux,
+                           int32_t degree, int32_t mode);
+
+/* ---------------------------------------------------------------------------------------- */
+/* layout (ingest); pure data movement, bitwise, plus FP64 -> FP32 round-to-nearest-even */
+
+/* U_soa[mu][18][V] (dtype) <- U_aos[mu][V][3][3] complex doubles.  Both device. */
+rmh_status rmh_pack_links(const int32_t L[4], const double* U_aos, void* U_soa, int32_t dtype,
+                          rmh_stream stream);
+/* U_aos <- U_soa (FP64 only).  Both device. */
+rmh_status rmh_unpack_links(const int32_t L[4], const double* U_soa, double* U_aos, rmh_stream stream);
+/* F_soa[n][4][8][V] (dtype) <- F_aos[n][V][4][8] doubles.  Both device. */
+rmh_status rmh_pack_fields(const int32_t L[4], int32_t n, const double* F_aos, void* F_soa, int32_t dtype,
+                           rmh_stream stream);
+/* F_aos (doubles) <- F_soa (dtype).  Both device. */
+rmh_status rmh_unpack_fields(const int32_t L[4], int32_t n, const void* F_soa, int32_t dtype, double* F_aos,
+                             rmh_stream stream);
+/* out[i] = (float) in[i] (round to nearest even), n elements, device. */
+rmh_status rmh_convert_f64_f32(const double* in, float* out, int64_t n, rmh_stream stream);
+
+/* ---------------------------------------------------------------------------------------- */
+/* the operator (section 2, Eq. 3) */
+
+/* y = (Delta + shift) x for n_rhs link fields.  U: device SoA links; x, y: device SoA link
+ * fields [n_rhs][4][8][V]; all of the given dtype.  y must not overlap x or U. */
+rmh_status rmh_laplacian_apply(const int32_t L[4], const void* U, int32_t dtype, const void* x, void* y,
+                               int32_t n_rhs, double shift, rmh_stream stream);
+
+/* Vector-Jacobian product of y = (Delta[U] + shift) x with cotangent g.
+ * grad_x (optional, device, dtype) = (Delta + shift) g.
+ * grad_omega (optional, device, FP64 [n_out][4][8][V]) = d<g, Delta[U] x>/d omega^c_mu(x) for
+ * U_mu(x) -> exp(i omega^c T^c) U_mu(x) (the left-multiplication derivative of section 2);
+ * n_out = n_rhs when per_rhs != 0 (one gradient per field pair) else 1 (summed).
+ * Computed in FP64: U, x, g must be RMH_F64 when grad_omega is requested. */
+rmh_status rmh_laplacian_apply_bwd(const int32_t L[4], const void* U, int32_t dtype, const void* x,
+                                   const void* g, int32_t n_rhs, double shift, void* grad_x,
+                                   double* grad_omega, int32_t per_rhs, rmh_stream stream);
+
+/* ---------------------------------------------------------------------------------------- */
+/* Chebyshev bandpass filters and power spectra (section 2, Eq. 4) */
+
+/* Host: coef[w][k] = g_k c^w_k, n_windows x (degree + 1). */
+rmh_status rmh_cheb_coefficients(const rmh_cheb* cheb, double* coef);
+
+/* Moments mu[n][k] = <F_n, T_k(A) F_n>, A = Delta/8 - 1, k = 0..degree, summed over nu, and
+ * power[n][w] = <F_n, B_w F_n> = sum_k g_k c^w_k mu[n][k] (the numerator of Eq. 4).
+ * The recursion t_{k+1} = 2 A t_k - t_{k-1} runs for ceil(degree/2) stencil sweeps and uses
+ * mu_{2k} = 2<t_k,t_k> - mu_0, mu_{2k+1} = 2<t_{k+1},t_k> - mu_1.
+ * U, F: device (dtype); moments: host [n_rhs][degree+1] (or NULL); power: host
+ * [n_rhs][n_windows] (or NULL).  Synchronizes the stream. */
+rmh_status rmh_power_spectrum(const int32_t L[4], const void* U, int32_t dtype, const void* F, int32_t n_rhs,
+                              const rmh_cheb* cheb, double* moments, double* power, void* ws, size_t ws_bytes,
+                              rmh_stream stream);
+
+/* Host: ratio[n][w] = power[n][w] / Tr B_w with Tr B_w = sum_k g_k c^w_k trace_moments[k]
+ * (Eq. 4, power per mode).  trace_moments[k] = Tr T_k(A) over the link-field space
+ * (e.g. rmh_trace_moments_free, or the mean moments of Gaussian sources). */
+rmh_status rmh_power_ratio(const rmh_cheb* cheb, const double* trace_moments, const double* power,
+                           int32_t n_rhs, double* ratio);
+
+/* Host: exact Tr T_k(A), k = 0..degree, over the link-field space (32 V) at U = 1, where the
+ * eigenvalues of Delta are 4 sum_mu sin^2(p_mu/2), p_mu = 2 pi n_mu / L_mu. */
+rmh_status rmh_trace_moments_free(const int32_t L[4], int32_t degree, double* trace_moments);
+
+/* y[w][n] = B_w x_n for every window (vector output).  x: device [n_rhs][4][8][V]; y: device
+ * [n_windows][n_rhs][4][8][V]; dtype for both.  At most 64 windows.  Runs degree sweeps. */
+rmh_status rmh_cheb_filter(const int32_t L[4], const void* U, int32_t dtype, const void* x, int32_t n_rhs,
+                           const rmh_cheb* cheb, void* y, void* ws, size_t ws_bytes, rmh_stream stream);
+
+/* Backward calls of the Chebyshev filters: not built. */
+rmh_status rmh_cheb_filter_bwd(void);
+rmh_status rmh_power_spectrum_bwd(void);
+
+/* ---------------------------------------------------------------------------------------- */
+/* rational mass term (section 3, Eq. 5 and Eq. 6) */
+
+/* Host: Eq. 6 terms (a0_i + a1_i L)/(b0_i + b1_i L + L^2), L = Delta/16, split into 2 n_terms
+ * real poles r/(Delta + sigma) (r = 16 rho, sigma = 16 s).  RMH_E_POLES when a term has no
+ * two distinct real roots or a root gives sigma <= 0.  r, sigma: host, 2 n_terms each. */
+rmh_status rmh_rational_from_quadratics(int32_t n_terms, const double* a0, const double* a1, const double* b0,
+                                        const double* b1, double* r, double* sigma);
+
+/* Host: n-pole R with R(Delta)^2 ~ (1 - kappa + kappa Delta)^{-1} on [0, 16] (midpoint rule on
+ * y^{-1/2} = (2/pi) sqrt(s) int_0^{pi/2} dt / (s sin^2 t + y cos^2 t), s = sqrt((1-kappa)(1+15 kappa))).
+ * c = 0; r, sigma: host, n values each.  0 < kappa < 1. */
+rmh_status rmh_rational_kappa(double kappa, int32_t n, double* c, double* r, double* sigma);
+
+/* y_n = c x_n + sum_j r_j (Delta + sigma_j)^{-1} x_n for n_rhs link fields, every shift solved to
+ * the FP64 true relative residual solver->tol by multi-shift CG (seed = smallest sigma),
+ * followed by per-shift refinement of any shift above tol.
+ * U: device FP64 SoA links; x, y: device FP64 [n_rhs][4][8][V];
+ * x_poles: optional device FP64 [n_rhs][n_poles][4][8][V] receiving x_j;
+ * K: optional host [n_rhs] receiving 1/2 <y_n, y_n> (Eq. 5 with M^{-1} = R^2);
+ * stats: optional host.  Synchronizes the stream.  RMH_E_NOCONV leaves the last iterate. */
+rmh_status rmh_rational_apply(const int32_t L[4], const double* U, const double* x, int32_t n_rhs,
+                              const rmh_rational* rat, const rmh_solver* solver, double* y, double* x_poles,
+                              double* K, rmh_stats* stats, void* ws, size_t ws_bytes, rmh_stream stream);
+
+/* Vector-Jacobian product of y = R(Delta[U]) x with cotangent g (both FP64 [n_rhs][4][8][V]):
+ * grad_x (optional, device FP64) = R(Delta) g;
+ * grad_omega (device FP64 [n_out][4][8][V], n_out = per_rhs ? n_rhs : 1)
+ *   = d<g, R(Delta[U]) x>/d omega = -sum_j r_j d<z_j, Delta x_j>/d omega,
+ *   x_j = (Delta + sigma_j)^{-1} x, z_j = (Delta + sigma_j)^{-1} g.
+ * Both multi-shift solves are recomputed; nothing is kept from a forward call.
+ * The kinetic force of section 3 is F_M = -grad_omega with g = y = R(Delta) P. */
+rmh_status rmh_rational_apply_bwd(const int32_t L[4], const double* U, const double* x, const double* g,
+                                  int32_t n_rhs, const rmh_rational* rat, const rmh_solver* solver,
+                                  double* grad_x, double* grad_omega, int32_t per_rhs, rmh_stats* stats,
+                                  void* ws, size_t ws_bytes, rmh_stream stream);
+
+/* One RMHMC kinetic-force evaluation: Y = R(Delta) P, K_n = 1/2 <Y_n, Y_n>, and
+ * dK/domega (device FP64 [n_out][4][8][V]); two multi-shift solves (P, then Y) and the link
+ * derivative.  Y (optional device FP64), K (optional host [n_rhs]).  Synchronizes. */
+rmh_status rmh_kinetic_force(const int32_t L[4], const double* U, const double* P, int32_t n_rhs,
+                             const rmh_rational* rat, const rmh_solver* solver, double* Y, double* K,
+                             double* dK_domega, int32_t per_rhs, rmh_stats* stats, void* ws, size_t ws_bytes,
+                             rmh_stream stream);
+
+/* ---------------------------------------------------------------------------------------- */
+/* stencil launch tuning */
+
+/* Fix the stencil launch configuration used for lattice L, dtype and launches over n_rhs link
+ * fields: form 0 = adjoint 8x8 action R(U), 1 = 3x3 matrix products U phi U^dag; block = 64, 128
+ * or 256 threads; xcd_remap = 1 maps consecutive lattice blocks onto one XCD (L2 locality).
+ * Every configuration computes the same operator; a form fixes the per-site arithmetic, so
+ * results are bitwise identical across block sizes and remaps of one form. */
+rmh_status rmh_tune_set(const int32_t L[4], int32_t dtype, int32_t n_rhs, int32_t form, int32_t block,
+                        int32_t xcd_remap);
+/* Time every configuration of rmh_laplacian_apply on the caller's buffers (y is overwritten;
+ * reps timed launches each, HIP events on the stream) and keep the fastest for (L, dtype, n_rhs).
+ * best (optional host int32[3]) receives (form, block, xcd_remap); best_ms (optional) its mean
+ * time per launch.  Synchronizes the stream. */
+rmh_status rmh_autotune_laplacian(const int32_t L[4], const void* U, int32_t dtype, const void* x, void* y,
+                                  int32_t n_rhs, int32_t reps, int32_t* best, double* best_ms, rmh_stream stream);
+/* Forget every stored configuration. */
+rmh_status rmh_tune_clear(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RMH_H */

@@ -1,0 +1,39 @@
+"""torch.autograd wrapper of the RMHMC kinetic energy (section 3, Eq. 5 with Eq. 6).
+
+K(omega, P) = 1/2 sum_n <Y_n, Y_n>,  Y = R(Delta[exp(i omega.T) U]) P,  evaluated at
+omega = 0.  ``omega`` is the (4, 8, V) Lie-algebra displacement of every link under
+left multiplication (the derivative convention of section 2); its gradient is the
+kinetic (mass-term) force with the opposite sign, F_M = -dK/d omega.  The backward
+recomputes both multi-shift solves in the HIP library (no solution is stored).
+"""
+from __future__ import annotations
+
+import torch
+
+from . import api
+
+
+class KineticEnergy(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, omega, P, U, L, rat, solver):
+        if omega.shape != (4, 8, api.volume(L)):
+            raise ValueError("omega must have shape (4, 8, V)")
+        if bool(torch.any(omega != 0)):
+            raise ValueError("the kinetic energy is differentiated at omega = 0; pass a zero displacement")
+        out = api.rational_apply(L, U, P, rat, solver, want_K=True)
+        ctx.save_for_backward(P, out["y"], U)
+        ctx.L, ctx.rat, ctx.solver = L, rat, solver
+        return torch.tensor(float(out["K"].sum()), dtype=torch.float64, device=P.device)
+
+    @staticmethod
+    def backward(ctx, gK):
+        P, Y, U = ctx.saved_tensors
+        gx, go, _ = api.rational_apply_bwd(ctx.L, U, P, Y, ctx.rat, ctx.solver,
+                                           grad_x=ctx.needs_input_grad[1], per_rhs=False)
+        grad_omega = go[0] * gK if ctx.needs_input_grad[0] else None
+        grad_P = gx * gK if gx is not None else None
+        return grad_omega, grad_P, None, None, None, None
+
+
+def kinetic_energy(omega, P, U, L, rat, solver=api.Solver()):
+    return KineticEnergy.apply(omega, P, U, L, rat, solver)

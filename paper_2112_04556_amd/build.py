@@ -1,0 +1,56 @@
+"""Build the HIP library librmh.so for gfx950 (in the package directory).
+
+Every source is compiled by hipcc; packed FP32 instructions are disabled for all
+device code.  Usage: ``python -m paper_2112_04556_amd.build``.
+"""
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "librmh.so")
+SOURCES = ["rmh_kernels.hip", "rmh_api.hip", "rmh_host.cpp", "rmh_tune.cpp"]
+ARCH = os.environ.get("RMH_OFFLOAD_ARCH", "gfx950")
+
+
+def hipcc() -> str:
+    for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
+        if cand and os.path.exists(cand):
+            return cand
+    raise RuntimeError("hipcc not found")
+
+
+def build(verbose: bool = False) -> str:
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    objs = []
+    common = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
+              f"-I{os.path.join(HERE, '..', 'include')}"]
+    for src in SOURCES:
+        path = os.path.join(CSRC, src)
+        obj = os.path.join(objdir, src + ".o")
+        if src.endswith(".hip"):
+            cmd = [hipcc(), "-x", "hip", f"--offload-arch={ARCH}", "-munsafe-fp-atomics",
+                   "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                   *common, "-c", path, "-o", obj]
+        else:
+            cmd = [hipcc(), *common, "-c", path, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        objs.append(obj)
+    tmp = LIB + ".tmp"
+    cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

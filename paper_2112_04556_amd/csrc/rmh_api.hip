@@ -1,0 +1,1255 @@
+// C ABI of the adjoint-Laplacian library: argument checks, workspace planning and the
+// host drivers (Chebyshev moment recursion, multi-shift CG with reliable updates and
+// per-shift refinement, rational combination, kinetic force).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <string>
+#include <vector>
+
+#include "../../include/rmh.h"
+#include "rmh_host.h"
+#include "rmh_internal.h"
+#include "rmh_tune.h"
+
+using namespace rmh;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+rmh_status fail(rmh_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) return fail(RMH_E_HIP, "%s: %s", #expr, hipGetErrorString(e_));    \
+  } while (0)
+
+#define RMH_TRY(expr)                  \
+  do {                                 \
+    rmh_status st_ = (expr);           \
+    if (st_ != RMH_OK) return st_;     \
+  } while (0)
+
+constexpr int64_t kMaxSites = int64_t(1) << 28;
+
+rmh_status make_geom(const int32_t* L, Geom* g) {
+  if (!L) return fail(RMH_E_ARG, "lattice extents pointer is NULL");
+  int64_t V = 1;
+  for (int mu = 0; mu < 4; ++mu) {
+    if (L[mu] < 2) return fail(RMH_E_SHAPE, "lattice extent L[%d] = %d must be >= 2", mu, L[mu]);
+    V *= L[mu];
+    if (V > kMaxSites) return fail(RMH_E_SHAPE, "lattice volume exceeds %lld sites", (long long)kMaxSites);
+  }
+  g->L0 = L[0];
+  g->L1 = L[1];
+  g->L2 = L[2];
+  g->L3 = L[3];
+  g->V = (int32_t)V;
+  return RMH_OK;
+}
+
+size_t dsize(int32_t dtype) { return dtype == RMH_F64 ? 8 : 4; }
+
+rmh_status check_dtype(int32_t dtype) {
+  if (dtype != RMH_F64 && dtype != RMH_F32) return fail(RMH_E_ARG, "dtype %d is neither RMH_F64 nor RMH_F32", dtype);
+  return RMH_OK;
+}
+
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  if (!a || !b || na == 0 || nb == 0) return false;
+  const char* pa = (const char*)a;
+  const char* pb = (const char*)b;
+  return pa < pb + nb && pb < pa + na;
+}
+
+rmh_status check_ptr(const void* p, const char* name) {
+  if (!p) return fail(RMH_E_ARG, "%s is NULL", name);
+  if (((uintptr_t)p) & 255) return fail(RMH_E_ARG, "%s is not 256-byte aligned", name);
+  return RMH_OK;
+}
+
+// Workspace carving: the same code computes sizes (base == nullptr) and pointers.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base((char*)b) {}
+  template <typename T>
+  T* take(size_t n) {
+    const size_t bytes = ((n * sizeof(T) + 255) / 256) * 256;
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += bytes;
+    return p;
+  }
+};
+
+// copies host -> device on the stream and waits (host buffers may be pageable)
+rmh_status h2d(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return RMH_OK;
+  HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return RMH_OK;
+}
+rmh_status d2h(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return RMH_OK;
+  HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return RMH_OK;
+}
+
+HopConfig hop_config(const Geom& g, int32_t dtype, int32_t n_rhs, int32_t purpose) {
+  return tune_hop(g, dtype, n_rhs, purpose);
+}
+
+// ------------------------------------------------------------------------------------------
+// Chebyshev plans
+
+struct ChebPlan {
+  void* bufA;
+  void* bufB;
+  double* partials;
+  double* sums;
+};
+
+ChebPlan plan_cheb(Carver& c, const Geom& g, int32_t dtype, int32_t n_rhs, int32_t sweeps, bool moments) {
+  ChebPlan p{};
+  const size_t fb = (size_t)n_rhs * 32 * g.V * dsize(dtype);
+  p.bufA = c.take<char>(fb);
+  p.bufB = c.take<char>(fb);
+  if (moments) {
+    const int nblk = (g.V + 63) / 64;  // upper bound over tuned block sizes (>= 64 threads)
+    p.partials = c.take<double>((size_t)sweeps * n_rhs * 3 * nblk);
+    p.sums = c.take<double>((size_t)sweeps * n_rhs * 3);
+  }
+  return p;
+}
+
+// ------------------------------------------------------------------------------------------
+// multi-shift CG engine
+
+struct Engine {
+  Geom g;
+  int32_t n_rhs = 0, n_shift = 0, mode = 0;
+  // device buffers
+  void* r = nullptr;      // [n_rhs] working precision
+  void* Ap = nullptr;     // [n_rhs]
+  void* p = nullptr;      // [n_rhs][n_shift]
+  float* x_lo = nullptr;  // [n_rhs][n_shift] (mixed)
+  double* r64 = nullptr;  // [n_rhs] (mixed)
+  double* sc = nullptr;
+  double* sh = nullptr;
+  int32_t* flags = nullptr;
+  int32_t* act = nullptr;
+  int32_t* act_next = nullptr;
+  double* sigma = nullptr;     // [n_rhs][n_shift]
+  int32_t* seed = nullptr;     // [n_rhs]
+  double* b_hop = nullptr;     // [n_rhs]  8 + sigma0
+  double* b_ru = nullptr;      // [n_rhs]  -(8 + sigma0)
+  double* b_true = nullptr;    // [n_rhs][n_shift]  -(8 + sigma_j)
+  double* tol_rhs = nullptr;   // [n_rhs]
+  double* part = nullptr;      // [n_rhs][max(3 nblk_hop, nblk_e)]
+  double* part_true = nullptr; // [n_rhs][n_shift][3][nblk_hop]
+  double* sums_true = nullptr; // [n_rhs][n_shift][3]
+  int32_t nblk_hop = 0, nblk_e = 0;
+};
+
+void plan_engine(Carver& c, Engine& e, const Geom& g, int32_t n_rhs, int32_t n_shift, int32_t mode) {
+  e.g = g;
+  e.n_rhs = n_rhs;
+  e.n_shift = n_shift;
+  e.mode = mode;
+  const int64_t n = field_reals(g);
+  const size_t ws = mode ? 4 : 8;
+  e.r = c.take<char>((size_t)n_rhs * n * ws);
+  e.Ap = c.take<char>((size_t)n_rhs * n * ws);
+  e.p = c.take<char>((size_t)n_rhs * n_shift * n * ws);
+  if (mode) {
+    e.x_lo = c.take<float>((size_t)n_rhs * n_shift * n);
+    e.r64 = c.take<double>((size_t)n_rhs * n);
+  }
+  e.sc = c.take<double>((size_t)n_rhs * kScN);
+  e.sh = c.take<double>((size_t)n_rhs * n_shift * kShN);
+  e.flags = c.take<int32_t>((size_t)n_rhs * kFlN);
+  e.act = c.take<int32_t>((size_t)n_rhs * n_shift);
+  e.act_next = c.take<int32_t>((size_t)n_rhs * n_shift);
+  e.sigma = c.take<double>((size_t)n_rhs * n_shift);
+  e.seed = c.take<int32_t>(n_rhs);
+  e.b_hop = c.take<double>(n_rhs);
+  e.b_ru = c.take<double>(n_rhs);
+  e.b_true = c.take<double>((size_t)n_rhs * n_shift);
+  e.tol_rhs = c.take<double>(n_rhs);
+  e.nblk_hop = (g.V + 63) / 64;
+  e.nblk_e = elem_num_blocks(n);
+  e.part = c.take<double>((size_t)n_rhs * std::max<int64_t>(3 * e.nblk_hop, e.nblk_e));
+  e.part_true = c.take<double>((size_t)n_rhs * n_shift * 3 * e.nblk_hop);
+  e.sums_true = c.take<double>((size_t)n_rhs * n_shift * 3);
+}
+
+CgDev cg_view(const Engine& e, int32_t nblk_hop) {
+  CgDev d;
+  d.n_rhs = e.n_rhs;
+  d.n_shift = e.n_shift;
+  d.sc = e.sc;
+  d.sh = e.sh;
+  d.flags = e.flags;
+  d.act = e.act;
+  d.act_next = e.act_next;
+  d.sigma = e.sigma;
+  d.seed = e.seed;
+  d.part = e.part;
+  d.nblk_hop = nblk_hop;
+  d.nblk_e = e.nblk_e;
+  return d;
+}
+
+struct SolveInfo {
+  int32_t iters = 0;
+  int32_t ru = 0;
+  int32_t status = kStOk;
+};
+
+// Solve (Delta + sigma[v][j]) x[v][j] = b[v] for all v, j to recursive residual tol_rel[v] * ||b_v||.
+// x_hi (FP64, [n_rhs][n_shift]) receives the solutions (zeroed here).
+template <typename T>
+rmh_status engine_solve(Engine& e, const double* U64, const float* U32, const double* b, double* x_hi,
+                        const std::vector<double>& sigma, const std::vector<double>& tol_rel, int32_t maxiter,
+                        double delta, int32_t check_every, hipStream_t s, SolveInfo* info) {
+  const Geom& g = e.g;
+  const int64_t n = field_reals(g);
+  const int32_t nr = e.n_rhs, ns = e.n_shift;
+  const bool mixed = e.mode != 0;
+  // host-side seeds and shift coefficients
+  std::vector<int32_t> seed(nr);
+  std::vector<double> bh(nr), bru(nr), btrue((size_t)nr * ns);
+  for (int v = 0; v < nr; ++v) {
+    int j0 = 0;
+    for (int j = 1; j < ns; ++j)
+      if (sigma[(size_t)v * ns + j] < sigma[(size_t)v * ns + j0]) j0 = j;
+    seed[v] = j0;
+    bh[v] = 8.0 + sigma[(size_t)v * ns + j0];
+    bru[v] = -bh[v];
+    for (int j = 0; j < ns; ++j) btrue[(size_t)v * ns + j] = -(8.0 + sigma[(size_t)v * ns + j]);
+  }
+  for (int v = 1; v < nr; ++v)
+    if (seed[v] != seed[0]) return fail(RMH_E_ARG, "internal: non-uniform seed shift");
+  RMH_TRY(h2d(e.sigma, sigma.data(), sigma.size() * 8, s));
+  RMH_TRY(h2d(e.seed, seed.data(), seed.size() * 4, s));
+  RMH_TRY(h2d(e.b_hop, bh.data(), bh.size() * 8, s));
+  RMH_TRY(h2d(e.b_ru, bru.data(), bru.size() * 8, s));
+  RMH_TRY(h2d(e.b_true, btrue.data(), btrue.size() * 8, s));
+  RMH_TRY(h2d(e.tol_rhs, tol_rel.data(), tol_rel.size() * 8, s));
+
+  const HopConfig cw = hop_config(g, mixed ? RMH_F32 : RMH_F64, nr, 1);
+  const HopConfig c64 = hop_config(g, RMH_F64, nr, 2);
+  const int32_t nblk_w = hop_num_blocks(g, cw), nblk_64 = hop_num_blocks(g, c64);
+  CgDev cg = cg_view(e, nblk_w);
+  CgDev cg64 = cg_view(e, nblk_64);
+
+  T* r = (T*)e.r;
+  T* Ap = (T*)e.Ap;
+  T* p = (T*)e.p;
+  HIP_TRY(launch_zero(x_hi, (size_t)nr * ns * n * 8, s));
+  if (mixed) HIP_TRY(launch_zero(e.x_lo, (size_t)nr * ns * n * 4, s));
+  HIP_TRY(launch_copy_cast<T>(b, r, (int64_t)nr * n, s));
+  for (int v = 0; v < nr; ++v)
+    for (int j = 0; j < ns; ++j) HIP_TRY(launch_copy_cast<T>(b + (size_t)v * n, p + ((size_t)v * ns + j) * n, n, s));
+  if (mixed) HIP_TRY(launch_copy_cast<double>(b, e.r64, (int64_t)nr * n, s));
+  // ||b||^2 and the initial scalars
+  HIP_TRY(launch_dot<double>(b, b, n, nr, e.part, s));
+  HIP_TRY(launch_cg_init(cg, e.part, e.nblk_e, e.tol_rhs, delta, maxiter, s));
+  std::vector<double> sc((size_t)nr * kScN);
+
+  // Stencil on the seed direction: Ap = (Delta + sigma0) p_seed = (8 + sigma0) p - H p
+  HopArgs<T> ha{};
+  ha.g = g;
+  ha.U = mixed ? (const T*)U32 : (const T*)U64;
+  ha.x = p;
+  ha.x_mul = ns;
+  ha.x_add = seed[0];
+  ha.out = Ap;
+  ha.z = nullptr;
+  ha.z_div = 1;
+  ha.a = -1.0;
+  ha.b = 0.0;
+  ha.b_rhs = e.b_hop;
+  ha.c = 0.0;
+  ha.n_rhs = nr;
+  ha.run = e.flags + kFlRun;
+  ha.run_stride = kFlN;
+  ha.store = 1;
+  ha.partials = e.part;
+  ha.dot_mask = 2;
+  // FP64 true residual of the seed for reliable updates: r64 = b - (Delta + sigma0) x_hi_seed
+  HopArgs<double> hr{};
+  hr.g = g;
+  hr.U = U64;
+  hr.x = x_hi;
+  hr.x_mul = ns;
+  hr.x_add = seed[0];
+  hr.out = e.r64;
+  hr.z = b;
+  hr.z_div = 1;
+  hr.a = 1.0;
+  hr.b_rhs = e.b_ru;
+  hr.c = 1.0;
+  hr.n_rhs = nr;
+  hr.run = e.flags + kFlNeedRU;
+  hr.run_stride = kFlN;
+  hr.store = 1;
+  hr.partials = e.part;
+  hr.dot_mask = 4;
+
+  if (check_every <= 0) check_every = 8;
+  std::vector<int32_t> fl((size_t)nr * kFlN);
+  int32_t it = 0;
+  while (true) {
+    for (int i = 0; i < check_every; ++i) {
+      HIP_TRY(launch_hop<T>(ha, cw, s));
+      HIP_TRY(launch_cg_alpha(cg, s));
+      HIP_TRY(launch_cg_r_update<T>(cg, r, Ap, n, s));
+      HIP_TRY(launch_cg_beta(cg, mixed ? 1 : 0, s));
+      if (mixed)
+        HIP_TRY((launch_cg_shift_update<T, T>(cg, r, p, (T*)e.x_lo, n, s)));
+      else
+        HIP_TRY((launch_cg_shift_update<T, T>(cg, r, p, (T*)x_hi, n, s)));
+    }
+    it += check_every;
+    RMH_TRY(d2h(fl.data(), e.flags, fl.size() * 4, s));
+    bool running = false, need_ru = false;
+    for (int v = 0; v < nr; ++v) {
+      running |= fl[(size_t)v * kFlN + kFlRun] != 0;
+      need_ru |= fl[(size_t)v * kFlN + kFlNeedRU] != 0;
+    }
+    if (!running) break;
+    if (mixed && need_ru) {
+      HIP_TRY(launch_ru_accumulate(cg, e.x_lo, x_hi, n, 0, s));
+      HIP_TRY(launch_hop<double>(hr, c64, s));
+      HIP_TRY(launch_ru_finish(cg64, s));
+      HIP_TRY(launch_ru_convert(cg, e.r64, (float*)r, n, s));
+    }
+    if (it > maxiter + 2 * check_every) break;  // safety net; the device sets NoConv first
+  }
+  if (mixed) HIP_TRY(launch_ru_accumulate(cg, e.x_lo, x_hi, n, 1, s));
+  RMH_TRY(d2h(sc.data(), e.sc, sc.size() * 8, s));
+  info->iters = 0;
+  info->ru = 0;
+  info->status = kStOk;
+  for (int v = 0; v < nr; ++v) {
+    info->iters = std::max(info->iters, (int32_t)sc[(size_t)v * kScN + kScIters]);
+    info->ru += (int32_t)sc[(size_t)v * kScN + kScRU];
+    const int32_t st = fl[(size_t)v * kFlN + kFlStatus];
+    if (st == kStBreakdown) info->status = kStBreakdown;
+    else if (st == kStNoConv && info->status == kStOk) info->status = kStNoConv;
+  }
+  return RMH_OK;
+}
+
+// FP64 true relative residuals ||b_v - (Delta + sigma_j) x_vj|| / ||b_v|| for all pairs.
+rmh_status true_residuals(Engine& e, const double* U64, const double* b, const double* x_hi,
+                          const std::vector<double>& bnorm, hipStream_t s, std::vector<double>* res) {
+  const Geom& g = e.g;
+  const int32_t nr = e.n_rhs, ns = e.n_shift;
+  const HopConfig c64 = hop_config(g, RMH_F64, nr * ns, 2);
+  const int32_t nblk = hop_num_blocks(g, c64);
+  HopArgs<double> h{};
+  h.g = g;
+  h.U = U64;
+  h.x = x_hi;
+  h.x_mul = 1;
+  h.x_add = 0;
+  h.out = nullptr;
+  h.z = b;
+  h.z_div = ns;
+  h.a = 1.0;
+  h.b_rhs = e.b_true;
+  h.c = 1.0;
+  h.n_rhs = nr * ns;
+  h.store = 0;
+  h.partials = e.part_true;
+  h.dot_mask = 4;
+  HIP_TRY(launch_hop<double>(h, c64, s));
+  // rows: for pair q the <out,out> partials sit at row 3 q + 2
+  HIP_TRY(launch_reduce_rows(e.part_true, nblk, nr * ns * 3, e.sums_true, s));
+  std::vector<double> sums((size_t)nr * ns * 3);
+  RMH_TRY(d2h(sums.data(), e.sums_true, sums.size() * 8, s));
+  res->resize((size_t)nr * ns);
+  for (int v = 0; v < nr; ++v)
+    for (int j = 0; j < ns; ++j) {
+      const double rr = sums[((size_t)v * ns + j) * 3 + 2];
+      (*res)[(size_t)v * ns + j] = bnorm[v] > 0 ? sqrt(rr) / bnorm[v] : 0.0;
+    }
+  return RMH_OK;
+}
+
+// Refinement engine buffers for a batch of (rhs, shift) pairs.
+struct RefinePlan {
+  Engine eng;
+  double* X;     // [nb] copies of x_hi of the pairs
+  double* Bsrc;  // [nb] copies of the sources
+  double* Res;   // [nb] residual vectors (sources of the correction solve)
+  double* E;     // [nb] corrections
+  int32_t nb;
+};
+
+int32_t refine_batch(int32_t n_rhs, int32_t n_shift) {
+  return std::max(1, std::min(n_rhs * n_shift, std::max(n_rhs, n_shift)));
+}
+
+void plan_refine(Carver& c, RefinePlan& rp, const Geom& g, int32_t nb, int32_t mode) {
+  const int64_t n = field_reals(g);
+  rp.nb = nb;
+  rp.X = c.take<double>((size_t)nb * n);
+  rp.Bsrc = c.take<double>((size_t)nb * n);
+  rp.Res = c.take<double>((size_t)nb * n);
+  rp.E = c.take<double>((size_t)nb * n);
+  plan_engine(c, rp.eng, g, nb, 1, mode);
+}
+
+struct SolvePlan {
+  Engine eng;
+  RefinePlan ref;
+  float* U32 = nullptr;
+  double* bn2_sums = nullptr;
+};
+
+void plan_solve(Carver& c, SolvePlan& sp, const Geom& g, int32_t n_rhs, int32_t n_shift, int32_t mode) {
+  plan_engine(c, sp.eng, g, n_rhs, n_shift, mode);
+  plan_refine(c, sp.ref, g, refine_batch(n_rhs, n_shift), mode);
+  if (mode) sp.U32 = c.take<float>((size_t)72 * g.V);
+  sp.bn2_sums = c.take<double>(n_rhs);
+}
+
+struct SolveResult {
+  int32_t iters = 0, ru = 0, refine_iters = 0, refine_rounds = 0;
+  double relres_max = 0.0;
+  int32_t status = kStOk;
+};
+
+// Full solve of every shift to the FP64 true residual tol: multi-shift CG, then per-shift
+// refinement of the pairs above tol (batched as independent single-shift systems).
+rmh_status solve_all(SolvePlan& sp, const double* U64, const double* b, double* x_hi, const std::vector<double>& sig,
+                     const rmh_solver& sv, hipStream_t s, SolveResult* out) {
+  Engine& e = sp.eng;
+  const Geom& g = e.g;
+  const int64_t n = field_reals(g);
+  const int32_t nr = e.n_rhs, ns = e.n_shift;
+  const int32_t mode = e.mode;
+  if (mode) HIP_TRY(launch_f64_to_f32(U64, sp.U32, (int64_t)72 * g.V, s));
+  std::vector<double> sigma((size_t)nr * ns);
+  for (int v = 0; v < nr; ++v)
+    for (int j = 0; j < ns; ++j) sigma[(size_t)v * ns + j] = sig[j];
+  // the recursive residual is driven below the target so the true residual lands under it
+  const double target = 0.5 * sv.tol;
+  std::vector<double> tol_rel(nr, target);
+  SolveInfo info;
+  if (mode)
+    RMH_TRY(engine_solve<float>(e, U64, sp.U32, b, x_hi, sigma, tol_rel, sv.maxiter, sv.delta, sv.check_every, s,
+                                &info));
+  else
+    RMH_TRY(engine_solve<double>(e, U64, nullptr, b, x_hi, sigma, tol_rel, sv.maxiter, sv.delta, sv.check_every,
+                                 s, &info));
+  out->iters = info.iters;
+  out->ru = info.ru;
+  out->status = info.status;
+  if (info.status == kStBreakdown) return RMH_OK;
+  // ||b_v||
+  std::vector<double> bnorm(nr);
+  {
+    std::vector<double> sc((size_t)nr * kScN);
+    RMH_TRY(d2h(sc.data(), e.sc, sc.size() * 8, s));
+    for (int v = 0; v < nr; ++v) bnorm[v] = sqrt(sc[(size_t)v * kScN + kScBnorm2]);
+  }
+  std::vector<double> res;
+  RMH_TRY(true_residuals(e, U64, b, x_hi, bnorm, s, &res));
+  RefinePlan& rp = sp.ref;
+  for (int round = 0; round < 4; ++round) {
+    std::vector<int32_t> bad;
+    for (int q = 0; q < nr * ns; ++q)
+      if (!(res[q] <= sv.tol)) bad.push_back(q);
+    if (bad.empty()) break;
+    out->refine_rounds = round + 1;
+    for (size_t i0 = 0; i0 < bad.size(); i0 += rp.nb) {
+      const int32_t nb = (int32_t)std::min<size_t>(rp.nb, bad.size() - i0);
+      std::vector<double> rsig(nb), rtol(nb);
+      for (int i = 0; i < nb; ++i) {
+        const int q = bad[i0 + i], v = q / ns, j = q % ns;
+        HIP_TRY(hipMemcpyAsync(rp.X + (size_t)i * n, x_hi + (size_t)q * n, n * 8, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(rp.Bsrc + (size_t)i * n, b + (size_t)v * n, n * 8, hipMemcpyDeviceToDevice, s));
+        rsig[i] = sig[j];
+        // correction solve target relative to its own source ||r|| = res * ||b||
+        rtol[i] = std::min(0.5, target / std::max(res[q], 1e-300));
+      }
+      // residual vectors Res_i = Bsrc_i - (Delta + sigma_i) X_i
+      Engine& re = rp.eng;
+      re.n_rhs = nb;
+      std::vector<double> btr(nb);
+      for (int i = 0; i < nb; ++i) btr[i] = -(8.0 + rsig[i]);
+      RMH_TRY(h2d(re.b_true, btr.data(), nb * 8, s));
+      HopArgs<double> h{};
+      h.g = g;
+      h.U = U64;
+      h.x = rp.X;
+      h.x_mul = 1;
+      h.out = rp.Res;
+      h.z = rp.Bsrc;
+      h.z_div = 1;
+      h.a = 1.0;
+      h.b_rhs = re.b_true;
+      h.c = 1.0;
+      h.n_rhs = nb;
+      h.store = 1;
+      HIP_TRY(launch_hop<double>(h, hop_config(g, RMH_F64, nb, 2), s));
+      SolveInfo ri;
+      if (mode)
+        RMH_TRY(engine_solve<float>(re, U64, sp.U32, rp.Res, rp.E, rsig, rtol, sv.maxiter, sv.delta,
+                                    sv.check_every, s, &ri));
+      else
+        RMH_TRY(engine_solve<double>(re, U64, nullptr, rp.Res, rp.E, rsig, rtol, sv.maxiter, sv.delta,
+                                     sv.check_every, s, &ri));
+      out->refine_iters += ri.iters;
+      if (ri.status == kStBreakdown) out->status = kStBreakdown;
+      HIP_TRY(launch_add(rp.X, rp.E, (int64_t)nb * n, s));
+      for (int i = 0; i < nb; ++i)
+        HIP_TRY(hipMemcpyAsync(x_hi + (size_t)bad[i0 + i] * n, rp.X + (size_t)i * n, n * 8,
+                               hipMemcpyDeviceToDevice, s));
+    }
+    RMH_TRY(true_residuals(e, U64, b, x_hi, bnorm, s, &res));
+  }
+  out->relres_max = 0.0;
+  for (double r : res) out->relres_max = std::max(out->relres_max, r);
+  if (!(out->relres_max <= sv.tol) && out->status == kStOk) out->status = kStNoConv;
+  return RMH_OK;
+}
+
+rmh_status check_rational(const rmh_rational* rat) {
+  if (!rat) return fail(RMH_E_ARG, "rational is NULL");
+  if (rat->n_poles < 1 || rat->n_poles > 64) return fail(RMH_E_ARG, "n_poles = %d outside [1, 64]", rat->n_poles);
+  if (!rat->r || !rat->sigma) return fail(RMH_E_ARG, "rational r or sigma is NULL");
+  for (int j = 0; j < rat->n_poles; ++j) {
+    if (!(rat->sigma[j] > 0.0) || !isfinite(rat->sigma[j]))
+      return fail(RMH_E_POLES, "sigma[%d] = %g must be positive and finite", j, rat->sigma[j]);
+    if (!isfinite(rat->r[j])) return fail(RMH_E_POLES, "r[%d] is not finite", j);
+  }
+  if (!isfinite(rat->c)) return fail(RMH_E_POLES, "c is not finite");
+  return RMH_OK;
+}
+
+rmh_status check_solver(const rmh_solver* sv) {
+  if (!sv) return fail(RMH_E_ARG, "solver is NULL");
+  if (!(sv->tol > 0.0) || sv->tol >= 1.0) return fail(RMH_E_ARG, "solver tol = %g must lie in (0, 1)", sv->tol);
+  if (sv->maxiter < 1) return fail(RMH_E_ARG, "solver maxiter = %d must be >= 1", sv->maxiter);
+  if (sv->mode != 0 && sv->mode != 1) return fail(RMH_E_ARG, "solver mode = %d must be 0 or 1", sv->mode);
+  if (sv->mode == 1 && !(sv->delta > 0.0 && sv->delta < 1.0))
+    return fail(RMH_E_ARG, "solver delta = %g must lie in (0, 1)", sv->delta);
+  return RMH_OK;
+}
+
+rmh_status status_of(const SolveResult& r, const char* what) {
+  if (r.status == kStBreakdown) return fail(RMH_E_BREAKDOWN, "%s: CG breakdown (non-finite or non-positive scalar)", what);
+  if (r.status == kStNoConv)
+    return fail(RMH_E_NOCONV, "%s: not converged (max true relative residual %g)", what, r.relres_max);
+  return RMH_OK;
+}
+
+void fill_stats(rmh_stats* st, const SolveResult* rs, int n, double seconds) {
+  if (!st) return;
+  memset(st, 0, sizeof(*st));
+  for (int i = 0; i < n; ++i) {
+    st->iters += rs[i].iters;
+    st->reliable_updates += rs[i].ru;
+    st->refine_iters += rs[i].refine_iters;
+    st->refine_rounds += rs[i].refine_rounds;
+    st->true_relres_max = std::max(st->true_relres_max, rs[i].relres_max);
+  }
+  st->seconds = seconds;
+}
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct RationalPlan {
+  SolvePlan sp;
+  double* X = nullptr;     // x_j of the first solve (if not caller-provided)
+  double* Z = nullptr;     // z_j of the second solve
+  double* Y = nullptr;     // combined vector (if not caller-provided)
+  double* coef = nullptr;  // c, r_0.. (device)
+  double* partK = nullptr; // partials for K
+  double* sumsK = nullptr;
+};
+
+void plan_rational(Carver& c, RationalPlan& rp, const Geom& g, int32_t n_rhs, int32_t n_poles, int32_t mode,
+                   int32_t op) {
+  const int64_t n = field_reals(g);
+  plan_solve(c, rp.sp, g, n_rhs, n_poles, mode);
+  rp.X = c.take<double>((size_t)n_rhs * n_poles * n);
+  if (op != RMH_OP_RATIONAL_APPLY) {
+    rp.Z = c.take<double>((size_t)n_rhs * n_poles * n);
+    rp.Y = c.take<double>((size_t)n_rhs * n);
+  }
+  rp.coef = c.take<double>(n_poles + 1);
+  rp.partK = c.take<double>((size_t)n_rhs * elem_num_blocks(n));
+  rp.sumsK = c.take<double>(n_rhs);
+}
+
+template <typename T>
+rmh_status power_spectrum_t(const Geom& g, const T* U, const T* F, int32_t n_rhs, int32_t D,
+                                   const ChebPlan& cp, std::vector<double>* sums_h, hipStream_t s) {
+  const int32_t K = std::max(1, (D + 1) / 2);
+  const HopConfig cfg = hop_config(g, sizeof(T) == 8 ? RMH_F64 : RMH_F32, n_rhs, 3);
+  const int32_t nblk = hop_num_blocks(g, cfg);
+  T* A = (T*)cp.bufA;
+  T* B = (T*)cp.bufB;
+  const T* cur = F;
+  const T* prev = nullptr;
+  for (int32_t k = 0; k < K; ++k) {
+    HopArgs<T> h{};
+    h.g = g;
+    h.U = U;
+    h.x_mul = 1;
+    h.z_div = 1;
+    h.n_rhs = n_rhs;
+    h.store = (k + 1 < K) ? 1 : 0;   // the last sweep only needs its dot products
+    h.partials = cp.partials + (size_t)k * n_rhs * 3 * nblk;
+    h.dot_mask = 7;
+    h.x = cur;
+    T* out;
+    if (k == 0) {
+      out = A;              // t1 = A t0 = -H t0 / 8
+      h.a = -0.125;
+      h.b = 0.0;
+    } else {
+      out = (k & 1) ? B : A;  // t_{k+1} = 2 A t_k - t_{k-1} = -H t_k / 4 - t_{k-1}, over t_{k-1}
+      h.a = -0.25;
+      h.b = 0.0;
+      h.c = -1.0;
+      h.z = prev;
+    }
+    h.out = out;
+    HIP_TRY(launch_hop<T>(h, cfg, s));
+    prev = cur;
+    cur = out;
+  }
+  HIP_TRY(launch_reduce_rows(cp.partials, nblk, K * n_rhs * 3, cp.sums, s));
+  sums_h->resize((size_t)K * n_rhs * 3);
+  RMH_TRY(d2h(sums_h->data(), cp.sums, sums_h->size() * 8, s));
+  return RMH_OK;
+}
+
+template <typename T>
+rmh_status cheb_filter_t(const Geom& g, const T* U, const T* x, int32_t n_rhs, int32_t D, int32_t nw,
+                                const std::vector<double>& coef, const ChebPlan& cp, T* y, hipStream_t s) {
+  const HopConfig cfg = hop_config(g, sizeof(T) == 8 ? RMH_F64 : RMH_F32, n_rhs, 4);
+  T* A = (T*)cp.bufA;
+  T* B = (T*)cp.bufB;
+  const T* cur = x;
+  const T* prev = nullptr;
+  for (int32_t k = 0; k < D; ++k) {
+    HopArgs<T> h{};
+    h.g = g;
+    h.U = U;
+    h.x_mul = 1;
+    h.z_div = 1;
+    h.n_rhs = n_rhs;
+    h.store = (k + 1 < D) ? 1 : 0;
+    h.x = cur;
+    h.yacc = y;
+    h.n_w = nw;
+    h.yacc_stride = (int64_t)n_rhs * 32 * g.V;
+    for (int w = 0; w < nw; ++w) {
+      h.wcoef[w] = coef[(size_t)w * (D + 1) + k + 1];
+      h.wcoef0[w] = coef[(size_t)w * (D + 1)];
+    }
+    h.filter_first = (k == 0) ? 1 : 0;
+    T* out;
+    if (k == 0) {
+      out = A;
+      h.a = -0.125;
+    } else {
+      out = (k & 1) ? B : A;
+      h.a = -0.25;
+      h.c = -1.0;
+      h.z = prev;
+    }
+    h.out = out;
+    HIP_TRY(launch_hop<T>(h, cfg, s));
+    prev = cur;
+    cur = out;
+  }
+  return RMH_OK;
+}
+
+}  // namespace
+
+// =============================================================================================
+extern "C" {
+
+const char* rmh_last_error(void) { return g_err.c_str(); }
+
+int32_t rmh_version(void) { return 100; }
+
+size_t rmh_workspace_bytes(int32_t op, const int32_t L[4], int32_t dtype, int32_t n_rhs, int32_t aux,
+                           int32_t degree, int32_t mode) {
+  Geom g;
+  if (make_geom(L, &g) != RMH_OK) return 0;
+  if (check_dtype(dtype) != RMH_OK) return 0;
+  if (n_rhs < 0) {
+    fail(RMH_E_ARG, "n_rhs < 0");
+    return 0;
+  }
+  Carver c(nullptr);
+  switch (op) {
+    case RMH_OP_LAPLACIAN:
+    case RMH_OP_LAPLACIAN_BWD:
+      c.take<char>(256);
+      break;
+    case RMH_OP_POWER_SPECTRUM:
+      plan_cheb(c, g, dtype, n_rhs, std::max(1, (degree + 1) / 2), true);
+      break;
+    case RMH_OP_CHEB_FILTER:
+      plan_cheb(c, g, dtype, n_rhs, std::max(1, degree), false);
+      break;
+    case RMH_OP_RATIONAL_APPLY:
+    case RMH_OP_RATIONAL_APPLY_BWD:
+    case RMH_OP_KINETIC_FORCE: {
+      if (aux < 1) {
+        fail(RMH_E_ARG, "n_poles < 1");
+        return 0;
+      }
+      RationalPlan rp;
+      plan_rational(c, rp, g, n_rhs, aux, mode ? 1 : 0, op);
+      break;
+    }
+    default:
+      fail(RMH_E_ARG, "unknown op %d", op);
+      return 0;
+  }
+  return c.off;
+}
+
+rmh_status rmh_pack_links(const int32_t L[4], const double* U_aos, void* U_soa, int32_t dtype, rmh_stream stream) {
+  Geom g;
+  RMH_TRY(make_geom(L, &g));
+  RMH_TRY(check_dtype(dtype));
+  RMH_TRY(check_ptr(U_aos, "U_aos"));
+  RMH_TRY(check_ptr(U_soa, "U_soa"));
+  if (overlap(U_aos, (size_t)72 * g.V * 8, U_soa, (size_t)72 * g.V * dsize(dtype)))
+    return fail(RMH_E_ARG, "U_soa overlaps U_aos");
+  HIP_TRY(launch_pack_links(g, U_aos, U_soa, dtype, (hipStream_t)stream));
+  return RMH_OK;
+}
+
+rmh_status rmh_unpack_links(const int32_t L[4], const double* U_soa, double* U_aos, rmh_stream stream) {
+  Geom g;
+  RMH_TRY(make_geom(L, &g));
+  RMH_TRY(check_ptr(U_aos, "U_aos"));
+  RMH_TRY(check_ptr(U_soa, "U_soa"));
+  if (overlap(U_aos, (size_t)72 * g.V * 8, U_soa, (size_t)72 * g.V * 8)) return fail(RMH_E_ARG, "U_aos overlaps U_soa");
+  HIP_TRY(launch_unpack_links(g, U_soa, U_aos, (hipStream_t)stream));
+  return RMH_OK;
+}
+
+rmh_status rmh_pack_fields(const int32_t L[4], int32_t n, const double* F_aos, void* F_soa, int32_t dtype,
+                           rmh_stream stream) {
+  Geom g;
+  RMH_TRY(make_geom(L, &g));
+  RMH_TRY(check_dtype(dtype));
+  if (n < 0) return fail(RMH_E_ARG, "n < 0");
+  if (n == 0) return RMH_OK;
+  RMH_TRY(check_ptr(F_aos, "F_aos"));
+  RMH_TRY(check_ptr(F_soa, "F_soa"));
+  if (overlap(F_aos, (size_t)n * 32 * g.V * 8, F_soa, (size_t)n * 32 * g.V * dsize(dtype)))
+    return fail(RMH_E_ARG, "F_soa overlaps F_aos");
+  HIP_TRY(launch_fields_aos_to_soa(g, n, F_aos, F_soa, dtype, (hipStream_t)stream));
+  return RMH_OK;
+}
+
+rmh_status rmh_unpack_fields(const int32_t L[4], int32_t n, const void* F_soa, int32_t dtype, double* F_aos,
+                             rmh_stream stream) {
+  Geom g;
+  RMH_TRY(make_geom(L, &g));
+  RMH_TRY(check_dtype(dtype));
+  if (n < 0) return fail(RMH_E_ARG, "n < 0");
+  if (n == 0) return RMH_OK;
+  RMH_TRY(check_ptr(F_aos, "F_aos"));
+  RMH_TRY(check_ptr(F_soa, "F_soa"));
+  if (overlap(F_aos, (size_t)n * 32 * g.V * 8, F_soa, (size_t)n * 32 * g.V * dsize(dtype)))
+    return fail(RMH_E_ARG, "F_aos overlaps F_soa");
+  HIP_TRY(launch_fields_soa_to_aos(g, n, F_soa, dtype, F_aos, (hipStream_t)stream));
+  return RMH_OK;
+}
+
+rmh_status rmh_convert_f64_f32(const double* in, float* out, int64_t n, rmh_stream stream) {
+  if (n < 0) return fail(RMH_E_ARG, "n < 0");
+  if (n == 0) return RMH_OK;
+  RMH_TRY(check_ptr(in, "in"));
+  RMH_TRY(check_ptr(out, "out"));
+  if (overlap(in, n * 8, out, n * 4)) return fail(RMH_E_ARG, "out overlaps in");
+  HIP_TRY(launch_f64_to_f32(in, out, n, (hipStream_t)stream));
+  return RMH_OK;
+}
+
+rmh_status rmh_laplacian_apply(const int32_t L[4], const void* U, int32_t dtype, const void* x, void* y,
+                               int32_t n_rhs, double shift, rmh_stream stream) {
+  Geom g;
+  RMH_TRY(make_geom(L, &g));
+  RMH_TRY(check_dtype(dtype));
+  if (n_rhs < 0) return fail(RMH_E_ARG, "n_rhs < 0");
+  if (!isfinite(shift)) return fail(RMH_E_ARG, "shift is not finite");
+  if (n_rhs == 0) return RMH_OK;
+  RMH_TRY(check_ptr(U, "U"));
+  RMH_TRY(check_ptr(x, "x"));
+  RMH_TRY(check_ptr(y, "y"));
+  const size_t fb = (size_t)n_rhs * 32 * g.V * dsize(dtype), ub = (size_t)72 * g.V * dsize(dtype);
+  if (overlap(x, fb, y, fb) || overlap(U, ub, y, fb)) return fail(RMH_E_ARG, "y overlaps x or U");
+  const HopConfig cfg = hop_config(g, dtype, n_rhs, 0);
+  if (dtype == RMH_F64) {
+    HopArgs<double> h{};
+    h.g = g;
+    h.U = (const double*)U;
+    h.x = (const double*)x;
+    h.x_mul = 1;
+    h.out = (double*)y;
+    h.z_div = 1;
+    h.a = -1.0;
+    h.b = 8.0 + shift;
+    h.n_rhs = n_rhs;
+    h.store = 1;
+    HIP_TRY(launch_hop<double>(h, cfg, (hipStream_t)stream));
+  } else {
+    HopArgs<float> h{};
+    h.g = g;
+    h.U = (const float*)U;
+    h.x = (const float*)x;
+    h.x_mul = 1;
+    h.out = (float*)y;
+    h.z_div = 1;
+    h.a = -1.0;
+    h.b = 8.0 + shift;
+    h.n_rhs = n_rhs;
+    h.store = 1;
+    HIP_TRY(launch_hop<float>(h, cfg, (hipStream_t)stream));
+  }
+  return RMH_OK;
+}
+
+rmh_status rmh_laplacian_apply_bwd(const int32_t L[4], const void* U, int32_t dtype, const void* x, const void* g_,
+                                   int32_t n_rhs, double shift, void* grad_x, double* grad_omega, int32_t per_rhs,
+                                   rmh_stream stream) {
+  Geom g;
+  RMH_TRY(make_geom(L, &g));
+  RMH_TRY(check_dtype(dtype));
+  if (n_rhs < 0) return fail(RMH_E_ARG, "n_rhs < 0");
+  if (n_rhs == 0) return RMH_OK;
+  RMH_TRY(check_ptr(U, "U"));
+  RMH_TRY(check_ptr(g_, "g"));
+  const size_t fb = (size_t)n_rhs * 32 * g.V * dsize(dtype);
+  if (grad_x) {
+    RMH_TRY(check_ptr(grad_x, "grad_x"));
+    if (overlap(grad_x, fb, g_, fb) || overlap(grad_x, fb, x, fb)) return fail(RMH_E_ARG, "grad_x overlaps an input");
+    RMH_TRY(rmh_laplacian_apply(L, U, dtype, g_, grad_x, n_rhs, shift, stream));
+  }
+  if (grad_omega) {
+    if (dtype != RMH_F64) return fail(RMH_E_ARG, "grad_omega needs RMH_F64 inputs");
+    RMH_TRY(check_ptr(x, "x"));
+    RMH_TRY(check_ptr(grad_omega, "grad_omega"));
+    const size_t gb = (size_t)(per_rhs ? n_rhs : 1) * 32 * g.V * 8;
+    if (overlap(grad_omega, gb, x, fb) || overlap(grad_omega, gb, g_, fb) || overlap(grad_omega, gb, grad_x, fb))
+      return fail(RMH_E_ARG, "grad_omega overlaps another buffer");
+    ForceArgs fa{};
+    fa.g = g;
+    fa.U = (const double*)U;
+    fa.A = (const double*)g_;
+    fa.B = (const double*)x;
+    fa.n_rhs = n_rhs;
+    fa.n_pair = 1;
+    fa.w[0] = 1.0;
+    fa.grad = grad_omega;
+    fa.per_rhs = per_rhs ? 1 : 0;
+    HIP_TRY(launch_force(fa, (hipStream_t)stream));
+  }
+  return RMH_OK;
+}
+
+rmh_status rmh_cheb_coefficients(const rmh_cheb* cheb, double* coef) {
+  if (!cheb || !coef) return fail(RMH_E_ARG, "cheb or coef is NULL");
+  if (cheb->degree < 0 || cheb->n_windows < 1) return fail(RMH_E_ARG, "degree < 0 or n_windows < 1");
+  if (cheb->kernel != 0 && cheb->kernel != 1) return fail(RMH_E_ARG, "kernel must be 0 or 1");
+  if (cheb_window_coefficients(cheb->degree, cheb->n_windows, cheb->edges, cheb->kernel, coef) != 0)
+    return fail(RMH_E_ARG, "window edges must ascend strictly within [0, 16]");
+  return RMH_OK;
+}
+
+rmh_status rmh_power_ratio(const rmh_cheb* cheb, const double* trace_moments, const double* power, int32_t n_rhs,
+                           double* ratio) {
+  if (!cheb || !trace_moments || !power || !ratio) return fail(RMH_E_ARG, "NULL argument");
+  const int32_t D = cheb->degree, nw = cheb->n_windows;
+  std::vector<double> coef((size_t)nw * (D + 1));
+  RMH_TRY(rmh_cheb_coefficients(cheb, coef.data()));
+  for (int32_t w = 0; w < nw; ++w) {
+    double den = 0.0;
+    for (int32_t k = 0; k <= D; ++k) den += coef[(size_t)w * (D + 1) + k] * trace_moments[k];
+    for (int32_t n = 0; n < n_rhs; ++n) ratio[(size_t)n * nw + w] = power[(size_t)n * nw + w] / den;
+  }
+  return RMH_OK;
+}
+
+rmh_status rmh_trace_moments_free(const int32_t L[4], int32_t degree, double* trace_moments) {
+  Geom g;
+  RMH_TRY(make_geom(L, &g));
+  if (degree < 0 || !trace_moments) return fail(RMH_E_ARG, "degree < 0 or NULL output");
+  trace_moments_free(L, degree, trace_moments);
+  return RMH_OK;
+}
+
+rmh_status rmh_power_spectrum(const int32_t L[4], const void* U, int32_t dtype, const void* F, int32_t n_rhs,
+                              const rmh_cheb* cheb, double* moments, double* power, void* ws, size_t ws_bytes,
+                              rmh_stream stream) {
+  Geom g;
+  RMH_TRY(make_geom(L, &g));
+  RMH_TRY(check_dtype(dtype));
+  if (!cheb) return fail(RMH_E_ARG, "cheb is NULL");
+  if (n_rhs < 0) return fail(RMH_E_ARG, "n_rhs < 0");
+  const int32_t D = cheb->degree, nw = cheb->n_windows;
+  if (D < 1 || D > 100000) return fail(RMH_E_ARG, "degree = %d must be in [1, 100000]", D);
+  std::vector<double> coef((size_t)nw * (D + 1));
+  RMH_TRY(rmh_cheb_coefficients(cheb, coef.data()));
+  if (n_rhs == 0) return RMH_OK;
+  RMH_TRY(check_ptr(U, "U"));
+  RMH_TRY(check_ptr(F, "F"));
+  RMH_TRY(check_ptr(ws, "ws"));
+  const int32_t K = std::max(1, (D + 1) / 2);
+  Carver c(ws);
+  ChebPlan cp = plan_cheb(c, g, dtype, n_rhs, K, true);
+  if (c.off > ws_bytes) return fail(RMH_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, c.off);
+  const size_t fb = (size_t)n_rhs * 32 * g.V * dsize(dtype);
+  if (overlap(ws, c.off, F, fb) || overlap(ws, c.off, U, (size_t)72 * g.V * dsize(dtype)))
+    return fail(RMH_E_ARG, "workspace overlaps an input");
+  std::vector<double> sums;
+  hipStream_t s = (hipStream_t)stream;
+  if (dtype == RMH_F64)
+    RMH_TRY(power_spectrum_t<double>(g, (const double*)U, (const double*)F, n_rhs, D, cp, &sums, s));
+  else
+    RMH_TRY(power_spectrum_t<float>(g, (const float*)U, (const float*)F, n_rhs, D, cp, &sums, s));
+  // moments from the doubling identities
+  std::vector<double> mu((size_t)n_rhs * (2 * K + 1));
+  for (int32_t n = 0; n < n_rhs; ++n) {
+    double* m = mu.data() + (size_t)n * (2 * K + 1);
+    auto S = [&](int k, int q) { return sums[((size_t)k * n_rhs + n) * 3 + q]; };
+    m[0] = S(0, 0);
+    m[1] = S(0, 1);
+    m[2] = 2.0 * S(0, 2) - m[0];
+    for (int32_t k = 1; k < K; ++k) {
+      m[2 * k + 1] = 2.0 * S(k, 1) - m[1];
+      m[2 * k + 2] = 2.0 * S(k, 2) - m[0];
+    }
+  }
+  for (int32_t n = 0; n < n_rhs; ++n) {
+    const double* m = mu.data() + (size_t)n * (2 * K + 1);
+    if (moments)
+      for (int32_t k = 0; k <= D; ++k) moments[(size_t)n * (D + 1) + k] = m[k];
+    if (power)
+      for (int32_t w = 0; w < nw; ++w) {
+        double acc = 0.0;
+        for (int32_t k = 0; k <= D; ++k) acc += coef[(size_t)w * (D + 1) + k] * m[k];
+        power[(size_t)n * nw + w] = acc;
+      }
+  }
+  return RMH_OK;
+}
+
+rmh_status rmh_cheb_filter(const int32_t L[4], const void* U, int32_t dtype, const void* x, int32_t n_rhs,
+                           const rmh_cheb* cheb, void* y, void* ws, size_t ws_bytes, rmh_stream stream) {
+  Geom g;
+  RMH_TRY(make_geom(L, &g));
+  RMH_TRY(check_dtype(dtype));
+  if (!cheb) return fail(RMH_E_ARG, "cheb is NULL");
+  if (n_rhs < 0) return fail(RMH_E_ARG, "n_rhs < 0");
+  const int32_t D = cheb->degree, nw = cheb->n_windows;
+  if (D < 1 || D > 100000) return fail(RMH_E_ARG, "degree = %d must be in [1, 100000]", D);
+  if (nw > kMaxFilterWindows) return fail(RMH_E_ARG, "n_windows = %d exceeds %d", nw, kMaxFilterWindows);
+  std::vector<double> coef((size_t)nw * (D + 1));
+  RMH_TRY(rmh_cheb_coefficients(cheb, coef.data()));
+  if (n_rhs == 0) return RMH_OK;
+  RMH_TRY(check_ptr(U, "U"));
+  RMH_TRY(check_ptr(x, "x"));
+  RMH_TRY(check_ptr(y, "y"));
+  RMH_TRY(check_ptr(ws, "ws"));
+  Carver c(ws);
+  ChebPlan cp = plan_cheb(c, g, dtype, n_rhs, D, false);
+  if (c.off > ws_bytes) return fail(RMH_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, c.off);
+  const size_t fb = (size_t)n_rhs * 32 * g.V * dsize(dtype);
+  if (overlap(y, fb * nw, x, fb) || overlap(y, fb * nw, ws, c.off) || overlap(y, fb * nw, U, (size_t)72 * g.V * dsize(dtype)))
+    return fail(RMH_E_ARG, "y overlaps an input or the workspace");
+  hipStream_t s = (hipStream_t)stream;
+  if (dtype == RMH_F64)
+    return cheb_filter_t<double>(g, (const double*)U, (const double*)x, n_rhs, D, nw, coef, cp, (double*)y, s);
+  return cheb_filter_t<float>(g, (const float*)U, (const float*)x, n_rhs, D, nw, coef, cp, (float*)y, s);
+}
+
+rmh_status rmh_cheb_filter_bwd(void) { return fail(RMH_E_UNIMPLEMENTED, "rmh_cheb_filter_bwd is not built"); }
+rmh_status rmh_power_spectrum_bwd(void) { return fail(RMH_E_UNIMPLEMENTED, "rmh_power_spectrum_bwd is not built"); }
+
+rmh_status rmh_rational_from_quadratics(int32_t n_terms, const double* a0, const double* a1, const double* b0,
+                                        const double* b1, double* r, double* sigma) {
+  if (n_terms < 1 || !a0 || !a1 || !b0 || !b1 || !r || !sigma) return fail(RMH_E_ARG, "bad arguments");
+  if (rational_from_quadratics(n_terms, a0, a1, b0, b1, r, sigma) != 0)
+    return fail(RMH_E_POLES, "a quadratic term has no two distinct real roots with positive shifts");
+  return RMH_OK;
+}
+
+rmh_status rmh_rational_kappa(double kappa, int32_t n, double* c, double* r, double* sigma) {
+  if (!c || !r || !sigma) return fail(RMH_E_ARG, "NULL output");
+  if (rational_kappa(kappa, n, c, r, sigma) != 0) return fail(RMH_E_ARG, "need 0 < kappa < 1 and n >= 1");
+  return RMH_OK;
+}
+
+static rmh_status rational_common(const int32_t L[4], const double* U, int32_t n_rhs, const rmh_rational* rat,
+                                  const rmh_solver* sv, Geom* g) {
+  RMH_TRY(make_geom(L, g));
+  if (n_rhs < 0) return fail(RMH_E_ARG, "n_rhs < 0");
+  RMH_TRY(check_rational(rat));
+  RMH_TRY(check_solver(sv));
+  RMH_TRY(check_ptr(U, "U"));
+  return RMH_OK;
+}
+
+rmh_status rmh_rational_apply(const int32_t L[4], const double* U, const double* x, int32_t n_rhs,
+                              const rmh_rational* rat, const rmh_solver* solver, double* y, double* x_poles,
+                              double* K, rmh_stats* stats, void* ws, size_t ws_bytes, rmh_stream stream) {
+  const double t0 = now_s();
+  Geom g;
+  RMH_TRY(rational_common(L, U, n_rhs, rat, solver, &g));
+  if (n_rhs == 0) return RMH_OK;
+  RMH_TRY(check_ptr(x, "x"));
+  RMH_TRY(check_ptr(y, "y"));
+  RMH_TRY(check_ptr(ws, "ws"));
+  const int32_t np = rat->n_poles;
+  Carver c(ws);
+  RationalPlan rp;
+  plan_rational(c, rp, g, n_rhs, np, solver->mode, RMH_OP_RATIONAL_APPLY);
+  if (c.off > ws_bytes) return fail(RMH_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, c.off);
+  const int64_t n = field_reals(g);
+  const size_t fb = (size_t)n_rhs * n * 8, pb = fb * np;
+  if (overlap(y, fb, x, fb) || overlap(y, fb, ws, c.off) || overlap(ws, c.off, x, fb) || overlap(ws, c.off, U, 72 * (size_t)g.V * 8))
+    return fail(RMH_E_ARG, "overlapping buffers");
+  if (x_poles) {
+    RMH_TRY(check_ptr(x_poles, "x_poles"));
+    if (overlap(x_poles, pb, x, fb) || overlap(x_poles, pb, y, fb) || overlap(x_poles, pb, ws, c.off))
+      return fail(RMH_E_ARG, "x_poles overlaps another buffer");
+  }
+  hipStream_t s = (hipStream_t)stream;
+  double* X = x_poles ? x_poles : rp.X;
+  std::vector<double> sig(rat->sigma, rat->sigma + np);
+  SolveResult res;
+  RMH_TRY(solve_all(rp.sp, U, x, X, sig, *solver, s, &res));
+  std::vector<double> coef(np + 1);
+  coef[0] = rat->c;
+  for (int j = 0; j < np; ++j) coef[1 + j] = rat->r[j];
+  RMH_TRY(h2d(rp.coef, coef.data(), coef.size() * 8, s));
+  HIP_TRY(launch_rational_combine(x, X, n_rhs, np, rp.coef, y, n, rp.partK, s));
+  if (K) {
+    HIP_TRY(launch_reduce_rows(rp.partK, elem_num_blocks(n), n_rhs, rp.sumsK, s));
+    RMH_TRY(d2h(K, rp.sumsK, n_rhs * 8, s));
+    for (int v = 0; v < n_rhs; ++v) K[v] *= 0.5;
+  } else {
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  fill_stats(stats, &res, 1, now_s() - t0);
+  return status_of(res, "rational_apply");
+}
+
+// second solve (source g) and the force; X holds the pole solutions of the first solve
+static rmh_status force_from_solves(RationalPlan& rp, const Geom& g, const double* U, const double* X,
+                                    const double* gsrc, int32_t n_rhs, const rmh_rational* rat,
+                                    const rmh_solver* sv, double* grad_x, double* grad_omega, int32_t per_rhs,
+                                    hipStream_t s, SolveResult* res2) {
+  const int32_t np = rat->n_poles;
+  const int64_t n = field_reals(g);
+  std::vector<double> sig(rat->sigma, rat->sigma + np);
+  RMH_TRY(solve_all(rp.sp, U, gsrc, rp.Z, sig, *sv, s, res2));
+  if (grad_x) HIP_TRY(launch_rational_combine(gsrc, rp.Z, n_rhs, np, rp.coef, grad_x, n, nullptr, s));
+  ForceArgs fa{};
+  for (int j = 0; j < np; ++j) fa.w[j] = -rat->r[j];
+  fa.g = g;
+  fa.U = U;
+  fa.A = rp.Z;
+  fa.B = X;
+  fa.n_rhs = n_rhs;
+  fa.n_pair = np;
+  fa.grad = grad_omega;
+  fa.per_rhs = per_rhs ? 1 : 0;
+  HIP_TRY(launch_force(fa, s));
+  return RMH_OK;
+}
+
+rmh_status rmh_rational_apply_bwd(const int32_t L[4], const double* U, const double* x, const double* g_,
+                                  int32_t n_rhs, const rmh_rational* rat, const rmh_solver* solver, double* grad_x,
+                                  double* grad_omega, int32_t per_rhs, rmh_stats* stats, void* ws, size_t ws_bytes,
+                                  rmh_stream stream) {
+  const double t0 = now_s();
+  Geom g;
+  RMH_TRY(rational_common(L, U, n_rhs, rat, solver, &g));
+  if (n_rhs == 0) return RMH_OK;
+  RMH_TRY(check_ptr(x, "x"));
+  RMH_TRY(check_ptr(g_, "g"));
+  RMH_TRY(check_ptr(grad_omega, "grad_omega"));
+  RMH_TRY(check_ptr(ws, "ws"));
+  const int32_t np = rat->n_poles;
+  Carver c(ws);
+  RationalPlan rp;
+  plan_rational(c, rp, g, n_rhs, np, solver->mode, RMH_OP_RATIONAL_APPLY_BWD);
+  if (c.off > ws_bytes) return fail(RMH_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, c.off);
+  const int64_t n = field_reals(g);
+  const size_t fb = (size_t)n_rhs * n * 8, gb = (size_t)(per_rhs ? n_rhs : 1) * n * 8;
+  if (overlap(grad_omega, gb, x, fb) || overlap(grad_omega, gb, g_, fb) || overlap(grad_omega, gb, ws, c.off) ||
+      (grad_x && (overlap(grad_x, fb, x, fb) || overlap(grad_x, fb, g_, fb) || overlap(grad_x, fb, ws, c.off) ||
+                  overlap(grad_x, fb, grad_omega, gb))) ||
+      overlap(ws, c.off, x, fb) || overlap(ws, c.off, g_, fb))
+    return fail(RMH_E_ARG, "overlapping buffers");
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<double> coef(np + 1);
+  coef[0] = rat->c;
+  for (int j = 0; j < np; ++j) coef[1 + j] = rat->r[j];
+  RMH_TRY(h2d(rp.coef, coef.data(), coef.size() * 8, s));
+  std::vector<double> sig(rat->sigma, rat->sigma + np);
+  SolveResult res[2];
+  RMH_TRY(solve_all(rp.sp, U, x, rp.X, sig, *solver, s, &res[0]));
+  RMH_TRY(force_from_solves(rp, g, U, rp.X, g_, n_rhs, rat, solver, grad_x, grad_omega, per_rhs, s, &res[1]));
+  HIP_TRY(hipStreamSynchronize(s));
+  fill_stats(stats, res, 2, now_s() - t0);
+  RMH_TRY(status_of(res[0], "rational_apply_bwd (solve of x)"));
+  return status_of(res[1], "rational_apply_bwd (solve of g)");
+}
+
+rmh_status rmh_kinetic_force(const int32_t L[4], const double* U, const double* P, int32_t n_rhs,
+                             const rmh_rational* rat, const rmh_solver* solver, double* Y, double* K,
+                             double* dK_domega, int32_t per_rhs, rmh_stats* stats, void* ws, size_t ws_bytes,
+                             rmh_stream stream) {
+  const double t0 = now_s();
+  Geom g;
+  RMH_TRY(rational_common(L, U, n_rhs, rat, solver, &g));
+  if (n_rhs == 0) return RMH_OK;
+  RMH_TRY(check_ptr(P, "P"));
+  RMH_TRY(check_ptr(dK_domega, "dK_domega"));
+  RMH_TRY(check_ptr(ws, "ws"));
+  const int32_t np = rat->n_poles;
+  Carver c(ws);
+  RationalPlan rp;
+  plan_rational(c, rp, g, n_rhs, np, solver->mode, RMH_OP_KINETIC_FORCE);
+  if (c.off > ws_bytes) return fail(RMH_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, c.off);
+  const int64_t n = field_reals(g);
+  const size_t fb = (size_t)n_rhs * n * 8, gb = (size_t)(per_rhs ? n_rhs : 1) * n * 8;
+  if (Y) RMH_TRY(check_ptr(Y, "Y"));
+  if (overlap(dK_domega, gb, P, fb) || overlap(dK_domega, gb, ws, c.off) || overlap(ws, c.off, P, fb) ||
+      (Y && (overlap(Y, fb, P, fb) || overlap(Y, fb, ws, c.off) || overlap(Y, fb, dK_domega, gb))))
+    return fail(RMH_E_ARG, "overlapping buffers");
+  hipStream_t s = (hipStream_t)stream;
+  double* Yb = Y ? Y : rp.Y;
+  std::vector<double> coef(np + 1);
+  coef[0] = rat->c;
+  for (int j = 0; j < np; ++j) coef[1 + j] = rat->r[j];
+  RMH_TRY(h2d(rp.coef, coef.data(), coef.size() * 8, s));
+  std::vector<double> sig(rat->sigma, rat->sigma + np);
+  SolveResult res[2];
+  RMH_TRY(solve_all(rp.sp, U, P, rp.X, sig, *solver, s, &res[0]));
+  HIP_TRY(launch_rational_combine(P, rp.X, n_rhs, np, rp.coef, Yb, n, rp.partK, s));
+  if (K) {
+    HIP_TRY(launch_reduce_rows(rp.partK, elem_num_blocks(n), n_rhs, rp.sumsK, s));
+    RMH_TRY(d2h(K, rp.sumsK, n_rhs * 8, s));
+    for (int v = 0; v < n_rhs; ++v) K[v] *= 0.5;
+  }
+  RMH_TRY(force_from_solves(rp, g, U, rp.X, Yb, n_rhs, rat, solver, nullptr, dK_domega, per_rhs, s, &res[1]));
+  HIP_TRY(hipStreamSynchronize(s));
+  fill_stats(stats, res, 2, now_s() - t0);
+  RMH_TRY(status_of(res[0], "kinetic_force (solve of P)"));
+  return status_of(res[1], "kinetic_force (solve of Y)");
+}
+
+rmh_status rmh_tune_set(const int32_t L[4], int32_t dtype, int32_t n_rhs, int32_t form, int32_t block,
+                        int32_t xcd_remap) {
+  Geom g;
+  RMH_TRY(make_geom(L, &g));
+  RMH_TRY(check_dtype(dtype));
+  if (form != kFormAdjoint && form != kFormMatrix) return fail(RMH_E_ARG, "form must be 0 or 1");
+  if (block != 64 && block != 128 && block != 256) return fail(RMH_E_ARG, "block must be 64, 128 or 256");
+  HopConfig c;
+  c.form = form;
+  c.block = block;
+  c.xcd_remap = xcd_remap ? 1 : 0;
+  tune_store(g, dtype, n_rhs, c);
+  return RMH_OK;
+}
+
+rmh_status rmh_tune_clear(void) {
+  tune_clear();
+  return RMH_OK;
+}
+
+rmh_status rmh_autotune_laplacian(const int32_t L[4], const void* U, int32_t dtype, const void* x, void* y,
+                                  int32_t n_rhs, int32_t reps, int32_t* best, double* best_ms, rmh_stream stream) {
+  Geom g;
+  RMH_TRY(make_geom(L, &g));
+  RMH_TRY(check_dtype(dtype));
+  if (n_rhs < 1 || reps < 1) return fail(RMH_E_ARG, "n_rhs and reps must be >= 1");
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  HopConfig bestc;
+  float bt = 1e30f;
+  rmh_status st = RMH_OK;
+  for (int form = 0; form < 2 && st == RMH_OK; ++form)
+    for (int block : {64, 128, 256}) {
+      for (int xcd = 0; xcd < 2 && st == RMH_OK; ++xcd) {
+        HopConfig c;
+        c.form = form;
+        c.block = block;
+        c.xcd_remap = xcd;
+        tune_store(g, dtype, n_rhs, c);
+        st = rmh_laplacian_apply(L, U, dtype, x, y, n_rhs, 0.0, stream);  // warm-up
+        if (st != RMH_OK) break;
+        if (hipEventRecord(e0, s) != hipSuccess) st = fail(RMH_E_HIP, "hipEventRecord");
+        for (int r = 0; r < reps && st == RMH_OK; ++r) st = rmh_laplacian_apply(L, U, dtype, x, y, n_rhs, 0.0, stream);
+        if (st != RMH_OK) break;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+          st = fail(RMH_E_HIP, "hipEventRecord/Synchronize");
+          break;
+        }
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        ms /= reps;
+        if (ms < bt) {
+          bt = ms;
+          bestc = c;
+        }
+      }
+    }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (st != RMH_OK) return st;
+  tune_store(g, dtype, n_rhs, bestc);
+  if (best) {
+    best[0] = bestc.form;
+    best[1] = bestc.block;
+    best[2] = bestc.xcd_remap;
+  }
+  if (best_ms) *best_ms = bt;
+  return RMH_OK;
+}
+
+}  // extern "C"

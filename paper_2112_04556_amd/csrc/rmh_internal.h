@@ -1,0 +1,145 @@
+// Internal declarations shared by the kernel and ABI translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "rmh_device.h"
+
+namespace rmh {
+
+constexpr int kBlock = 256;        // threads per block for site and element kernels
+constexpr int kRedBlock = 256;     // threads of the per-rhs scalar kernels
+constexpr int kMaxFilterWindows = 64;
+
+// Stencil variants chosen by the tuner.
+enum HopForm : int32_t { kFormAdjoint = 0, kFormMatrix = 1 };
+
+struct HopConfig {
+  int32_t form = kFormAdjoint;
+  int32_t block = 256;
+  int32_t xcd_remap = 1;
+};
+
+// out[v] = a * (H x)[v] + b_v * x[v] + c * z[v / z_div]   for v in [0, n_rhs) link fields,
+// where H = sum_mu (forward hop + backward hop), so Delta = 8 - H.
+// Optional: per-block partial dot products, filter accumulation into yacc.
+template <typename T>
+struct HopArgs {
+  Geom g;
+  const T* U;               // [4][18][V]
+  const T* x;               // field index v * x_mul + x_add, [*][4][8][V]
+  int32_t x_mul, x_add;
+  T* out;                   // [n_rhs][4][8][V] (may alias z)
+  const T* z;               // optional, [*][4][8][V]
+  int32_t z_div;            // z field index = v / z_div
+  double a, b, c;
+  const double* b_rhs;      // optional per-field b (device), replaces b
+  int32_t n_rhs;
+  const int32_t* run;       // optional per-field flag (device) run[v * run_stride]: 0 = skip
+  int32_t run_stride;
+  int32_t store;            // write out
+  double* partials;         // [n_rhs][3][nblk]: <x,x>, <out,x>, <out,out>
+  int32_t dot_mask;         // bit q set -> compute dot q
+  // filter accumulation: yacc[w][v] (= y_w) += wcoef[w] * out   (first: y_w = wcoef0[w] x + wcoef[w] out)
+  T* yacc;
+  int32_t n_w;
+  int64_t yacc_stride;      // elements between consecutive windows
+  double wcoef[kMaxFilterWindows];
+  double wcoef0[kMaxFilterWindows];
+  int32_t filter_first;
+};
+
+int hop_num_blocks(const Geom& g, const HopConfig& cfg);
+
+template <typename T>
+hipError_t launch_hop(const HopArgs<T>& args, const HopConfig& cfg, hipStream_t s);
+
+// Element-wise helpers over link fields of 32 V reals each.
+int64_t field_reals(const Geom& g);
+int elem_num_blocks(int64_t n_reals);
+
+hipError_t launch_pack_links(const Geom& g, const double* aos, void* soa, int dtype, hipStream_t s);
+hipError_t launch_unpack_links(const Geom& g, const double* soa, double* aos, hipStream_t s);
+hipError_t launch_fields_aos_to_soa(const Geom& g, int32_t n, const double* aos, void* soa, int dtype,
+                                    hipStream_t s);
+hipError_t launch_fields_soa_to_aos(const Geom& g, int32_t n, const void* soa, int dtype, double* aos,
+                                    hipStream_t s);
+hipError_t launch_f64_to_f32(const double* in, float* out, int64_t n, hipStream_t s);
+hipError_t launch_f32_to_f64(const float* in, double* out, int64_t n, hipStream_t s);
+
+// Reduce partials[m][nblk] -> sums[m] (fixed order), one block per m.
+hipError_t launch_reduce_rows(const double* partials, int32_t nblk, int32_t m, double* sums, hipStream_t s);
+
+// Dot products <a_v, b_v> of n fields (per-block partials [n][nblk_e]).
+template <typename T>
+hipError_t launch_dot(const T* a, const T* b, int64_t n_reals, int32_t n, double* partials, hipStream_t s);
+
+// ---------------------------------------------------------------------------------------------
+// Multi-shift CG engine state (all device pointers, carved from the caller's workspace).
+struct CgDev {
+  int32_t n_rhs, n_shift;
+  double* sc;            // [n_rhs][kScN]
+  double* sh;            // [n_rhs][n_shift][kShN]
+  int32_t* flags;        // [n_rhs][kFlN]
+  int32_t* act;          // [n_rhs][n_shift]
+  int32_t* act_next;     // [n_rhs][n_shift]
+  const double* sigma;   // [n_rhs][n_shift]
+  const int32_t* seed;   // [n_rhs]
+  double* part;          // partials scratch [n_rhs][nblk_max]
+  int32_t nblk_hop, nblk_e;
+};
+// scalar slots per rhs
+enum : int { kScRR = 0, kScAlpha, kScAlphaPrev, kScBetaPrev, kScBnorm2, kScMaxR, kScTolAbs, kScIters,
+             kScRU, kScDelta, kScMaxIter, kScN };
+// per (rhs, shift) slots
+enum : int { kShZeta = 0, kShZetaPrev, kShZetaNext, kShCx, kShCr, kShCp, kShN };
+// int flags per rhs
+// Run: the rhs still iterates (read by the stencil of the next iteration);
+// Live: the current iteration is being carried out (set by the alpha kernel), so the
+// update kernels of the iteration in which a rhs converges still run once.
+enum : int { kFlRun = 0, kFlLive, kFlStatus, kFlNeedRU, kFlRUMask, kFlN };
+enum : int { kStOk = 0, kStNoConv = 1, kStBreakdown = 2 };
+
+hipError_t launch_cg_init(const CgDev& cg, const double* bn2_partials, int32_t nblk, const double* tol_rel,
+                          double delta, int32_t maxiter, hipStream_t s);
+hipError_t launch_cg_alpha(const CgDev& cg, hipStream_t s);
+hipError_t launch_cg_beta(const CgDev& cg, int32_t mixed, hipStream_t s);
+template <typename T>
+hipError_t launch_cg_r_update(const CgDev& cg, T* r, const T* Ap, int64_t n_reals, hipStream_t s);
+template <typename T, typename TX>
+hipError_t launch_cg_shift_update(const CgDev& cg, const T* r, T* p, TX* x, int64_t n_reals, hipStream_t s);
+// mixed precision reliable update pieces
+hipError_t launch_ru_accumulate(const CgDev& cg, float* x_lo, double* x_hi, int64_t n_reals, int32_t all,
+                                hipStream_t s);
+hipError_t launch_ru_finish(const CgDev& cg, hipStream_t s);
+hipError_t launch_ru_convert(const CgDev& cg, const double* r64, float* r, int64_t n_reals, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+template <typename T>
+hipError_t launch_copy_cast(const double* in, T* out, int64_t n, hipStream_t s);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+
+// y[v] = c * x[v] + sum_j r_j * xp[v][j]  (FP64), with optional partial <y,y>
+hipError_t launch_rational_combine(const double* x, const double* xp, int32_t n_rhs, int32_t n_poles,
+                                   const double* coef /* device: c, r_0..r_{n-1} */, double* y,
+                                   int64_t n_reals, double* partials, hipStream_t s);
+// x[v] += e[v] (FP64 axpy with unit weight)
+hipError_t launch_add(double* x, const double* e, int64_t n, hipStream_t s);
+
+// Link derivative: grad[o][mu][c][V] (+)= sum_k w_k d<A_k, Delta B_k>/d omega
+struct ForceArgs {
+  Geom g;
+  const double* U;
+  const double* A;   // [n_rhs][n_pair][4][8][V]
+  const double* B;   // same layout
+  int32_t n_rhs, n_pair;
+  double w[64];      // weight of each pair
+  double* grad;      // [n_out][4][8][V]
+  int32_t per_rhs;
+};
+hipError_t launch_force(const ForceArgs& a, hipStream_t s);
+
+}  // namespace rmh

@@ -1,0 +1,847 @@
+// HIP kernels for gfx950: the adjoint-Laplacian stencil with fused epilogues, layout
+// conversion, deterministic reductions, the multi-shift CG vector and scalar kernels,
+// mixed-precision reliable updates, and the link-derivative (force) kernel.
+//
+// Wave size is 64.  Every reduction is a fixed tree: per-thread FP64 sums, a wave
+// butterfly (__shfl_xor), a fixed-order sum of the waves of a block into one partial
+// per block, then a fixed-order strided sum of the partials in a later kernel, so
+// results are bitwise reproducible run to run.
+#include <hip/hip_runtime.h>
+
+#include "rmh_internal.h"
+
+namespace rmh {
+
+// ------------------------------------------------------------------------------------------
+// reductions
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+// Sum over the block (any multiple of 64 threads up to 1024); result valid in thread 0.
+template <int NQ>
+__device__ __forceinline__ void block_sum(double (&v)[NQ], double (*lds)[16]) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    double w = wave_sum(v[q]);
+    if (lane == 0) lds[q][wid] = w;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      double s = 0.0;
+      for (int i = 0; i < nw; ++i) s += lds[q][i];
+      v[q] = s;
+    }
+  }
+}
+
+// Strided fixed-order sum of n values by a whole block; result in thread 0.
+__device__ double block_sum_array(const double* p, int32_t n, double (*lds)[16]) {
+  double v[1] = {0.0};
+  for (int32_t i = threadIdx.x; i < n; i += blockDim.x) v[0] += p[i];
+  block_sum<1>(v, lds);
+  return v[0];
+}
+
+__device__ __forceinline__ int32_t remap_block(int32_t b, int32_t G, int32_t xcd) {
+  // Consecutive hardware block ids go round-robin over the 8 XCDs; give each XCD a
+  // contiguous range of the lattice so neighbouring sites share its L2.
+  if (xcd && (G & 7) == 0) return (b & 7) * (G >> 3) + (b >> 3);
+  return b;
+}
+
+// ------------------------------------------------------------------------------------------
+// the stencil
+
+template <typename T, int FORM, bool DOTS, bool FILTER>
+__global__ void __launch_bounds__(256) k_hop(const HopArgs<T> A, int32_t xcd) {
+  const int32_t v = blockIdx.y;
+  if (A.run && A.run[(int64_t)v * A.run_stride] == 0) return;
+  const int32_t V = A.g.V;
+  const int32_t blk = remap_block(blockIdx.x, gridDim.x, xcd);
+  const int32_t s = blk * blockDim.x + threadIdx.x;
+  double dsum[3] = {0.0, 0.0, 0.0};
+  if (s < V) {
+    const int64_t FV = 32 * (int64_t)V;
+    const T* __restrict__ xf = A.x + ((int64_t)v * A.x_mul + A.x_add) * FV;
+    const T* __restrict__ U = A.U;
+    T acc[4][8];
+#pragma unroll
+    for (int nu = 0; nu < 4; ++nu)
+#pragma unroll
+      for (int a = 0; a < 8; ++a) acc[nu][a] = T(0);
+    int32_t xc[4];
+    site_coords(A.g, s, xc);
+#pragma unroll 1
+    for (int mu = 0; mu < 4; ++mu) {
+      const T* __restrict__ Um = U + (int64_t)mu * 18 * V;
+      // forward hop: U_mu(x) phi(x+mu) U_mu(x)^dag
+      {
+        const int32_t sf = site_shift(A.g, s, xc, mu, +1);
+        T u[18];
+#pragma unroll
+        for (int c = 0; c < 18; ++c) u[c] = Um[(int64_t)c * V + s];
+        if (FORM == kFormAdjoint) {
+          T R[64];
+          adjoint_matrix<T>(u, R);
+#pragma unroll
+          for (int nu = 0; nu < 4; ++nu) {
+            T phi[8];
+#pragma unroll
+            for (int b = 0; b < 8; ++b) phi[b] = xf[(int64_t)(nu * 8 + b) * V + sf];
+            adj_apply<T>(R, phi, acc[nu]);
+          }
+        } else {
+#pragma unroll
+          for (int nu = 0; nu < 4; ++nu) {
+            T phi[8];
+#pragma unroll
+            for (int b = 0; b < 8; ++b) phi[b] = xf[(int64_t)(nu * 8 + b) * V + sf];
+            mat_hop<T, false>(u, phi, acc[nu]);
+          }
+        }
+      }
+      // backward hop: U_mu(x-mu)^dag phi(x-mu) U_mu(x-mu)
+      {
+        const int32_t sb = site_shift(A.g, s, xc, mu, -1);
+        T u[18];
+#pragma unroll
+        for (int c = 0; c < 18; ++c) u[c] = Um[(int64_t)c * V + sb];
+        if (FORM == kFormAdjoint) {
+          T R[64];
+          adjoint_matrix<T>(u, R);
+#pragma unroll
+          for (int nu = 0; nu < 4; ++nu) {
+            T phi[8];
+#pragma unroll
+            for (int b = 0; b < 8; ++b) phi[b] = xf[(int64_t)(nu * 8 + b) * V + sb];
+            adj_apply_t<T>(R, phi, acc[nu]);
+          }
+        } else {
+#pragma unroll
+          for (int nu = 0; nu < 4; ++nu) {
+            T phi[8];
+#pragma unroll
+            for (int b = 0; b < 8; ++b) phi[b] = xf[(int64_t)(nu * 8 + b) * V + sb];
+            mat_hop<T, true>(u, phi, acc[nu]);
+          }
+        }
+      }
+    }
+    // epilogue: out = a H x + b x + c z
+    const T ca = T(A.a);
+    const T cb = T(A.b_rhs ? A.b_rhs[v] : A.b);
+    const T cc = T(A.c);
+    const T* zf = A.z ? A.z + (int64_t)(v / A.z_div) * FV : nullptr;  // may alias out
+    T* outf = A.out + (int64_t)v * FV;
+#pragma unroll
+    for (int nu = 0; nu < 4; ++nu)
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        const int64_t e = (int64_t)(nu * 8 + a) * V + s;
+        const T xv = xf[e];
+        T o = ca * acc[nu][a] + cb * xv;
+        if (zf) o += cc * zf[e];
+        if (A.store) outf[e] = o;
+        if (DOTS) {
+          const double xd = (double)xv, od = (double)o;
+          dsum[0] += xd * xd;
+          dsum[1] += od * xd;
+          dsum[2] += od * od;
+        }
+        if (FILTER) {
+          T* y = A.yacc + (int64_t)v * FV + e;
+          for (int w = 0; w < A.n_w; ++w) {
+            T* yw = y + w * A.yacc_stride;
+            if (A.filter_first)
+              *yw = T(A.wcoef0[w]) * xv + T(A.wcoef[w]) * o;
+            else
+              *yw += T(A.wcoef[w]) * o;
+          }
+        }
+      }
+  }
+  if (DOTS) {
+    __shared__ double lds[3][16];
+    block_sum<3>(dsum, lds);
+    if (threadIdx.x == 0) {
+      const int32_t nblk = gridDim.x;
+      double* p = A.partials + (int64_t)v * 3 * nblk + blockIdx.x;
+      if (A.dot_mask & 1) p[0] = dsum[0];
+      if (A.dot_mask & 2) p[nblk] = dsum[1];
+      if (A.dot_mask & 4) p[2 * nblk] = dsum[2];
+    }
+  }
+}
+
+int hop_num_blocks(const Geom& g, const HopConfig& cfg) { return (g.V + cfg.block - 1) / cfg.block; }
+
+template <typename T, int FORM>
+static hipError_t launch_hop_form(const HopArgs<T>& A, const HopConfig& cfg, hipStream_t s) {
+  dim3 grid(hop_num_blocks(A.g, cfg), A.n_rhs), block(cfg.block);
+  const bool dots = A.partials && A.dot_mask;
+  const bool filt = A.yacc && A.n_w > 0;
+  if (dots && filt)
+    hipLaunchKernelGGL((k_hop<T, FORM, true, true>), grid, block, 0, s, A, cfg.xcd_remap);
+  else if (dots)
+    hipLaunchKernelGGL((k_hop<T, FORM, true, false>), grid, block, 0, s, A, cfg.xcd_remap);
+  else if (filt)
+    hipLaunchKernelGGL((k_hop<T, FORM, false, true>), grid, block, 0, s, A, cfg.xcd_remap);
+  else
+    hipLaunchKernelGGL((k_hop<T, FORM, false, false>), grid, block, 0, s, A, cfg.xcd_remap);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_hop(const HopArgs<T>& A, const HopConfig& cfg, hipStream_t s) {
+  if (A.n_rhs == 0 || A.g.V == 0) return hipSuccess;
+  if (cfg.form == kFormMatrix) return launch_hop_form<T, kFormMatrix>(A, cfg, s);
+  return launch_hop_form<T, kFormAdjoint>(A, cfg, s);
+}
+template hipError_t launch_hop<double>(const HopArgs<double>&, const HopConfig&, hipStream_t);
+template hipError_t launch_hop<float>(const HopArgs<float>&, const HopConfig&, hipStream_t);
+
+// ------------------------------------------------------------------------------------------
+// element-wise helpers
+
+int64_t field_reals(const Geom& g) { return 32 * (int64_t)g.V; }
+int elem_num_blocks(int64_t n_reals) { return (int)((n_reals / 4 + kBlock - 1) / kBlock); }
+
+template <typename T>
+__global__ void k_dot(const T* __restrict__ a, const T* __restrict__ b, int64_t n, double* partials) {
+  const int32_t v = blockIdx.y;
+  const T* av = a + (int64_t)v * n;
+  const T* bv = b + (int64_t)v * n;
+  double d[1] = {0.0};
+  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  if (i0 < n) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) d[0] += (double)av[i0 + k] * (double)bv[i0 + k];
+  }
+  __shared__ double lds[1][16];
+  block_sum<1>(d, lds);
+  if (threadIdx.x == 0) partials[(int64_t)v * gridDim.x + blockIdx.x] = d[0];
+}
+
+template <typename T>
+hipError_t launch_dot(const T* a, const T* b, int64_t n_reals, int32_t n, double* partials, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  dim3 grid(elem_num_blocks(n_reals), n);
+  hipLaunchKernelGGL((k_dot<T>), grid, dim3(kBlock), 0, s, a, b, n_reals, partials);
+  return hipGetLastError();
+}
+template hipError_t launch_dot<double>(const double*, const double*, int64_t, int32_t, double*, hipStream_t);
+template hipError_t launch_dot<float>(const float*, const float*, int64_t, int32_t, double*, hipStream_t);
+
+__global__ void k_reduce_rows(const double* partials, int32_t nblk, double* sums) {
+  __shared__ double lds[1][16];
+  const double v = block_sum_array(partials + (int64_t)blockIdx.x * nblk, nblk, lds);
+  if (threadIdx.x == 0) sums[blockIdx.x] = v;
+}
+
+hipError_t launch_reduce_rows(const double* partials, int32_t nblk, int32_t m, double* sums, hipStream_t s) {
+  if (m == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce_rows, dim3(m), dim3(kRedBlock), 0, s, partials, nblk, sums);
+  return hipGetLastError();
+}
+
+__global__ void k_zero(uint32_t* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+  // every buffer is carved at 256-byte granularity, so bytes is a multiple of 4
+  const int64_t n = (int64_t)(bytes / 4);
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                     (uint32_t*)p, n);
+  return hipGetLastError();
+}
+
+__global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+template <typename TI, typename TO>
+__global__ void k_cast(const TI* __restrict__ in, TO* __restrict__ out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (TO)in[i];  // FP64 -> FP32 rounds to nearest even
+}
+
+hipError_t launch_f64_to_f32(const double* in, float* out, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_cast<double, float>), dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                     in, out, n);
+  return hipGetLastError();
+}
+hipError_t launch_f32_to_f64(const float* in, double* out, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_cast<float, double>), dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                     in, out, n);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_copy_cast(const double* in, T* out, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_cast<double, T>), dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, in,
+                     out, n);
+  return hipGetLastError();
+}
+template hipError_t launch_copy_cast<double>(const double*, double*, int64_t, hipStream_t);
+template hipError_t launch_copy_cast<float>(const double*, float*, int64_t, hipStream_t);
+
+__global__ void k_add(double* __restrict__ x, const double* __restrict__ e, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] += e[i];
+}
+hipError_t launch_add(double* x, const double* e, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_add, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, x, e, n);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// layout conversion (bitwise: pure data movement plus FP64 -> FP32 round to nearest even)
+
+template <typename T>
+__global__ void k_pack_links(Geom g, const double* __restrict__ aos, T* __restrict__ soa) {
+  const int32_t mu = blockIdx.y;
+  const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= g.V) return;
+  const double* src = aos + ((int64_t)mu * g.V + s) * 18;
+#pragma unroll
+  for (int c = 0; c < 18; ++c) soa[((int64_t)mu * 18 + c) * g.V + s] = (T)src[c];
+}
+
+__global__ void k_unpack_links(Geom g, const double* __restrict__ soa, double* __restrict__ aos) {
+  const int32_t mu = blockIdx.y;
+  const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= g.V) return;
+  double* dst = aos + ((int64_t)mu * g.V + s) * 18;
+#pragma unroll
+  for (int c = 0; c < 18; ++c) dst[c] = soa[((int64_t)mu * 18 + c) * g.V + s];
+}
+
+hipError_t launch_pack_links(const Geom& g, const double* aos, void* soa, int dtype, hipStream_t s) {
+  dim3 grid((g.V + kBlock - 1) / kBlock, 4);
+  if (dtype == 0)
+    hipLaunchKernelGGL((k_pack_links<double>), grid, dim3(kBlock), 0, s, g, aos, (double*)soa);
+  else
+    hipLaunchKernelGGL((k_pack_links<float>), grid, dim3(kBlock), 0, s, g, aos, (float*)soa);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack_links(const Geom& g, const double* soa, double* aos, hipStream_t s) {
+  dim3 grid((g.V + kBlock - 1) / kBlock, 4);
+  hipLaunchKernelGGL(k_unpack_links, grid, dim3(kBlock), 0, s, g, soa, aos);
+  return hipGetLastError();
+}
+
+// fields: AoS [n][V][4][8]  <->  SoA [n][4][8][V]
+template <typename T>
+__global__ void k_fields_aos_to_soa(Geom g, const double* __restrict__ aos, T* __restrict__ soa) {
+  const int32_t n = blockIdx.y;
+  const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= g.V) return;
+  const double* src = aos + ((int64_t)n * g.V + s) * 32;
+  T* dst = soa + (int64_t)n * 32 * g.V;
+#pragma unroll
+  for (int c = 0; c < 32; ++c) dst[(int64_t)c * g.V + s] = (T)src[c];
+}
+
+template <typename T>
+__global__ void k_fields_soa_to_aos(Geom g, const T* __restrict__ soa, double* __restrict__ aos) {
+  const int32_t n = blockIdx.y;
+  const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= g.V) return;
+  double* dst = aos + ((int64_t)n * g.V + s) * 32;
+  const T* src = soa + (int64_t)n * 32 * g.V;
+#pragma unroll
+  for (int c = 0; c < 32; ++c) dst[c] = (double)src[(int64_t)c * g.V + s];
+}
+
+hipError_t launch_fields_aos_to_soa(const Geom& g, int32_t n, const double* aos, void* soa, int dtype,
+                                    hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  dim3 grid((g.V + kBlock - 1) / kBlock, n);
+  if (dtype == 0)
+    hipLaunchKernelGGL((k_fields_aos_to_soa<double>), grid, dim3(kBlock), 0, s, g, aos, (double*)soa);
+  else
+    hipLaunchKernelGGL((k_fields_aos_to_soa<float>), grid, dim3(kBlock), 0, s, g, aos, (float*)soa);
+  return hipGetLastError();
+}
+
+hipError_t launch_fields_soa_to_aos(const Geom& g, int32_t n, const void* soa, int dtype, double* aos,
+                                    hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  dim3 grid((g.V + kBlock - 1) / kBlock, n);
+  if (dtype == 0)
+    hipLaunchKernelGGL((k_fields_soa_to_aos<double>), grid, dim3(kBlock), 0, s, g, (const double*)soa, aos);
+  else
+    hipLaunchKernelGGL((k_fields_soa_to_aos<float>), grid, dim3(kBlock), 0, s, g, (const float*)soa, aos);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// multi-shift CG (Jegerlehner's shifted recurrences on a seed system; every shift's
+// residual is zeta_j times the seed residual)
+
+__global__ void k_cg_init(CgDev cg, const double* bn2_part, int32_t nblk, const double* tol_rel, double delta,
+                          int32_t maxiter) {
+  __shared__ double lds[1][16];
+  const int32_t v = blockIdx.x;
+  const double bn2 = block_sum_array(bn2_part + (int64_t)v * nblk, nblk, lds);
+  __shared__ double s_bn2;
+  if (threadIdx.x == 0) {
+    double* sc = cg.sc + (int64_t)v * kScN;
+    int32_t* fl = cg.flags + (int64_t)v * kFlN;
+    sc[kScRR] = bn2;
+    sc[kScBnorm2] = bn2;
+    sc[kScAlpha] = 0.0;
+    sc[kScAlphaPrev] = 1.0;
+    sc[kScBetaPrev] = 0.0;
+    sc[kScMaxR] = sqrt(bn2);
+    sc[kScTolAbs] = tol_rel[v] * sqrt(bn2);
+    sc[kScIters] = 0.0;
+    sc[kScRU] = 0.0;
+    sc[kScDelta] = delta;
+    sc[kScMaxIter] = (double)maxiter;
+    fl[kFlRun] = (bn2 > 0.0) ? 1 : 0;
+    fl[kFlStatus] = (bn2 == bn2) ? kStOk : kStBreakdown;   // NaN source
+    if (!(bn2 == bn2)) fl[kFlRun] = 0;
+    fl[kFlNeedRU] = 0;
+    fl[kFlRUMask] = 0;
+    fl[kFlLive] = 0;
+    s_bn2 = bn2;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < cg.n_shift; j += blockDim.x) {
+    double* sh = cg.sh + ((int64_t)v * cg.n_shift + j) * kShN;
+    sh[kShZeta] = 1.0;
+    sh[kShZetaPrev] = 1.0;
+    sh[kShZetaNext] = 1.0;
+    sh[kShCx] = 0.0;
+    sh[kShCr] = 0.0;
+    sh[kShCp] = 0.0;
+    const int32_t on = (s_bn2 > 0.0) ? 1 : 0;
+    cg.act[(int64_t)v * cg.n_shift + j] = on;
+    cg.act_next[(int64_t)v * cg.n_shift + j] = on;
+  }
+}
+
+hipError_t launch_cg_init(const CgDev& cg, const double* bn2_partials, int32_t nblk, const double* tol_rel,
+                          double delta, int32_t maxiter, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_init, dim3(cg.n_rhs), dim3(kRedBlock), 0, s, cg, bn2_partials, nblk, tol_rel, delta,
+                     maxiter);
+  return hipGetLastError();
+}
+
+// alpha_k = rr / <p, A0 p>;  zeta_{k+1}^j and the x-update coefficient of every active shift
+__global__ void k_cg_alpha(CgDev cg) {
+  const int32_t v = blockIdx.x;
+  int32_t* fl = cg.flags + (int64_t)v * kFlN;
+  if (fl[kFlRun] == 0) {
+    if (threadIdx.x == 0) fl[kFlLive] = 0;
+    return;
+  }
+  __shared__ double lds[1][16];
+  const double pAp = block_sum_array(cg.part + ((int64_t)v * 3 + 1) * cg.nblk_hop, cg.nblk_hop, lds);
+  __shared__ double s_alpha;
+  __shared__ int s_ok;
+  double* sc = cg.sc + (int64_t)v * kScN;
+  if (threadIdx.x == 0) {
+    const double rr = sc[kScRR];
+    const double alpha = rr / pAp;
+    s_ok = (pAp > 0.0 && alpha == alpha && alpha < 1e300) ? 1 : 0;
+    s_alpha = alpha;
+    if (s_ok) {
+      sc[kScAlpha] = alpha;
+      fl[kFlLive] = 1;
+    } else {
+      fl[kFlStatus] = kStBreakdown;
+      fl[kFlRun] = 0;
+      fl[kFlLive] = 0;
+    }
+  }
+  __syncthreads();
+  if (!s_ok) return;
+  const double alpha = s_alpha;
+  const double ap = sc[kScAlphaPrev], bp = sc[kScBetaPrev];
+  const double s0 = cg.sigma[(int64_t)v * cg.n_shift + cg.seed[v]];
+  for (int j = threadIdx.x; j < cg.n_shift; j += blockDim.x) {
+    const int64_t vj = (int64_t)v * cg.n_shift + j;
+    const int32_t on = cg.act_next[vj];
+    cg.act[vj] = on;
+    double* sh = cg.sh + vj * kShN;
+    if (on) {
+      const double z = sh[kShZeta], zp = sh[kShZetaPrev];
+      const double ds = cg.sigma[vj] - s0;
+      const double zn = z * zp * ap / (ap * zp * (1.0 + alpha * ds) + alpha * bp * (zp - z));
+      sh[kShZetaNext] = zn;
+      sh[kShCx] = alpha * zn / z;
+    } else {
+      sh[kShCx] = 0.0;
+    }
+  }
+}
+
+hipError_t launch_cg_alpha(const CgDev& cg, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_alpha, dim3(cg.n_rhs), dim3(kRedBlock), 0, s, cg);
+  return hipGetLastError();
+}
+
+// beta_k = rr_new / rr; shifted beta and p-update coefficients; convergence and freezing
+__global__ void k_cg_beta(CgDev cg, int32_t mixed) {
+  const int32_t v = blockIdx.x;
+  int32_t* fl = cg.flags + (int64_t)v * kFlN;
+  if (fl[kFlLive] == 0) return;
+  __shared__ double lds[1][16];
+  const double rrn = block_sum_array(cg.part + (int64_t)v * cg.nblk_e, cg.nblk_e, lds);
+  double* sc = cg.sc + (int64_t)v * kScN;
+  const double beta = rrn / sc[kScRR];
+  const double rnorm = sqrt(rrn);
+  const double tolabs = sc[kScTolAbs];
+  const int32_t seed = cg.seed[v];
+  int any_other = 0;
+  for (int j = threadIdx.x; j < cg.n_shift; j += blockDim.x) {
+    const int64_t vj = (int64_t)v * cg.n_shift + j;
+    double* sh = cg.sh + vj * kShN;
+    if (cg.act[vj]) {
+      const double z = sh[kShZeta], zn = sh[kShZetaNext];
+      const double ratio = zn / z;
+      sh[kShCr] = zn;
+      sh[kShCp] = beta * ratio * ratio;
+      const int32_t keep = (fabs(zn) * rnorm > tolabs) ? 1 : 0;
+      cg.act_next[vj] = keep;
+      if (j != seed) any_other |= keep;
+      sh[kShZetaPrev] = z;
+      sh[kShZeta] = zn;
+    } else {
+      cg.act_next[vj] = 0;
+    }
+  }
+  any_other = __syncthreads_or(any_other);
+  if (threadIdx.x == 0) {
+    const int64_t vs = (int64_t)v * cg.n_shift + seed;
+    if (any_other) cg.act_next[vs] = 1;     // the seed carries the Krylov space for the others
+    const int32_t any = any_other | cg.act_next[vs];
+    sc[kScAlphaPrev] = sc[kScAlpha];
+    sc[kScBetaPrev] = beta;
+    sc[kScRR] = rrn;
+    sc[kScIters] += 1.0;
+    if (!(rrn == rrn)) {
+      fl[kFlStatus] = kStBreakdown;
+      fl[kFlRun] = 0;
+    } else if (!any) {
+      fl[kFlRun] = 0;
+    } else if (sc[kScIters] >= sc[kScMaxIter]) {
+      fl[kFlStatus] = kStNoConv;
+      fl[kFlRun] = 0;
+    }
+    if (mixed) {
+      if (rnorm > sc[kScMaxR]) sc[kScMaxR] = rnorm;
+      if (rnorm < sc[kScDelta] * sc[kScMaxR]) fl[kFlNeedRU] = 1;
+    }
+  }
+}
+
+hipError_t launch_cg_beta(const CgDev& cg, int32_t mixed, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_beta, dim3(cg.n_rhs), dim3(kRedBlock), 0, s, cg, mixed);
+  return hipGetLastError();
+}
+
+// r -= alpha Ap, partial <r, r>
+template <typename T>
+__global__ void k_cg_r(CgDev cg, T* __restrict__ r, const T* __restrict__ Ap, int64_t n) {
+  const int32_t v = blockIdx.y;
+  if (cg.flags[(int64_t)v * kFlN + kFlLive] == 0) return;
+  const T alpha = (T)cg.sc[(int64_t)v * kScN + kScAlpha];
+  T* rv = r + (int64_t)v * n;
+  const T* av = Ap + (int64_t)v * n;
+  double d[1] = {0.0};
+  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  if (i0 < n) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const T rn = rv[i0 + k] - alpha * av[i0 + k];
+      rv[i0 + k] = rn;
+      d[0] += (double)rn * (double)rn;
+    }
+  }
+  __shared__ double lds[1][16];
+  block_sum<1>(d, lds);
+  if (threadIdx.x == 0) cg.part[(int64_t)v * cg.nblk_e + blockIdx.x] = d[0];
+}
+
+template <typename T>
+hipError_t launch_cg_r_update(const CgDev& cg, T* r, const T* Ap, int64_t n_reals, hipStream_t s) {
+  dim3 grid(elem_num_blocks(n_reals), cg.n_rhs);
+  hipLaunchKernelGGL((k_cg_r<T>), grid, dim3(kBlock), 0, s, cg, r, Ap, n_reals);
+  return hipGetLastError();
+}
+template hipError_t launch_cg_r_update<double>(const CgDev&, double*, const double*, int64_t, hipStream_t);
+template hipError_t launch_cg_r_update<float>(const CgDev&, float*, const float*, int64_t, hipStream_t);
+
+// x_j += cx_j p_j (shifts updated this iteration); p_j = cr_j r + cp_j p_j (shifts still active)
+template <typename T, typename TX>
+__global__ void k_cg_shift(CgDev cg, const T* __restrict__ r, T* __restrict__ p, TX* __restrict__ x,
+                           int64_t n) {
+  const int32_t v = blockIdx.y;
+  if (cg.flags[(int64_t)v * kFlN + kFlLive] == 0) return;
+  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  if (i0 >= n) return;
+  T rv[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) rv[k] = r[(int64_t)v * n + i0 + k];
+  for (int j = 0; j < cg.n_shift; ++j) {
+    const int64_t vj = (int64_t)v * cg.n_shift + j;
+    const int32_t ux = cg.act[vj];
+    const int32_t up = cg.act_next[vj];
+    if (!ux) continue;
+    const double* sh = cg.sh + vj * kShN;
+    const T cx = (T)sh[kShCx];
+    T* pj = p + vj * n + i0;
+    TX* xj = x + vj * n + i0;
+    T pv[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pv[k] = pj[k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) xj[k] += (TX)(cx * pv[k]);
+    if (up) {
+      const T cr = (T)sh[kShCr], cp = (T)sh[kShCp];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) pj[k] = cr * rv[k] + cp * pv[k];
+    }
+  }
+}
+
+template <typename T, typename TX>
+hipError_t launch_cg_shift_update(const CgDev& cg, const T* r, T* p, TX* x, int64_t n_reals, hipStream_t s) {
+  dim3 grid(elem_num_blocks(n_reals), cg.n_rhs);
+  hipLaunchKernelGGL((k_cg_shift<T, TX>), grid, dim3(kBlock), 0, s, cg, r, p, x, n_reals);
+  return hipGetLastError();
+}
+template hipError_t launch_cg_shift_update<double, double>(const CgDev&, const double*, double*, double*,
+                                                             int64_t, hipStream_t);
+template hipError_t launch_cg_shift_update<float, float>(const CgDev&, const float*, float*, float*, int64_t,
+                                                           hipStream_t);
+
+// reliable update: x_hi += x_lo, x_lo = 0 for every shift of the flagged rhs
+__global__ void k_ru_accumulate(CgDev cg, float* __restrict__ x_lo, double* __restrict__ x_hi, int64_t n,
+                                int32_t all) {
+  const int32_t v = blockIdx.y;
+  if (!all && cg.flags[(int64_t)v * kFlN + kFlNeedRU] == 0) return;
+  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  if (i0 >= n) return;
+  for (int j = 0; j < cg.n_shift; ++j) {
+    const int64_t off = ((int64_t)v * cg.n_shift + j) * n + i0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      x_hi[off + k] += (double)x_lo[off + k];
+      x_lo[off + k] = 0.0f;
+    }
+  }
+}
+
+hipError_t launch_ru_accumulate(const CgDev& cg, float* x_lo, double* x_hi, int64_t n_reals, int32_t all,
+                                hipStream_t s) {
+  dim3 grid(elem_num_blocks(n_reals), cg.n_rhs);
+  hipLaunchKernelGGL(k_ru_accumulate, grid, dim3(kBlock), 0, s, cg, x_lo, x_hi, n_reals, all);
+  return hipGetLastError();
+}
+
+// after the FP64 true residual r64 = b - (Delta + sigma0) x_hi of the flagged rhs
+__global__ void k_ru_finish(CgDev cg) {
+  const int32_t v = blockIdx.x;
+  int32_t* fl = cg.flags + (int64_t)v * kFlN;
+  const int32_t need = fl[kFlNeedRU];
+  __shared__ double lds[1][16];
+  if (!need) {
+    if (threadIdx.x == 0) fl[kFlRUMask] = 0;
+    return;
+  }
+  const double rr = block_sum_array(cg.part + ((int64_t)v * 3 + 2) * cg.nblk_hop, cg.nblk_hop, lds);
+  if (threadIdx.x == 0) {
+    double* sc = cg.sc + (int64_t)v * kScN;
+    sc[kScRR] = rr;
+    sc[kScMaxR] = sqrt(rr);
+    sc[kScRU] += 1.0;
+    fl[kFlNeedRU] = 0;
+    fl[kFlRUMask] = 1;
+  }
+}
+
+hipError_t launch_ru_finish(const CgDev& cg, hipStream_t s) {
+  hipLaunchKernelGGL(k_ru_finish, dim3(cg.n_rhs), dim3(kRedBlock), 0, s, cg);
+  return hipGetLastError();
+}
+
+__global__ void k_ru_convert(CgDev cg, const double* __restrict__ r64, float* __restrict__ r, int64_t n) {
+  const int32_t v = blockIdx.y;
+  if (cg.flags[(int64_t)v * kFlN + kFlRUMask] == 0) return;
+  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  if (i0 >= n) return;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) r[(int64_t)v * n + i0 + k] = (float)r64[(int64_t)v * n + i0 + k];
+}
+
+hipError_t launch_ru_convert(const CgDev& cg, const double* r64, float* r, int64_t n_reals, hipStream_t s) {
+  dim3 grid(elem_num_blocks(n_reals), cg.n_rhs);
+  hipLaunchKernelGGL(k_ru_convert, grid, dim3(kBlock), 0, s, cg, r64, r, n_reals);
+  return hipGetLastError();
+}
+
+// y = c x + sum_j r_j x_j  (FP64) with partial <y, y>
+__global__ void k_rational_combine(const double* __restrict__ x, const double* __restrict__ xp, int32_t n_poles,
+                                   const double* __restrict__ coef, double* __restrict__ y, int64_t n,
+                                   double* partials) {
+  const int32_t v = blockIdx.y;
+  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  double d[1] = {0.0};
+  if (i0 < n) {
+    const double c = coef[0];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      double acc = c * x[(int64_t)v * n + i0 + k];
+      for (int j = 0; j < n_poles; ++j) acc += coef[1 + j] * xp[((int64_t)v * n_poles + j) * n + i0 + k];
+      y[(int64_t)v * n + i0 + k] = acc;
+      d[0] += acc * acc;
+    }
+  }
+  if (partials) {
+    __shared__ double lds[1][16];
+    block_sum<1>(d, lds);
+    if (threadIdx.x == 0) partials[(int64_t)v * gridDim.x + blockIdx.x] = d[0];
+  }
+}
+
+hipError_t launch_rational_combine(const double* x, const double* xp, int32_t n_rhs, int32_t n_poles,
+                                   const double* coef, double* y, int64_t n_reals, double* partials,
+                                   hipStream_t s) {
+  if (n_rhs == 0) return hipSuccess;
+  dim3 grid(elem_num_blocks(n_reals), n_rhs);
+  hipLaunchKernelGGL(k_rational_combine, grid, dim3(kBlock), 0, s, x, xp, n_poles, coef, y, n_reals, partials);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// link derivative
+//
+// For the link U = U_mu(x):  d<A, Delta B>/d omega^c = sum_{d,e} f^{dec} (R(U) C)^{de},
+// C^{be} = B(x+mu)^b A(x)^e + A(x+mu)^b B(x)^e (summed over nu and over the pairs with
+// weights w_k).  f^{abc} are the su(3) structure constants; with the antisymmetric part
+// S = RC - (RC)^T each independent triple (a, b, c; f) contributes
+// f S_ab to component c, f S_bc to component a and f S_ca to component b.
+
+struct FTriple {
+  int a, b, c;
+  double f;
+};
+__constant__ FTriple kF[9] = {{0, 1, 2, 1.0},
+                              {0, 3, 6, 0.5},
+                              {0, 4, 5, -0.5},
+                              {1, 3, 5, 0.5},
+                              {1, 4, 6, 0.5},
+                              {2, 3, 4, 0.5},
+                              {2, 5, 6, -0.5},
+                              {3, 4, 7, 0.86602540378443864676},
+                              {5, 6, 7, 0.86602540378443864676}};
+
+__global__ void __launch_bounds__(256) k_force(const ForceArgs F, int32_t xcd) {
+  const int32_t o = blockIdx.y;
+  const int32_t V = F.g.V;
+  const int32_t blk = remap_block(blockIdx.x, gridDim.x, xcd);
+  const int32_t s = blk * blockDim.x + threadIdx.x;
+  if (s >= V) return;
+  const int64_t FV = 32 * (int64_t)V;
+  int32_t xc[4];
+  site_coords(F.g, s, xc);
+  const int32_t r0 = F.per_rhs ? o : 0;
+  const int32_t r1 = F.per_rhs ? o + 1 : F.n_rhs;
+#pragma unroll 1
+  for (int mu = 0; mu < 4; ++mu) {
+    const int32_t sf = site_shift(F.g, s, xc, mu, +1);
+    double C[64];
+#pragma unroll
+    for (int i = 0; i < 64; ++i) C[i] = 0.0;
+#pragma unroll 1
+    for (int32_t rh = r0; rh < r1; ++rh)
+#pragma unroll 1
+      for (int32_t k = 0; k < F.n_pair; ++k) {
+        const double w = F.w[k];
+        const double* Ak = F.A + ((int64_t)rh * F.n_pair + k) * FV;
+        const double* Bk = F.B + ((int64_t)rh * F.n_pair + k) * FV;
+#pragma unroll 1
+        for (int nu = 0; nu < 4; ++nu) {
+          double ax[8], bx[8], af[8], bf[8];
+#pragma unroll
+          for (int a = 0; a < 8; ++a) {
+            const int64_t e = (int64_t)(nu * 8 + a) * V;
+            ax[a] = w * Ak[e + s];
+            bx[a] = w * Bk[e + s];
+            af[a] = Ak[e + sf];
+            bf[a] = Bk[e + sf];
+          }
+#pragma unroll
+          for (int b = 0; b < 8; ++b)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) C[b * 8 + e] += bf[b] * ax[e] + af[b] * bx[e];
+        }
+      }
+    double u[18];
+    const double* Um = F.U + (int64_t)mu * 18 * V;
+#pragma unroll
+    for (int c = 0; c < 18; ++c) u[c] = Um[(int64_t)c * V + s];
+    double R[64];
+    adjoint_matrix<double>(u, R);
+    double RC[64];
+#pragma unroll
+    for (int d = 0; d < 8; ++d)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        double t = 0.0;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) t += R[d * 8 + b] * C[b * 8 + e];
+        RC[d * 8 + e] = t;
+      }
+    double G[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) G[c] = 0.0;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int a = kF[t].a, b = kF[t].b, c = kF[t].c;
+      const double f = kF[t].f;
+      G[c] += f * (RC[a * 8 + b] - RC[b * 8 + a]);
+      G[a] += f * (RC[b * 8 + c] - RC[c * 8 + b]);
+      G[b] += f * (RC[c * 8 + a] - RC[a * 8 + c]);
+    }
+    double* go = F.grad + ((int64_t)o * 4 + mu) * 8 * V;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) go[(int64_t)c * V + s] = G[c];
+  }
+}
+
+hipError_t launch_force(const ForceArgs& a, hipStream_t s) {
+  const int32_t n_out = a.per_rhs ? a.n_rhs : 1;
+  if (n_out == 0) return hipSuccess;
+  dim3 grid((a.g.V + kBlock - 1) / kBlock, n_out);
+  hipLaunchKernelGGL(k_force, grid, dim3(kBlock), 0, s, a, 1);
+  return hipGetLastError();
+}
+
+}  // namespace rmh

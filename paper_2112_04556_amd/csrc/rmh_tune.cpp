@@ -1,0 +1,68 @@
+// Stencil launch configuration cache.  Entries are keyed by lattice extents, dtype and
+// the number of link fields per launch; the autotuner (rmh_autotune_laplacian) fills
+// them from timed candidates, otherwise the defaults apply.  RMH_HOP_FORM (0 adjoint,
+// 1 matrix) and RMH_HOP_BLOCK override the defaults for experiments.
+#include <stdlib.h>
+
+#include <cstdlib>
+
+#include <map>
+#include <mutex>
+#include <tuple>
+
+#include "rmh_tune.h"
+
+namespace rmh {
+
+namespace {
+using Key = std::tuple<int32_t, int32_t, int32_t, int32_t, int32_t, int32_t>;
+std::mutex g_mu;
+std::map<Key, HopConfig> g_cache;
+
+Key key_of(const Geom& g, int32_t dtype, int32_t n_rhs) {
+  return Key(g.L0, g.L1, g.L2, g.L3, dtype, n_rhs);
+}
+
+HopConfig defaults() {
+  HopConfig c;
+  if (const char* e = getenv("RMH_HOP_FORM")) c.form = atoi(e) ? kFormMatrix : kFormAdjoint;
+  if (const char* e = getenv("RMH_HOP_BLOCK")) {
+    const int b = atoi(e);
+    if (b == 64 || b == 128 || b == 256) c.block = b;
+  }
+  return c;
+}
+}  // namespace
+
+HopConfig tune_hop(const Geom& g, int32_t dtype, int32_t n_rhs, int32_t /*purpose*/) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_cache.find(key_of(g, dtype, n_rhs));
+  if (it != g_cache.end()) return it->second;
+  // else the entry of this lattice and dtype with the nearest batch size
+  const HopConfig* best = nullptr;
+  int32_t dist = 0;
+  for (auto& kv : g_cache) {
+    const Key& k = kv.first;
+    if (std::get<0>(k) != g.L0 || std::get<1>(k) != g.L1 || std::get<2>(k) != g.L2 || std::get<3>(k) != g.L3 ||
+        std::get<4>(k) != dtype)
+      continue;
+    const int32_t d = std::abs(std::get<5>(k) - n_rhs);
+    if (!best || d < dist) {
+      best = &kv.second;
+      dist = d;
+    }
+  }
+  return best ? *best : defaults();
+}
+
+void tune_clear() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_cache.clear();
+}
+
+void tune_store(const Geom& g, int32_t dtype, int32_t n_rhs, const HopConfig& cfg) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_cache[key_of(g, dtype, n_rhs)] = cfg;
+}
+
+}  // namespace rmh

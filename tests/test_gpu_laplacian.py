@@ -1,0 +1,133 @@
+"""GPU parity of layout conversion, the stencil and its link derivative against the oracle.
+
+Tolerances: FP64 results within 1e-12 of the oracle relative to the largest output
+magnitude.  FP32 stencil: every output is a sum of 65 terms bounded by max|x| (R(U) is
+orthogonal) with R itself rounded once per entry; the typical error is ~sqrt(65) * 8 u
+max|x| with u = 2^-24, so the test takes max error <= 1e-5 max|y| and rms error <= 1e-6 rms(y).
+"""
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import announce, dev, rel_max, setup
+from oracle import laplacian as olap
+from paper_2112_04556_amd import api, inputs
+
+pytestmark = pytest.mark.gpu
+
+# (L, link kind, seed): L = 2 edges, ragged volumes (not a multiple of 64), anisotropic shapes
+CASES = [((2, 2, 2, 2), "eps", 1), ((4, 4, 4, 4), "haar", 2), ((3, 5, 2, 7), "eps", 3),
+         ((8, 4, 6, 4), "unit", 4), ((2, 6, 4, 3), "haar", 5)]
+
+
+@pytest.mark.parametrize("L,kind,seed", CASES)
+def test_pack_links_bitwise(L, kind, seed):
+    announce(f"pack_links {L} {kind}")
+    U = inputs.random_links(L, kind, 0.5, seed=seed)
+    Ud = U.to(dev())
+    soa = api.pack_links(L, Ud, torch.float64).cpu().numpy()
+    ref = np.moveaxis(torch.view_as_real(U).numpy().reshape(4, -1, 18), 1, 2)
+    assert np.array_equal(soa, ref)
+    soa32 = api.pack_links(L, Ud, torch.float32).cpu().numpy()
+    assert np.array_equal(soa32, ref.astype(np.float32))     # round to nearest even
+    back = api.unpack_links(L, api.pack_links(L, Ud, torch.float64)).cpu()
+    assert torch.equal(back, U)
+
+
+def test_pack_fields_and_convert_bitwise():
+    L = (3, 5, 2, 7)
+    F = inputs.gaussian_fields(L, 3, seed=4)                         # (n, 4, 8, V) SoA
+    aos = F.permute(0, 3, 1, 2).contiguous()                          # (n, V, 4, 8)
+    soa = api.pack_fields(L, aos.to(dev()), torch.float64)
+    assert torch.equal(soa.cpu(), F)
+    assert torch.equal(api.unpack_fields(L, soa).cpu(), aos)
+    soa32 = api.pack_fields(L, aos.to(dev()), torch.float32)
+    assert np.array_equal(soa32.cpu().numpy(), F.numpy().astype(np.float32))
+    c = api.convert_f64_f32(F.to(dev()))
+    assert np.array_equal(c.cpu().numpy(), F.numpy().astype(np.float32))
+
+
+@pytest.mark.parametrize("L,kind,seed", CASES)
+@pytest.mark.parametrize("shift", [0.0, 0.7])
+def test_laplacian_fp64_parity(L, kind, seed, shift):
+    announce(f"laplacian fp64 {L} {kind} shift={shift}")
+    U, P, Ud, Pd = setup(L, kind, 0.5, seed, n=2)
+    y = api.laplacian_apply(L, Ud, Pd, shift).cpu().numpy()
+    ref = olap.laplacian(U, P, L, shift)
+    assert rel_max(y, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("form", [0, 1])
+@pytest.mark.parametrize("L,kind,seed", CASES[:3])
+def test_laplacian_fp32_parity(L, kind, seed, form):
+    announce(f"laplacian fp32 form={form} {L}")
+    U, P, Ud, Pd = setup(L, kind, 0.5, seed, n=2, dtype=torch.float32)
+    api.tune_set(L, torch.float32, 2, form, 256, 1)
+    try:
+        y = api.laplacian_apply(L, Ud, Pd).cpu().numpy().astype(np.float64)
+    finally:
+        api.tune_clear()
+    ref = olap.laplacian(U, P, L)
+    err = y - ref
+    assert np.abs(err).max() <= 1e-5 * np.abs(ref).max()
+    assert np.sqrt((err ** 2).mean()) <= 1e-6 * np.sqrt((ref ** 2).mean())
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_laplacian_configs_batched_and_deterministic(dtype):
+    """Bitwise identity across block sizes and XCD remaps of one form, batched vs single, run to run."""
+    L = (6, 4, 5, 6)
+    announce(f"laplacian configs {dtype}")
+    _, _, Ud, Pd = setup(L, "haar", 0.0, 7, n=3, dtype=dtype)
+    for form in (0, 1):
+        outs = []
+        for block in (64, 128, 256):
+            for xcd in (0, 1):
+                api.tune_set(L, dtype, 3, form, block, xcd)
+                api.tune_set(L, dtype, 1, form, block, xcd)
+                y = api.laplacian_apply(L, Ud, Pd)
+                y1 = api.laplacian_apply(L, Ud, Pd[1:2].contiguous())
+                assert torch.equal(y[1:2], y1)
+                outs.append(y)
+        api.tune_clear()
+        for o in outs[1:]:
+            assert torch.equal(o, outs[0])
+    y_a = api.laplacian_apply(L, Ud, Pd)
+    y_b = api.laplacian_apply(L, Ud, Pd)
+    assert torch.equal(y_a, y_b)
+
+
+def test_laplacian_empty_batch_and_autotune():
+    L = (4, 4, 4, 4)
+    _, _, Ud, Pd = setup(L, "eps", 0.3, 1, n=1)
+    empty = torch.empty((0, 4, 8, api.volume(L)), dtype=torch.float64, device=dev())
+    api.laplacian_apply(L, Ud, empty)
+    (form, block, xcd), ms = api.autotune_laplacian(L, Ud, Pd, reps=2)
+    assert form in (0, 1) and block in (64, 128, 256) and ms > 0
+    U, P, _, _ = setup(L, "eps", 0.3, 1, n=1)
+    assert rel_max(api.laplacian_apply(L, Ud, Pd).cpu().numpy(), olap.laplacian(U, P, L)) <= 1e-12
+    api.tune_clear()
+
+
+@pytest.mark.parametrize("L,kind,seed", CASES[:4])
+def test_laplacian_bwd_parity(L, kind, seed):
+    announce(f"laplacian bwd {L} {kind}")
+    U, x, Ud, xd = setup(L, kind, 0.5, seed, n=2)
+    g = inputs.gaussian_fields(L, 2, seed=seed + 100)
+    gx, go = api.laplacian_apply_bwd(L, Ud, xd, g.to(dev()), 0.3, per_rhs=False)
+    ref_go = olap.bilinear_link_derivative(U, g.numpy(), x, L)
+    assert rel_max(go[0].cpu().numpy(), ref_go) <= 1e-12
+    assert rel_max(gx.cpu().numpy(), olap.laplacian(U, g.numpy(), L, 0.3)) <= 1e-12
+    _, go_r = api.laplacian_apply_bwd(L, Ud, xd, g.to(dev()), 0.0, grad_x=False, per_rhs=True)
+    for i in range(2):
+        ref_i = olap.bilinear_link_derivative(U, g.numpy()[i:i + 1], x[i:i + 1], L)
+        assert rel_max(go_r[i].cpu().numpy(), ref_i) <= 1e-12
+
+
+def test_laplacian_full_size_16():
+    """The 16^4 lattice at eps = 0.5 (the FP64 rational-solve workload): whole-lattice parity."""
+    L = (16, 16, 16, 16)
+    announce("laplacian 16^4")
+    U, P, Ud, Pd = setup(L, "eps", 0.5, 2, n=1)
+    y = api.laplacian_apply(L, Ud, Pd).cpu().numpy()
+    assert rel_max(y, olap.laplacian(U, P, L)) <= 1e-12
