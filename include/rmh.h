@@ -270,6 +270,28 @@ rmh_status rmh_autotune_laplacian(const int32_t L[4], const void* U, int32_t dty
 /* Forget every stored configuration. */
 rmh_status rmh_tune_clear(void);
 
+/* ---------------------------------------------------------------------------------------- */
+/* kernel timing */
+
+/* Kernel classes of rmh_profile_read. */
+typedef enum {
+  RMH_PROF_STENCIL = 0,      /* every Delta application (all drivers) */
+  RMH_PROF_CG_RESIDUAL = 1,  /* r -= alpha A p with <r, r> */
+  RMH_PROF_CG_SHIFTS = 2,    /* x_j += a_j p_j, p_j = z_j r + b_j p_j over the active shifts */
+  RMH_PROF_FORCE = 3,        /* link derivative */
+  RMH_PROF_N = 4
+} rmh_prof_class;
+
+/* enable != 0: record a HIP event pair on the call's stream around every launch of the classes
+ * above and accumulate launches, event time and algorithmic bytes (links, inputs and outputs
+ * counted once per launch; for the shift updates only the shifts still active).  Enabling or
+ * disabling resets the counters. */
+rmh_status rmh_profile_enable(int32_t enable);
+/* Totals of one class since the last reset (waits for the recorded events).  total_items counts
+ * link fields processed (for the stencil: link-field applications of Delta). */
+rmh_status rmh_profile_read(int32_t cls, int64_t* launches, double* total_ms, double* total_bytes,
+                            double* total_items);
+
 #ifdef __cplusplus
 }
 #endif

@@ -76,6 +76,8 @@ SIGNATURES = {
     "rmh_tune_set": (c_i32, [P_i32, c_i32, c_i32, c_i32, c_i32, c_i32]),
     "rmh_autotune_laplacian": (c_i32, [P_i32, c_vp, c_i32, c_vp, c_vp, c_i32, c_i32, P_i32, P_f64, c_vp]),
     "rmh_tune_clear": (c_i32, []),
+    "rmh_profile_enable": (c_i32, [c_i32]),
+    "rmh_profile_read": (c_i32, [c_i32, ctypes.POINTER(c_i64), P_f64, P_f64, P_f64]),
     "rmh_kinetic_force": (c_i32, [P_i32, c_vp, c_vp, c_i32, ctypes.POINTER(RmhRational),
                                   ctypes.POINTER(RmhSolver), c_vp, P_f64, c_vp, c_i32,
                                   ctypes.POINTER(RmhStats), c_vp, c_sz, c_vp]),

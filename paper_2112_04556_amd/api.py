@@ -22,7 +22,7 @@ __all__ = [
     "laplacian_apply", "laplacian_apply_bwd", "cheb_coefficients", "power_spectrum", "power_ratio",
     "trace_moments_free", "cheb_filter", "rational_from_quadratics", "rational_kappa", "rational_apply",
     "rational_apply_bwd", "kinetic_force", "workspace_bytes", "volume", "tune_set", "tune_clear",
-    "autotune_laplacian",
+    "autotune_laplacian", "profile_enable", "profile_read", "PROF_CLASSES",
 ]
 
 
@@ -324,3 +324,26 @@ def autotune_laplacian(L, U, x, reps: int = 5):
                                        x.shape[0], int(reps), best, ctypes.byref(ms), _stream(x.device)),
           "rmh_autotune_laplacian")
     return (best[0], best[1], best[2]), ms.value
+
+
+# ------------------------------------------------------------------------------------------
+# kernel timing
+
+PROF_CLASSES = {"stencil": 0, "cg_residual": 1, "cg_shifts": 2, "force": 3}
+
+
+def profile_enable(on: bool = True) -> None:
+    check(lib().rmh_profile_enable(int(bool(on))), "rmh_profile_enable")
+
+
+def profile_read(cls: str) -> dict:
+    """{launches, ms, bytes, items, avg_ms, gbs} accumulated for one kernel class since the last reset."""
+    n = L_.c_i64()
+    ms = ctypes.c_double()
+    by = ctypes.c_double()
+    it = ctypes.c_double()
+    check(lib().rmh_profile_read(PROF_CLASSES[cls], ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by),
+                                 ctypes.byref(it)), "rmh_profile_read")
+    avg = ms.value / n.value if n.value else 0.0
+    gbs = by.value / (ms.value * 1e-3) / 1e9 if ms.value > 0 else 0.0
+    return {"launches": n.value, "ms": ms.value, "bytes": by.value, "items": it.value, "avg_ms": avg, "gbs": gbs}

@@ -5,10 +5,12 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
 #include <chrono>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -111,6 +113,85 @@ rmh_status d2h(void* dst, const void* src, size_t bytes, hipStream_t s) {
   return RMH_OK;
 }
 
+// ------------------------------------------------------------------------------------------
+// kernel timing (HIP events around launches of the instrumented classes)
+
+struct ProfRec {
+  int cls;
+  hipEvent_t e0, e1;
+  double bytes, items;
+};
+
+struct ProfState {
+  std::mutex mu;
+  bool on = false;
+  std::vector<ProfRec> pending;
+  std::vector<hipEvent_t> pool;
+  int64_t launches[RMH_PROF_N] = {};
+  double ms[RMH_PROF_N] = {};
+  double bytes[RMH_PROF_N] = {};
+  double items[RMH_PROF_N] = {};
+};
+ProfState g_prof;
+
+hipEvent_t prof_event() {
+  if (!g_prof.pool.empty()) {
+    hipEvent_t e = g_prof.pool.back();
+    g_prof.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void prof_flush_locked() {
+  for (auto& r : g_prof.pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.e1) == hipSuccess && hipEventElapsedTime(&ms, r.e0, r.e1) == hipSuccess) {
+      g_prof.launches[r.cls] += 1;
+      g_prof.ms[r.cls] += ms;
+      g_prof.bytes[r.cls] += r.bytes;
+      g_prof.items[r.cls] += r.items;
+    }
+    g_prof.pool.push_back(r.e0);
+    g_prof.pool.push_back(r.e1);
+  }
+  g_prof.pending.clear();
+}
+
+// Records an event pair around the enclosed launch when timing is enabled.
+struct ProfScope {
+  int cls;
+  double bytes, items;
+  hipStream_t s;
+  hipEvent_t e0 = nullptr;
+  ProfScope(int c, double b, hipStream_t st, double it = 0.0) : cls(c), bytes(b), items(it), s(st) {
+    if (!g_prof.on) return;
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    e0 = prof_event();
+    if (e0 && hipEventRecord(e0, s) != hipSuccess) e0 = nullptr;
+  }
+  ~ProfScope() {
+    if (!e0) return;
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    hipEvent_t e1 = prof_event();
+    if (e1 && hipEventRecord(e1, s) == hipSuccess) g_prof.pending.push_back({cls, e0, e1, bytes, items});
+    if (g_prof.pending.size() > 4096) prof_flush_locked();
+  }
+};
+
+void prof_add_bytes(int cls, double bytes) {
+  if (!g_prof.on) return;
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  g_prof.bytes[cls] += bytes;
+}
+
+// algorithmic bytes of one stencil launch over n fields: links once, x, optional z, optional out
+double hop_bytes(const Geom& g, int32_t n, size_t ts, bool z, bool store) {
+  return (double)g.V * ts * (72.0 + (double)n * 32.0 * (1.0 + (z ? 1.0 : 0.0) + (store ? 1.0 : 0.0)));
+}
+
 HopConfig hop_config(const Geom& g, int32_t dtype, int32_t n_rhs, int32_t purpose) {
   return tune_hop(g, dtype, n_rhs, purpose);
 }
@@ -162,6 +243,7 @@ struct Engine {
   double* b_true = nullptr;    // [n_rhs][n_shift]  -(8 + sigma_j)
   double* tol_rhs = nullptr;   // [n_rhs]
   double* part = nullptr;      // [n_rhs][max(3 nblk_hop, nblk_e)]
+  double* part_ru = nullptr;   // [n_rhs][3][nblk_hop]  (mixed precision)
   double* part_true = nullptr; // [n_rhs][n_shift][3][nblk_hop]
   double* sums_true = nullptr; // [n_rhs][n_shift][3]
   int32_t nblk_hop = 0, nblk_e = 0;
@@ -195,6 +277,7 @@ void plan_engine(Carver& c, Engine& e, const Geom& g, int32_t n_rhs, int32_t n_s
   e.nblk_hop = (g.V + 63) / 64;
   e.nblk_e = elem_num_blocks(n);
   e.part = c.take<double>((size_t)n_rhs * std::max<int64_t>(3 * e.nblk_hop, e.nblk_e));
+  if (mode) e.part_ru = c.take<double>((size_t)n_rhs * 3 * e.nblk_hop);
   e.part_true = c.take<double>((size_t)n_rhs * n_shift * 3 * e.nblk_hop);
   e.sums_true = c.take<double>((size_t)n_rhs * n_shift * 3);
 }
@@ -211,9 +294,20 @@ CgDev cg_view(const Engine& e, int32_t nblk_hop) {
   d.sigma = e.sigma;
   d.seed = e.seed;
   d.part = e.part;
+  d.part_ru = e.part_ru;
   d.nblk_hop = nblk_hop;
   d.nblk_e = e.nblk_e;
+  d.nblk_ru = 0;
   return d;
+}
+
+int log_level() {
+  static int lvl = -1;
+  if (lvl < 0) {
+    const char* e = getenv("RMH_LOG");
+    lvl = e ? atoi(e) : 0;
+  }
+  return lvl;
 }
 
 struct SolveInfo {
@@ -257,7 +351,7 @@ rmh_status engine_solve(Engine& e, const double* U64, const float* U32, const do
   const HopConfig c64 = hop_config(g, RMH_F64, nr, 2);
   const int32_t nblk_w = hop_num_blocks(g, cw), nblk_64 = hop_num_blocks(g, c64);
   CgDev cg = cg_view(e, nblk_w);
-  CgDev cg64 = cg_view(e, nblk_64);
+  cg.nblk_ru = nblk_64;
 
   T* r = (T*)e.r;
   T* Ap = (T*)e.Ap;
@@ -310,7 +404,7 @@ rmh_status engine_solve(Engine& e, const double* U64, const float* U32, const do
   hr.run = e.flags + kFlNeedRU;
   hr.run_stride = kFlN;
   hr.store = 1;
-  hr.partials = e.part;
+  hr.partials = e.part_ru;
   hr.dot_mask = 4;
 
   if (check_every <= 0) check_every = 8;
@@ -318,14 +412,28 @@ rmh_status engine_solve(Engine& e, const double* U64, const float* U32, const do
   int32_t it = 0;
   while (true) {
     for (int i = 0; i < check_every; ++i) {
-      HIP_TRY(launch_hop<T>(ha, cw, s));
+      {
+        ProfScope ps(RMH_PROF_STENCIL, hop_bytes(g, nr, sizeof(T), false, true), s, nr);
+        HIP_TRY(launch_hop<T>(ha, cw, s));
+      }
       HIP_TRY(launch_cg_alpha(cg, s));
-      HIP_TRY(launch_cg_r_update<T>(cg, r, Ap, n, s));
+      {
+        ProfScope ps(RMH_PROF_CG_RESIDUAL, 3.0 * nr * n * sizeof(T), s, nr);
+        HIP_TRY(launch_cg_r_update<T>(cg, r, Ap, mixed ? e.r64 : nullptr, n, s));
+      }
       HIP_TRY(launch_cg_beta(cg, mixed ? 1 : 0, s));
-      if (mixed)
-        HIP_TRY((launch_cg_shift_update<T, T>(cg, r, p, (T*)e.x_lo, n, s)));
-      else
-        HIP_TRY((launch_cg_shift_update<T, T>(cg, r, p, (T*)x_hi, n, s)));
+      {
+        ProfScope ps(RMH_PROF_CG_SHIFTS, 0.0, s);  // bytes added after the solve (active shifts only)
+        if (mixed)
+          HIP_TRY((launch_cg_shift_update<T, T>(cg, r, p, (T*)e.x_lo, x_hi, n, s)));
+        else
+          HIP_TRY((launch_cg_shift_update<T, T>(cg, r, p, (T*)x_hi, nullptr, n, s)));
+      }
+      if (mixed) {
+        // reliable update decided by this iteration's beta kernel: FP64 residual of the seed
+        // (blocks of rhs without a pending update exit at once)
+        HIP_TRY(launch_hop<double>(hr, c64, s));
+      }
     }
     it += check_every;
     RMH_TRY(d2h(fl.data(), e.flags, fl.size() * 4, s));
@@ -335,16 +443,47 @@ rmh_status engine_solve(Engine& e, const double* U64, const float* U32, const do
       need_ru |= fl[(size_t)v * kFlN + kFlNeedRU] != 0;
     }
     if (!running) break;
-    if (mixed && need_ru) {
-      HIP_TRY(launch_ru_accumulate(cg, e.x_lo, x_hi, n, 0, s));
-      HIP_TRY(launch_hop<double>(hr, c64, s));
-      HIP_TRY(launch_ru_finish(cg64, s));
-      HIP_TRY(launch_ru_convert(cg, e.r64, (float*)r, n, s));
-    }
+    (void)need_ru;
     if (it > maxiter + 2 * check_every) break;  // safety net; the device sets NoConv first
   }
   if (mixed) HIP_TRY(launch_ru_accumulate(cg, e.x_lo, x_hi, n, 1, s));
   RMH_TRY(d2h(sc.data(), e.sc, sc.size() * 8, s));
+  if (log_level() > 0) {
+    for (int v = 0; v < nr; ++v)
+      fprintf(stderr, "[rmh] engine mode=%d rhs %d/%d shifts=%d sigma0=%.4g iters=%g ru=%g status=%d |b|^2=%.4g rr=%.4g tol=%.3g\n",
+              e.mode, v, nr, ns, sigma[(size_t)v * ns + seed[v]], sc[(size_t)v * kScN + kScIters],
+              sc[(size_t)v * kScN + kScRU], fl[(size_t)v * kFlN + kFlStatus], sc[(size_t)v * kScN + kScBnorm2],
+              sc[(size_t)v * kScN + kScRR], tol_rel[v]);
+  }
+  if (log_level() > 1) {
+    std::vector<double> shv((size_t)nr * ns * kShN);
+    std::vector<int32_t> a0((size_t)nr * ns), a1((size_t)nr * ns);
+    RMH_TRY(d2h(shv.data(), e.sh, shv.size() * 8, s));
+    RMH_TRY(d2h(a0.data(), e.act, a0.size() * 4, s));
+    RMH_TRY(d2h(a1.data(), e.act_next, a1.size() * 4, s));
+    for (int v = 0; v < nr; ++v)
+      for (int j = 0; j < ns; ++j) {
+        const double* h = shv.data() + ((size_t)v * ns + j) * kShN;
+        fprintf(stderr, "[rmh]   shift %d sigma %.4g upd=%g zeta=%.3e zeta_prev=%.3e cx=%.3e cr=%.3e cp=%.3e act=%d/%d\n", j,
+                sigma[(size_t)v * ns + j], h[kShUpd], h[kShZeta], h[kShZetaPrev], h[kShCx], h[kShCr], h[kShCp],
+                a0[(size_t)v * ns + j], a1[(size_t)v * ns + j]);
+      }
+  }
+  if (g_prof.on) {
+    // exact algorithmic bytes of the shift updates: per update of shift j, p_j read, x_j read and
+    // written, p_j written unless it was the shift's last update; r read once per live iteration
+    std::vector<double> shv((size_t)nr * ns * kShN);
+    RMH_TRY(d2h(shv.data(), e.sh, shv.size() * 8, s));
+    double bytes = 0.0;
+    for (int v = 0; v < nr; ++v) {
+      bytes += sc[(size_t)v * kScN + kScIters] * n * sizeof(T);
+      for (int j = 0; j < ns; ++j) {
+        const double upd = shv[((size_t)v * ns + j) * kShN + kShUpd];
+        if (upd > 0) bytes += (upd * 3.0 + (upd - 1.0)) * n * sizeof(T);
+      }
+    }
+    prof_add_bytes(RMH_PROF_CG_SHIFTS, bytes);
+  }
   info->iters = 0;
   info->ru = 0;
   info->status = kStOk;
@@ -381,7 +520,10 @@ rmh_status true_residuals(Engine& e, const double* U64, const double* b, const d
   h.store = 0;
   h.partials = e.part_true;
   h.dot_mask = 4;
-  HIP_TRY(launch_hop<double>(h, c64, s));
+  {
+    ProfScope ps(RMH_PROF_STENCIL, hop_bytes(g, nr * ns, 8, true, false), s, nr * ns);
+    HIP_TRY(launch_hop<double>(h, c64, s));
+  }
   // rows: for pair q the <out,out> partials sit at row 3 q + 2
   HIP_TRY(launch_reduce_rows(e.part_true, nblk, nr * ns * 3, e.sums_true, s));
   std::vector<double> sums((size_t)nr * ns * 3);
@@ -477,6 +619,10 @@ rmh_status solve_all(SolvePlan& sp, const double* U64, const double* b, double* 
   RMH_TRY(true_residuals(e, U64, b, x_hi, bnorm, s, &res));
   RefinePlan& rp = sp.ref;
   for (int round = 0; round < 4; ++round) {
+    if (log_level() > 0)
+      for (int q = 0; q < nr * ns; ++q)
+        fprintf(stderr, "[rmh] round %d pair %d (rhs %d shift %d sigma %.4g) true relres %.3e\n", round, q, q / ns,
+                q % ns, sig[q % ns], res[q]);
     std::vector<int32_t> bad;
     for (int q = 0; q < nr * ns; ++q)
       if (!(res[q] <= sv.tol)) bad.push_back(q);
@@ -512,7 +658,10 @@ rmh_status solve_all(SolvePlan& sp, const double* U64, const double* b, double* 
       h.c = 1.0;
       h.n_rhs = nb;
       h.store = 1;
-      HIP_TRY(launch_hop<double>(h, hop_config(g, RMH_F64, nb, 2), s));
+      {
+        ProfScope ps(RMH_PROF_STENCIL, hop_bytes(g, nb, 8, true, true), s, nb);
+        HIP_TRY(launch_hop<double>(h, hop_config(g, RMH_F64, nb, 2), s));
+      }
       SolveInfo ri;
       if (mode)
         RMH_TRY(engine_solve<float>(re, U64, sp.U32, rp.Res, rp.E, rsig, rtol, sv.maxiter, sv.delta,
@@ -640,7 +789,10 @@ rmh_status power_spectrum_t(const Geom& g, const T* U, const T* F, int32_t n_rhs
       h.z = prev;
     }
     h.out = out;
-    HIP_TRY(launch_hop<T>(h, cfg, s));
+    {
+      ProfScope ps(RMH_PROF_STENCIL, hop_bytes(g, n_rhs, sizeof(T), k > 0, h.store != 0), s, n_rhs);
+      HIP_TRY(launch_hop<T>(h, cfg, s));
+    }
     prev = cur;
     cur = out;
   }
@@ -686,7 +838,12 @@ rmh_status cheb_filter_t(const Geom& g, const T* U, const T* x, int32_t n_rhs, i
       h.z = prev;
     }
     h.out = out;
-    HIP_TRY(launch_hop<T>(h, cfg, s));
+    {
+      // the filter also reads (after the first sweep) and writes every window output
+      const double yb = (double)nw * n_rhs * 32.0 * g.V * sizeof(T) * (k == 0 ? 1.0 : 2.0);
+      ProfScope ps(RMH_PROF_STENCIL, hop_bytes(g, n_rhs, sizeof(T), k > 0, h.store != 0) + yb, s, n_rhs);
+      HIP_TRY(launch_hop<T>(h, cfg, s));
+    }
     prev = cur;
     cur = out;
   }
@@ -829,6 +986,7 @@ rmh_status rmh_laplacian_apply(const int32_t L[4], const void* U, int32_t dtype,
     h.b = 8.0 + shift;
     h.n_rhs = n_rhs;
     h.store = 1;
+    ProfScope ps(RMH_PROF_STENCIL, hop_bytes(g, n_rhs, 8, false, true), (hipStream_t)stream, n_rhs);
     HIP_TRY(launch_hop<double>(h, cfg, (hipStream_t)stream));
   } else {
     HopArgs<float> h{};
@@ -842,6 +1000,7 @@ rmh_status rmh_laplacian_apply(const int32_t L[4], const void* U, int32_t dtype,
     h.b = 8.0 + shift;
     h.n_rhs = n_rhs;
     h.store = 1;
+    ProfScope ps(RMH_PROF_STENCIL, hop_bytes(g, n_rhs, 4, false, true), (hipStream_t)stream, n_rhs);
     HIP_TRY(launch_hop<float>(h, cfg, (hipStream_t)stream));
   }
   return RMH_OK;
@@ -880,6 +1039,8 @@ rmh_status rmh_laplacian_apply_bwd(const int32_t L[4], const void* U, int32_t dt
     fa.w[0] = 1.0;
     fa.grad = grad_omega;
     fa.per_rhs = per_rhs ? 1 : 0;
+    const double fbytes = (double)g.V * 8.0 * (72.0 + 64.0 * n_rhs + 32.0 * (per_rhs ? n_rhs : 1));
+    ProfScope ps(RMH_PROF_FORCE, fbytes, (hipStream_t)stream, n_rhs);
     HIP_TRY(launch_force(fa, (hipStream_t)stream));
   }
   return RMH_OK;
@@ -1093,7 +1254,11 @@ static rmh_status force_from_solves(RationalPlan& rp, const Geom& g, const doubl
   fa.n_pair = np;
   fa.grad = grad_omega;
   fa.per_rhs = per_rhs ? 1 : 0;
-  HIP_TRY(launch_force(fa, s));
+  {
+    const double fbytes = (double)g.V * 8.0 * (72.0 + 64.0 * n_rhs * np + 32.0 * (per_rhs ? n_rhs : 1));
+    ProfScope ps(RMH_PROF_FORCE, fbytes, s, n_rhs);
+    HIP_TRY(launch_force(fa, s));
+  }
   return RMH_OK;
 }
 
@@ -1249,6 +1414,31 @@ rmh_status rmh_autotune_laplacian(const int32_t L[4], const void* U, int32_t dty
     best[2] = bestc.xcd_remap;
   }
   if (best_ms) *best_ms = bt;
+  return RMH_OK;
+}
+
+rmh_status rmh_profile_enable(int32_t enable) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  prof_flush_locked();
+  g_prof.on = enable != 0;
+  for (int c = 0; c < RMH_PROF_N; ++c) {
+    g_prof.launches[c] = 0;
+    g_prof.ms[c] = 0.0;
+    g_prof.bytes[c] = 0.0;
+    g_prof.items[c] = 0.0;
+  }
+  return RMH_OK;
+}
+
+rmh_status rmh_profile_read(int32_t cls, int64_t* launches, double* total_ms, double* total_bytes,
+                            double* total_items) {
+  if (cls < 0 || cls >= RMH_PROF_N) return fail(RMH_E_ARG, "profile class %d out of range", cls);
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  prof_flush_locked();
+  if (launches) *launches = g_prof.launches[cls];
+  if (total_ms) *total_ms = g_prof.ms[cls];
+  if (total_bytes) *total_bytes = g_prof.bytes[cls];
+  if (total_items) *total_items = g_prof.items[cls];
   return RMH_OK;
 }
 

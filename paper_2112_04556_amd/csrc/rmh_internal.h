@@ -90,13 +90,14 @@ struct CgDev {
   const double* sigma;   // [n_rhs][n_shift]
   const int32_t* seed;   // [n_rhs]
   double* part;          // partials scratch [n_rhs][nblk_max]
-  int32_t nblk_hop, nblk_e;
+  double* part_ru;       // partials of the FP64 residual stencil [n_rhs][3][nblk_ru] (mixed precision)
+  int32_t nblk_hop, nblk_e, nblk_ru;
 };
 // scalar slots per rhs
 enum : int { kScRR = 0, kScAlpha, kScAlphaPrev, kScBetaPrev, kScBnorm2, kScMaxR, kScTolAbs, kScIters,
              kScRU, kScDelta, kScMaxIter, kScN };
 // per (rhs, shift) slots
-enum : int { kShZeta = 0, kShZetaPrev, kShZetaNext, kShCx, kShCr, kShCp, kShN };
+enum : int { kShZeta = 0, kShZetaPrev, kShZetaNext, kShCx, kShCr, kShCp, kShUpd, kShN };
 // int flags per rhs
 // Run: the rhs still iterates (read by the stencil of the next iteration);
 // Live: the current iteration is being carried out (set by the alpha kernel), so the
@@ -108,15 +109,17 @@ hipError_t launch_cg_init(const CgDev& cg, const double* bn2_partials, int32_t n
                           double delta, int32_t maxiter, hipStream_t s);
 hipError_t launch_cg_alpha(const CgDev& cg, hipStream_t s);
 hipError_t launch_cg_beta(const CgDev& cg, int32_t mixed, hipStream_t s);
+// r -= alpha Ap (starting from r64 when a reliable update was consumed), partial <r, r>
 template <typename T>
-hipError_t launch_cg_r_update(const CgDev& cg, T* r, const T* Ap, int64_t n_reals, hipStream_t s);
+hipError_t launch_cg_r_update(const CgDev& cg, T* r, const T* Ap, const double* r64, int64_t n_reals,
+                              hipStream_t s);
+// shift updates; with x_hi non-null a pending reliable update also moves x into x_hi
 template <typename T, typename TX>
-hipError_t launch_cg_shift_update(const CgDev& cg, const T* r, T* p, TX* x, int64_t n_reals, hipStream_t s);
-// mixed precision reliable update pieces
+hipError_t launch_cg_shift_update(const CgDev& cg, const T* r, T* p, TX* x, double* x_hi, int64_t n_reals,
+                                  hipStream_t s);
+// final x_hi += x_lo, x_lo = 0 (all rhs, or those with a pending reliable update)
 hipError_t launch_ru_accumulate(const CgDev& cg, float* x_lo, double* x_hi, int64_t n_reals, int32_t all,
                                 hipStream_t s);
-hipError_t launch_ru_finish(const CgDev& cg, hipStream_t s);
-hipError_t launch_ru_convert(const CgDev& cg, const double* r64, float* r, int64_t n_reals, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 template <typename T>
 hipError_t launch_copy_cast(const double* in, T* out, int64_t n, hipStream_t s);

@@ -40,6 +40,7 @@ __device__ __forceinline__ void block_sum(double (&v)[NQ], double (*lds)[16]) {
       v[q] = s;
     }
   }
+  __syncthreads();  // lds may be reused by the caller right away
 }
 
 // Strided fixed-order sum of n values by a whole block; result in thread 0.
@@ -438,6 +439,7 @@ __global__ void k_cg_init(CgDev cg, const double* bn2_part, int32_t nblk, const 
     sh[kShCx] = 0.0;
     sh[kShCr] = 0.0;
     sh[kShCp] = 0.0;
+    sh[kShUpd] = 0.0;
     const int32_t on = (s_bn2 > 0.0) ? 1 : 0;
     cg.act[(int64_t)v * cg.n_shift + j] = on;
     cg.act_next[(int64_t)v * cg.n_shift + j] = on;
@@ -460,11 +462,23 @@ __global__ void k_cg_alpha(CgDev cg) {
     return;
   }
   __shared__ double lds[1][16];
+  double* sc = cg.sc + (int64_t)v * kScN;
+  // a reliable update issued at the end of the previous iteration: its FP64 residual
+  // r64 = b - (Delta + sigma0) x_hi replaces the recursive residual from now on
+  const int32_t ru = cg.part_ru ? fl[kFlNeedRU] : 0;
+  double rr_true = 0.0;
+  if (ru) rr_true = block_sum_array(cg.part_ru + ((int64_t)v * 3 + 2) * cg.nblk_ru, cg.nblk_ru, lds);
   const double pAp = block_sum_array(cg.part + ((int64_t)v * 3 + 1) * cg.nblk_hop, cg.nblk_hop, lds);
   __shared__ double s_alpha;
   __shared__ int s_ok;
-  double* sc = cg.sc + (int64_t)v * kScN;
   if (threadIdx.x == 0) {
+    if (ru) {
+      sc[kScRR] = rr_true;
+      sc[kScMaxR] = sqrt(rr_true);
+      sc[kScRU] += 1.0;
+      fl[kFlNeedRU] = 0;
+      fl[kFlRUMask] = 1;
+    }
     const double rr = sc[kScRR];
     const double alpha = rr / pAp;
     s_ok = (pAp > 0.0 && alpha == alpha && alpha < 1e300) ? 1 : 0;
@@ -494,6 +508,7 @@ __global__ void k_cg_alpha(CgDev cg) {
       const double zn = z * zp * ap / (ap * zp * (1.0 + alpha * ds) + alpha * bp * (zp - z));
       sh[kShZetaNext] = zn;
       sh[kShCx] = alpha * zn / z;
+      sh[kShUpd] += 1.0;
     } else {
       sh[kShCx] = 0.0;
     }
@@ -511,7 +526,13 @@ __global__ void k_cg_beta(CgDev cg, int32_t mixed) {
   int32_t* fl = cg.flags + (int64_t)v * kFlN;
   if (fl[kFlLive] == 0) return;
   __shared__ double lds[1][16];
-  const double rrn = block_sum_array(cg.part + (int64_t)v * cg.nblk_e, cg.nblk_e, lds);
+  __shared__ double s_rrn;
+  {
+    const double t = block_sum_array(cg.part + (int64_t)v * cg.nblk_e, cg.nblk_e, lds);
+    if (threadIdx.x == 0) s_rrn = t;  // the block sum is valid in thread 0 only
+    __syncthreads();
+  }
+  const double rrn = s_rrn;
   double* sc = cg.sc + (int64_t)v * kScN;
   const double beta = rrn / sc[kScRR];
   const double rnorm = sqrt(rrn);
@@ -544,6 +565,7 @@ __global__ void k_cg_beta(CgDev cg, int32_t mixed) {
     sc[kScBetaPrev] = beta;
     sc[kScRR] = rrn;
     sc[kScIters] += 1.0;
+    fl[kFlRUMask] = 0;  // the residual update of this iteration has consumed it
     if (!(rrn == rrn)) {
       fl[kFlStatus] = kStBreakdown;
       fl[kFlRun] = 0;
@@ -567,18 +589,22 @@ hipError_t launch_cg_beta(const CgDev& cg, int32_t mixed, hipStream_t s) {
 
 // r -= alpha Ap, partial <r, r>
 template <typename T>
-__global__ void k_cg_r(CgDev cg, T* __restrict__ r, const T* __restrict__ Ap, int64_t n) {
+__global__ void k_cg_r(CgDev cg, T* __restrict__ r, const T* __restrict__ Ap, const double* __restrict__ r64,
+                       int64_t n) {
   const int32_t v = blockIdx.y;
   if (cg.flags[(int64_t)v * kFlN + kFlLive] == 0) return;
+  const int32_t from64 = r64 ? cg.flags[(int64_t)v * kFlN + kFlRUMask] : 0;
   const T alpha = (T)cg.sc[(int64_t)v * kScN + kScAlpha];
   T* rv = r + (int64_t)v * n;
   const T* av = Ap + (int64_t)v * n;
+  const double* r64v = r64 ? r64 + (int64_t)v * n : nullptr;
   double d[1] = {0.0};
   const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
   if (i0 < n) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const T rn = rv[i0 + k] - alpha * av[i0 + k];
+      const T r0 = from64 ? (T)r64v[i0 + k] : rv[i0 + k];
+      const T rn = r0 - alpha * av[i0 + k];
       rv[i0 + k] = rn;
       d[0] += (double)rn * (double)rn;
     }
@@ -589,22 +615,26 @@ __global__ void k_cg_r(CgDev cg, T* __restrict__ r, const T* __restrict__ Ap, in
 }
 
 template <typename T>
-hipError_t launch_cg_r_update(const CgDev& cg, T* r, const T* Ap, int64_t n_reals, hipStream_t s) {
+hipError_t launch_cg_r_update(const CgDev& cg, T* r, const T* Ap, const double* r64, int64_t n_reals,
+                              hipStream_t s) {
   dim3 grid(elem_num_blocks(n_reals), cg.n_rhs);
-  hipLaunchKernelGGL((k_cg_r<T>), grid, dim3(kBlock), 0, s, cg, r, Ap, n_reals);
+  hipLaunchKernelGGL((k_cg_r<T>), grid, dim3(kBlock), 0, s, cg, r, Ap, r64, n_reals);
   return hipGetLastError();
 }
-template hipError_t launch_cg_r_update<double>(const CgDev&, double*, const double*, int64_t, hipStream_t);
-template hipError_t launch_cg_r_update<float>(const CgDev&, float*, const float*, int64_t, hipStream_t);
+template hipError_t launch_cg_r_update<double>(const CgDev&, double*, const double*, const double*, int64_t,
+                                               hipStream_t);
+template hipError_t launch_cg_r_update<float>(const CgDev&, float*, const float*, const double*, int64_t,
+                                              hipStream_t);
 
 // x_j += cx_j p_j (shifts updated this iteration); p_j = cr_j r + cp_j p_j (shifts still active)
 template <typename T, typename TX>
 __global__ void k_cg_shift(CgDev cg, const T* __restrict__ r, T* __restrict__ p, TX* __restrict__ x,
-                           int64_t n) {
+                           double* __restrict__ x_hi, int64_t n) {
   const int32_t v = blockIdx.y;
   if (cg.flags[(int64_t)v * kFlN + kFlLive] == 0) return;
   const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
   if (i0 >= n) return;
+  const int32_t acc_hi = x_hi ? cg.flags[(int64_t)v * kFlN + kFlNeedRU] : 0;
   T rv[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) rv[k] = r[(int64_t)v * n + i0 + k];
@@ -628,18 +658,30 @@ __global__ void k_cg_shift(CgDev cg, const T* __restrict__ r, T* __restrict__ p,
       for (int k = 0; k < 4; ++k) pj[k] = cr * rv[k] + cp * pv[k];
     }
   }
+  if (acc_hi) {
+    // reliable update: move every shift's low-precision increment into the FP64 solution
+    for (int j = 0; j < cg.n_shift; ++j) {
+      const int64_t off = ((int64_t)v * cg.n_shift + j) * n + i0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        x_hi[off + k] += (double)x[off + k];
+        x[off + k] = TX(0);
+      }
+    }
+  }
 }
 
 template <typename T, typename TX>
-hipError_t launch_cg_shift_update(const CgDev& cg, const T* r, T* p, TX* x, int64_t n_reals, hipStream_t s) {
+hipError_t launch_cg_shift_update(const CgDev& cg, const T* r, T* p, TX* x, double* x_hi, int64_t n_reals,
+                                  hipStream_t s) {
   dim3 grid(elem_num_blocks(n_reals), cg.n_rhs);
-  hipLaunchKernelGGL((k_cg_shift<T, TX>), grid, dim3(kBlock), 0, s, cg, r, p, x, n_reals);
+  hipLaunchKernelGGL((k_cg_shift<T, TX>), grid, dim3(kBlock), 0, s, cg, r, p, x, x_hi, n_reals);
   return hipGetLastError();
 }
 template hipError_t launch_cg_shift_update<double, double>(const CgDev&, const double*, double*, double*,
-                                                             int64_t, hipStream_t);
-template hipError_t launch_cg_shift_update<float, float>(const CgDev&, const float*, float*, float*, int64_t,
-                                                           hipStream_t);
+                                                             double*, int64_t, hipStream_t);
+template hipError_t launch_cg_shift_update<float, float>(const CgDev&, const float*, float*, float*, double*,
+                                                           int64_t, hipStream_t);
 
 // reliable update: x_hi += x_lo, x_lo = 0 for every shift of the flagged rhs
 __global__ void k_ru_accumulate(CgDev cg, float* __restrict__ x_lo, double* __restrict__ x_hi, int64_t n,
@@ -662,47 +704,6 @@ hipError_t launch_ru_accumulate(const CgDev& cg, float* x_lo, double* x_hi, int6
                                 hipStream_t s) {
   dim3 grid(elem_num_blocks(n_reals), cg.n_rhs);
   hipLaunchKernelGGL(k_ru_accumulate, grid, dim3(kBlock), 0, s, cg, x_lo, x_hi, n_reals, all);
-  return hipGetLastError();
-}
-
-// after the FP64 true residual r64 = b - (Delta + sigma0) x_hi of the flagged rhs
-__global__ void k_ru_finish(CgDev cg) {
-  const int32_t v = blockIdx.x;
-  int32_t* fl = cg.flags + (int64_t)v * kFlN;
-  const int32_t need = fl[kFlNeedRU];
-  __shared__ double lds[1][16];
-  if (!need) {
-    if (threadIdx.x == 0) fl[kFlRUMask] = 0;
-    return;
-  }
-  const double rr = block_sum_array(cg.part + ((int64_t)v * 3 + 2) * cg.nblk_hop, cg.nblk_hop, lds);
-  if (threadIdx.x == 0) {
-    double* sc = cg.sc + (int64_t)v * kScN;
-    sc[kScRR] = rr;
-    sc[kScMaxR] = sqrt(rr);
-    sc[kScRU] += 1.0;
-    fl[kFlNeedRU] = 0;
-    fl[kFlRUMask] = 1;
-  }
-}
-
-hipError_t launch_ru_finish(const CgDev& cg, hipStream_t s) {
-  hipLaunchKernelGGL(k_ru_finish, dim3(cg.n_rhs), dim3(kRedBlock), 0, s, cg);
-  return hipGetLastError();
-}
-
-__global__ void k_ru_convert(CgDev cg, const double* __restrict__ r64, float* __restrict__ r, int64_t n) {
-  const int32_t v = blockIdx.y;
-  if (cg.flags[(int64_t)v * kFlN + kFlRUMask] == 0) return;
-  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
-  if (i0 >= n) return;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) r[(int64_t)v * n + i0 + k] = (float)r64[(int64_t)v * n + i0 + k];
-}
-
-hipError_t launch_ru_convert(const CgDev& cg, const double* r64, float* r, int64_t n_reals, hipStream_t s) {
-  dim3 grid(elem_num_blocks(n_reals), cg.n_rhs);
-  hipLaunchKernelGGL(k_ru_convert, grid, dim3(kBlock), 0, s, cg, r64, r, n_reals);
   return hipGetLastError();
 }
 

@@ -181,7 +181,7 @@ def test_force_gauge_covariance():
     nb = lattice.neighbour_table(L)
     UO = np.stack([Om @ U[mu] @ su3.dagger(Om[nb[:, 2 * mu]]) for mu in range(4)])
     M = su3.to_matrix(np.moveaxis(P, -2, -1))
-    PO = np.moveaxis(su3.from_matrix(Om @ M @ su3.dagger(Om)), -1, -2)
+    PO = np.ascontiguousarray(np.moveaxis(su3.from_matrix(Om @ M @ su3.dagger(Om)), -1, -2))
     rat = _rat_kappa(0.9, 8)
     sv = api.Solver(tol=1e-12)
     G = api.kinetic_force(L, Ud, Pd, rat, sv)["dK"][0].cpu().numpy()
