@@ -91,23 +91,27 @@ typedef struct {
 
 /* Shifted-solve controls.  tol: per-shift FP64 true relative residual
  * ||x - (Delta + sigma_j) x_j|| / ||x|| that every shift must reach.  mode 0: FP64 multi-shift
- * CG; mode 1: FP32 stencil and vectors with FP64 reliable updates of the residual and of
- * the shift solutions (delta = reliable-update threshold, e.g. 0.1).  check_every:
- * iterations between host convergence checks (0 = default 8). */
+ * CG; mode 1: mixed precision -- FP64 iterations while the seed residual is above
+ * mixed_switch * ||x|| (0 = default 1e-4, negative = none), then FP32 stencil and vectors with
+ * FP64 reliable updates of the residual and of the shift solutions (delta = reliable-update
+ * threshold, e.g. 0.1).  check_every: iterations between host convergence checks (0 = 8). */
 typedef struct {
   double tol;
   int32_t maxiter;
   int32_t mode;
   double delta;
   int32_t check_every;
+  double mixed_switch;
 } rmh_solver;
 
 /* Per-call solver statistics (host). */
 typedef struct {
-  int32_t iters;            /* multi-shift iterations (max over fields) */
-  int32_t reliable_updates; /* FP64 reliable updates (sum over fields) */
+  int32_t iters;            /* multi-shift iterations (summed over the solves of the call) */
+  int32_t reliable_updates; /* FP64 reliable updates */
   int32_t refine_iters;     /* iterations spent in per-shift refinement */
   int32_t refine_rounds;
+  int32_t fp64_iters;       /* iterations done in FP64 (mode 1: before the switch) */
+  int32_t reserved;
   double true_relres_max;   /* max over fields and shifts of the final FP64 true residual */
   double seconds;           /* wall time of the call */
 } rmh_stats;
@@ -255,16 +259,19 @@ rmh_status rmh_kinetic_force(const int32_t L[4], const double* U, const double* 
 /* stencil launch tuning */
 
 /* Fix the stencil launch configuration used for lattice L, dtype and launches over n_rhs link
- * fields: form 0 = adjoint 8x8 action R(U), 1 = 3x3 matrix products U phi U^dag; block = 64, 128
- * or 256 threads; xcd_remap = 1 maps consecutive lattice blocks onto one XCD (L2 locality).
- * Every configuration computes the same operator; a form fixes the per-site arithmetic, so
- * results are bitwise identical across block sizes and remaps of one form. */
+ * fields: form 0 = adjoint 8x8 action R(U) built per hop, 1 = 3x3 matrix products U phi U^dag,
+ * 2 = R(U) built and applied two columns at a time; block = 64, 128 or 256 threads; xcd_remap = 1
+ * maps consecutive lattice blocks onto one XCD (L2 locality); nv = 4 or 2 directions per thread;
+ * order = 1 visits the blocks with x3 fastest (x2/x3 neighbours resident together; used when
+ * L0*L1 is a multiple of the sites per block).  Every configuration computes the same operator;
+ * a form fixes the per-site arithmetic, so results are bitwise identical across block sizes,
+ * remaps, nv and orders of one form. */
 rmh_status rmh_tune_set(const int32_t L[4], int32_t dtype, int32_t n_rhs, int32_t form, int32_t block,
-                        int32_t xcd_remap);
+                        int32_t xcd_remap, int32_t nv, int32_t order);
 /* Time every configuration of rmh_laplacian_apply on the caller's buffers (y is overwritten;
  * reps timed launches each, HIP events on the stream) and keep the fastest for (L, dtype, n_rhs).
- * best (optional host int32[3]) receives (form, block, xcd_remap); best_ms (optional) its mean
- * time per launch.  Synchronizes the stream. */
+ * best (optional host int32[5]) receives (form, block, xcd_remap, nv, order); best_ms (optional)
+ * its mean time per launch.  Synchronizes the stream. */
 rmh_status rmh_autotune_laplacian(const int32_t L[4], const void* U, int32_t dtype, const void* x, void* y,
                                   int32_t n_rhs, int32_t reps, int32_t* best, double* best_ms, rmh_stream stream);
 /* Forget every stored configuration. */

@@ -34,12 +34,14 @@ class RmhRational(ctypes.Structure):
 
 
 class RmhSolver(ctypes.Structure):
-    _fields_ = [("tol", c_f64), ("maxiter", c_i32), ("mode", c_i32), ("delta", c_f64), ("check_every", c_i32)]
+    _fields_ = [("tol", c_f64), ("maxiter", c_i32), ("mode", c_i32), ("delta", c_f64), ("check_every", c_i32),
+                ("mixed_switch", c_f64)]
 
 
 class RmhStats(ctypes.Structure):
     _fields_ = [("iters", c_i32), ("reliable_updates", c_i32), ("refine_iters", c_i32),
-                ("refine_rounds", c_i32), ("true_relres_max", c_f64), ("seconds", c_f64)]
+                ("refine_rounds", c_i32), ("fp64_iters", c_i32), ("reserved", c_i32),
+                ("true_relres_max", c_f64), ("seconds", c_f64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -73,7 +75,7 @@ SIGNATURES = {
     "rmh_rational_apply_bwd": (c_i32, [P_i32, c_vp, c_vp, c_vp, c_i32, ctypes.POINTER(RmhRational),
                                        ctypes.POINTER(RmhSolver), c_vp, c_vp, c_i32, ctypes.POINTER(RmhStats),
                                        c_vp, c_sz, c_vp]),
-    "rmh_tune_set": (c_i32, [P_i32, c_i32, c_i32, c_i32, c_i32, c_i32]),
+    "rmh_tune_set": (c_i32, [P_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32]),
     "rmh_autotune_laplacian": (c_i32, [P_i32, c_vp, c_i32, c_vp, c_vp, c_i32, c_i32, P_i32, P_f64, c_vp]),
     "rmh_tune_clear": (c_i32, []),
     "rmh_profile_enable": (c_i32, [c_i32]),

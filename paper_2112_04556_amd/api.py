@@ -73,12 +73,13 @@ class Rational:
 class Solver:
     tol: float = 1e-10
     maxiter: int = 20000
-    mode: int = 0          # 0 = FP64, 1 = FP32 + FP64 reliable updates
+    mode: int = 0          # 0 = FP64, 1 = FP64 then FP32 with FP64 reliable updates
     delta: float = 0.1
     check_every: int = 8
+    mixed_switch: float = 0.0   # 0: library default (1e-4); < 0: FP32 from the first iteration
 
     def c_struct(self):
-        return L_.RmhSolver(self.tol, self.maxiter, self.mode, self.delta, self.check_every)
+        return L_.RmhSolver(self.tol, self.maxiter, self.mode, self.delta, self.check_every, self.mixed_switch)
 
 
 def workspace_bytes(op: int, L, dtype: int, n_rhs: int, aux: int = 0, degree: int = 0, mode: int = 0) -> int:
@@ -305,10 +306,11 @@ def kinetic_force(L, U, P, rat: Rational, solver: Solver = Solver(), per_rhs: bo
 # ------------------------------------------------------------------------------------------
 # stencil tuning
 
-def tune_set(L, dtype, n_rhs: int, form: int, block: int = 256, xcd_remap: int = 1) -> None:
+def tune_set(L, dtype, n_rhs: int, form: int, block: int = 256, xcd_remap: int = 1, nv: int = 4,
+             order: int = 0) -> None:
     code = RMH_F64 if dtype == torch.float64 else RMH_F32
-    check(lib().rmh_tune_set(lattice_arg(L), code, int(n_rhs), int(form), int(block), int(xcd_remap)),
-          "rmh_tune_set")
+    check(lib().rmh_tune_set(lattice_arg(L), code, int(n_rhs), int(form), int(block), int(xcd_remap), int(nv),
+                             int(order)), "rmh_tune_set")
 
 
 def tune_clear() -> None:
@@ -316,14 +318,14 @@ def tune_clear() -> None:
 
 
 def autotune_laplacian(L, U, x, reps: int = 5):
-    """((form, block, xcd_remap), ms per launch) of the fastest stencil configuration, now stored."""
+    """((form, block, xcd_remap, nv, order), ms per launch) of the fastest stencil configuration, now stored."""
     y = torch.empty_like(x)
-    best = (L_.c_i32 * 3)()
+    best = (L_.c_i32 * 5)()
     ms = ctypes.c_double()
     check(lib().rmh_autotune_laplacian(lattice_arg(L), _dev(U, "U"), _dtype_code(x), _dev(x, "x"), _dev(y, "y"),
                                        x.shape[0], int(reps), best, ctypes.byref(ms), _stream(x.device)),
           "rmh_autotune_laplacian")
-    return (best[0], best[1], best[2]), ms.value
+    return (best[0], best[1], best[2], best[3], best[4]), ms.value
 
 
 # ------------------------------------------------------------------------------------------

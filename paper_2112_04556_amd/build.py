@@ -28,7 +28,7 @@ def build(verbose: bool = False) -> str:
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     objs = []
-    common = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
+    common = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function", "-ffp-contract=off",
               f"-I{os.path.join(HERE, '..', 'include')}"]
     for src in SOURCES:
         path = os.path.join(CSRC, src)

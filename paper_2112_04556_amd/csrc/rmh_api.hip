@@ -212,7 +212,7 @@ ChebPlan plan_cheb(Carver& c, const Geom& g, int32_t dtype, int32_t n_rhs, int32
   p.bufA = c.take<char>(fb);
   p.bufB = c.take<char>(fb);
   if (moments) {
-    const int nblk = (g.V + 63) / 64;  // upper bound over tuned block sizes (>= 64 threads)
+    const int nblk = hop_max_blocks(g);
     p.partials = c.take<double>((size_t)sweeps * n_rhs * 3 * nblk);
     p.sums = c.take<double>((size_t)sweeps * n_rhs * 3);
   }
@@ -225,23 +225,32 @@ ChebPlan plan_cheb(Carver& c, const Geom& g, int32_t dtype, int32_t n_rhs, int32
 struct Engine {
   Geom g;
   int32_t n_rhs = 0, n_shift = 0, mode = 0;
-  // device buffers
-  void* r = nullptr;      // [n_rhs] working precision
-  void* Ap = nullptr;     // [n_rhs]
-  void* p = nullptr;      // [n_rhs][n_shift]
-  float* x_lo = nullptr;  // [n_rhs][n_shift] (mixed)
-  double* r64 = nullptr;  // [n_rhs] (mixed)
+  // FP64 vectors: the whole FP64 solve, or the FP64 phase of a mixed solve (r64 also holds the
+  // FP64 residual of every reliable update)
+  double* r64 = nullptr;   // [n_rhs]
+  double* Ap64 = nullptr;  // [n_rhs]
+  double* p64 = nullptr;   // [n_rhs][n_shift]
+  // FP32 vectors of the mixed phase
+  float* r32 = nullptr;
+  float* Ap32 = nullptr;
+  float* p32 = nullptr;
+  float* x_lo = nullptr;
+  // scalar state, contiguous so one copy brings it to the host: sc then flags
   double* sc = nullptr;
-  double* sh = nullptr;
   int32_t* flags = nullptr;
+  size_t state_bytes = 0;
+  double* sh = nullptr;
   int32_t* act = nullptr;
   int32_t* act_next = nullptr;
-  double* sigma = nullptr;     // [n_rhs][n_shift]
-  int32_t* seed = nullptr;     // [n_rhs]
-  double* b_hop = nullptr;     // [n_rhs]  8 + sigma0
-  double* b_ru = nullptr;      // [n_rhs]  -(8 + sigma0)
-  double* b_true = nullptr;    // [n_rhs][n_shift]  -(8 + sigma_j)
-  double* tol_rhs = nullptr;   // [n_rhs]
+  // parameters, uploaded by one copy per solve
+  char* params = nullptr;
+  size_t params_bytes = 0;
+  double* sigma = nullptr;   // [n_rhs][n_shift]
+  double* b_hop = nullptr;   // [n_rhs]  8 + sigma0
+  double* b_ru = nullptr;    // [n_rhs]  -(8 + sigma0)
+  double* b_true = nullptr;  // [n_rhs][n_shift]  -(8 + sigma_j)
+  double* tol_rhs = nullptr; // [n_rhs]
+  int32_t* seed = nullptr;   // [n_rhs]
   double* part = nullptr;      // [n_rhs][max(3 nblk_hop, nblk_e)]
   double* part_ru = nullptr;   // [n_rhs][3][nblk_hop]  (mixed precision)
   double* part_true = nullptr; // [n_rhs][n_shift][3][nblk_hop]
@@ -249,37 +258,50 @@ struct Engine {
   int32_t nblk_hop = 0, nblk_e = 0;
 };
 
+size_t rup(size_t b) { return ((b + 255) / 256) * 256; }
+
 void plan_engine(Carver& c, Engine& e, const Geom& g, int32_t n_rhs, int32_t n_shift, int32_t mode) {
   e.g = g;
   e.n_rhs = n_rhs;
   e.n_shift = n_shift;
   e.mode = mode;
   const int64_t n = field_reals(g);
-  const size_t ws = mode ? 4 : 8;
-  e.r = c.take<char>((size_t)n_rhs * n * ws);
-  e.Ap = c.take<char>((size_t)n_rhs * n * ws);
-  e.p = c.take<char>((size_t)n_rhs * n_shift * n * ws);
+  const size_t nr = n_rhs, np = (size_t)n_rhs * n_shift;
+  e.r64 = c.take<double>(nr * n);
+  e.Ap64 = c.take<double>(nr * n);
+  e.p64 = c.take<double>(np * n);
   if (mode) {
-    e.x_lo = c.take<float>((size_t)n_rhs * n_shift * n);
-    e.r64 = c.take<double>((size_t)n_rhs * n);
+    e.r32 = c.take<float>(nr * n);
+    e.Ap32 = c.take<float>(nr * n);
+    e.p32 = c.take<float>(np * n);
+    e.x_lo = c.take<float>(np * n);
   }
-  e.sc = c.take<double>((size_t)n_rhs * kScN);
-  e.sh = c.take<double>((size_t)n_rhs * n_shift * kShN);
-  e.flags = c.take<int32_t>((size_t)n_rhs * kFlN);
-  e.act = c.take<int32_t>((size_t)n_rhs * n_shift);
-  e.act_next = c.take<int32_t>((size_t)n_rhs * n_shift);
-  e.sigma = c.take<double>((size_t)n_rhs * n_shift);
-  e.seed = c.take<int32_t>(n_rhs);
-  e.b_hop = c.take<double>(n_rhs);
-  e.b_ru = c.take<double>(n_rhs);
-  e.b_true = c.take<double>((size_t)n_rhs * n_shift);
-  e.tol_rhs = c.take<double>(n_rhs);
-  e.nblk_hop = (g.V + 63) / 64;
+  const size_t scb = rup(nr * kScN * 8), flb = rup(nr * kFlN * 4);
+  char* st = c.take<char>(scb + flb);
+  e.sc = (double*)st;
+  e.flags = st ? (int32_t*)(st + scb) : nullptr;
+  e.state_bytes = scb + flb;
+  e.sh = c.take<double>(np * kShN);
+  e.act = c.take<int32_t>(np);
+  e.act_next = c.take<int32_t>(np);
+  const size_t pb = rup(np * 8) * 2 + rup(nr * 8) * 3 + rup(nr * 4);
+  e.params = c.take<char>(pb);
+  e.params_bytes = pb;
+  if (e.params) {
+    char* q = e.params;
+    e.sigma = (double*)q;   q += rup(np * 8);
+    e.b_true = (double*)q;  q += rup(np * 8);
+    e.b_hop = (double*)q;   q += rup(nr * 8);
+    e.b_ru = (double*)q;    q += rup(nr * 8);
+    e.tol_rhs = (double*)q; q += rup(nr * 8);
+    e.seed = (int32_t*)q;
+  }
+  e.nblk_hop = hop_max_blocks(g);
   e.nblk_e = elem_num_blocks(n);
-  e.part = c.take<double>((size_t)n_rhs * std::max<int64_t>(3 * e.nblk_hop, e.nblk_e));
-  if (mode) e.part_ru = c.take<double>((size_t)n_rhs * 3 * e.nblk_hop);
-  e.part_true = c.take<double>((size_t)n_rhs * n_shift * 3 * e.nblk_hop);
-  e.sums_true = c.take<double>((size_t)n_rhs * n_shift * 3);
+  e.part = c.take<double>(nr * std::max<int64_t>(3 * e.nblk_hop, e.nblk_e));
+  if (mode) e.part_ru = c.take<double>(nr * 3 * e.nblk_hop);
+  e.part_true = c.take<double>(np * 3 * e.nblk_hop);
+  e.sums_true = c.take<double>(np * 3);
 }
 
 CgDev cg_view(const Engine& e, int32_t nblk_hop) {
@@ -313,80 +335,104 @@ int log_level() {
 struct SolveInfo {
   int32_t iters = 0;
   int32_t ru = 0;
+  int32_t fp64_iters = 0;  // iterations done in the FP64 phase
   int32_t status = kStOk;
 };
 
 // Solve (Delta + sigma[v][j]) x[v][j] = b[v] for all v, j to recursive residual tol_rel[v] * ||b_v||.
 // x_hi (FP64, [n_rhs][n_shift]) receives the solutions (zeroed here).
-template <typename T>
+// FP64 engines iterate in FP64 throughout.  Mixed engines iterate in FP64 while the seed residual
+// is above switch_rel * ||b|| (switch_rel <= 0: not at all), then in FP32 with FP64 reliable updates.
 rmh_status engine_solve(Engine& e, const double* U64, const float* U32, const double* b, double* x_hi,
                         const std::vector<double>& sigma, const std::vector<double>& tol_rel, int32_t maxiter,
-                        double delta, int32_t check_every, hipStream_t s, SolveInfo* info) {
+                        double delta, int32_t check_every, double switch_rel, hipStream_t s, SolveInfo* info) {
   const Geom& g = e.g;
   const int64_t n = field_reals(g);
   const int32_t nr = e.n_rhs, ns = e.n_shift;
   const bool mixed = e.mode != 0;
-  // host-side seeds and shift coefficients
+  // parameters: seeds and shift coefficients, one upload
+  std::vector<char> hp(e.params_bytes, 0);
   std::vector<int32_t> seed(nr);
-  std::vector<double> bh(nr), bru(nr), btrue((size_t)nr * ns);
-  for (int v = 0; v < nr; ++v) {
-    int j0 = 0;
-    for (int j = 1; j < ns; ++j)
-      if (sigma[(size_t)v * ns + j] < sigma[(size_t)v * ns + j0]) j0 = j;
-    seed[v] = j0;
-    bh[v] = 8.0 + sigma[(size_t)v * ns + j0];
-    bru[v] = -bh[v];
-    for (int j = 0; j < ns; ++j) btrue[(size_t)v * ns + j] = -(8.0 + sigma[(size_t)v * ns + j]);
+  {
+    const size_t np = (size_t)nr * ns;
+    double* h_sigma = (double*)hp.data();
+    double* h_btrue = (double*)(hp.data() + rup(np * 8));
+    double* h_bhop = (double*)(hp.data() + 2 * rup(np * 8));
+    double* h_bru = h_bhop + rup(nr * 8) / 8;
+    double* h_tol = h_bru + rup(nr * 8) / 8;
+    int32_t* h_seed = (int32_t*)(h_tol + rup(nr * 8) / 8);
+    for (int v = 0; v < nr; ++v) {
+      int j0 = 0;
+      for (int j = 1; j < ns; ++j)
+        if (sigma[(size_t)v * ns + j] < sigma[(size_t)v * ns + j0]) j0 = j;
+      seed[v] = j0;
+      h_seed[v] = j0;
+      h_bhop[v] = 8.0 + sigma[(size_t)v * ns + j0];
+      h_bru[v] = -h_bhop[v];
+      h_tol[v] = tol_rel[v];
+      for (int j = 0; j < ns; ++j) {
+        h_sigma[(size_t)v * ns + j] = sigma[(size_t)v * ns + j];
+        h_btrue[(size_t)v * ns + j] = -(8.0 + sigma[(size_t)v * ns + j]);
+      }
+    }
+    for (int v = 1; v < nr; ++v)
+      if (seed[v] != seed[0]) return fail(RMH_E_ARG, "internal: non-uniform seed shift");
+    HIP_TRY(hipMemcpyAsync(e.params, hp.data(), hp.size(), hipMemcpyHostToDevice, s));
   }
-  for (int v = 1; v < nr; ++v)
-    if (seed[v] != seed[0]) return fail(RMH_E_ARG, "internal: non-uniform seed shift");
-  RMH_TRY(h2d(e.sigma, sigma.data(), sigma.size() * 8, s));
-  RMH_TRY(h2d(e.seed, seed.data(), seed.size() * 4, s));
-  RMH_TRY(h2d(e.b_hop, bh.data(), bh.size() * 8, s));
-  RMH_TRY(h2d(e.b_ru, bru.data(), bru.size() * 8, s));
-  RMH_TRY(h2d(e.b_true, btrue.data(), btrue.size() * 8, s));
-  RMH_TRY(h2d(e.tol_rhs, tol_rel.data(), tol_rel.size() * 8, s));
-
-  const HopConfig cw = hop_config(g, mixed ? RMH_F32 : RMH_F64, nr, 1);
+  const HopConfig c32 = hop_config(g, RMH_F32, nr, 1);
   const HopConfig c64 = hop_config(g, RMH_F64, nr, 2);
-  const int32_t nblk_w = hop_num_blocks(g, cw), nblk_64 = hop_num_blocks(g, c64);
-  CgDev cg = cg_view(e, nblk_w);
-  cg.nblk_ru = nblk_64;
+  const int32_t nblk_32 = hop_num_blocks(g, c32), nblk_64 = hop_num_blocks(g, c64);
+  CgDev cg64 = cg_view(e, nblk_64);
+  CgDev cg32 = cg_view(e, nblk_32);
+  cg32.nblk_ru = nblk_64;
 
-  T* r = (T*)e.r;
-  T* Ap = (T*)e.Ap;
-  T* p = (T*)e.p;
+  bool fp32_phase = mixed && !(switch_rel > 0.0);
   HIP_TRY(launch_zero(x_hi, (size_t)nr * ns * n * 8, s));
   if (mixed) HIP_TRY(launch_zero(e.x_lo, (size_t)nr * ns * n * 4, s));
-  HIP_TRY(launch_copy_cast<T>(b, r, (int64_t)nr * n, s));
-  for (int v = 0; v < nr; ++v)
-    for (int j = 0; j < ns; ++j) HIP_TRY(launch_copy_cast<T>(b + (size_t)v * n, p + ((size_t)v * ns + j) * n, n, s));
-  if (mixed) HIP_TRY(launch_copy_cast<double>(b, e.r64, (int64_t)nr * n, s));
-  // ||b||^2 and the initial scalars
+  if (fp32_phase) {
+    HIP_TRY(launch_copy_cast<float>(b, e.r32, (int64_t)nr * n, s));
+    HIP_TRY(launch_bcast_cast<float>(b, e.p32, nr, ns, n, s));
+  } else {
+    HIP_TRY(launch_copy_cast<double>(b, e.r64, (int64_t)nr * n, s));
+    HIP_TRY(launch_bcast_cast<double>(b, e.p64, nr, ns, n, s));
+  }
   HIP_TRY(launch_dot<double>(b, b, n, nr, e.part, s));
-  HIP_TRY(launch_cg_init(cg, e.part, e.nblk_e, e.tol_rhs, delta, maxiter, s));
-  std::vector<double> sc((size_t)nr * kScN);
+  HIP_TRY(launch_cg_init(cg64, e.part, e.nblk_e, e.tol_rhs, delta, maxiter, s));
 
-  // Stencil on the seed direction: Ap = (Delta + sigma0) p_seed = (8 + sigma0) p - H p
-  HopArgs<T> ha{};
-  ha.g = g;
-  ha.U = mixed ? (const T*)U32 : (const T*)U64;
-  ha.x = p;
-  ha.x_mul = ns;
-  ha.x_add = seed[0];
-  ha.out = Ap;
-  ha.z = nullptr;
-  ha.z_div = 1;
-  ha.a = -1.0;
-  ha.b = 0.0;
-  ha.b_rhs = e.b_hop;
-  ha.c = 0.0;
-  ha.n_rhs = nr;
-  ha.run = e.flags + kFlRun;
-  ha.run_stride = kFlN;
-  ha.store = 1;
-  ha.partials = e.part;
-  ha.dot_mask = 2;
+  // FP64 stencil on the seed direction: Ap = (8 + sigma0) p - H p, partial <p, Ap>
+  HopArgs<double> h64{};
+  h64.g = g;
+  h64.U = U64;
+  h64.x = e.p64;
+  h64.x_mul = ns;
+  h64.x_add = seed[0];
+  h64.out = e.Ap64;
+  h64.z_div = 1;
+  h64.a = -1.0;
+  h64.b_rhs = e.b_hop;
+  h64.n_rhs = nr;
+  h64.run = e.flags + kFlRun;
+  h64.run_stride = kFlN;
+  h64.store = 1;
+  h64.partials = e.part;
+  h64.dot_mask = 2;
+  // FP32 stencil of the mixed phase
+  HopArgs<float> h32{};
+  h32.g = g;
+  h32.U = U32;
+  h32.x = e.p32;
+  h32.x_mul = ns;
+  h32.x_add = seed[0];
+  h32.out = e.Ap32;
+  h32.z_div = 1;
+  h32.a = -1.0;
+  h32.b_rhs = e.b_hop;
+  h32.n_rhs = nr;
+  h32.run = e.flags + kFlRun;
+  h32.run_stride = kFlN;
+  h32.store = 1;
+  h32.partials = e.part;
+  h32.dot_mask = 2;
   // FP64 true residual of the seed for reliable updates: r64 = b - (Delta + sigma0) x_hi_seed
   HopArgs<double> hr{};
   hr.g = g;
@@ -408,78 +454,90 @@ rmh_status engine_solve(Engine& e, const double* U64, const float* U32, const do
   hr.dot_mask = 4;
 
   if (check_every <= 0) check_every = 8;
-  std::vector<int32_t> fl((size_t)nr * kFlN);
+  std::vector<char> st(e.state_bytes);
+  const double* hsc = (const double*)st.data();
+  const int32_t* hfl = (const int32_t*)(st.data() + ((char*)e.flags - (char*)e.sc));
   int32_t it = 0;
+  info->fp64_iters = 0;
   while (true) {
     for (int i = 0; i < check_every; ++i) {
-      {
-        ProfScope ps(RMH_PROF_STENCIL, hop_bytes(g, nr, sizeof(T), false, true), s, nr);
-        HIP_TRY(launch_hop<T>(ha, cw, s));
-      }
-      HIP_TRY(launch_cg_alpha(cg, s));
-      {
-        ProfScope ps(RMH_PROF_CG_RESIDUAL, 3.0 * nr * n * sizeof(T), s, nr);
-        HIP_TRY(launch_cg_r_update<T>(cg, r, Ap, mixed ? e.r64 : nullptr, n, s));
-      }
-      HIP_TRY(launch_cg_beta(cg, mixed ? 1 : 0, s));
-      {
-        ProfScope ps(RMH_PROF_CG_SHIFTS, 0.0, s);  // bytes added after the solve (active shifts only)
-        if (mixed)
-          HIP_TRY((launch_cg_shift_update<T, T>(cg, r, p, (T*)e.x_lo, x_hi, n, s)));
-        else
-          HIP_TRY((launch_cg_shift_update<T, T>(cg, r, p, (T*)x_hi, nullptr, n, s)));
-      }
-      if (mixed) {
-        // reliable update decided by this iteration's beta kernel: FP64 residual of the seed
-        // (blocks of rhs without a pending update exit at once)
+      if (!fp32_phase) {
+        {
+          ProfScope ps(RMH_PROF_STENCIL, hop_bytes(g, nr, 8, false, true), s, nr);
+          HIP_TRY(launch_hop<double>(h64, c64, s));
+        }
+        HIP_TRY(launch_cg_alpha(cg64, s));
+        {
+          ProfScope ps(RMH_PROF_CG_RESIDUAL, 3.0 * nr * n * 8, s, nr);
+          HIP_TRY(launch_cg_r_update<double>(cg64, e.r64, e.Ap64, nullptr, n, s));
+        }
+        HIP_TRY(launch_cg_beta(cg64, 0, s));
+        {
+          ProfScope ps(RMH_PROF_CG_SHIFTS, 0.0, s);
+          HIP_TRY((launch_cg_shift_update<double, double>(cg64, e.r64, e.p64, x_hi, nullptr, n, s)));
+        }
+      } else {
+        {
+          ProfScope ps(RMH_PROF_STENCIL, hop_bytes(g, nr, 4, false, true), s, nr);
+          HIP_TRY(launch_hop<float>(h32, c32, s));
+        }
+        HIP_TRY(launch_cg_alpha(cg32, s));
+        {
+          ProfScope ps(RMH_PROF_CG_RESIDUAL, 3.0 * nr * n * 4, s, nr);
+          HIP_TRY(launch_cg_r_update<float>(cg32, e.r32, e.Ap32, e.r64, n, s));
+        }
+        HIP_TRY(launch_cg_beta(cg32, 1, s));
+        {
+          ProfScope ps(RMH_PROF_CG_SHIFTS, 0.0, s);
+          HIP_TRY((launch_cg_shift_update<float, float>(cg32, e.r32, e.p32, e.x_lo, x_hi, n, s)));
+        }
+        // reliable update decided by this iteration's beta kernel (blocks of rhs without a
+        // pending update exit at once)
         HIP_TRY(launch_hop<double>(hr, c64, s));
       }
     }
     it += check_every;
-    RMH_TRY(d2h(fl.data(), e.flags, fl.size() * 4, s));
-    bool running = false, need_ru = false;
+    if (!fp32_phase) info->fp64_iters = it;
+    RMH_TRY(d2h(st.data(), e.sc, e.state_bytes, s));
+    bool running = false, below = true;
     for (int v = 0; v < nr; ++v) {
-      running |= fl[(size_t)v * kFlN + kFlRun] != 0;
-      need_ru |= fl[(size_t)v * kFlN + kFlNeedRU] != 0;
+      if (hfl[(size_t)v * kFlN + kFlRun] == 0) continue;
+      running = true;
+      const double rr = hsc[(size_t)v * kScN + kScRR], bb = hsc[(size_t)v * kScN + kScBnorm2];
+      if (!(sqrt(rr) <= switch_rel * sqrt(bb))) below = false;
     }
     if (!running) break;
-    (void)need_ru;
+    if (mixed && !fp32_phase && below) {
+      // switch to FP32: the remaining increments are small, so their rounding no longer matters
+      HIP_TRY(launch_copy_cast<float>(e.r64, e.r32, (int64_t)nr * n, s));
+      HIP_TRY(launch_f64_to_f32(e.p64, e.p32, (int64_t)nr * ns * n, s));
+      HIP_TRY(launch_cg_reset_maxr(cg32, s));
+      fp32_phase = true;
+    }
     if (it > maxiter + 2 * check_every) break;  // safety net; the device sets NoConv first
   }
-  if (mixed) HIP_TRY(launch_ru_accumulate(cg, e.x_lo, x_hi, n, 1, s));
-  RMH_TRY(d2h(sc.data(), e.sc, sc.size() * 8, s));
+  if (mixed) HIP_TRY(launch_ru_accumulate(cg32, e.x_lo, x_hi, n, 1, s));
+  RMH_TRY(d2h(st.data(), e.sc, e.state_bytes, s));
   if (log_level() > 0) {
     for (int v = 0; v < nr; ++v)
-      fprintf(stderr, "[rmh] engine mode=%d rhs %d/%d shifts=%d sigma0=%.4g iters=%g ru=%g status=%d |b|^2=%.4g rr=%.4g tol=%.3g\n",
-              e.mode, v, nr, ns, sigma[(size_t)v * ns + seed[v]], sc[(size_t)v * kScN + kScIters],
-              sc[(size_t)v * kScN + kScRU], fl[(size_t)v * kFlN + kFlStatus], sc[(size_t)v * kScN + kScBnorm2],
-              sc[(size_t)v * kScN + kScRR], tol_rel[v]);
-  }
-  if (log_level() > 1) {
-    std::vector<double> shv((size_t)nr * ns * kShN);
-    std::vector<int32_t> a0((size_t)nr * ns), a1((size_t)nr * ns);
-    RMH_TRY(d2h(shv.data(), e.sh, shv.size() * 8, s));
-    RMH_TRY(d2h(a0.data(), e.act, a0.size() * 4, s));
-    RMH_TRY(d2h(a1.data(), e.act_next, a1.size() * 4, s));
-    for (int v = 0; v < nr; ++v)
-      for (int j = 0; j < ns; ++j) {
-        const double* h = shv.data() + ((size_t)v * ns + j) * kShN;
-        fprintf(stderr, "[rmh]   shift %d sigma %.4g upd=%g zeta=%.3e zeta_prev=%.3e cx=%.3e cr=%.3e cp=%.3e act=%d/%d\n", j,
-                sigma[(size_t)v * ns + j], h[kShUpd], h[kShZeta], h[kShZetaPrev], h[kShCx], h[kShCr], h[kShCp],
-                a0[(size_t)v * ns + j], a1[(size_t)v * ns + j]);
-      }
+      fprintf(stderr, "[rmh] engine mode=%d rhs %d/%d shifts=%d sigma0=%.4g iters=%g (fp64 %d) ru=%g status=%d |b|^2=%.4g rr=%.4g tol=%.3g\n",
+              e.mode, v, nr, ns, sigma[(size_t)v * ns + seed[v]], hsc[(size_t)v * kScN + kScIters], info->fp64_iters,
+              hsc[(size_t)v * kScN + kScRU], hfl[(size_t)v * kFlN + kFlStatus], hsc[(size_t)v * kScN + kScBnorm2],
+              hsc[(size_t)v * kScN + kScRR], tol_rel[v]);
   }
   if (g_prof.on) {
     // exact algorithmic bytes of the shift updates: per update of shift j, p_j read, x_j read and
     // written, p_j written unless it was the shift's last update; r read once per live iteration
+    // (counted at the FP64 width: an upper bound for the iterations done in FP32)
     std::vector<double> shv((size_t)nr * ns * kShN);
     RMH_TRY(d2h(shv.data(), e.sh, shv.size() * 8, s));
+    const double ts = mixed ? 4.0 : 8.0;
     double bytes = 0.0;
     for (int v = 0; v < nr; ++v) {
-      bytes += sc[(size_t)v * kScN + kScIters] * n * sizeof(T);
+      bytes += hsc[(size_t)v * kScN + kScIters] * n * ts;
       for (int j = 0; j < ns; ++j) {
         const double upd = shv[((size_t)v * ns + j) * kShN + kShUpd];
-        if (upd > 0) bytes += (upd * 3.0 + (upd - 1.0)) * n * sizeof(T);
+        if (upd > 0) bytes += (upd * 3.0 + (upd - 1.0)) * n * ts;
       }
     }
     prof_add_bytes(RMH_PROF_CG_SHIFTS, bytes);
@@ -488,11 +546,11 @@ rmh_status engine_solve(Engine& e, const double* U64, const float* U32, const do
   info->ru = 0;
   info->status = kStOk;
   for (int v = 0; v < nr; ++v) {
-    info->iters = std::max(info->iters, (int32_t)sc[(size_t)v * kScN + kScIters]);
-    info->ru += (int32_t)sc[(size_t)v * kScN + kScRU];
-    const int32_t st = fl[(size_t)v * kFlN + kFlStatus];
-    if (st == kStBreakdown) info->status = kStBreakdown;
-    else if (st == kStNoConv && info->status == kStOk) info->status = kStNoConv;
+    info->iters = std::max(info->iters, (int32_t)hsc[(size_t)v * kScN + kScIters]);
+    info->ru += (int32_t)hsc[(size_t)v * kScN + kScRU];
+    const int32_t stv = hfl[(size_t)v * kFlN + kFlStatus];
+    if (stv == kStBreakdown) info->status = kStBreakdown;
+    else if (stv == kStNoConv && info->status == kStOk) info->status = kStNoConv;
   }
   return RMH_OK;
 }
@@ -537,13 +595,15 @@ rmh_status true_residuals(Engine& e, const double* U64, const double* b, const d
   return RMH_OK;
 }
 
-// Refinement engine buffers for a batch of (rhs, shift) pairs.
+// Refinement buffers for a batch of (rhs, shift) pairs solved as independent single-shift systems.
 struct RefinePlan {
   Engine eng;
-  double* X;     // [nb] copies of x_hi of the pairs
-  double* Bsrc;  // [nb] copies of the sources
-  double* Res;   // [nb] residual vectors (sources of the correction solve)
-  double* E;     // [nb] corrections
+  double* X;      // [nb] copies of the pairs' solutions
+  double* Bsrc;   // [nb] copies of their sources
+  double* Res;    // [nb] residual vectors (sources of the correction solve)
+  double* E;      // [nb] corrections
+  int32_t* idx;   // [nb] pair indices, then [nb] doubles -(8 + sigma) (one upload)
+  double* bneg;
   int32_t nb;
 };
 
@@ -558,6 +618,9 @@ void plan_refine(Carver& c, RefinePlan& rp, const Geom& g, int32_t nb, int32_t m
   rp.Bsrc = c.take<double>((size_t)nb * n);
   rp.Res = c.take<double>((size_t)nb * n);
   rp.E = c.take<double>((size_t)nb * n);
+  char* q = c.take<char>(rup((size_t)nb * 4) + rup((size_t)nb * 8));
+  rp.idx = (int32_t*)q;
+  rp.bneg = q ? (double*)(q + rup((size_t)nb * 4)) : nullptr;
   plan_engine(c, rp.eng, g, nb, 1, mode);
 }
 
@@ -565,24 +628,22 @@ struct SolvePlan {
   Engine eng;
   RefinePlan ref;
   float* U32 = nullptr;
-  double* bn2_sums = nullptr;
 };
 
 void plan_solve(Carver& c, SolvePlan& sp, const Geom& g, int32_t n_rhs, int32_t n_shift, int32_t mode) {
   plan_engine(c, sp.eng, g, n_rhs, n_shift, mode);
   plan_refine(c, sp.ref, g, refine_batch(n_rhs, n_shift), mode);
   if (mode) sp.U32 = c.take<float>((size_t)72 * g.V);
-  sp.bn2_sums = c.take<double>(n_rhs);
 }
 
 struct SolveResult {
-  int32_t iters = 0, ru = 0, refine_iters = 0, refine_rounds = 0;
+  int32_t iters = 0, ru = 0, refine_iters = 0, refine_rounds = 0, fp64_iters = 0;
   double relres_max = 0.0;
   int32_t status = kStOk;
 };
 
 // Full solve of every shift to the FP64 true residual tol: multi-shift CG, then per-shift
-// refinement of the pairs above tol (batched as independent single-shift systems).
+// refinement of any pair above tol (batched as independent single-shift systems).
 rmh_status solve_all(SolvePlan& sp, const double* U64, const double* b, double* x_hi, const std::vector<double>& sig,
                      const rmh_solver& sv, hipStream_t s, SolveResult* out) {
   Engine& e = sp.eng;
@@ -596,24 +657,21 @@ rmh_status solve_all(SolvePlan& sp, const double* U64, const double* b, double* 
     for (int j = 0; j < ns; ++j) sigma[(size_t)v * ns + j] = sig[j];
   // the recursive residual is driven below the target so the true residual lands under it
   const double target = 0.5 * sv.tol;
+  const double sw = sv.mixed_switch > 0.0 ? sv.mixed_switch : (sv.mixed_switch < 0.0 ? 0.0 : 1e-4);
   std::vector<double> tol_rel(nr, target);
   SolveInfo info;
-  if (mode)
-    RMH_TRY(engine_solve<float>(e, U64, sp.U32, b, x_hi, sigma, tol_rel, sv.maxiter, sv.delta, sv.check_every, s,
-                                &info));
-  else
-    RMH_TRY(engine_solve<double>(e, U64, nullptr, b, x_hi, sigma, tol_rel, sv.maxiter, sv.delta, sv.check_every,
-                                 s, &info));
+  RMH_TRY(engine_solve(e, U64, sp.U32, b, x_hi, sigma, tol_rel, sv.maxiter, sv.delta, sv.check_every, sw, s,
+                       &info));
   out->iters = info.iters;
   out->ru = info.ru;
+  out->fp64_iters = info.fp64_iters;
   out->status = info.status;
   if (info.status == kStBreakdown) return RMH_OK;
-  // ||b_v||
   std::vector<double> bnorm(nr);
   {
-    std::vector<double> sc((size_t)nr * kScN);
-    RMH_TRY(d2h(sc.data(), e.sc, sc.size() * 8, s));
-    for (int v = 0; v < nr; ++v) bnorm[v] = sqrt(sc[(size_t)v * kScN + kScBnorm2]);
+    std::vector<double> scv((size_t)nr * kScN);
+    RMH_TRY(d2h(scv.data(), e.sc, scv.size() * 8, s));
+    for (int v = 0; v < nr; ++v) bnorm[v] = sqrt(scv[(size_t)v * kScN + kScBnorm2]);
   }
   std::vector<double> res;
   RMH_TRY(true_residuals(e, U64, b, x_hi, bnorm, s, &res));
@@ -631,20 +689,20 @@ rmh_status solve_all(SolvePlan& sp, const double* U64, const double* b, double* 
     for (size_t i0 = 0; i0 < bad.size(); i0 += rp.nb) {
       const int32_t nb = (int32_t)std::min<size_t>(rp.nb, bad.size() - i0);
       std::vector<double> rsig(nb), rtol(nb);
+      std::vector<char> up(rup((size_t)rp.nb * 4) + rup((size_t)rp.nb * 8), 0);
+      int32_t* hidx = (int32_t*)up.data();
+      double* hbn = (double*)(up.data() + rup((size_t)rp.nb * 4));
       for (int i = 0; i < nb; ++i) {
-        const int q = bad[i0 + i], v = q / ns, j = q % ns;
-        HIP_TRY(hipMemcpyAsync(rp.X + (size_t)i * n, x_hi + (size_t)q * n, n * 8, hipMemcpyDeviceToDevice, s));
-        HIP_TRY(hipMemcpyAsync(rp.Bsrc + (size_t)i * n, b + (size_t)v * n, n * 8, hipMemcpyDeviceToDevice, s));
-        rsig[i] = sig[j];
+        const int q = bad[i0 + i];
+        hidx[i] = q;
+        rsig[i] = sig[q % ns];
+        hbn[i] = -(8.0 + rsig[i]);
         // correction solve target relative to its own source ||r|| = res * ||b||
         rtol[i] = std::min(0.5, target / std::max(res[q], 1e-300));
       }
+      HIP_TRY(hipMemcpyAsync(rp.idx, up.data(), up.size(), hipMemcpyHostToDevice, s));
+      HIP_TRY(launch_gather_pairs(x_hi, b, rp.idx, ns, rp.X, rp.Bsrc, nb, n, s));
       // residual vectors Res_i = Bsrc_i - (Delta + sigma_i) X_i
-      Engine& re = rp.eng;
-      re.n_rhs = nb;
-      std::vector<double> btr(nb);
-      for (int i = 0; i < nb; ++i) btr[i] = -(8.0 + rsig[i]);
-      RMH_TRY(h2d(re.b_true, btr.data(), nb * 8, s));
       HopArgs<double> h{};
       h.g = g;
       h.U = U64;
@@ -654,7 +712,7 @@ rmh_status solve_all(SolvePlan& sp, const double* U64, const double* b, double* 
       h.z = rp.Bsrc;
       h.z_div = 1;
       h.a = 1.0;
-      h.b_rhs = re.b_true;
+      h.b_rhs = rp.bneg;
       h.c = 1.0;
       h.n_rhs = nb;
       h.store = 1;
@@ -662,19 +720,15 @@ rmh_status solve_all(SolvePlan& sp, const double* U64, const double* b, double* 
         ProfScope ps(RMH_PROF_STENCIL, hop_bytes(g, nb, 8, true, true), s, nb);
         HIP_TRY(launch_hop<double>(h, hop_config(g, RMH_F64, nb, 2), s));
       }
+      Engine& re = rp.eng;
+      re.n_rhs = nb;
       SolveInfo ri;
-      if (mode)
-        RMH_TRY(engine_solve<float>(re, U64, sp.U32, rp.Res, rp.E, rsig, rtol, sv.maxiter, sv.delta,
-                                    sv.check_every, s, &ri));
-      else
-        RMH_TRY(engine_solve<double>(re, U64, nullptr, rp.Res, rp.E, rsig, rtol, sv.maxiter, sv.delta,
-                                     sv.check_every, s, &ri));
+      // corrections need only a few digits: FP32 from the start when mixed
+      RMH_TRY(engine_solve(re, U64, sp.U32, rp.Res, rp.E, rsig, rtol, sv.maxiter, sv.delta, sv.check_every, 0.0,
+                           s, &ri));
       out->refine_iters += ri.iters;
       if (ri.status == kStBreakdown) out->status = kStBreakdown;
-      HIP_TRY(launch_add(rp.X, rp.E, (int64_t)nb * n, s));
-      for (int i = 0; i < nb; ++i)
-        HIP_TRY(hipMemcpyAsync(x_hi + (size_t)bad[i0 + i] * n, rp.X + (size_t)i * n, n * 8,
-                               hipMemcpyDeviceToDevice, s));
+      HIP_TRY(launch_scatter_add_pairs(x_hi, rp.idx, rp.E, nb, n, s));
     }
     RMH_TRY(true_residuals(e, U64, b, x_hi, bnorm, s, &res));
   }
@@ -704,6 +758,8 @@ rmh_status check_solver(const rmh_solver* sv) {
   if (sv->mode != 0 && sv->mode != 1) return fail(RMH_E_ARG, "solver mode = %d must be 0 or 1", sv->mode);
   if (sv->mode == 1 && !(sv->delta > 0.0 && sv->delta < 1.0))
     return fail(RMH_E_ARG, "solver delta = %g must lie in (0, 1)", sv->delta);
+  if (!(sv->mixed_switch < 1.0) || sv->mixed_switch != sv->mixed_switch)
+    return fail(RMH_E_ARG, "solver mixed_switch = %g must be < 1", sv->mixed_switch);
   return RMH_OK;
 }
 
@@ -722,6 +778,7 @@ void fill_stats(rmh_stats* st, const SolveResult* rs, int n, double seconds) {
     st->reliable_updates += rs[i].ru;
     st->refine_iters += rs[i].refine_iters;
     st->refine_rounds += rs[i].refine_rounds;
+    st->fp64_iters += rs[i].fp64_iters;
     st->true_relres_max = std::max(st->true_relres_max, rs[i].relres_max);
   }
   st->seconds = seconds;
@@ -1346,16 +1403,19 @@ rmh_status rmh_kinetic_force(const int32_t L[4], const double* U, const double* 
 }
 
 rmh_status rmh_tune_set(const int32_t L[4], int32_t dtype, int32_t n_rhs, int32_t form, int32_t block,
-                        int32_t xcd_remap) {
+                        int32_t xcd_remap, int32_t nv, int32_t order) {
   Geom g;
   RMH_TRY(make_geom(L, &g));
   RMH_TRY(check_dtype(dtype));
-  if (form != kFormAdjoint && form != kFormMatrix) return fail(RMH_E_ARG, "form must be 0 or 1");
+  if (form < kFormAdjoint || form > kFormStream) return fail(RMH_E_ARG, "form must be 0, 1 or 2");
   if (block != 64 && block != 128 && block != 256) return fail(RMH_E_ARG, "block must be 64, 128 or 256");
+  if (nv != 2 && nv != 4) return fail(RMH_E_ARG, "nv must be 2 or 4");
   HopConfig c;
   c.form = form;
   c.block = block;
   c.xcd_remap = xcd_remap ? 1 : 0;
+  c.nv = nv;
+  c.order = order ? 1 : 0;
   tune_store(g, dtype, n_rhs, c);
   return RMH_OK;
 }
@@ -1378,13 +1438,18 @@ rmh_status rmh_autotune_laplacian(const int32_t L[4], const void* U, int32_t dty
   HopConfig bestc;
   float bt = 1e30f;
   rmh_status st = RMH_OK;
-  for (int form = 0; form < 2 && st == RMH_OK; ++form)
-    for (int block : {64, 128, 256}) {
+  for (int form = 0; form < 3 && st == RMH_OK; ++form)
+    for (int nv : {4, 2})
+    for (int block : {64, 128, 256})
+    for (int order = 0; order < 2 && st == RMH_OK; ++order) {
       for (int xcd = 0; xcd < 2 && st == RMH_OK; ++xcd) {
         HopConfig c;
         c.form = form;
         c.block = block;
         c.xcd_remap = xcd;
+        c.nv = nv;
+        c.order = order;
+        if (order && !hop_order_ok(g, c)) continue;
         tune_store(g, dtype, n_rhs, c);
         st = rmh_laplacian_apply(L, U, dtype, x, y, n_rhs, 0.0, stream);  // warm-up
         if (st != RMH_OK) break;
@@ -1396,22 +1461,27 @@ rmh_status rmh_autotune_laplacian(const int32_t L[4], const void* U, int32_t dty
           break;
         }
         float ms = 0.f;
-        hipEventElapsedTime(&ms, e0, e1);
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) ms = 1e30f;
         ms /= reps;
+        if (log_level() > 0)
+          fprintf(stderr, "[rmh] tune L=%dx%dx%dx%d dtype=%d n=%d form=%d nv=%d block=%d order=%d xcd=%d: %.4f ms\n",
+                  g.L0, g.L1, g.L2, g.L3, dtype, n_rhs, form, nv, block, order, xcd, ms);
         if (ms < bt) {
           bt = ms;
           bestc = c;
         }
       }
     }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (st != RMH_OK) return st;
   tune_store(g, dtype, n_rhs, bestc);
   if (best) {
     best[0] = bestc.form;
     best[1] = bestc.block;
     best[2] = bestc.xcd_remap;
+    best[3] = bestc.nv;
+    best[4] = bestc.order;
   }
   if (best_ms) *best_ms = bt;
   return RMH_OK;

@@ -23,6 +23,12 @@ namespace rmh {
 
 constexpr double kInvSqrt3 = 0.57735026918962576451;
 
+// Every multiply-add of the per-site arithmetic is an explicit fused multiply-add and the
+// library is compiled with -ffp-contract=off, so the rounding of a result is fixed by the
+// source alone (identical for every launch configuration of one form).
+RMH_HD double fmadd(double a, double b, double c) { return fma(a, b, c); }
+RMH_HD float fmadd(float a, float b, float c) { return fmaf(a, b, c); }
+
 // Lattice geometry passed by value to kernels.
 struct Geom {
   int32_t L0, L1, L2, L3;
@@ -73,8 +79,8 @@ RMH_HD void adjoint_matrix(const T* u, T* R) {
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
-        mre[i][j] = URE(i, k) * URE(j, l) + UIM(i, k) * UIM(j, l);
-        mim[i][j] = UIM(i, k) * URE(j, l) - URE(i, k) * UIM(j, l);
+        mre[i][j] = fmadd(URE(i, k), URE(j, l), UIM(i, k) * UIM(j, l));
+        mim[i][j] = fmadd(UIM(i, k), URE(j, l), -(URE(i, k) * UIM(j, l)));
       }
     const int bs = pr_s[q], ba = pr_s[q] + 1;
 #pragma unroll
@@ -87,21 +93,21 @@ RMH_HD void adjoint_matrix(const T* u, T* R) {
       R[aa * 8 + ba] = mre[i][j] - mre[j][i];
     }
     R[2 * 8 + bs] = mre[0][0] - mre[1][1];
-    R[7 * 8 + bs] = (mre[0][0] + mre[1][1] - T(2) * mre[2][2]) * T(kInvSqrt3);
+    R[7 * 8 + bs] = fmadd(T(-2), mre[2][2], mre[0][0] + mre[1][1]) * T(kInvSqrt3);
     R[2 * 8 + ba] = mim[0][0] - mim[1][1];
-    R[7 * 8 + ba] = (mim[0][0] + mim[1][1] - T(2) * mim[2][2]) * T(kInvSqrt3);
+    R[7 * 8 + ba] = fmadd(T(-2), mim[2][2], mim[0][0] + mim[1][1]) * T(kInvSqrt3);
   }
   // Columns of T^3 and T^8 from N_k = u_k u_k^dag (Hermitian).
   T nre[3][3][3], nim[3][3];  // nre[k][i][j] for i<=j used; nim[k][pair]
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
 #pragma unroll
-    for (int i = 0; i < 3; ++i) nre[k][i][i] = URE(i, k) * URE(i, k) + UIM(i, k) * UIM(i, k);
+    for (int i = 0; i < 3; ++i) nre[k][i][i] = fmadd(URE(i, k), URE(i, k), UIM(i, k) * UIM(i, k));
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
       const int i = pr_i[p], j = pr_j[p];
-      nre[k][i][j] = URE(i, k) * URE(j, k) + UIM(i, k) * UIM(j, k);
-      nim[k][p] = UIM(i, k) * URE(j, k) - URE(i, k) * UIM(j, k);
+      nre[k][i][j] = fmadd(URE(i, k), URE(j, k), UIM(i, k) * UIM(j, k));
+      nim[k][p] = fmadd(UIM(i, k), URE(j, k), -(URE(i, k) * UIM(j, k)));
     }
   }
   // Y3 = (N0 - N1)/2, Y8 = (N0 + N1 - 2 N2)/(2 sqrt 3)
@@ -111,8 +117,8 @@ RMH_HD void adjoint_matrix(const T* u, T* R) {
     const int as = pr_s[p], aa = pr_s[p] + 1;
     const T d3re = nre[0][i][j] - nre[1][i][j];
     const T d3im = nim[0][p] - nim[1][p];
-    const T d8re = (nre[0][i][j] + nre[1][i][j] - T(2) * nre[2][i][j]) * T(kInvSqrt3);
-    const T d8im = (nim[0][p] + nim[1][p] - T(2) * nim[2][p]) * T(kInvSqrt3);
+    const T d8re = fmadd(T(-2), nre[2][i][j], nre[0][i][j] + nre[1][i][j]) * T(kInvSqrt3);
+    const T d8im = fmadd(T(-2), nim[2][p], nim[0][p] + nim[1][p]) * T(kInvSqrt3);
     R[as * 8 + 2] = d3re;   // 2 Re Y_ij with Y = (N0 - N1)/2
     R[aa * 8 + 2] = -d3im;
     R[as * 8 + 7] = d8re;
@@ -123,15 +129,125 @@ RMH_HD void adjoint_matrix(const T* u, T* R) {
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       y3[i] = T(0.5) * (nre[0][i][i] - nre[1][i][i]);
-      y8[i] = T(0.5) * T(kInvSqrt3) * (nre[0][i][i] + nre[1][i][i] - T(2) * nre[2][i][i]);
+      y8[i] = T(0.5) * T(kInvSqrt3) * fmadd(T(-2), nre[2][i][i], nre[0][i][i] + nre[1][i][i]);
     }
     R[2 * 8 + 2] = y3[0] - y3[1];
-    R[7 * 8 + 2] = (y3[0] + y3[1] - T(2) * y3[2]) * T(kInvSqrt3);
+    R[7 * 8 + 2] = fmadd(T(-2), y3[2], y3[0] + y3[1]) * T(kInvSqrt3);
     R[2 * 8 + 7] = y8[0] - y8[1];
-    R[7 * 8 + 7] = (y8[0] + y8[1] - T(2) * y8[2]) * T(kInvSqrt3);
+    R[7 * 8 + 7] = fmadd(T(-2), y8[2], y8[0] + y8[1]) * T(kInvSqrt3);
   }
 #undef URE
 #undef UIM
+}
+
+// The two columns of R(U) that belong to generator group q, written into c1[8], c2[8]:
+// q = 0, 1, 2: the symmetric / antisymmetric generators of the pair (0,1), (0,2), (1,2)
+// (columns 0/1, 3/4, 5/6); q = 3: the diagonal generators T^3, T^8 (columns 2 and 7).
+// Same bilinears of the columns of U as adjoint_matrix, one group at a time.
+template <typename T, int q>
+RMH_HD void adjoint_columns(const T* u, T* c1, T* c2) {
+  constexpr int pr_i[3] = {0, 0, 1};
+  constexpr int pr_j[3] = {1, 2, 2};
+  constexpr int pr_s[3] = {0, 3, 5};
+#define URE(i, k) u[2 * (3 * (i) + (k))]
+#define UIM(i, k) u[2 * (3 * (i) + (k)) + 1]
+  if (q < 3) {
+    constexpr int k = pr_i[q < 3 ? q : 0], l = pr_j[q < 3 ? q : 0];
+    T mre[3][3], mim[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        mre[i][j] = fmadd(URE(i, k), URE(j, l), UIM(i, k) * UIM(j, l));
+        mim[i][j] = fmadd(UIM(i, k), URE(j, l), -(URE(i, k) * UIM(j, l)));
+      }
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      const int i = pr_i[p], j = pr_j[p];
+      const int as = pr_s[p], aa = pr_s[p] + 1;
+      c1[as] = mre[i][j] + mre[j][i];
+      c1[aa] = mim[j][i] - mim[i][j];
+      c2[as] = mim[i][j] + mim[j][i];
+      c2[aa] = mre[i][j] - mre[j][i];
+    }
+    c1[2] = mre[0][0] - mre[1][1];
+    c1[7] = fmadd(T(-2), mre[2][2], mre[0][0] + mre[1][1]) * T(kInvSqrt3);
+    c2[2] = mim[0][0] - mim[1][1];
+    c2[7] = fmadd(T(-2), mim[2][2], mim[0][0] + mim[1][1]) * T(kInvSqrt3);
+  } else {
+    T nd[3][3], nre[3][3], nim[3][3];  // [k][i] diagonal |U_ik|^2; [k][pair] off-diagonal of u_k u_k^dag
+#pragma unroll
+    for (int kk = 0; kk < 3; ++kk) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) nd[kk][i] = fmadd(URE(i, kk), URE(i, kk), UIM(i, kk) * UIM(i, kk));
+#pragma unroll
+      for (int p = 0; p < 3; ++p) {
+        const int i = pr_i[p], j = pr_j[p];
+        nre[kk][p] = fmadd(URE(i, kk), URE(j, kk), UIM(i, kk) * UIM(j, kk));
+        nim[kk][p] = fmadd(UIM(i, kk), URE(j, kk), -(URE(i, kk) * UIM(j, kk)));
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      const int as = pr_s[p], aa = pr_s[p] + 1;
+      c1[as] = nre[0][p] - nre[1][p];
+      c1[aa] = -(nim[0][p] - nim[1][p]);
+      c2[as] = fmadd(T(-2), nre[2][p], nre[0][p] + nre[1][p]) * T(kInvSqrt3);
+      c2[aa] = -fmadd(T(-2), nim[2][p], nim[0][p] + nim[1][p]) * T(kInvSqrt3);
+    }
+    T y3[3], y8[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      y3[i] = T(0.5) * (nd[0][i] - nd[1][i]);
+      y8[i] = T(0.5) * T(kInvSqrt3) * fmadd(T(-2), nd[2][i], nd[0][i] + nd[1][i]);
+    }
+    c1[2] = y3[0] - y3[1];
+    c1[7] = fmadd(T(-2), y3[2], y3[0] + y3[1]) * T(kInvSqrt3);
+    c2[2] = y8[0] - y8[1];
+    c2[7] = fmadd(T(-2), y8[2], y8[0] + y8[1]) * T(kInvSqrt3);
+  }
+#undef URE
+#undef UIM
+}
+
+// Column indices of group q (see adjoint_columns).
+template <int q>
+struct ColPair {
+  static constexpr int b1 = q == 0 ? 0 : q == 1 ? 3 : q == 2 ? 5 : 2;
+  static constexpr int b2 = q == 0 ? 1 : q == 1 ? 4 : q == 2 ? 6 : 7;
+};
+
+// Streamed adjoint action on NV vectors: acc += R phi (kT = false) or acc += R^T phi (kT = true),
+// building R two columns at a time so the 8x8 matrix is never held in registers.
+template <typename T, int NV, bool kT, int q>
+RMH_HD void adj_stream_group(const T* u, const T (*phi)[8], T (*acc)[8]) {
+  T c1[8], c2[8];
+  adjoint_columns<T, q>(u, c1, c2);
+  constexpr int b1 = ColPair<q>::b1, b2 = ColPair<q>::b2;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    if (!kT) {
+#pragma unroll
+      for (int a = 0; a < 8; ++a) acc[v][a] = fmadd(c2[a], phi[v][b2], fmadd(c1[a], phi[v][b1], acc[v][a]));
+    } else {
+      T s1 = acc[v][b1], s2 = acc[v][b2];
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        s1 = fmadd(c1[a], phi[v][a], s1);
+        s2 = fmadd(c2[a], phi[v][a], s2);
+      }
+      acc[v][b1] = s1;
+      acc[v][b2] = s2;
+    }
+  }
+}
+
+template <typename T, int NV, bool kT>
+RMH_HD void adj_stream(const T* u, const T (*phi)[8], T (*acc)[8]) {
+  adj_stream_group<T, NV, kT, 0>(u, phi, acc);
+  adj_stream_group<T, NV, kT, 1>(u, phi, acc);
+  adj_stream_group<T, NV, kT, 2>(u, phi, acc);
+  adj_stream_group<T, NV, kT, 3>(u, phi, acc);
 }
 
 // acc += R phi   (forward hop: U phi U^dag)
@@ -141,7 +257,7 @@ RMH_HD void adj_apply(const T* R, const T* phi, T* acc) {
   for (int a = 0; a < 8; ++a) {
     T s = acc[a];
 #pragma unroll
-    for (int b = 0; b < 8; ++b) s += R[a * 8 + b] * phi[b];
+    for (int b = 0; b < 8; ++b) s = fmadd(R[a * 8 + b], phi[b], s);
     acc[a] = s;
   }
 }
@@ -153,7 +269,7 @@ RMH_HD void adj_apply_t(const T* R, const T* phi, T* acc) {
   for (int b = 0; b < 8; ++b) {
     const T p = phi[b];
 #pragma unroll
-    for (int a = 0; a < 8; ++a) acc[a] += R[b * 8 + a] * p;
+    for (int a = 0; a < 8; ++a) acc[a] = fmadd(R[b * 8 + a], p, acc[a]);
   }
 }
 
@@ -164,8 +280,8 @@ RMH_HD void mat_hop(const T* u, const T* phi, T* acc) {
   // Phi (Hermitian): diagonal d[i], upper off-diagonal o[p] for pairs (0,1),(0,2),(1,2)
   const T h = T(0.5);
   T dre[3], ore[3], oim[3];
-  dre[0] = h * phi[2] + h * T(kInvSqrt3) * phi[7];
-  dre[1] = -h * phi[2] + h * T(kInvSqrt3) * phi[7];
+  dre[0] = fmadd(h, phi[2], h * T(kInvSqrt3) * phi[7]);
+  dre[1] = fmadd(-h, phi[2], h * T(kInvSqrt3) * phi[7]);
   dre[2] = -T(kInvSqrt3) * phi[7];
   ore[0] = h * phi[0]; oim[0] = -h * phi[1];
   ore[1] = h * phi[3]; oim[1] = -h * phi[4];
@@ -201,8 +317,8 @@ RMH_HD void mat_hop(const T* u, const T* phi, T* acc) {
       T sr = 0, si = 0;
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        sr += are[i][k] * pre[k][j] - aim[i][k] * pim[k][j];
-        si += are[i][k] * pim[k][j] + aim[i][k] * pre[k][j];
+        sr = fmadd(are[i][k], pre[k][j], fmadd(-aim[i][k], pim[k][j], sr));
+        si = fmadd(are[i][k], pim[k][j], fmadd(aim[i][k], pre[k][j], si));
       }
       wre[i][j] = sr;
       wim[i][j] = si;
@@ -213,7 +329,7 @@ RMH_HD void mat_hop(const T* u, const T* phi, T* acc) {
   for (int i = 0; i < 3; ++i) {
     T sr = 0;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) sr += wre[i][k] * are[i][k] + wim[i][k] * aim[i][k];
+    for (int k = 0; k < 3; ++k) sr = fmadd(wre[i][k], are[i][k], fmadd(wim[i][k], aim[i][k], sr));
     yd[i] = sr;
   }
   constexpr int pi_[3] = {0, 0, 1};
@@ -225,14 +341,14 @@ RMH_HD void mat_hop(const T* u, const T* phi, T* acc) {
     T sr = 0, si = 0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      sr += wre[i][k] * are[j][k] + wim[i][k] * aim[j][k];
-      si += wim[i][k] * are[j][k] - wre[i][k] * aim[j][k];
+      sr = fmadd(wre[i][k], are[j][k], fmadd(wim[i][k], aim[j][k], sr));
+      si = fmadd(wim[i][k], are[j][k], fmadd(-wre[i][k], aim[j][k], si));
     }
-    acc[ps_[p]] += T(2) * sr;
-    acc[ps_[p] + 1] += -T(2) * si;
+    acc[ps_[p]] = fmadd(T(2), sr, acc[ps_[p]]);
+    acc[ps_[p] + 1] = fmadd(T(-2), si, acc[ps_[p] + 1]);
   }
   acc[2] += yd[0] - yd[1];
-  acc[7] += (yd[0] + yd[1] - T(2) * yd[2]) * T(kInvSqrt3);
+  acc[7] = fmadd(fmadd(T(-2), yd[2], yd[0] + yd[1]), T(kInvSqrt3), acc[7]);
 }
 
 }  // namespace rmh

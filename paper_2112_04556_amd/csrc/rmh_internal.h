@@ -16,12 +16,22 @@ constexpr int kRedBlock = 256;     // threads of the per-rhs scalar kernels
 constexpr int kMaxFilterWindows = 64;
 
 // Stencil variants chosen by the tuner.
-enum HopForm : int32_t { kFormAdjoint = 0, kFormMatrix = 1 };
+// kFormAdjoint: the 8x8 adjoint matrix R(U) built once per hop and applied to every vector;
+// kFormMatrix: U phi U^dag as 3x3 complex products per vector;
+// kFormStream: R(U) built and applied two columns at a time (fewest registers).
+enum HopForm : int32_t { kFormAdjoint = 0, kFormMatrix = 1, kFormStream = 2 };
 
+// nv = directions nu per thread (4: a whole link field, 2: half of one; the threads of a
+// site's halves sit in the same block).
+// order = 1 walks the blocks with x3 fastest, then x2, then the (x0, x1) chunks, so the blocks
+// holding a site's x2 and x3 neighbours are resident at the same time and share the L2; it needs
+// L0 * L1 to be a multiple of the sites per block (else the lexicographic order 0 is used).
 struct HopConfig {
-  int32_t form = kFormAdjoint;
+  int32_t form = kFormStream;
   int32_t block = 256;
   int32_t xcd_remap = 1;
+  int32_t nv = 4;
+  int32_t order = 1;
 };
 
 // out[v] = a * (H x)[v] + b_v * x[v] + c * z[v / z_div]   for v in [0, n_rhs) link fields,
@@ -54,6 +64,10 @@ struct HopArgs {
 };
 
 int hop_num_blocks(const Geom& g, const HopConfig& cfg);
+// whether the x3-fastest block order applies to this lattice and configuration
+int hop_order_ok(const Geom& g, const HopConfig& cfg);
+// upper bound of hop_num_blocks over every configuration (32 sites per block at least)
+inline int hop_max_blocks(const Geom& g) { return (g.V + 31) / 32; }
 
 template <typename T>
 hipError_t launch_hop(const HopArgs<T>& args, const HopConfig& cfg, hipStream_t s);
@@ -121,6 +135,13 @@ hipError_t launch_cg_shift_update(const CgDev& cg, const T* r, T* p, TX* x, doub
 hipError_t launch_ru_accumulate(const CgDev& cg, float* x_lo, double* x_hi, int64_t n_reals, int32_t all,
                                 hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+template <typename T>
+hipError_t launch_bcast_cast(const double* b, T* p, int32_t nr, int32_t ns, int64_t n, hipStream_t s);
+hipError_t launch_cg_reset_maxr(const CgDev& cg, hipStream_t s);
+hipError_t launch_gather_pairs(const double* x_hi, const double* b, const int32_t* idx, int32_t ns, double* X,
+                               double* B, int32_t nb, int64_t n, hipStream_t s);
+hipError_t launch_scatter_add_pairs(double* x_hi, const int32_t* idx, const double* E, int32_t nb, int64_t n,
+                                    hipStream_t s);
 template <typename T>
 hipError_t launch_copy_cast(const double* in, T* out, int64_t n, hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);

@@ -61,79 +61,87 @@ __device__ __forceinline__ int32_t remap_block(int32_t b, int32_t G, int32_t xcd
 // ------------------------------------------------------------------------------------------
 // the stencil
 
-template <typename T, int FORM, bool DOTS, bool FILTER>
-__global__ void __launch_bounds__(256) k_hop(const HopArgs<T> A, int32_t xcd) {
+// One hop's contribution to NV vectors: forward (kT = false, link U_mu(x), neighbour x+mu) or
+// backward (kT = true, link U_mu(x-mu), neighbour x-mu).
+template <typename T, int FORM, int NV, bool kT>
+__device__ __forceinline__ void hop_apply(const T* u, const T (*phi)[8], T (*acc)[8]) {
+  if (FORM == kFormAdjoint) {
+    T R[64];
+    adjoint_matrix<T>(u, R);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      if (!kT)
+        adj_apply<T>(R, phi[v], acc[v]);
+      else
+        adj_apply_t<T>(R, phi[v], acc[v]);
+    }
+  } else if (FORM == kFormMatrix) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) mat_hop<T, kT>(u, phi[v], acc[v]);
+  } else {
+    adj_stream<T, NV, kT>(u, phi, acc);
+  }
+}
+
+// out[v] = a (H x)[v] + b x[v] + c z[v]: a block of B threads covers B * NV / 4 sites; the
+// 4 / NV thread groups of a site (direction subsets) are wave-aligned slices of the block.
+template <typename T, int FORM, int NV, bool DOTS, bool FILTER>
+__global__ void __launch_bounds__(256) k_hop(const HopArgs<T> A, int32_t xcd, int32_t order) {
+  constexpr int G = 4 / NV;  // thread groups per site
   const int32_t v = blockIdx.y;
   if (A.run && A.run[(int64_t)v * A.run_stride] == 0) return;
   const int32_t V = A.g.V;
-  const int32_t blk = remap_block(blockIdx.x, gridDim.x, xcd);
-  const int32_t s = blk * blockDim.x + threadIdx.x;
+  const int32_t lb = remap_block(blockIdx.x, gridDim.x, xcd);
+  const int32_t spb = blockDim.x / G;              // sites per block
+  const int32_t grp = threadIdx.x / spb;           // direction subset of this thread
+  int32_t blk = lb;
+  if (order) {
+    // lb = ((chunk * L2) + x2) * L3 + x3  ->  lexicographic block of that (x0 x1 chunk, x2, x3)
+    const int32_t x3 = lb % A.g.L3;
+    const int32_t t = lb / A.g.L3;
+    const int32_t x2 = t % A.g.L2;
+    const int32_t chunk = t / A.g.L2;
+    const int32_t cpp = (A.g.L0 * A.g.L1) / spb;   // chunks per (x2, x3) plane
+    blk = (x3 * A.g.L2 + x2) * cpp + chunk;
+  }
+  const int32_t s = blk * spb + (threadIdx.x - grp * spb);
+  const int nu0 = grp * NV;
   double dsum[3] = {0.0, 0.0, 0.0};
   if (s < V) {
     const int64_t FV = 32 * (int64_t)V;
     const T* __restrict__ xf = A.x + ((int64_t)v * A.x_mul + A.x_add) * FV;
     const T* __restrict__ U = A.U;
-    T acc[4][8];
+    T acc[NV][8];
 #pragma unroll
-    for (int nu = 0; nu < 4; ++nu)
+    for (int i = 0; i < NV; ++i)
 #pragma unroll
-      for (int a = 0; a < 8; ++a) acc[nu][a] = T(0);
+      for (int a = 0; a < 8; ++a) acc[i][a] = T(0);
     int32_t xc[4];
     site_coords(A.g, s, xc);
 #pragma unroll 1
     for (int mu = 0; mu < 4; ++mu) {
       const T* __restrict__ Um = U + (int64_t)mu * 18 * V;
-      // forward hop: U_mu(x) phi(x+mu) U_mu(x)^dag
       {
         const int32_t sf = site_shift(A.g, s, xc, mu, +1);
-        T u[18];
+        T u[18], phi[NV][8];
 #pragma unroll
         for (int c = 0; c < 18; ++c) u[c] = Um[(int64_t)c * V + s];
-        if (FORM == kFormAdjoint) {
-          T R[64];
-          adjoint_matrix<T>(u, R);
 #pragma unroll
-          for (int nu = 0; nu < 4; ++nu) {
-            T phi[8];
+        for (int i = 0; i < NV; ++i)
 #pragma unroll
-            for (int b = 0; b < 8; ++b) phi[b] = xf[(int64_t)(nu * 8 + b) * V + sf];
-            adj_apply<T>(R, phi, acc[nu]);
-          }
-        } else {
-#pragma unroll
-          for (int nu = 0; nu < 4; ++nu) {
-            T phi[8];
-#pragma unroll
-            for (int b = 0; b < 8; ++b) phi[b] = xf[(int64_t)(nu * 8 + b) * V + sf];
-            mat_hop<T, false>(u, phi, acc[nu]);
-          }
-        }
+          for (int b = 0; b < 8; ++b) phi[i][b] = xf[(int64_t)((nu0 + i) * 8 + b) * V + sf];
+        hop_apply<T, FORM, NV, false>(u, phi, acc);
       }
-      // backward hop: U_mu(x-mu)^dag phi(x-mu) U_mu(x-mu)
       {
         const int32_t sb = site_shift(A.g, s, xc, mu, -1);
-        T u[18];
+        T u[18], phi[NV][8];
 #pragma unroll
         for (int c = 0; c < 18; ++c) u[c] = Um[(int64_t)c * V + sb];
-        if (FORM == kFormAdjoint) {
-          T R[64];
-          adjoint_matrix<T>(u, R);
 #pragma unroll
-          for (int nu = 0; nu < 4; ++nu) {
-            T phi[8];
+        for (int i = 0; i < NV; ++i)
 #pragma unroll
-            for (int b = 0; b < 8; ++b) phi[b] = xf[(int64_t)(nu * 8 + b) * V + sb];
-            adj_apply_t<T>(R, phi, acc[nu]);
-          }
-        } else {
-#pragma unroll
-          for (int nu = 0; nu < 4; ++nu) {
-            T phi[8];
-#pragma unroll
-            for (int b = 0; b < 8; ++b) phi[b] = xf[(int64_t)(nu * 8 + b) * V + sb];
-            mat_hop<T, true>(u, phi, acc[nu]);
-          }
-        }
+          for (int b = 0; b < 8; ++b) phi[i][b] = xf[(int64_t)((nu0 + i) * 8 + b) * V + sb];
+        hop_apply<T, FORM, NV, true>(u, phi, acc);
       }
     }
     // epilogue: out = a H x + b x + c z
@@ -143,28 +151,28 @@ __global__ void __launch_bounds__(256) k_hop(const HopArgs<T> A, int32_t xcd) {
     const T* zf = A.z ? A.z + (int64_t)(v / A.z_div) * FV : nullptr;  // may alias out
     T* outf = A.out + (int64_t)v * FV;
 #pragma unroll
-    for (int nu = 0; nu < 4; ++nu)
+    for (int i = 0; i < NV; ++i)
 #pragma unroll
       for (int a = 0; a < 8; ++a) {
-        const int64_t e = (int64_t)(nu * 8 + a) * V + s;
+        const int64_t e = (int64_t)((nu0 + i) * 8 + a) * V + s;
         const T xv = xf[e];
-        T o = ca * acc[nu][a] + cb * xv;
-        if (zf) o += cc * zf[e];
+        T o = fmadd(ca, acc[i][a], cb * xv);
+        if (zf) o = fmadd(cc, zf[e], o);
         if (A.store) outf[e] = o;
         if (DOTS) {
           const double xd = (double)xv, od = (double)o;
-          dsum[0] += xd * xd;
-          dsum[1] += od * xd;
-          dsum[2] += od * od;
+          dsum[0] = fma(xd, xd, dsum[0]);
+          dsum[1] = fma(od, xd, dsum[1]);
+          dsum[2] = fma(od, od, dsum[2]);
         }
         if (FILTER) {
           T* y = A.yacc + (int64_t)v * FV + e;
           for (int w = 0; w < A.n_w; ++w) {
             T* yw = y + w * A.yacc_stride;
             if (A.filter_first)
-              *yw = T(A.wcoef0[w]) * xv + T(A.wcoef[w]) * o;
+              *yw = fmadd(T(A.wcoef[w]), o, T(A.wcoef0[w]) * xv);
             else
-              *yw += T(A.wcoef[w]) * o;
+              *yw = fmadd(T(A.wcoef[w]), o, *yw);
           }
         }
       }
@@ -182,29 +190,45 @@ __global__ void __launch_bounds__(256) k_hop(const HopArgs<T> A, int32_t xcd) {
   }
 }
 
-int hop_num_blocks(const Geom& g, const HopConfig& cfg) { return (g.V + cfg.block - 1) / cfg.block; }
+int hop_num_blocks(const Geom& g, const HopConfig& cfg) {
+  const int spb = cfg.block * cfg.nv / 4;
+  return (g.V + spb - 1) / spb;
+}
 
-template <typename T, int FORM>
+int hop_order_ok(const Geom& g, const HopConfig& cfg) {
+  const int spb = cfg.block * cfg.nv / 4;
+  return ((g.L0 * g.L1) % spb) == 0 ? 1 : 0;
+}
+
+template <typename T, int FORM, int NV>
 static hipError_t launch_hop_form(const HopArgs<T>& A, const HopConfig& cfg, hipStream_t s) {
   dim3 grid(hop_num_blocks(A.g, cfg), A.n_rhs), block(cfg.block);
   const bool dots = A.partials && A.dot_mask;
   const bool filt = A.yacc && A.n_w > 0;
+  const int32_t order = (cfg.order && hop_order_ok(A.g, cfg)) ? 1 : 0;
   if (dots && filt)
-    hipLaunchKernelGGL((k_hop<T, FORM, true, true>), grid, block, 0, s, A, cfg.xcd_remap);
+    hipLaunchKernelGGL((k_hop<T, FORM, NV, true, true>), grid, block, 0, s, A, cfg.xcd_remap, order);
   else if (dots)
-    hipLaunchKernelGGL((k_hop<T, FORM, true, false>), grid, block, 0, s, A, cfg.xcd_remap);
+    hipLaunchKernelGGL((k_hop<T, FORM, NV, true, false>), grid, block, 0, s, A, cfg.xcd_remap, order);
   else if (filt)
-    hipLaunchKernelGGL((k_hop<T, FORM, false, true>), grid, block, 0, s, A, cfg.xcd_remap);
+    hipLaunchKernelGGL((k_hop<T, FORM, NV, false, true>), grid, block, 0, s, A, cfg.xcd_remap, order);
   else
-    hipLaunchKernelGGL((k_hop<T, FORM, false, false>), grid, block, 0, s, A, cfg.xcd_remap);
+    hipLaunchKernelGGL((k_hop<T, FORM, NV, false, false>), grid, block, 0, s, A, cfg.xcd_remap, order);
   return hipGetLastError();
+}
+
+template <typename T, int FORM>
+static hipError_t launch_hop_nv(const HopArgs<T>& A, const HopConfig& cfg, hipStream_t s) {
+  if (cfg.nv == 2) return launch_hop_form<T, FORM, 2>(A, cfg, s);
+  return launch_hop_form<T, FORM, 4>(A, cfg, s);
 }
 
 template <typename T>
 hipError_t launch_hop(const HopArgs<T>& A, const HopConfig& cfg, hipStream_t s) {
   if (A.n_rhs == 0 || A.g.V == 0) return hipSuccess;
-  if (cfg.form == kFormMatrix) return launch_hop_form<T, kFormMatrix>(A, cfg, s);
-  return launch_hop_form<T, kFormAdjoint>(A, cfg, s);
+  if (cfg.form == kFormMatrix) return launch_hop_nv<T, kFormMatrix>(A, cfg, s);
+  if (cfg.form == kFormAdjoint) return launch_hop_nv<T, kFormAdjoint>(A, cfg, s);
+  return launch_hop_nv<T, kFormStream>(A, cfg, s);
 }
 template hipError_t launch_hop<double>(const HopArgs<double>&, const HopConfig&, hipStream_t);
 template hipError_t launch_hop<float>(const HopArgs<float>&, const HopConfig&, hipStream_t);
@@ -224,7 +248,7 @@ __global__ void k_dot(const T* __restrict__ a, const T* __restrict__ b, int64_t 
   const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
   if (i0 < n) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) d[0] += (double)av[i0 + k] * (double)bv[i0 + k];
+    for (int k = 0; k < 4; ++k) d[0] = fma((double)av[i0 + k], (double)bv[i0 + k], d[0]);
   }
   __shared__ double lds[1][16];
   block_sum<1>(d, lds);
@@ -604,9 +628,9 @@ __global__ void k_cg_r(CgDev cg, T* __restrict__ r, const T* __restrict__ Ap, co
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const T r0 = from64 ? (T)r64v[i0 + k] : rv[i0 + k];
-      const T rn = r0 - alpha * av[i0 + k];
+      const T rn = fmadd(-alpha, av[i0 + k], r0);
       rv[i0 + k] = rn;
-      d[0] += (double)rn * (double)rn;
+      d[0] = fma((double)rn, (double)rn, d[0]);
     }
   }
   __shared__ double lds[1][16];
@@ -651,11 +675,11 @@ __global__ void k_cg_shift(CgDev cg, const T* __restrict__ r, T* __restrict__ p,
 #pragma unroll
     for (int k = 0; k < 4; ++k) pv[k] = pj[k];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) xj[k] += (TX)(cx * pv[k]);
+    for (int k = 0; k < 4; ++k) xj[k] = fmadd(cx, pv[k], xj[k]);
     if (up) {
       const T cr = (T)sh[kShCr], cp = (T)sh[kShCp];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) pj[k] = cr * rv[k] + cp * pv[k];
+      for (int k = 0; k < 4; ++k) pj[k] = fmadd(cr, rv[k], cp * pv[k]);
     }
   }
   if (acc_hi) {
@@ -707,6 +731,80 @@ hipError_t launch_ru_accumulate(const CgDev& cg, float* x_lo, double* x_hi, int6
   return hipGetLastError();
 }
 
+// p[v][j] = (T) b[v] for every shift j (initial search directions)
+template <typename T>
+__global__ void k_bcast_cast(const double* __restrict__ b, T* __restrict__ p, int32_t ns, int64_t n) {
+  const int32_t vj = blockIdx.y;
+  const int32_t v = vj / ns;
+  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  if (i0 >= n) return;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) p[(int64_t)vj * n + i0 + k] = (T)b[(int64_t)v * n + i0 + k];
+}
+
+template <typename T>
+hipError_t launch_bcast_cast(const double* b, T* p, int32_t nr, int32_t ns, int64_t n, hipStream_t s) {
+  if (nr * ns == 0) return hipSuccess;
+  dim3 grid(elem_num_blocks(n), nr * ns);
+  hipLaunchKernelGGL((k_bcast_cast<T>), grid, dim3(kBlock), 0, s, b, p, ns, n);
+  return hipGetLastError();
+}
+template hipError_t launch_bcast_cast<double>(const double*, double*, int32_t, int32_t, int64_t, hipStream_t);
+template hipError_t launch_bcast_cast<float>(const double*, float*, int32_t, int32_t, int64_t, hipStream_t);
+
+// entering the FP32 phase: the reliable-update reference becomes the current residual norm
+__global__ void k_cg_reset_maxr(CgDev cg) {
+  for (int v = threadIdx.x; v < cg.n_rhs; v += blockDim.x) {
+    double* sc = cg.sc + (int64_t)v * kScN;
+    sc[kScMaxR] = sqrt(sc[kScRR]);
+  }
+}
+
+hipError_t launch_cg_reset_maxr(const CgDev& cg, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_reset_maxr, dim3(1), dim3(kRedBlock), 0, s, cg);
+  return hipGetLastError();
+}
+
+// X[i] = x_hi[idx[i]], B[i] = b[idx[i] / ns] for the pairs of a refinement batch
+__global__ void k_gather_pairs(const double* __restrict__ x_hi, const double* __restrict__ b,
+                               const int32_t* __restrict__ idx, int32_t ns, double* __restrict__ X,
+                               double* __restrict__ B, int64_t n) {
+  const int32_t i = blockIdx.y;
+  const int32_t q = idx[i];
+  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  if (i0 >= n) return;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    X[(int64_t)i * n + i0 + k] = x_hi[(int64_t)q * n + i0 + k];
+    B[(int64_t)i * n + i0 + k] = b[(int64_t)(q / ns) * n + i0 + k];
+  }
+}
+
+hipError_t launch_gather_pairs(const double* x_hi, const double* b, const int32_t* idx, int32_t ns, double* X,
+                               double* B, int32_t nb, int64_t n, hipStream_t s) {
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_pairs, dim3(elem_num_blocks(n), nb), dim3(kBlock), 0, s, x_hi, b, idx, ns, X, B, n);
+  return hipGetLastError();
+}
+
+// x_hi[idx[i]] += E[i]
+__global__ void k_scatter_add_pairs(double* __restrict__ x_hi, const int32_t* __restrict__ idx,
+                                    const double* __restrict__ E, int64_t n) {
+  const int32_t i = blockIdx.y;
+  const int32_t q = idx[i];
+  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  if (i0 >= n) return;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) x_hi[(int64_t)q * n + i0 + k] += E[(int64_t)i * n + i0 + k];
+}
+
+hipError_t launch_scatter_add_pairs(double* x_hi, const int32_t* idx, const double* E, int32_t nb, int64_t n,
+                                    hipStream_t s) {
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter_add_pairs, dim3(elem_num_blocks(n), nb), dim3(kBlock), 0, s, x_hi, idx, E, n);
+  return hipGetLastError();
+}
+
 // y = c x + sum_j r_j x_j  (FP64) with partial <y, y>
 __global__ void k_rational_combine(const double* __restrict__ x, const double* __restrict__ xp, int32_t n_poles,
                                    const double* __restrict__ coef, double* __restrict__ y, int64_t n,
@@ -719,9 +817,9 @@ __global__ void k_rational_combine(const double* __restrict__ x, const double* _
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       double acc = c * x[(int64_t)v * n + i0 + k];
-      for (int j = 0; j < n_poles; ++j) acc += coef[1 + j] * xp[((int64_t)v * n_poles + j) * n + i0 + k];
+      for (int j = 0; j < n_poles; ++j) acc = fma(coef[1 + j], xp[((int64_t)v * n_poles + j) * n + i0 + k], acc);
       y[(int64_t)v * n + i0 + k] = acc;
-      d[0] += acc * acc;
+      d[0] = fma(acc, acc, d[0]);
     }
   }
   if (partials) {
@@ -801,7 +899,7 @@ __global__ void __launch_bounds__(256) k_force(const ForceArgs F, int32_t xcd) {
 #pragma unroll
           for (int b = 0; b < 8; ++b)
 #pragma unroll
-            for (int e = 0; e < 8; ++e) C[b * 8 + e] += bf[b] * ax[e] + af[b] * bx[e];
+            for (int e = 0; e < 8; ++e) C[b * 8 + e] = fma(af[b], bx[e], fma(bf[b], ax[e], C[b * 8 + e]));
         }
       }
     double u[18];
@@ -817,7 +915,7 @@ __global__ void __launch_bounds__(256) k_force(const ForceArgs F, int32_t xcd) {
       for (int e = 0; e < 8; ++e) {
         double t = 0.0;
 #pragma unroll
-        for (int b = 0; b < 8; ++b) t += R[d * 8 + b] * C[b * 8 + e];
+        for (int b = 0; b < 8; ++b) t = fma(R[d * 8 + b], C[b * 8 + e], t);
         RC[d * 8 + e] = t;
       }
     double G[8];

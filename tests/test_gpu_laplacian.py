@@ -52,12 +52,16 @@ def test_pack_fields_and_convert_bitwise():
 def test_laplacian_fp64_parity(L, kind, seed, shift):
     announce(f"laplacian fp64 {L} {kind} shift={shift}")
     U, P, Ud, Pd = setup(L, kind, 0.5, seed, n=2)
-    y = api.laplacian_apply(L, Ud, Pd, shift).cpu().numpy()
     ref = olap.laplacian(U, P, L, shift)
-    assert rel_max(y, ref) <= 1e-12
+    for form in (0, 1, 2):
+        for nv in (4, 2):
+            api.tune_set(L, torch.float64, 2, form, 128, 1, nv, 1)
+            y = api.laplacian_apply(L, Ud, Pd, shift).cpu().numpy()
+            assert rel_max(y, ref) <= 1e-12, (form, nv)
+    api.tune_clear()
 
 
-@pytest.mark.parametrize("form", [0, 1])
+@pytest.mark.parametrize("form", [0, 1, 2])
 @pytest.mark.parametrize("L,kind,seed", CASES[:3])
 def test_laplacian_fp32_parity(L, kind, seed, form):
     announce(f"laplacian fp32 form={form} {L}")
@@ -76,19 +80,20 @@ def test_laplacian_fp32_parity(L, kind, seed, form):
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_laplacian_configs_batched_and_deterministic(dtype):
     """Bitwise identity across block sizes and XCD remaps of one form, batched vs single, run to run."""
-    L = (6, 4, 5, 6)
+    L = (8, 8, 5, 6)   # L0 * L1 = 64: the x3-fastest order applies for 64 sites per block
     announce(f"laplacian configs {dtype}")
     _, _, Ud, Pd = setup(L, "haar", 0.0, 7, n=3, dtype=dtype)
-    for form in (0, 1):
+    for form in (0, 1, 2):
         outs = []
         for block in (64, 128, 256):
-            for xcd in (0, 1):
-                api.tune_set(L, dtype, 3, form, block, xcd)
-                api.tune_set(L, dtype, 1, form, block, xcd)
-                y = api.laplacian_apply(L, Ud, Pd)
-                y1 = api.laplacian_apply(L, Ud, Pd[1:2].contiguous())
-                assert torch.equal(y[1:2], y1)
-                outs.append(y)
+            for xcd, order in ((0, 0), (1, 1), (0, 1)):
+                for nv in (4, 2):
+                    api.tune_set(L, dtype, 3, form, block, xcd, nv, order)
+                    api.tune_set(L, dtype, 1, form, block, xcd, nv, order)
+                    y = api.laplacian_apply(L, Ud, Pd)
+                    y1 = api.laplacian_apply(L, Ud, Pd[1:2].contiguous())
+                    assert torch.equal(y[1:2], y1)
+                    outs.append(y)
         api.tune_clear()
         for o in outs[1:]:
             assert torch.equal(o, outs[0])
@@ -102,8 +107,8 @@ def test_laplacian_empty_batch_and_autotune():
     _, _, Ud, Pd = setup(L, "eps", 0.3, 1, n=1)
     empty = torch.empty((0, 4, 8, api.volume(L)), dtype=torch.float64, device=dev())
     api.laplacian_apply(L, Ud, empty)
-    (form, block, xcd), ms = api.autotune_laplacian(L, Ud, Pd, reps=2)
-    assert form in (0, 1) and block in (64, 128, 256) and ms > 0
+    (form, block, xcd, nv, order), ms = api.autotune_laplacian(L, Ud, Pd, reps=2)
+    assert form in (0, 1, 2) and block in (64, 128, 256) and nv in (2, 4) and ms > 0
     U, P, _, _ = setup(L, "eps", 0.3, 1, n=1)
     assert rel_max(api.laplacian_apply(L, Ud, Pd).cpu().numpy(), olap.laplacian(U, P, L)) <= 1e-12
     api.tune_clear()
