@@ -228,7 +228,7 @@ def run_extras(api, inputs, torch, np, dev, L, U_aos, Ud, Pd):
                       "achieved_GBs": round(p["gbs"], 1), "hbm_frac": round(p["gbs"] / HBM_PEAK_GBS, 4),
                       "bytes_per_site": 136 * ts,
                       "config": {"form": cfg[0], "block": cfg[1], "xcd_remap": cfg[2], "nv": cfg[3],
-                                 "order": cfg[4]}}
+                                 "order": cfg[4], "walk": cfg[5]}}
         log(f"stencil 32^3x64 {name}: {sten[name]}")
         del Ubd, Fbd, y
     out["laplacian_32x32x32x64"] = sten

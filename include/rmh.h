@@ -263,15 +263,16 @@ rmh_status rmh_kinetic_force(const int32_t L[4], const double* U, const double* 
  * 2 = R(U) built and applied two columns at a time; block = 64, 128 or 256 threads; xcd_remap = 1
  * maps consecutive lattice blocks onto one XCD (L2 locality); nv = 4 or 2 directions per thread;
  * order = 1 visits the blocks with x3 fastest (x2/x3 neighbours resident together; used when
- * L0*L1 is a multiple of the sites per block).  Every configuration computes the same operator;
- * a form fixes the per-site arithmetic, so results are bitwise identical across block sizes,
- * remaps, nv and orders of one form. */
+ * L0*L1 is a multiple of the sites per block); walk = K > 0 makes each thread walk K consecutive
+ * x3 sites carrying the x3 neighbours in registers (used when K divides L3).  Every configuration
+ * computes the same operator; a form fixes the per-site arithmetic, so results are bitwise
+ * identical across block sizes, remaps, nv, orders and walks of one form. */
 rmh_status rmh_tune_set(const int32_t L[4], int32_t dtype, int32_t n_rhs, int32_t form, int32_t block,
-                        int32_t xcd_remap, int32_t nv, int32_t order);
+                        int32_t xcd_remap, int32_t nv, int32_t order, int32_t walk);
 /* Time every configuration of rmh_laplacian_apply on the caller's buffers (y is overwritten;
  * reps timed launches each, HIP events on the stream) and keep the fastest for (L, dtype, n_rhs).
- * best (optional host int32[5]) receives (form, block, xcd_remap, nv, order); best_ms (optional)
- * its mean time per launch.  Synchronizes the stream. */
+ * best (optional host int32[6]) receives (form, block, xcd_remap, nv, order, walk); best_ms
+ * (optional) its mean time per launch.  Synchronizes the stream. */
 rmh_status rmh_autotune_laplacian(const int32_t L[4], const void* U, int32_t dtype, const void* x, void* y,
                                   int32_t n_rhs, int32_t reps, int32_t* best, double* best_ms, rmh_stream stream);
 /* Forget every stored configuration. */

@@ -138,3 +138,21 @@ def trace_moments_dense(eigenvalues: np.ndarray, degree: int) -> np.ndarray:
     x = np.clip(np.asarray(eigenvalues) / 8.0 - 1.0, -1.0, 1.0)
     k = np.arange(degree + 1)
     return 4.0 * np.cos(np.outer(k, np.arccos(x))).sum(axis=1)
+
+
+def free_moments_fft(F, L, degree: int) -> np.ndarray:
+    """mu[n, k] at U = 1 from the plane-wave decomposition: Delta is diagonal in momentum space with
+    eigenvalue 4 sum_mu sin^2(p_mu/2) on every colour and direction, so
+    mu_k = sum_p |F(p)|^2 T_k(lambda_p/8 - 1) / V (Parseval).  F: (n, 4, 8, V)."""
+    F = np.asarray(F, np.float64)
+    shp = (int(L[3]), int(L[2]), int(L[1]), int(L[0]))
+    V = F.shape[-1]
+    ks = np.meshgrid(*[2.0 * np.pi * np.fft.fftfreq(m) for m in shp], indexing="ij")
+    lam = sum(4.0 * np.sin(k / 2.0) ** 2 for k in ks)
+    th = np.arccos(np.clip(lam / 8.0 - 1.0, -1.0, 1.0)).ravel()
+    mu = np.empty((F.shape[0], degree + 1))
+    for i in range(F.shape[0]):
+        Fh = np.fft.fftn(F[i].reshape((4, 8) + shp), axes=(2, 3, 4, 5))
+        pw = ((np.abs(Fh) ** 2).sum(axis=(0, 1)) / V).ravel()
+        mu[i] = np.cos(np.outer(np.arange(degree + 1), th)) @ pw
+    return mu

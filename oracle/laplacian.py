@@ -89,3 +89,35 @@ def bilinear_link_derivative(U: np.ndarray, a: np.ndarray, b: np.ndarray, L) -> 
         tr = np.einsum("cij,...ji->c...", su3.T, comm)  # Tr(T^c comm)
         out[mu] = (-2j * tr).real
     return out.reshape(4, 8, -1)
+
+
+def laplacian_at(U: np.ndarray, P: np.ndarray, L, sites, shift_: float = 0.0) -> np.ndarray:
+    """(Delta + shift) P evaluated only at the given flat site indices (same definition as
+    ``laplacian``, one site at a time, for lattices too large for the whole-field version).
+
+    U: (4, V, 3, 3); P: (..., 8, V) component fields.  Returns (..., 8, len(sites)).
+    """
+    sites = np.asarray(sites, dtype=np.int64)
+    stride = [1, L[0], L[0] * L[1], L[0] * L[1] * L[2]]
+    c = np.stack([(sites // stride[mu]) % L[mu] for mu in range(4)], axis=1)
+    P = np.asarray(P, np.float64)
+
+    def site_shift(mu, sign):
+        d = c.copy()
+        d[:, mu] = (d[:, mu] + sign) % L[mu]
+        return d[:, 0] + L[0] * (d[:, 1] + L[1] * (d[:, 2] + L[2] * d[:, 3]))
+
+    def mats(idx):                       # (..., len, 3, 3)
+        return su3.to_matrix(np.moveaxis(P[..., idx], -2, -1))
+
+    out = 2.0 * D * mats(sites)
+    for mu in range(4):
+        fwd, bwd = site_shift(mu, +1), site_shift(mu, -1)
+        Uf = U[mu][sites]
+        Ub = U[mu][bwd]
+        out = out - Uf @ mats(fwd) @ su3.dagger(Uf)
+        out = out - su3.dagger(Ub) @ mats(bwd) @ Ub
+    res = np.moveaxis(su3.from_matrix(out), -1, -2)
+    if shift_ != 0.0:
+        res = res + shift_ * P[..., sites]
+    return res

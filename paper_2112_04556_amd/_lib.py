@@ -75,7 +75,7 @@ SIGNATURES = {
     "rmh_rational_apply_bwd": (c_i32, [P_i32, c_vp, c_vp, c_vp, c_i32, ctypes.POINTER(RmhRational),
                                        ctypes.POINTER(RmhSolver), c_vp, c_vp, c_i32, ctypes.POINTER(RmhStats),
                                        c_vp, c_sz, c_vp]),
-    "rmh_tune_set": (c_i32, [P_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32]),
+    "rmh_tune_set": (c_i32, [P_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32]),
     "rmh_autotune_laplacian": (c_i32, [P_i32, c_vp, c_i32, c_vp, c_vp, c_i32, c_i32, P_i32, P_f64, c_vp]),
     "rmh_tune_clear": (c_i32, []),
     "rmh_profile_enable": (c_i32, [c_i32]),

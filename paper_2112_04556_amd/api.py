@@ -307,10 +307,10 @@ def kinetic_force(L, U, P, rat: Rational, solver: Solver = Solver(), per_rhs: bo
 # stencil tuning
 
 def tune_set(L, dtype, n_rhs: int, form: int, block: int = 256, xcd_remap: int = 1, nv: int = 4,
-             order: int = 0) -> None:
+             order: int = 0, walk: int = 0) -> None:
     code = RMH_F64 if dtype == torch.float64 else RMH_F32
     check(lib().rmh_tune_set(lattice_arg(L), code, int(n_rhs), int(form), int(block), int(xcd_remap), int(nv),
-                             int(order)), "rmh_tune_set")
+                             int(order), int(walk)), "rmh_tune_set")
 
 
 def tune_clear() -> None:
@@ -318,14 +318,14 @@ def tune_clear() -> None:
 
 
 def autotune_laplacian(L, U, x, reps: int = 5):
-    """((form, block, xcd_remap, nv, order), ms per launch) of the fastest stencil configuration, now stored."""
+    """((form, block, xcd_remap, nv, order, walk), ms per launch) of the fastest configuration, now stored."""
     y = torch.empty_like(x)
-    best = (L_.c_i32 * 5)()
+    best = (L_.c_i32 * 6)()
     ms = ctypes.c_double()
     check(lib().rmh_autotune_laplacian(lattice_arg(L), _dev(U, "U"), _dtype_code(x), _dev(x, "x"), _dev(y, "y"),
                                        x.shape[0], int(reps), best, ctypes.byref(ms), _stream(x.device)),
           "rmh_autotune_laplacian")
-    return (best[0], best[1], best[2], best[3], best[4]), ms.value
+    return tuple(best[i] for i in range(6)), ms.value
 
 
 # ------------------------------------------------------------------------------------------

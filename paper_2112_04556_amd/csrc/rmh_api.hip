@@ -1403,19 +1403,22 @@ rmh_status rmh_kinetic_force(const int32_t L[4], const double* U, const double* 
 }
 
 rmh_status rmh_tune_set(const int32_t L[4], int32_t dtype, int32_t n_rhs, int32_t form, int32_t block,
-                        int32_t xcd_remap, int32_t nv, int32_t order) {
+                        int32_t xcd_remap, int32_t nv, int32_t order, int32_t walk) {
   Geom g;
   RMH_TRY(make_geom(L, &g));
   RMH_TRY(check_dtype(dtype));
   if (form < kFormAdjoint || form > kFormStream) return fail(RMH_E_ARG, "form must be 0, 1 or 2");
   if (block != 64 && block != 128 && block != 256) return fail(RMH_E_ARG, "block must be 64, 128 or 256");
   if (nv != 2 && nv != 4) return fail(RMH_E_ARG, "nv must be 2 or 4");
+  if ((block * nv / 4) % 64) return fail(RMH_E_ARG, "block * nv / 4 must be a multiple of 64");
   HopConfig c;
   c.form = form;
   c.block = block;
   c.xcd_remap = xcd_remap ? 1 : 0;
   c.nv = nv;
   c.order = order ? 1 : 0;
+  if (walk < 0 || walk > 64) return fail(RMH_E_ARG, "walk must be in [0, 64]");
+  c.walk = walk;
   tune_store(g, dtype, n_rhs, c);
   return RMH_OK;
 }
@@ -1441,6 +1444,7 @@ rmh_status rmh_autotune_laplacian(const int32_t L[4], const void* U, int32_t dty
   for (int form = 0; form < 3 && st == RMH_OK; ++form)
     for (int nv : {4, 2})
     for (int block : {64, 128, 256})
+    for (int walk : {0, 4, 8, 16})
     for (int order = 0; order < 2 && st == RMH_OK; ++order) {
       for (int xcd = 0; xcd < 2 && st == RMH_OK; ++xcd) {
         HopConfig c;
@@ -1449,7 +1453,10 @@ rmh_status rmh_autotune_laplacian(const int32_t L[4], const void* U, int32_t dty
         c.xcd_remap = xcd;
         c.nv = nv;
         c.order = order;
+        c.walk = walk;
         if (order && !hop_order_ok(g, c)) continue;
+        if (walk && (order || !hop_walk_ok(g, c))) continue;
+        if ((block * nv / 4) % 64) continue;  // direction groups must be whole waves
         tune_store(g, dtype, n_rhs, c);
         st = rmh_laplacian_apply(L, U, dtype, x, y, n_rhs, 0.0, stream);  // warm-up
         if (st != RMH_OK) break;
@@ -1464,8 +1471,8 @@ rmh_status rmh_autotune_laplacian(const int32_t L[4], const void* U, int32_t dty
         if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) ms = 1e30f;
         ms /= reps;
         if (log_level() > 0)
-          fprintf(stderr, "[rmh] tune L=%dx%dx%dx%d dtype=%d n=%d form=%d nv=%d block=%d order=%d xcd=%d: %.4f ms\n",
-                  g.L0, g.L1, g.L2, g.L3, dtype, n_rhs, form, nv, block, order, xcd, ms);
+          fprintf(stderr, "[rmh] tune L=%dx%dx%dx%d dtype=%d n=%d form=%d nv=%d block=%d order=%d walk=%d xcd=%d: %.4f ms\n",
+                  g.L0, g.L1, g.L2, g.L3, dtype, n_rhs, form, nv, block, order, walk, xcd, ms);
         if (ms < bt) {
           bt = ms;
           bestc = c;
@@ -1482,6 +1489,7 @@ rmh_status rmh_autotune_laplacian(const int32_t L[4], const void* U, int32_t dty
     best[2] = bestc.xcd_remap;
     best[3] = bestc.nv;
     best[4] = bestc.order;
+    best[5] = bestc.walk;
   }
   if (best_ms) *best_ms = bt;
   return RMH_OK;

@@ -26,12 +26,16 @@ enum HopForm : int32_t { kFormAdjoint = 0, kFormMatrix = 1, kFormStream = 2 };
 // order = 1 walks the blocks with x3 fastest, then x2, then the (x0, x1) chunks, so the blocks
 // holding a site's x2 and x3 neighbours are resident at the same time and share the L2; it needs
 // L0 * L1 to be a multiple of the sites per block (else the lexicographic order 0 is used).
+// walk = K > 0: each thread walks K consecutive sites along x3 (K divides L3), carrying the
+// centre field, the x-3 field and the x-3 link in registers, so every x3-direction field and
+// link is fetched once per column instead of being re-read from the caches.
 struct HopConfig {
   int32_t form = kFormStream;
   int32_t block = 256;
   int32_t xcd_remap = 1;
   int32_t nv = 4;
-  int32_t order = 1;
+  int32_t order = 0;
+  int32_t walk = 0;
 };
 
 // out[v] = a * (H x)[v] + b_v * x[v] + c * z[v / z_div]   for v in [0, n_rhs) link fields,
@@ -66,8 +70,10 @@ struct HopArgs {
 int hop_num_blocks(const Geom& g, const HopConfig& cfg);
 // whether the x3-fastest block order applies to this lattice and configuration
 int hop_order_ok(const Geom& g, const HopConfig& cfg);
+// whether the x3 walk applies (K divides L3)
+int hop_walk_ok(const Geom& g, const HopConfig& cfg);
 // upper bound of hop_num_blocks over every configuration (32 sites per block at least)
-inline int hop_max_blocks(const Geom& g) { return (g.V + 31) / 32; }
+inline int hop_max_blocks(const Geom& g) { return (g.V + 31) / 32 + g.L3; }
 
 template <typename T>
 hipError_t launch_hop(const HopArgs<T>& args, const HopConfig& cfg, hipStream_t s);

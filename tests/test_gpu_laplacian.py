@@ -12,6 +12,7 @@ import torch
 from gpu_helpers import announce, dev, rel_max, setup
 from oracle import laplacian as olap
 from paper_2112_04556_amd import api, inputs
+from paper_2112_04556_amd._lib import RmhError
 
 pytestmark = pytest.mark.gpu
 
@@ -54,10 +55,10 @@ def test_laplacian_fp64_parity(L, kind, seed, shift):
     U, P, Ud, Pd = setup(L, kind, 0.5, seed, n=2)
     ref = olap.laplacian(U, P, L, shift)
     for form in (0, 1, 2):
-        for nv in (4, 2):
-            api.tune_set(L, torch.float64, 2, form, 128, 1, nv, 1)
+        for nv, walk in ((4, 0), (2, 0), (2, L[3]), (4, 1)):
+            api.tune_set(L, torch.float64, 2, form, 128, 1, nv, 1, walk)
             y = api.laplacian_apply(L, Ud, Pd, shift).cpu().numpy()
-            assert rel_max(y, ref) <= 1e-12, (form, nv)
+            assert rel_max(y, ref) <= 1e-12, (form, nv, walk)
     api.tune_clear()
 
 
@@ -86,10 +87,15 @@ def test_laplacian_configs_batched_and_deterministic(dtype):
     for form in (0, 1, 2):
         outs = []
         for block in (64, 128, 256):
-            for xcd, order in ((0, 0), (1, 1), (0, 1)):
+            for xcd, order, walk in ((0, 0, 0), (1, 1, 0), (0, 1, 0), (1, 0, 2), (0, 0, 3), (0, 0, 6)):
                 for nv in (4, 2):
-                    api.tune_set(L, dtype, 3, form, block, xcd, nv, order)
-                    api.tune_set(L, dtype, 1, form, block, xcd, nv, order)
+                    if (block * nv // 4) % 64:
+                        # a direction group must span whole wavefronts
+                        with pytest.raises(RmhError):
+                            api.tune_set(L, dtype, 3, form, block, xcd, nv, order, walk)
+                        continue
+                    api.tune_set(L, dtype, 3, form, block, xcd, nv, order, walk)
+                    api.tune_set(L, dtype, 1, form, block, xcd, nv, order, walk)
                     y = api.laplacian_apply(L, Ud, Pd)
                     y1 = api.laplacian_apply(L, Ud, Pd[1:2].contiguous())
                     assert torch.equal(y[1:2], y1)
@@ -107,7 +113,7 @@ def test_laplacian_empty_batch_and_autotune():
     _, _, Ud, Pd = setup(L, "eps", 0.3, 1, n=1)
     empty = torch.empty((0, 4, 8, api.volume(L)), dtype=torch.float64, device=dev())
     api.laplacian_apply(L, Ud, empty)
-    (form, block, xcd, nv, order), ms = api.autotune_laplacian(L, Ud, Pd, reps=2)
+    (form, block, xcd, nv, order, walk), ms = api.autotune_laplacian(L, Ud, Pd, reps=2)
     assert form in (0, 1, 2) and block in (64, 128, 256) and nv in (2, 4) and ms > 0
     U, P, _, _ = setup(L, "eps", 0.3, 1, n=1)
     assert rel_max(api.laplacian_apply(L, Ud, Pd).cpu().numpy(), olap.laplacian(U, P, L)) <= 1e-12

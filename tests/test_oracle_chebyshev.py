@@ -128,3 +128,12 @@ def test_free_moments_by_fft():
     x = np.arccos(np.clip(lam / 8 - 1, -1, 1))
     ref = np.array([(pw * np.cos(k * x)).sum() for k in range(D + 1)])
     assert np.allclose(mu, ref, atol=1e-10 * ref[0])
+
+
+def test_free_moments_fft_matches_recursion():
+    L = (4, 6, 2, 8)
+    U = inputs.random_links(L, "unit").numpy()
+    F = inputs.gaussian_fields(L, 2, seed=10).numpy()
+    D = 12
+    ref = ch.moments(U, F, L, D)
+    assert np.allclose(ch.free_moments_fft(F, L, D), ref, atol=1e-10 * ref[:, :1].max())

@@ -143,3 +143,12 @@ def test_link_derivative_central_differences():
 
         fd = (F(h) - F(-h)) / (2 * h)
         assert abs(fd - G[mu, c, s]) <= 1e-7 * max(1.0, abs(G[mu, c, s]))
+
+
+def test_laplacian_at_sites_matches_whole_field():
+    L = (3, 4, 2, 5)
+    U = inputs.random_links(L, "haar", seed=21).numpy()
+    P = inputs.gaussian_fields(L, 2, seed=22).numpy()
+    sites = np.array([0, 7, 11, 50, lattice.volume(L) - 1])
+    full = lap.laplacian(U, P, L, 0.3)
+    assert np.allclose(lap.laplacian_at(U, P, L, sites, 0.3), full[..., sites], atol=1e-13)
