@@ -93,8 +93,11 @@ typedef struct {
  * ||x - (Delta + sigma_j) x_j|| / ||x|| that every shift must reach.  mode 0: FP64 multi-shift
  * CG; mode 1: mixed precision -- FP64 iterations while the seed residual is above
  * mixed_switch * ||x|| (0 = default 1e-4, negative = none), then FP32 stencil and vectors with
- * FP64 reliable updates of the residual and of the shift solutions (delta = reliable-update
- * threshold, e.g. 0.1).  check_every: iterations between host convergence checks (0 = 8). */
+ * FP64 reliable updates of the seed residual (delta = reliable-update threshold, e.g. 0.1).
+ * check_every: iterations between host convergence checks (0 = 8).  basis: iterations per
+ * segment of the shift solutions (0 = 16, at most 32): the shifts other than the seed are
+ * carried as coefficients over the stored seed residuals of a segment and folded into their
+ * FP64 vectors once per segment, so the workspace holds basis + 1 extra link fields per source. */
 typedef struct {
   double tol;
   int32_t maxiter;
@@ -102,6 +105,7 @@ typedef struct {
   double delta;
   int32_t check_every;
   double mixed_switch;
+  int32_t basis;
 } rmh_solver;
 
 /* Per-call solver statistics (host). */
@@ -135,8 +139,9 @@ const char* rmh_last_error(void);
 /* ABI version (major * 100 + minor). */
 int32_t rmh_version(void);
 /* Workspace bytes for op at this shape.  aux = n_windows (POWER_SPECTRUM, CHEB_FILTER) or
- * n_poles (RATIONAL_*, KINETIC_FORCE), degree = Chebyshev degree (else 0), mode = solver
- * mode (else 0).  Returns 0 on a bad argument (and sets the error string). */
+ * n_poles (RATIONAL_*, KINETIC_FORCE); degree = Chebyshev degree (POWER_SPECTRUM,
+ * CHEB_FILTER) or the solver's basis (RATIONAL_*, KINETIC_FORCE; 0 = default), else 0;
+ * mode = solver mode (else 0).  Returns 0 on a bad argument (and sets the error string). */
 size_t rmh_workspace_bytes(int32_t op, const int32_t L[4], int32_t dtype, int32_t n_rhs, int32_t aux,
                            int32_t degree, int32_t mode);
 

@@ -77,9 +77,11 @@ class Solver:
     delta: float = 0.1
     check_every: int = 8
     mixed_switch: float = 0.0   # 0: library default (1e-4); < 0: FP32 from the first iteration
+    basis: int = 0              # iterations per shift-solution segment (0: library default, 16)
 
     def c_struct(self):
-        return L_.RmhSolver(self.tol, self.maxiter, self.mode, self.delta, self.check_every, self.mixed_switch)
+        return L_.RmhSolver(self.tol, self.maxiter, self.mode, self.delta, self.check_every, self.mixed_switch,
+                            self.basis)
 
 
 def workspace_bytes(op: int, L, dtype: int, n_rhs: int, aux: int = 0, degree: int = 0, mode: int = 0) -> int:
@@ -256,7 +258,7 @@ def rational_apply(L, U, x, rat: Rational, solver: Solver = Solver(), want_poles
     xp = torch.empty((n, np_) + tuple(x.shape[1:]), dtype=torch.float64, device=x.device) if want_poles else None
     K = np.empty(n) if want_K else None
     stats = L_.RmhStats()
-    ws = _workspace(workspace_bytes(L_.OP_RATIONAL_APPLY, L, RMH_F64, n, np_, 0, solver.mode), x.device)
+    ws = _workspace(workspace_bytes(L_.OP_RATIONAL_APPLY, L, RMH_F64, n, np_, solver.basis, solver.mode), x.device)
     rs, ss = rat.c_struct(), solver.c_struct()
     check(lib().rmh_rational_apply(lattice_arg(L), _dev(U, "U"), _dev(x, "x"), n, ctypes.byref(rs),
                                    ctypes.byref(ss), _dev(y, "y"), xp.data_ptr() if xp is not None else None,
@@ -273,7 +275,7 @@ def rational_apply_bwd(L, U, x, g, rat: Rational, solver: Solver = Solver(), gra
     gx = torch.empty_like(g) if grad_x else None
     go = torch.empty((n if per_rhs else 1, 4, 8, volume(L)), dtype=torch.float64, device=x.device)
     stats = L_.RmhStats()
-    ws = _workspace(workspace_bytes(L_.OP_RATIONAL_APPLY_BWD, L, RMH_F64, n, np_, 0, solver.mode), x.device)
+    ws = _workspace(workspace_bytes(L_.OP_RATIONAL_APPLY_BWD, L, RMH_F64, n, np_, solver.basis, solver.mode), x.device)
     rs, ss = rat.c_struct(), solver.c_struct()
     check(lib().rmh_rational_apply_bwd(lattice_arg(L), _dev(U, "U"), _dev(x, "x"), _dev(g, "g"), n,
                                        ctypes.byref(rs), ctypes.byref(ss),
@@ -292,7 +294,7 @@ def kinetic_force(L, U, P, rat: Rational, solver: Solver = Solver(), per_rhs: bo
     K = np.empty(n)
     dK = torch.empty((n if per_rhs else 1, 4, 8, volume(L)), dtype=torch.float64, device=P.device)
     stats = L_.RmhStats()
-    need = workspace_bytes(L_.OP_KINETIC_FORCE, L, RMH_F64, n, np_, 0, solver.mode)
+    need = workspace_bytes(L_.OP_KINETIC_FORCE, L, RMH_F64, n, np_, solver.basis, solver.mode)
     if ws is None or ws.numel() < need:
         ws = _workspace(need, P.device)
     rs, ss = rat.c_struct(), solver.c_struct()

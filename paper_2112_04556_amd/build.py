@@ -38,7 +38,9 @@ def build(verbose: bool = False) -> str:
                    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                    *common, "-c", path, "-o", obj]
         else:
-            cmd = [hipcc(), *common, "-c", path, "-o", obj]
+            # host sources: hipcc still runs a device pass over them, for the same target
+            cmd = [hipcc(), f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                   *common, "-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)

@@ -224,17 +224,16 @@ ChebPlan plan_cheb(Carver& c, const Geom& g, int32_t dtype, int32_t n_rhs, int32
 
 struct Engine {
   Geom g;
-  int32_t n_rhs = 0, n_shift = 0, mode = 0;
-  // FP64 vectors: the whole FP64 solve, or the FP64 phase of a mixed solve (r64 also holds the
-  // FP64 residual of every reliable update)
-  double* r64 = nullptr;   // [n_rhs]
+  int32_t n_rhs = 0, n_shift = 0, mode = 0, nslot = 2, nslot32 = 4;
+  // seed vectors: direction and its image, FP64 (FP64 phase) and FP32 (FP32 phase)
+  double* p64 = nullptr;   // [n_rhs]
   double* Ap64 = nullptr;  // [n_rhs]
-  double* p64 = nullptr;   // [n_rhs][n_shift]
-  // FP32 vectors of the mixed phase
-  float* r32 = nullptr;
-  float* Ap32 = nullptr;
   float* p32 = nullptr;
-  float* x_lo = nullptr;
+  float* Ap32 = nullptr;
+  double* r64 = nullptr;   // [n_rhs] FP64 residual of a reliable update (mixed)
+  char* ring = nullptr;    // [n_rhs][nslot] seed residuals, FP64-sized slots
+  double* pj = nullptr;    // [n_rhs][n_shift] shift directions at the segment start (n_shift > 1)
+  double* coef = nullptr;  // [n_rhs][n_shift][2 + 2 nslot]
   // scalar state, contiguous so one copy brings it to the host: sc then flags
   double* sc = nullptr;
   int32_t* flags = nullptr;
@@ -260,22 +259,34 @@ struct Engine {
 
 size_t rup(size_t b) { return ((b + 255) / 256) * 256; }
 
-void plan_engine(Carver& c, Engine& e, const Geom& g, int32_t n_rhs, int32_t n_shift, int32_t mode) {
+// Residual ring length for a solver: basis iterations per segment + 1 (single-shift engines
+// keep only the current and the next residual).
+int32_t ring_slots(int32_t n_shift, int32_t basis) {
+  if (n_shift <= 1) return 2;
+  const int32_t m = basis > 0 ? basis : 16;
+  return std::min<int32_t>(m, kMaxSlots - 1) + 1;
+}
+
+void plan_engine(Carver& c, Engine& e, const Geom& g, int32_t n_rhs, int32_t n_shift, int32_t mode,
+                 int32_t basis) {
   e.g = g;
   e.n_rhs = n_rhs;
   e.n_shift = n_shift;
   e.mode = mode;
+  e.nslot = ring_slots(n_shift, basis);
+  e.nslot32 = std::min<int32_t>(2 * e.nslot, kMaxSlots);
   const int64_t n = field_reals(g);
   const size_t nr = n_rhs, np = (size_t)n_rhs * n_shift;
-  e.r64 = c.take<double>(nr * n);
+  e.p64 = c.take<double>(nr * n);
   e.Ap64 = c.take<double>(nr * n);
-  e.p64 = c.take<double>(np * n);
   if (mode) {
-    e.r32 = c.take<float>(nr * n);
+    e.p32 = c.take<float>(nr * n);
     e.Ap32 = c.take<float>(nr * n);
-    e.p32 = c.take<float>(np * n);
-    e.x_lo = c.take<float>(np * n);
+    e.r64 = c.take<double>(nr * n);
   }
+  e.ring = c.take<char>(nr * e.nslot * n * 8);
+  if (n_shift > 1) e.pj = c.take<double>(np * n);
+  e.coef = c.take<double>(np * (2 + 2 * std::max(e.nslot, e.nslot32)));
   const size_t scb = rup(nr * kScN * 8), flb = rup(nr * kFlN * 4);
   char* st = c.take<char>(scb + flb);
   e.sc = (double*)st;
@@ -297,14 +308,14 @@ void plan_engine(Carver& c, Engine& e, const Geom& g, int32_t n_rhs, int32_t n_s
     e.seed = (int32_t*)q;
   }
   e.nblk_hop = hop_max_blocks(g);
-  e.nblk_e = elem_num_blocks(n);
+  e.nblk_e = red_num_blocks(n);
   e.part = c.take<double>(nr * std::max<int64_t>(3 * e.nblk_hop, e.nblk_e));
   if (mode) e.part_ru = c.take<double>(nr * 3 * e.nblk_hop);
   e.part_true = c.take<double>(np * 3 * e.nblk_hop);
   e.sums_true = c.take<double>(np * 3);
 }
 
-CgDev cg_view(const Engine& e, int32_t nblk_hop) {
+CgDev cg_view(const Engine& e, int32_t nblk_hop, bool fp32) {
   CgDev d;
   d.n_rhs = e.n_rhs;
   d.n_shift = e.n_shift;
@@ -317,6 +328,13 @@ CgDev cg_view(const Engine& e, int32_t nblk_hop) {
   d.seed = e.seed;
   d.part = e.part;
   d.part_ru = e.part_ru;
+  d.coef = e.coef;
+  d.nslot = fp32 ? e.nslot32 : e.nslot;
+  d.cslots = std::max(e.nslot, e.nslot32);
+  d.ring_rhs_bytes = (int64_t)e.nslot * field_reals(e.g) * 8;
+  d.ring_on = e.n_shift > 1 ? 1 : 0;
+  // the seed's solution is updated each iteration where reliable updates read it
+  d.seed_explicit = (e.n_shift == 1 || fp32) ? 1 : 0;
   d.nblk_hop = nblk_hop;
   d.nblk_e = e.nblk_e;
   d.nblk_ru = 0;
@@ -343,6 +361,7 @@ struct SolveInfo {
 // x_hi (FP64, [n_rhs][n_shift]) receives the solutions (zeroed here).
 // FP64 engines iterate in FP64 throughout.  Mixed engines iterate in FP64 while the seed residual
 // is above switch_rel * ||b|| (switch_rel <= 0: not at all), then in FP32 with FP64 reliable updates.
+// Every shift solution is accumulated in FP64: the seed's each iteration, the others at flushes.
 rmh_status engine_solve(Engine& e, const double* U64, const float* U32, const double* b, double* x_hi,
                         const std::vector<double>& sigma, const std::vector<double>& tol_rel, int32_t maxiter,
                         double delta, int32_t check_every, double switch_rel, hipStream_t s, SolveInfo* info) {
@@ -382,20 +401,20 @@ rmh_status engine_solve(Engine& e, const double* U64, const float* U32, const do
   const HopConfig c32 = hop_config(g, RMH_F32, nr, 1);
   const HopConfig c64 = hop_config(g, RMH_F64, nr, 2);
   const int32_t nblk_32 = hop_num_blocks(g, c32), nblk_64 = hop_num_blocks(g, c64);
-  CgDev cg64 = cg_view(e, nblk_64);
-  CgDev cg32 = cg_view(e, nblk_32);
+  CgDev cg64 = cg_view(e, nblk_64, false);
+  CgDev cg32 = cg_view(e, nblk_32, true);
   cg32.nblk_ru = nblk_64;
 
   bool fp32_phase = mixed && !(switch_rel > 0.0);
-  HIP_TRY(launch_zero(x_hi, (size_t)nr * ns * n * 8, s));
-  if (mixed) HIP_TRY(launch_zero(e.x_lo, (size_t)nr * ns * n * 4, s));
-  if (fp32_phase) {
-    HIP_TRY(launch_copy_cast<float>(b, e.r32, (int64_t)nr * n, s));
-    HIP_TRY(launch_bcast_cast<float>(b, e.p32, nr, ns, n, s));
-  } else {
-    HIP_TRY(launch_copy_cast<double>(b, e.r64, (int64_t)nr * n, s));
-    HIP_TRY(launch_bcast_cast<double>(b, e.p64, nr, ns, n, s));
-  }
+  // a seed updated each iteration starts from zero; the flushes write x of the other shifts
+  if (ns == 1)
+    HIP_TRY(launch_zero(x_hi, (size_t)nr * n * 8, s));
+  else if (fp32_phase)
+    for (int v = 0; v < nr; ++v) HIP_TRY(launch_zero(x_hi + ((size_t)v * ns + seed[v]) * n, (size_t)n * 8, s));
+  if (fp32_phase)
+    HIP_TRY(launch_cg_start<float>(b, e.ring, e.p32, nr, cg32.ring_rhs_bytes, n, s));
+  else
+    HIP_TRY(launch_cg_start<double>(b, e.ring, e.p64, nr, cg64.ring_rhs_bytes, n, s));
   HIP_TRY(launch_dot<double>(b, b, n, nr, e.part, s));
   HIP_TRY(launch_cg_init(cg64, e.part, e.nblk_e, e.tol_rhs, delta, maxiter, s));
 
@@ -404,8 +423,7 @@ rmh_status engine_solve(Engine& e, const double* U64, const float* U32, const do
   h64.g = g;
   h64.U = U64;
   h64.x = e.p64;
-  h64.x_mul = ns;
-  h64.x_add = seed[0];
+  h64.x_mul = 1;
   h64.out = e.Ap64;
   h64.z_div = 1;
   h64.a = -1.0;
@@ -421,8 +439,7 @@ rmh_status engine_solve(Engine& e, const double* U64, const float* U32, const do
   h32.g = g;
   h32.U = U32;
   h32.x = e.p32;
-  h32.x_mul = ns;
-  h32.x_add = seed[0];
+  h32.x_mul = 1;
   h32.out = e.Ap32;
   h32.z_div = 1;
   h32.a = -1.0;
@@ -433,7 +450,7 @@ rmh_status engine_solve(Engine& e, const double* U64, const float* U32, const do
   h32.store = 1;
   h32.partials = e.part;
   h32.dot_mask = 2;
-  // FP64 true residual of the seed for reliable updates: r64 = b - (Delta + sigma0) x_hi_seed
+  // FP64 true residual of the seed for reliable updates: r64 = b - (Delta + sigma0) x_seed
   HopArgs<double> hr{};
   hr.g = g;
   hr.U = U64;
@@ -453,13 +470,35 @@ rmh_status engine_solve(Engine& e, const double* U64, const float* U32, const do
   hr.partials = e.part_ru;
   hr.dot_mask = 4;
 
+  // shift solutions through the residual ring (more than one shift): flush before the ring
+  // would overflow; a single shift updates its solution each iteration
+  const bool multi = ns > 1;
+  const int32_t seg64 = e.nslot - 1, seg32 = e.nslot32 - 1;
   if (check_every <= 0) check_every = 8;
+  if (multi) check_every = std::min(check_every, std::min(seg64, seg32));
+  int32_t since = 0;
+  bool first = true;
+  auto flush = [&](bool fin) -> rmh_status {
+    if (!multi) return RMH_OK;
+    const double ts = fp32_phase ? 4.0 : 8.0;
+    const double bytes = (double)nr * n * ((since + 1) * ts + ns * (16.0 + (first ? 0.0 : 8.0) + (fin ? 0.0 : 8.0)));
+    ProfScope ps(RMH_PROF_CG_SHIFTS, bytes, s, nr);
+    if (fp32_phase)
+      HIP_TRY(launch_cg_flush<float>(cg32, e.ring, x_hi, e.pj, fin ? 1 : 0, first ? 1 : 0, n, s));
+    else
+      HIP_TRY(launch_cg_flush<double>(cg64, e.ring, x_hi, e.pj, fin ? 1 : 0, first ? 1 : 0, n, s));
+    first = false;
+    since = 0;
+    return RMH_OK;
+  };
+
   std::vector<char> st(e.state_bytes);
   const double* hsc = (const double*)st.data();
   const int32_t* hfl = (const int32_t*)(st.data() + ((char*)e.flags - (char*)e.sc));
   int32_t it = 0;
   info->fp64_iters = 0;
   while (true) {
+    if (multi && since + check_every > (fp32_phase ? seg32 : seg64)) RMH_TRY(flush(false));
     for (int i = 0; i < check_every; ++i) {
       if (!fp32_phase) {
         {
@@ -468,13 +507,13 @@ rmh_status engine_solve(Engine& e, const double* U64, const float* U32, const do
         }
         HIP_TRY(launch_cg_alpha(cg64, s));
         {
-          ProfScope ps(RMH_PROF_CG_RESIDUAL, 3.0 * nr * n * 8, s, nr);
-          HIP_TRY(launch_cg_r_update<double>(cg64, e.r64, e.Ap64, nullptr, n, s));
+          ProfScope ps(RMH_PROF_CG_RESIDUAL, (double)nr * n * (3 * 8.0 + (multi ? 0.0 : 24.0)), s, nr);
+          HIP_TRY(launch_cg_r_update<double>(cg64, e.ring, e.Ap64, e.p64, multi ? nullptr : x_hi, nullptr, n, s));
         }
         HIP_TRY(launch_cg_beta(cg64, 0, s));
         {
-          ProfScope ps(RMH_PROF_CG_SHIFTS, 0.0, s);
-          HIP_TRY((launch_cg_shift_update<double, double>(cg64, e.r64, e.p64, x_hi, nullptr, n, s)));
+          ProfScope ps(RMH_PROF_CG_RESIDUAL, (double)nr * n * 3 * 8.0, s, nr);
+          HIP_TRY(launch_cg_p_update<double>(cg64, e.ring, e.p64, n, s));
         }
       } else {
         {
@@ -483,13 +522,13 @@ rmh_status engine_solve(Engine& e, const double* U64, const float* U32, const do
         }
         HIP_TRY(launch_cg_alpha(cg32, s));
         {
-          ProfScope ps(RMH_PROF_CG_RESIDUAL, 3.0 * nr * n * 4, s, nr);
-          HIP_TRY(launch_cg_r_update<float>(cg32, e.r32, e.Ap32, e.r64, n, s));
+          ProfScope ps(RMH_PROF_CG_RESIDUAL, (double)nr * n * (3 * 4.0 + 20.0), s, nr);
+          HIP_TRY(launch_cg_r_update<float>(cg32, e.ring, e.Ap32, e.p32, x_hi, e.r64, n, s));
         }
         HIP_TRY(launch_cg_beta(cg32, 1, s));
         {
-          ProfScope ps(RMH_PROF_CG_SHIFTS, 0.0, s);
-          HIP_TRY((launch_cg_shift_update<float, float>(cg32, e.r32, e.p32, e.x_lo, x_hi, n, s)));
+          ProfScope ps(RMH_PROF_CG_RESIDUAL, (double)nr * n * 3 * 4.0, s, nr);
+          HIP_TRY(launch_cg_p_update<float>(cg32, e.ring, e.p32, n, s));
         }
         // reliable update decided by this iteration's beta kernel (blocks of rhs without a
         // pending update exit at once)
@@ -497,6 +536,7 @@ rmh_status engine_solve(Engine& e, const double* U64, const float* U32, const do
       }
     }
     it += check_every;
+    since += check_every;
     if (!fp32_phase) info->fp64_iters = it;
     RMH_TRY(d2h(st.data(), e.sc, e.state_bytes, s));
     bool running = false, below = true;
@@ -509,14 +549,13 @@ rmh_status engine_solve(Engine& e, const double* U64, const float* U32, const do
     if (!running) break;
     if (mixed && !fp32_phase && below) {
       // switch to FP32: the remaining increments are small, so their rounding no longer matters
-      HIP_TRY(launch_copy_cast<float>(e.r64, e.r32, (int64_t)nr * n, s));
-      HIP_TRY(launch_f64_to_f32(e.p64, e.p32, (int64_t)nr * ns * n, s));
-      HIP_TRY(launch_cg_reset_maxr(cg32, s));
+      RMH_TRY(flush(false));
+      HIP_TRY(launch_cg_to_f32(cg64, e.ring, e.p64, e.p32, n, s));
       fp32_phase = true;
     }
     if (it > maxiter + 2 * check_every) break;  // safety net; the device sets NoConv first
   }
-  if (mixed) HIP_TRY(launch_ru_accumulate(cg32, e.x_lo, x_hi, n, 1, s));
+  RMH_TRY(flush(true));
   RMH_TRY(d2h(st.data(), e.sc, e.state_bytes, s));
   if (log_level() > 0) {
     for (int v = 0; v < nr; ++v)
@@ -524,23 +563,6 @@ rmh_status engine_solve(Engine& e, const double* U64, const float* U32, const do
               e.mode, v, nr, ns, sigma[(size_t)v * ns + seed[v]], hsc[(size_t)v * kScN + kScIters], info->fp64_iters,
               hsc[(size_t)v * kScN + kScRU], hfl[(size_t)v * kFlN + kFlStatus], hsc[(size_t)v * kScN + kScBnorm2],
               hsc[(size_t)v * kScN + kScRR], tol_rel[v]);
-  }
-  if (g_prof.on) {
-    // exact algorithmic bytes of the shift updates: per update of shift j, p_j read, x_j read and
-    // written, p_j written unless it was the shift's last update; r read once per live iteration
-    // (counted at the FP64 width: an upper bound for the iterations done in FP32)
-    std::vector<double> shv((size_t)nr * ns * kShN);
-    RMH_TRY(d2h(shv.data(), e.sh, shv.size() * 8, s));
-    const double ts = mixed ? 4.0 : 8.0;
-    double bytes = 0.0;
-    for (int v = 0; v < nr; ++v) {
-      bytes += hsc[(size_t)v * kScN + kScIters] * n * ts;
-      for (int j = 0; j < ns; ++j) {
-        const double upd = shv[((size_t)v * ns + j) * kShN + kShUpd];
-        if (upd > 0) bytes += (upd * 3.0 + (upd - 1.0)) * n * ts;
-      }
-    }
-    prof_add_bytes(RMH_PROF_CG_SHIFTS, bytes);
   }
   info->iters = 0;
   info->ru = 0;
@@ -621,7 +643,7 @@ void plan_refine(Carver& c, RefinePlan& rp, const Geom& g, int32_t nb, int32_t m
   char* q = c.take<char>(rup((size_t)nb * 4) + rup((size_t)nb * 8));
   rp.idx = (int32_t*)q;
   rp.bneg = q ? (double*)(q + rup((size_t)nb * 4)) : nullptr;
-  plan_engine(c, rp.eng, g, nb, 1, mode);
+  plan_engine(c, rp.eng, g, nb, 1, mode, 0);
 }
 
 struct SolvePlan {
@@ -630,8 +652,9 @@ struct SolvePlan {
   float* U32 = nullptr;
 };
 
-void plan_solve(Carver& c, SolvePlan& sp, const Geom& g, int32_t n_rhs, int32_t n_shift, int32_t mode) {
-  plan_engine(c, sp.eng, g, n_rhs, n_shift, mode);
+void plan_solve(Carver& c, SolvePlan& sp, const Geom& g, int32_t n_rhs, int32_t n_shift, int32_t mode,
+                int32_t basis) {
+  plan_engine(c, sp.eng, g, n_rhs, n_shift, mode, basis);
   plan_refine(c, sp.ref, g, refine_batch(n_rhs, n_shift), mode);
   if (mode) sp.U32 = c.take<float>((size_t)72 * g.V);
 }
@@ -760,6 +783,8 @@ rmh_status check_solver(const rmh_solver* sv) {
     return fail(RMH_E_ARG, "solver delta = %g must lie in (0, 1)", sv->delta);
   if (!(sv->mixed_switch < 1.0) || sv->mixed_switch != sv->mixed_switch)
     return fail(RMH_E_ARG, "solver mixed_switch = %g must be < 1", sv->mixed_switch);
+  if (sv->basis < 0 || sv->basis > kMaxSlots - 1)
+    return fail(RMH_E_ARG, "solver basis = %d outside [0, %d]", sv->basis, kMaxSlots - 1);
   return RMH_OK;
 }
 
@@ -799,16 +824,17 @@ struct RationalPlan {
 };
 
 void plan_rational(Carver& c, RationalPlan& rp, const Geom& g, int32_t n_rhs, int32_t n_poles, int32_t mode,
+                   int32_t basis,
                    int32_t op) {
   const int64_t n = field_reals(g);
-  plan_solve(c, rp.sp, g, n_rhs, n_poles, mode);
+  plan_solve(c, rp.sp, g, n_rhs, n_poles, mode, basis);
   rp.X = c.take<double>((size_t)n_rhs * n_poles * n);
   if (op != RMH_OP_RATIONAL_APPLY) {
     rp.Z = c.take<double>((size_t)n_rhs * n_poles * n);
     rp.Y = c.take<double>((size_t)n_rhs * n);
   }
   rp.coef = c.take<double>(n_poles + 1);
-  rp.partK = c.take<double>((size_t)n_rhs * elem_num_blocks(n));
+  rp.partK = c.take<double>((size_t)n_rhs * red_num_blocks(n));
   rp.sumsK = c.take<double>(n_rhs);
 }
 
@@ -945,7 +971,7 @@ size_t rmh_workspace_bytes(int32_t op, const int32_t L[4], int32_t dtype, int32_
         return 0;
       }
       RationalPlan rp;
-      plan_rational(c, rp, g, n_rhs, aux, mode ? 1 : 0, op);
+      plan_rational(c, rp, g, n_rhs, aux, mode ? 1 : 0, degree, op);
       break;
     }
     default:
@@ -1259,7 +1285,7 @@ rmh_status rmh_rational_apply(const int32_t L[4], const double* U, const double*
   const int32_t np = rat->n_poles;
   Carver c(ws);
   RationalPlan rp;
-  plan_rational(c, rp, g, n_rhs, np, solver->mode, RMH_OP_RATIONAL_APPLY);
+  plan_rational(c, rp, g, n_rhs, np, solver->mode, solver->basis, RMH_OP_RATIONAL_APPLY);
   if (c.off > ws_bytes) return fail(RMH_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, c.off);
   const int64_t n = field_reals(g);
   const size_t fb = (size_t)n_rhs * n * 8, pb = fb * np;
@@ -1281,7 +1307,7 @@ rmh_status rmh_rational_apply(const int32_t L[4], const double* U, const double*
   RMH_TRY(h2d(rp.coef, coef.data(), coef.size() * 8, s));
   HIP_TRY(launch_rational_combine(x, X, n_rhs, np, rp.coef, y, n, rp.partK, s));
   if (K) {
-    HIP_TRY(launch_reduce_rows(rp.partK, elem_num_blocks(n), n_rhs, rp.sumsK, s));
+    HIP_TRY(launch_reduce_rows(rp.partK, red_num_blocks(n), n_rhs, rp.sumsK, s));
     RMH_TRY(d2h(K, rp.sumsK, n_rhs * 8, s));
     for (int v = 0; v < n_rhs; ++v) K[v] *= 0.5;
   } else {
@@ -1334,7 +1360,7 @@ rmh_status rmh_rational_apply_bwd(const int32_t L[4], const double* U, const dou
   const int32_t np = rat->n_poles;
   Carver c(ws);
   RationalPlan rp;
-  plan_rational(c, rp, g, n_rhs, np, solver->mode, RMH_OP_RATIONAL_APPLY_BWD);
+  plan_rational(c, rp, g, n_rhs, np, solver->mode, solver->basis, RMH_OP_RATIONAL_APPLY_BWD);
   if (c.off > ws_bytes) return fail(RMH_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, c.off);
   const int64_t n = field_reals(g);
   const size_t fb = (size_t)n_rhs * n * 8, gb = (size_t)(per_rhs ? n_rhs : 1) * n * 8;
@@ -1372,7 +1398,7 @@ rmh_status rmh_kinetic_force(const int32_t L[4], const double* U, const double* 
   const int32_t np = rat->n_poles;
   Carver c(ws);
   RationalPlan rp;
-  plan_rational(c, rp, g, n_rhs, np, solver->mode, RMH_OP_KINETIC_FORCE);
+  plan_rational(c, rp, g, n_rhs, np, solver->mode, solver->basis, RMH_OP_KINETIC_FORCE);
   if (c.off > ws_bytes) return fail(RMH_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, c.off);
   const int64_t n = field_reals(g);
   const size_t fb = (size_t)n_rhs * n * 8, gb = (size_t)(per_rhs ? n_rhs : 1) * n * 8;
@@ -1391,7 +1417,7 @@ rmh_status rmh_kinetic_force(const int32_t L[4], const double* U, const double* 
   RMH_TRY(solve_all(rp.sp, U, P, rp.X, sig, *solver, s, &res[0]));
   HIP_TRY(launch_rational_combine(P, rp.X, n_rhs, np, rp.coef, Yb, n, rp.partK, s));
   if (K) {
-    HIP_TRY(launch_reduce_rows(rp.partK, elem_num_blocks(n), n_rhs, rp.sumsK, s));
+    HIP_TRY(launch_reduce_rows(rp.partK, red_num_blocks(n), n_rhs, rp.sumsK, s));
     RMH_TRY(d2h(K, rp.sumsK, n_rhs * 8, s));
     for (int v = 0; v < n_rhs; ++v) K[v] *= 0.5;
   }

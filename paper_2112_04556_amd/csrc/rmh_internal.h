@@ -81,6 +81,11 @@ hipError_t launch_hop(const HopArgs<T>& args, const HopConfig& cfg, hipStream_t 
 // Element-wise helpers over link fields of 32 V reals each.
 int64_t field_reals(const Geom& g);
 int elem_num_blocks(int64_t n_reals);
+// Element-wise kernels with a reduction: each block covers red_steps(n) chunks of 4 kBlock
+// reals, so the per-block partials stay few on large lattices; red_num_blocks(n) partials
+// per row.
+int red_steps(int64_t n_reals);
+int red_num_blocks(int64_t n_reals);
 
 hipError_t launch_pack_links(const Geom& g, const double* aos, void* soa, int dtype, hipStream_t s);
 hipError_t launch_unpack_links(const Geom& g, const double* soa, double* aos, hipStream_t s);
@@ -100,6 +105,16 @@ hipError_t launch_dot(const T* a, const T* b, int64_t n_reals, int32_t n, double
 
 // ---------------------------------------------------------------------------------------------
 // Multi-shift CG engine state (all device pointers, carved from the caller's workspace).
+//
+// The seed system (smallest shift) is iterated with explicit vectors: residual, direction p and
+// A p.  The shift solutions and directions are not updated vector by vector: they are linear
+// combinations of the seed residuals of the current segment (a ring of stored residuals) and of
+// their own vectors at the segment start,
+//   x_j = x_j0 + a_j p_j0 + sum_i d_ji r_i,   p_j = b_j p_j0 + sum_i e_ji r_i,
+// with the scalar coefficients updated each iteration on the device and the combination folded
+// into x_j, p_j (flush) when the ring is full, at a precision switch and at the end.  The seed's
+// own solution is updated each iteration instead where reliable updates need it (FP32 phase)
+// and in single-shift engines.
 struct CgDev {
   int32_t n_rhs, n_shift;
   double* sc;            // [n_rhs][kScN]
@@ -111,39 +126,60 @@ struct CgDev {
   const int32_t* seed;   // [n_rhs]
   double* part;          // partials scratch [n_rhs][nblk_max]
   double* part_ru;       // partials of the FP64 residual stencil [n_rhs][3][nblk_ru] (mixed precision)
+  double* coef;          // [n_rhs][n_shift][2 + 2 cslots]: a, b, d[cslots], e[cslots]
+  int32_t nslot;         // residual ring length of this precision (segment of nslot - 1 iterations)
+  int32_t cslots;        // coefficient slots (the longer of the FP64 and FP32 rings)
+  int64_t ring_rhs_bytes;  // ring bytes per rhs (FP32 slots are half as long, twice as many)
+  int32_t ring_on;       // shift solutions through the ring (n_shift > 1); else the seed's
+                         // solution is updated each iteration and nslot = 2
+  int32_t seed_explicit; // the seed's solution is updated each iteration (single shift, FP32 phase)
   int32_t nblk_hop, nblk_e, nblk_ru;
 };
+// the residual ring: per rhs ring_rhs_bytes holding nslot FP64 slots of n_reals, or in FP32
+// phases twice as many FP32 slots (at most kMaxSlots)
+constexpr int kMaxSlots = 33;
 // scalar slots per rhs
 enum : int { kScRR = 0, kScAlpha, kScAlphaPrev, kScBetaPrev, kScBnorm2, kScMaxR, kScTolAbs, kScIters,
              kScRU, kScDelta, kScMaxIter, kScN };
-// per (rhs, shift) slots
-enum : int { kShZeta = 0, kShZetaPrev, kShZetaNext, kShCx, kShCr, kShCp, kShUpd, kShN };
+// per (rhs, shift) slots; Seg: the shift was updated in the current segment
+enum : int { kShZeta = 0, kShZetaPrev, kShZetaNext, kShCx, kShCr, kShCp, kShUpd, kShSeg, kShN };
 // int flags per rhs
 // Run: the rhs still iterates (read by the stencil of the next iteration);
 // Live: the current iteration is being carried out (set by the alpha kernel), so the
 // update kernels of the iteration in which a rhs converges still run once.
-enum : int { kFlRun = 0, kFlLive, kFlStatus, kFlNeedRU, kFlRUMask, kFlN };
+// Base, M: ring slot of the segment's first residual, index of the current residual in it.
+enum : int { kFlRun = 0, kFlLive, kFlStatus, kFlNeedRU, kFlRUMask, kFlBase, kFlM, kFlN };
 enum : int { kStOk = 0, kStNoConv = 1, kStBreakdown = 2 };
 
 hipError_t launch_cg_init(const CgDev& cg, const double* bn2_partials, int32_t nblk, const double* tol_rel,
                           double delta, int32_t maxiter, hipStream_t s);
 hipError_t launch_cg_alpha(const CgDev& cg, hipStream_t s);
 hipError_t launch_cg_beta(const CgDev& cg, int32_t mixed, hipStream_t s);
-// r -= alpha Ap (starting from r64 when a reliable update was consumed), partial <r, r>
+// ring slot 0 = (T) b, p = (T) b for every rhs
 template <typename T>
-hipError_t launch_cg_r_update(const CgDev& cg, T* r, const T* Ap, const double* r64, int64_t n_reals,
-                              hipStream_t s);
-// shift updates; with x_hi non-null a pending reliable update also moves x into x_hi
-template <typename T, typename TX>
-hipError_t launch_cg_shift_update(const CgDev& cg, const T* r, T* p, TX* x, double* x_hi, int64_t n_reals,
-                                  hipStream_t s);
-// final x_hi += x_lo, x_lo = 0 (all rhs, or those with a pending reliable update)
-hipError_t launch_ru_accumulate(const CgDev& cg, float* x_lo, double* x_hi, int64_t n_reals, int32_t all,
-                                hipStream_t s);
+hipError_t launch_cg_start(const double* b, void* ring, T* p, int32_t nr, int64_t rhs_bytes, int64_t n_reals,
+                           hipStream_t s);
+// next residual r' = r - alpha Ap into the next ring slot (r taken from r64 when a reliable
+// update was consumed), partial <r', r'>; with x_hi non-null also x_hi[seed] += alpha p
+template <typename T>
+hipError_t launch_cg_r_update(const CgDev& cg, void* ring, const T* Ap, const T* p, double* x_hi,
+                              const double* r64, int64_t n_reals, hipStream_t s);
+// seed direction p = r' + beta p
+template <typename T>
+hipError_t launch_cg_p_update(const CgDev& cg, const void* ring, T* p, int64_t n_reals, hipStream_t s);
+// fold the segment into x_j (and p_j unless final) of every shift updated in it (p_j0 is read
+// only where its coefficient is nonzero: before the first flush it holds nothing), then reset
+// the coefficients and restart the ring at the current residual
+// first: no flush yet in this solve (x_j holds nothing: written, not accumulated)
+template <typename T>
+hipError_t launch_cg_flush(const CgDev& cg, const void* ring, double* x_hi, double* pj, int32_t final_,
+                           int32_t first, int64_t n_reals, hipStream_t s);
+// precision switch (after a flush): current residual (FP64 slot) -> an FP32 slot outside it,
+// p64 -> p32; the FP32 ring (cg32 view) restarts there and the reliable-update reference
+// becomes the current residual norm
+hipError_t launch_cg_to_f32(const CgDev& cg64, void* ring, const double* p64, float* p32, int64_t n_reals,
+                            hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
-template <typename T>
-hipError_t launch_bcast_cast(const double* b, T* p, int32_t nr, int32_t ns, int64_t n, hipStream_t s);
-hipError_t launch_cg_reset_maxr(const CgDev& cg, hipStream_t s);
 hipError_t launch_gather_pairs(const double* x_hi, const double* b, const int32_t* idx, int32_t ns, double* X,
                                double* B, int32_t nb, int64_t n, hipStream_t s);
 hipError_t launch_scatter_add_pairs(double* x_hi, const int32_t* idx, const double* E, int32_t nb, int64_t n,

@@ -403,17 +403,27 @@ template hipError_t launch_hop<float>(const HopArgs<float>&, const HopConfig&, h
 
 int64_t field_reals(const Geom& g) { return 32 * (int64_t)g.V; }
 int elem_num_blocks(int64_t n_reals) { return (int)((n_reals / 4 + kBlock - 1) / kBlock); }
+int red_steps(int64_t n_reals) {
+  const int64_t s = n_reals / (4LL * kBlock * 2048);   // keep at least ~2048 blocks
+  return (int)std::max<int64_t>(1, std::min<int64_t>(8, s));
+}
+int red_num_blocks(int64_t n_reals) {
+  const int64_t c = 4LL * kBlock * red_steps(n_reals);
+  return (int)((n_reals + c - 1) / c);
+}
 
 template <typename T>
-__global__ void k_dot(const T* __restrict__ a, const T* __restrict__ b, int64_t n, double* partials) {
+__global__ void k_dot(const T* __restrict__ a, const T* __restrict__ b, int64_t n, int32_t steps, double* partials) {
   const int32_t v = blockIdx.y;
   const T* av = a + (int64_t)v * n;
   const T* bv = b + (int64_t)v * n;
   double d[1] = {0.0};
-  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
-  if (i0 < n) {
+  for (int32_t t = 0; t < steps; ++t) {
+    const int64_t i0 = (((int64_t)blockIdx.x * steps + t) * blockDim.x + threadIdx.x) * 4;
+    if (i0 < n) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) d[0] = fma((double)av[i0 + k], (double)bv[i0 + k], d[0]);
+      for (int k = 0; k < 4; ++k) d[0] = fma((double)av[i0 + k], (double)bv[i0 + k], d[0]);
+    }
   }
   __shared__ double lds[1][16];
   block_sum<1>(d, lds);
@@ -423,8 +433,8 @@ __global__ void k_dot(const T* __restrict__ a, const T* __restrict__ b, int64_t 
 template <typename T>
 hipError_t launch_dot(const T* a, const T* b, int64_t n_reals, int32_t n, double* partials, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  dim3 grid(elem_num_blocks(n_reals), n);
-  hipLaunchKernelGGL((k_dot<T>), grid, dim3(kBlock), 0, s, a, b, n_reals, partials);
+  dim3 grid(red_num_blocks(n_reals), n);
+  hipLaunchKernelGGL((k_dot<T>), grid, dim3(kBlock), 0, s, a, b, n_reals, red_steps(n_reals), partials);
   return hipGetLastError();
 }
 template hipError_t launch_dot<double>(const double*, const double*, int64_t, int32_t, double*, hipStream_t);
@@ -617,11 +627,15 @@ __global__ void k_cg_init(CgDev cg, const double* bn2_part, int32_t nblk, const 
     fl[kFlNeedRU] = 0;
     fl[kFlRUMask] = 0;
     fl[kFlLive] = 0;
+    fl[kFlBase] = 0;
+    fl[kFlM] = 0;
     s_bn2 = bn2;
   }
   __syncthreads();
+  const int32_t nc = 2 + 2 * cg.cslots;
   for (int j = threadIdx.x; j < cg.n_shift; j += blockDim.x) {
-    double* sh = cg.sh + ((int64_t)v * cg.n_shift + j) * kShN;
+    const int64_t vj = (int64_t)v * cg.n_shift + j;
+    double* sh = cg.sh + vj * kShN;
     sh[kShZeta] = 1.0;
     sh[kShZetaPrev] = 1.0;
     sh[kShZetaNext] = 1.0;
@@ -629,9 +643,14 @@ __global__ void k_cg_init(CgDev cg, const double* bn2_part, int32_t nblk, const 
     sh[kShCr] = 0.0;
     sh[kShCp] = 0.0;
     sh[kShUpd] = 0.0;
+    sh[kShSeg] = 0.0;
+    // x_j = 0, p_j = b = ring slot 0
+    double* cf = cg.coef + vj * nc;
+    for (int i = 0; i < nc; ++i) cf[i] = 0.0;
+    cf[2 + cg.cslots] = 1.0;
     const int32_t on = (s_bn2 > 0.0) ? 1 : 0;
-    cg.act[(int64_t)v * cg.n_shift + j] = on;
-    cg.act_next[(int64_t)v * cg.n_shift + j] = on;
+    cg.act[vj] = on;
+    cg.act_next[vj] = on;
   }
 }
 
@@ -642,7 +661,8 @@ hipError_t launch_cg_init(const CgDev& cg, const double* bn2_partials, int32_t n
   return hipGetLastError();
 }
 
-// alpha_k = rr / <p, A0 p>;  zeta_{k+1}^j and the x-update coefficient of every active shift
+// alpha_k = rr / <p, A0 p>;  zeta_{k+1}^j and the x-update coefficient of every active shift,
+// applied to the segment coefficients of the non-seed shifts: x_j += cx_j p_j
 __global__ void k_cg_alpha(CgDev cg) {
   const int32_t v = blockIdx.x;
   int32_t* fl = cg.flags + (int64_t)v * kFlN;
@@ -653,7 +673,7 @@ __global__ void k_cg_alpha(CgDev cg) {
   __shared__ double lds[1][16];
   double* sc = cg.sc + (int64_t)v * kScN;
   // a reliable update issued at the end of the previous iteration: its FP64 residual
-  // r64 = b - (Delta + sigma0) x_hi replaces the recursive residual from now on
+  // r64 = b - (Delta + sigma0) x_seed replaces the recursive residual from now on
   const int32_t ru = cg.part_ru ? fl[kFlNeedRU] : 0;
   double rr_true = 0.0;
   if (ru) rr_true = block_sum_array(cg.part_ru + ((int64_t)v * 3 + 2) * cg.nblk_ru, cg.nblk_ru, lds);
@@ -685,7 +705,10 @@ __global__ void k_cg_alpha(CgDev cg) {
   if (!s_ok) return;
   const double alpha = s_alpha;
   const double ap = sc[kScAlphaPrev], bp = sc[kScBetaPrev];
-  const double s0 = cg.sigma[(int64_t)v * cg.n_shift + cg.seed[v]];
+  const int32_t seed = cg.seed[v];
+  const double s0 = cg.sigma[(int64_t)v * cg.n_shift + seed];
+  const int32_t m = fl[kFlM];
+  const int32_t nc = 2 + 2 * cg.cslots;
   for (int j = threadIdx.x; j < cg.n_shift; j += blockDim.x) {
     const int64_t vj = (int64_t)v * cg.n_shift + j;
     const int32_t on = cg.act_next[vj];
@@ -695,9 +718,18 @@ __global__ void k_cg_alpha(CgDev cg) {
       const double z = sh[kShZeta], zp = sh[kShZetaPrev];
       const double ds = cg.sigma[vj] - s0;
       const double zn = z * zp * ap / (ap * zp * (1.0 + alpha * ds) + alpha * bp * (zp - z));
+      const double cx = alpha * zn / z;
       sh[kShZetaNext] = zn;
-      sh[kShCx] = alpha * zn / z;
+      sh[kShCx] = cx;
       sh[kShUpd] += 1.0;
+      if (cg.ring_on && m < cg.nslot && !(cg.seed_explicit && j == seed)) {
+        double* cf = cg.coef + vj * nc;
+        const double* e = cf + 2 + cg.cslots;
+        double* d = cf + 2;
+        cf[0] = fma(cx, cf[1], cf[0]);
+        for (int i = 0; i <= m; ++i) d[i] = fma(cx, e[i], d[i]);
+        sh[kShSeg] = 1.0;
+      }
     } else {
       sh[kShCx] = 0.0;
     }
@@ -709,7 +741,9 @@ hipError_t launch_cg_alpha(const CgDev& cg, hipStream_t s) {
   return hipGetLastError();
 }
 
-// beta_k = rr_new / rr; shifted beta and p-update coefficients; convergence and freezing
+// beta_k = rr_new / rr; shifted beta and p-update coefficients (applied to the segment
+// coefficients of the non-seed shifts: p_j = cr_j r' + cp_j p_j); convergence and freezing;
+// the new residual becomes the current ring entry
 __global__ void k_cg_beta(CgDev cg, int32_t mixed) {
   const int32_t v = blockIdx.x;
   int32_t* fl = cg.flags + (int64_t)v * kFlN;
@@ -727,6 +761,8 @@ __global__ void k_cg_beta(CgDev cg, int32_t mixed) {
   const double rnorm = sqrt(rrn);
   const double tolabs = sc[kScTolAbs];
   const int32_t seed = cg.seed[v];
+  const int32_t m = fl[kFlM];
+  const int32_t nc = 2 + 2 * cg.cslots;
   int any_other = 0;
   for (int j = threadIdx.x; j < cg.n_shift; j += blockDim.x) {
     const int64_t vj = (int64_t)v * cg.n_shift + j;
@@ -734,11 +770,21 @@ __global__ void k_cg_beta(CgDev cg, int32_t mixed) {
     if (cg.act[vj]) {
       const double z = sh[kShZeta], zn = sh[kShZetaNext];
       const double ratio = zn / z;
-      sh[kShCr] = zn;
-      sh[kShCp] = beta * ratio * ratio;
+      const double cr = zn, cp = beta * ratio * ratio;
+      sh[kShCr] = cr;
+      sh[kShCp] = cp;
       const int32_t keep = (fabs(zn) * rnorm > tolabs) ? 1 : 0;
       cg.act_next[vj] = keep;
       if (j != seed) any_other |= keep;
+      if (!(cg.seed_explicit && j == seed)) {
+        if (cg.ring_on && keep && m + 1 < cg.nslot) {
+          double* cf = cg.coef + vj * nc;
+          double* e = cf + 2 + cg.cslots;
+          cf[1] *= cp;
+          for (int i = 0; i <= m; ++i) e[i] *= cp;
+          e[m + 1] = cr;
+        }
+      }
       sh[kShZetaPrev] = z;
       sh[kShZeta] = zn;
     } else {
@@ -748,13 +794,26 @@ __global__ void k_cg_beta(CgDev cg, int32_t mixed) {
   any_other = __syncthreads_or(any_other);
   if (threadIdx.x == 0) {
     const int64_t vs = (int64_t)v * cg.n_shift + seed;
-    if (any_other) cg.act_next[vs] = 1;     // the seed carries the Krylov space for the others
+    if (any_other && !cg.act_next[vs] && cg.act[vs]) {
+      // the seed carries the Krylov space for the others: its direction keeps being updated
+      cg.act_next[vs] = 1;
+      if (cg.ring_on && !cg.seed_explicit && m + 1 < cg.nslot) {
+        double* cf = cg.coef + vs * nc;
+        double* e = cf + 2 + cg.cslots;
+        const double cp = cg.sh[vs * kShN + kShCp];
+        cf[1] *= cp;
+        for (int i = 0; i <= m; ++i) e[i] *= cp;
+        e[m + 1] = cg.sh[vs * kShN + kShCr];
+      }
+    }
+    if (any_other) cg.act_next[vs] = 1;
     const int32_t any = any_other | cg.act_next[vs];
     sc[kScAlphaPrev] = sc[kScAlpha];
     sc[kScBetaPrev] = beta;
     sc[kScRR] = rrn;
     sc[kScIters] += 1.0;
     fl[kFlRUMask] = 0;  // the residual update of this iteration has consumed it
+    fl[kFlM] = m + 1;
     if (!(rrn == rrn)) {
       fl[kFlStatus] = kStBreakdown;
       fl[kFlRun] = 0;
@@ -776,26 +835,74 @@ hipError_t launch_cg_beta(const CgDev& cg, int32_t mixed, hipStream_t s) {
   return hipGetLastError();
 }
 
-// r -= alpha Ap, partial <r, r>
+// ring slot i of rhs v, viewed as T (FP32 slots are n_reals floats)
 template <typename T>
-__global__ void k_cg_r(CgDev cg, T* __restrict__ r, const T* __restrict__ Ap, const double* __restrict__ r64,
-                       int64_t n) {
+__device__ __forceinline__ T* ring_slot(const void* ring, int64_t rhs_bytes, int32_t v, int32_t i, int64_t n) {
+  return (T*)((char*)ring + (int64_t)v * rhs_bytes + (int64_t)i * n * (int64_t)sizeof(T));
+}
+
+template <typename T>
+__global__ void k_cg_start(const double* __restrict__ b, void* ring, T* __restrict__ p, int64_t rhs_bytes,
+                           int64_t n) {
   const int32_t v = blockIdx.y;
-  if (cg.flags[(int64_t)v * kFlN + kFlLive] == 0) return;
-  const int32_t from64 = r64 ? cg.flags[(int64_t)v * kFlN + kFlRUMask] : 0;
-  const T alpha = (T)cg.sc[(int64_t)v * kScN + kScAlpha];
-  T* rv = r + (int64_t)v * n;
+  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  if (i0 >= n) return;
+  T* r0 = ring_slot<T>(ring, rhs_bytes, v, 0, n);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const T x = (T)b[(int64_t)v * n + i0 + k];
+    r0[i0 + k] = x;
+    p[(int64_t)v * n + i0 + k] = x;
+  }
+}
+
+template <typename T>
+hipError_t launch_cg_start(const double* b, void* ring, T* p, int32_t nr, int64_t rhs_bytes, int64_t n_reals,
+                           hipStream_t s) {
+  if (nr == 0) return hipSuccess;
+  dim3 grid(elem_num_blocks(n_reals), nr);
+  hipLaunchKernelGGL((k_cg_start<T>), grid, dim3(kBlock), 0, s, b, ring, p, rhs_bytes, n_reals);
+  return hipGetLastError();
+}
+template hipError_t launch_cg_start<double>(const double*, void*, double*, int32_t, int64_t, int64_t, hipStream_t);
+template hipError_t launch_cg_start<float>(const double*, void*, float*, int32_t, int64_t, int64_t, hipStream_t);
+
+template <typename T>
+__global__ void k_cg_r(CgDev cg, void* ring, const T* __restrict__ Ap, const T* __restrict__ p,
+                       double* __restrict__ x_hi, const double* __restrict__ r64, int64_t n, int32_t steps) {
+  const int32_t v = blockIdx.y;
+  const int32_t* fl = cg.flags + (int64_t)v * kFlN;
+  if (fl[kFlLive] == 0) return;
+  const int32_t from64 = r64 ? fl[kFlRUMask] : 0;
+  const int32_t m = fl[kFlM], base = fl[kFlBase];
+  const T* rc = ring_slot<T>(ring, cg.ring_rhs_bytes, v, (base + m) % cg.nslot, n);
+  T* rn = ring_slot<T>(ring, cg.ring_rhs_bytes, v, (base + m + 1) % cg.nslot, n);
+  const double alpha_d = cg.sc[(int64_t)v * kScN + kScAlpha];
+  const T alpha = (T)alpha_d;
   const T* av = Ap + (int64_t)v * n;
+  const T* pv = p + (int64_t)v * n;
+  double* xs = x_hi ? x_hi + ((int64_t)v * cg.n_shift + cg.seed[v]) * n : nullptr;
   const double* r64v = r64 ? r64 + (int64_t)v * n : nullptr;
   double d[1] = {0.0};
-  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
-  if (i0 < n) {
+  for (int32_t t = 0; t < steps; ++t) {
+    const int64_t i0 = (((int64_t)blockIdx.x * steps + t) * blockDim.x + threadIdx.x) * 4;
+    if (i0 < n) {
+      T r0[4], a4[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const T r0 = from64 ? (T)r64v[i0 + k] : rv[i0 + k];
-      const T rn = fmadd(-alpha, av[i0 + k], r0);
-      rv[i0 + k] = rn;
-      d[0] = fma((double)rn, (double)rn, d[0]);
+      for (int k = 0; k < 4; ++k) {
+        r0[k] = from64 ? (T)r64v[i0 + k] : rc[i0 + k];
+        a4[k] = av[i0 + k];
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const T r1 = fmadd(-alpha, a4[k], r0[k]);
+        rn[i0 + k] = r1;
+        d[0] = fma((double)r1, (double)r1, d[0]);
+      }
+      if (xs) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) xs[i0 + k] = fma(alpha_d, (double)pv[i0 + k], xs[i0 + k]);
+      }
     }
   }
   __shared__ double lds[1][16];
@@ -804,129 +911,173 @@ __global__ void k_cg_r(CgDev cg, T* __restrict__ r, const T* __restrict__ Ap, co
 }
 
 template <typename T>
-hipError_t launch_cg_r_update(const CgDev& cg, T* r, const T* Ap, const double* r64, int64_t n_reals,
-                              hipStream_t s) {
-  dim3 grid(elem_num_blocks(n_reals), cg.n_rhs);
-  hipLaunchKernelGGL((k_cg_r<T>), grid, dim3(kBlock), 0, s, cg, r, Ap, r64, n_reals);
+hipError_t launch_cg_r_update(const CgDev& cg, void* ring, const T* Ap, const T* p, double* x_hi,
+                              const double* r64, int64_t n_reals, hipStream_t s) {
+  if (cg.nblk_e != red_num_blocks(n_reals)) return hipErrorInvalidValue;
+  dim3 grid(cg.nblk_e, cg.n_rhs);
+  hipLaunchKernelGGL((k_cg_r<T>), grid, dim3(kBlock), 0, s, cg, ring, Ap, p, x_hi, r64, n_reals,
+                     red_steps(n_reals));
   return hipGetLastError();
 }
-template hipError_t launch_cg_r_update<double>(const CgDev&, double*, const double*, const double*, int64_t,
-                                               hipStream_t);
-template hipError_t launch_cg_r_update<float>(const CgDev&, float*, const float*, const double*, int64_t,
-                                              hipStream_t);
+template hipError_t launch_cg_r_update<double>(const CgDev&, void*, const double*, const double*, double*,
+                                               const double*, int64_t, hipStream_t);
+template hipError_t launch_cg_r_update<float>(const CgDev&, void*, const float*, const float*, double*,
+                                              const double*, int64_t, hipStream_t);
 
-// x_j += cx_j p_j (shifts updated this iteration); p_j = cr_j r + cp_j p_j (shifts still active)
-template <typename T, typename TX>
-__global__ void k_cg_shift(CgDev cg, const T* __restrict__ r, T* __restrict__ p, TX* __restrict__ x,
-                           double* __restrict__ x_hi, int64_t n) {
+template <typename T>
+__global__ void k_cg_p(CgDev cg, const void* ring, T* __restrict__ p, int64_t n) {
   const int32_t v = blockIdx.y;
-  if (cg.flags[(int64_t)v * kFlN + kFlLive] == 0) return;
+  const int32_t* fl = cg.flags + (int64_t)v * kFlN;
+  if (fl[kFlLive] == 0 || fl[kFlRun] == 0) return;
   const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
   if (i0 >= n) return;
-  const int32_t acc_hi = x_hi ? cg.flags[(int64_t)v * kFlN + kFlNeedRU] : 0;
-  T rv[4];
+  const T* r = ring_slot<T>(ring, cg.ring_rhs_bytes, v, (fl[kFlBase] + fl[kFlM]) % cg.nslot, n);
+  const T beta = (T)cg.sc[(int64_t)v * kScN + kScBetaPrev];
+  T* pv = p + (int64_t)v * n;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) rv[k] = r[(int64_t)v * n + i0 + k];
-  for (int j = 0; j < cg.n_shift; ++j) {
+  for (int k = 0; k < 4; ++k) pv[i0 + k] = fmadd(beta, pv[i0 + k], r[i0 + k]);
+}
+
+template <typename T>
+hipError_t launch_cg_p_update(const CgDev& cg, const void* ring, T* p, int64_t n_reals, hipStream_t s) {
+  dim3 grid(elem_num_blocks(n_reals), cg.n_rhs);
+  hipLaunchKernelGGL((k_cg_p<T>), grid, dim3(kBlock), 0, s, cg, ring, p, n_reals);
+  return hipGetLastError();
+}
+template hipError_t launch_cg_p_update<double>(const CgDev&, const void*, double*, int64_t, hipStream_t);
+template hipError_t launch_cg_p_update<float>(const CgDev&, const void*, float*, int64_t, hipStream_t);
+
+// One element per thread: the segment's residuals at this element are loaded once and every
+// non-seed shift touched in the segment is folded from registers.
+template <typename T>
+__global__ void __launch_bounds__(256) k_cg_flush(CgDev cg, const void* ring, double* __restrict__ x_hi,
+                                                  double* __restrict__ pj, int32_t final_, int32_t first,
+                                                  int64_t n) {
+  const int32_t v = blockIdx.y;
+  const int32_t* fl = cg.flags + (int64_t)v * kFlN;
+  const int32_t m = min(fl[kFlM], cg.nslot - 1), base = fl[kFlBase];   // the host flushes before m passes nslot - 1
+  const int32_t seed = cg.seed[v];
+  const int32_t nc = 2 + 2 * cg.cslots;
+  const int32_t ns = cg.n_shift;
+  // the segment coefficients of this rhs (and per shift: updated in the segment, still active)
+  extern __shared__ double s_cf[];
+  int32_t* s_fl = (int32_t*)(s_cf + (size_t)ns * nc);
+  for (int i = threadIdx.x; i < ns * nc; i += blockDim.x) s_cf[i] = cg.coef[(int64_t)v * ns * nc + i];
+  for (int j = threadIdx.x; j < ns; j += blockDim.x) {
+    const int64_t vj = (int64_t)v * ns + j;
+    s_fl[2 * j] = cg.sh[vj * kShN + kShSeg] != 0.0 ? 1 : 0;
+    s_fl[2 * j + 1] = cg.act_next[vj];
+  }
+  __syncthreads();
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  double rv[kMaxSlots];
+#pragma unroll
+  for (int i = 0; i < kMaxSlots; ++i) {
+    rv[i] = 0.0;
+    if (i <= m) rv[i] = (double)ring_slot<T>(ring, cg.ring_rhs_bytes, v, (base + i) % cg.nslot, n)[e];
+  }
+  for (int j = 0; j < ns; ++j) {
+    if (cg.seed_explicit && j == seed) continue;   // kept current by the residual update
+    const int64_t vj = (int64_t)v * ns + j;
+    const double* cf = s_cf + (size_t)j * nc;
+    const double* d = cf + 2;
+    const double* ec = cf + 2 + cg.cslots;
+    double* xj = x_hi + vj * n + e;
+    double* pp = pj + vj * n + e;
+    if (!s_fl[2 * j]) {
+      if (first) *xj = 0.0;   // never updated (zero source)
+      continue;
+    }
+    // p_j0 exists once a flush has written it; before that its coefficients are exactly zero
+    const double p0 = (cf[0] != 0.0 || cf[1] != 0.0) ? *pp : 0.0;
+    double x = fma(cf[0], p0, first ? 0.0 : *xj);
+#pragma unroll
+    for (int i = 0; i < kMaxSlots; ++i)
+      if (i <= m) x = fma(d[i], rv[i], x);
+    *xj = x;
+    if (!final_ && s_fl[2 * j + 1]) {
+      double q = cf[1] * p0;
+#pragma unroll
+      for (int i = 0; i < kMaxSlots; ++i)
+        if (i <= m) q = fma(ec[i], rv[i], q);
+      *pp = q;
+    }
+  }
+}
+
+// after a flush: coefficients of the fresh segment (x_j = x_j0, p_j = p_j0) and the ring restarts
+// at the current residual
+__global__ void k_cg_flush_reset(CgDev cg) {
+  const int32_t v = blockIdx.x;
+  int32_t* fl = cg.flags + (int64_t)v * kFlN;
+  const int32_t nc = 2 + 2 * cg.cslots;
+  for (int j = threadIdx.x; j < cg.n_shift; j += blockDim.x) {
     const int64_t vj = (int64_t)v * cg.n_shift + j;
-    const int32_t ux = cg.act[vj];
-    const int32_t up = cg.act_next[vj];
-    if (!ux) continue;
-    const double* sh = cg.sh + vj * kShN;
-    const T cx = (T)sh[kShCx];
-    T* pj = p + vj * n + i0;
-    TX* xj = x + vj * n + i0;
-    T pv[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) pv[k] = pj[k];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) xj[k] = fmadd(cx, pv[k], xj[k]);
-    if (up) {
-      const T cr = (T)sh[kShCr], cp = (T)sh[kShCp];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) pj[k] = fmadd(cr, rv[k], cp * pv[k]);
-    }
+    double* cf = cg.coef + vj * nc;
+    for (int i = 0; i < nc; ++i) cf[i] = 0.0;
+    cf[1] = 1.0;
+    cg.sh[vj * kShN + kShSeg] = 0.0;
   }
-  if (acc_hi) {
-    // reliable update: move every shift's low-precision increment into the FP64 solution
-    for (int j = 0; j < cg.n_shift; ++j) {
-      const int64_t off = ((int64_t)v * cg.n_shift + j) * n + i0;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        x_hi[off + k] += (double)x[off + k];
-        x[off + k] = TX(0);
-      }
-    }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    fl[kFlBase] = (fl[kFlBase] + fl[kFlM]) % cg.nslot;
+    fl[kFlM] = 0;
   }
 }
 
-template <typename T, typename TX>
-hipError_t launch_cg_shift_update(const CgDev& cg, const T* r, T* p, TX* x, double* x_hi, int64_t n_reals,
-                                  hipStream_t s) {
-  dim3 grid(elem_num_blocks(n_reals), cg.n_rhs);
-  hipLaunchKernelGGL((k_cg_shift<T, TX>), grid, dim3(kBlock), 0, s, cg, r, p, x, x_hi, n_reals);
+size_t flush_lds_bytes(const CgDev& cg) {
+  return (size_t)cg.n_shift * (2 + 2 * cg.cslots) * 8 + (size_t)cg.n_shift * 2 * 4;
+}
+
+template <typename T>
+hipError_t launch_cg_flush(const CgDev& cg, const void* ring, double* x_hi, double* pj, int32_t final_,
+                           int32_t first, int64_t n_reals, hipStream_t s) {
+  if (cg.nslot > kMaxSlots || cg.nslot > cg.cslots) return hipErrorInvalidValue;
+  dim3 grid((unsigned)((n_reals + kBlock - 1) / kBlock), cg.n_rhs);
+  hipLaunchKernelGGL((k_cg_flush<T>), grid, dim3(kBlock), flush_lds_bytes(cg), s, cg, ring, x_hi, pj, final_,
+                     first, n_reals);
+  hipLaunchKernelGGL(k_cg_flush_reset, dim3(cg.n_rhs), dim3(kRedBlock), 0, s, cg);
   return hipGetLastError();
 }
-template hipError_t launch_cg_shift_update<double, double>(const CgDev&, const double*, double*, double*,
-                                                             double*, int64_t, hipStream_t);
-template hipError_t launch_cg_shift_update<float, float>(const CgDev&, const float*, float*, float*, double*,
-                                                           int64_t, hipStream_t);
+template hipError_t launch_cg_flush<double>(const CgDev&, const void*, double*, double*, int32_t, int32_t,
+                                            int64_t, hipStream_t);
+template hipError_t launch_cg_flush<float>(const CgDev&, const void*, double*, double*, int32_t, int32_t,
+                                           int64_t, hipStream_t);
 
-// reliable update: x_hi += x_lo, x_lo = 0 for every shift of the flagged rhs
-__global__ void k_ru_accumulate(CgDev cg, float* __restrict__ x_lo, double* __restrict__ x_hi, int64_t n,
-                                int32_t all) {
+// FP64 slot cur -> FP32 slot 0 (inside FP64 slot 0), or FP32 slot 2 (inside FP64 slot 1) when
+// cur is 0: the copy never overlaps its source and the FP32 ring restarts at that slot
+__global__ void k_cg_to_f32(CgDev cg, void* ring, const double* __restrict__ p64, float* __restrict__ p32,
+                            int64_t n) {
   const int32_t v = blockIdx.y;
-  if (!all && cg.flags[(int64_t)v * kFlN + kFlNeedRU] == 0) return;
+  const int32_t* fl = cg.flags + (int64_t)v * kFlN;
+  const int32_t cur = (fl[kFlBase] + fl[kFlM]) % cg.nslot;
+  const double* r = ring_slot<double>(ring, cg.ring_rhs_bytes, v, cur, n);
+  float* r32 = ring_slot<float>(ring, cg.ring_rhs_bytes, v, cur == 0 ? 2 : 0, n);
   const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
   if (i0 >= n) return;
-  for (int j = 0; j < cg.n_shift; ++j) {
-    const int64_t off = ((int64_t)v * cg.n_shift + j) * n + i0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      x_hi[off + k] += (double)x_lo[off + k];
-      x_lo[off + k] = 0.0f;
-    }
+  for (int k = 0; k < 4; ++k) {
+    r32[i0 + k] = (float)r[i0 + k];
+    p32[(int64_t)v * n + i0 + k] = (float)p64[(int64_t)v * n + i0 + k];
   }
 }
 
-hipError_t launch_ru_accumulate(const CgDev& cg, float* x_lo, double* x_hi, int64_t n_reals, int32_t all,
-                                hipStream_t s) {
-  dim3 grid(elem_num_blocks(n_reals), cg.n_rhs);
-  hipLaunchKernelGGL(k_ru_accumulate, grid, dim3(kBlock), 0, s, cg, x_lo, x_hi, n_reals, all);
-  return hipGetLastError();
-}
-
-// p[v][j] = (T) b[v] for every shift j (initial search directions)
-template <typename T>
-__global__ void k_bcast_cast(const double* __restrict__ b, T* __restrict__ p, int32_t ns, int64_t n) {
-  const int32_t vj = blockIdx.y;
-  const int32_t v = vj / ns;
-  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
-  if (i0 >= n) return;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) p[(int64_t)vj * n + i0 + k] = (T)b[(int64_t)v * n + i0 + k];
-}
-
-template <typename T>
-hipError_t launch_bcast_cast(const double* b, T* p, int32_t nr, int32_t ns, int64_t n, hipStream_t s) {
-  if (nr * ns == 0) return hipSuccess;
-  dim3 grid(elem_num_blocks(n), nr * ns);
-  hipLaunchKernelGGL((k_bcast_cast<T>), grid, dim3(kBlock), 0, s, b, p, ns, n);
-  return hipGetLastError();
-}
-template hipError_t launch_bcast_cast<double>(const double*, double*, int32_t, int32_t, int64_t, hipStream_t);
-template hipError_t launch_bcast_cast<float>(const double*, float*, int32_t, int32_t, int64_t, hipStream_t);
-
-// entering the FP32 phase: the reliable-update reference becomes the current residual norm
-__global__ void k_cg_reset_maxr(CgDev cg) {
+__global__ void k_cg_to_f32_scalars(CgDev cg) {
   for (int v = threadIdx.x; v < cg.n_rhs; v += blockDim.x) {
+    int32_t* fl = cg.flags + (int64_t)v * kFlN;
     double* sc = cg.sc + (int64_t)v * kScN;
+    fl[kFlBase] = ((fl[kFlBase] + fl[kFlM]) % cg.nslot) == 0 ? 2 : 0;
+    fl[kFlM] = 0;
     sc[kScMaxR] = sqrt(sc[kScRR]);
   }
 }
 
-hipError_t launch_cg_reset_maxr(const CgDev& cg, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_reset_maxr, dim3(1), dim3(kRedBlock), 0, s, cg);
+hipError_t launch_cg_to_f32(const CgDev& cg64, void* ring, const double* p64, float* p32, int64_t n_reals,
+                            hipStream_t s) {
+  dim3 grid(elem_num_blocks(n_reals), cg64.n_rhs);
+  hipLaunchKernelGGL(k_cg_to_f32, grid, dim3(kBlock), 0, s, cg64, ring, p64, p32, n_reals);
+  hipLaunchKernelGGL(k_cg_to_f32_scalars, dim3(1), dim3(kRedBlock), 0, s, cg64);
   return hipGetLastError();
 }
 
@@ -973,18 +1124,30 @@ hipError_t launch_scatter_add_pairs(double* x_hi, const int32_t* idx, const doub
 // y = c x + sum_j r_j x_j  (FP64) with partial <y, y>
 __global__ void k_rational_combine(const double* __restrict__ x, const double* __restrict__ xp, int32_t n_poles,
                                    const double* __restrict__ coef, double* __restrict__ y, int64_t n,
-                                   double* partials) {
+                                   int32_t steps, double* partials) {
   const int32_t v = blockIdx.y;
-  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
   double d[1] = {0.0};
-  if (i0 < n) {
-    const double c = coef[0];
+  const double c = coef[0];
+  for (int32_t t = 0; t < steps; ++t) {
+    const int64_t i0 = (((int64_t)blockIdx.x * steps + t) * blockDim.x + threadIdx.x) * 4;
+    if (i0 < n) {
+      double acc[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      double acc = c * x[(int64_t)v * n + i0 + k];
-      for (int j = 0; j < n_poles; ++j) acc = fma(coef[1 + j], xp[((int64_t)v * n_poles + j) * n + i0 + k], acc);
-      y[(int64_t)v * n + i0 + k] = acc;
-      d[0] = fma(acc, acc, d[0]);
+      for (int k = 0; k < 4; ++k) acc[k] = c * x[(int64_t)v * n + i0 + k];
+      for (int j = 0; j < n_poles; ++j) {
+        const double* xj = xp + ((int64_t)v * n_poles + j) * n + i0;
+        const double rj = coef[1 + j];
+        double t4[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) t4[k] = xj[k];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[k] = fma(rj, t4[k], acc[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        y[(int64_t)v * n + i0 + k] = acc[k];
+        d[0] = fma(acc[k], acc[k], d[0]);
+      }
     }
   }
   if (partials) {
@@ -998,8 +1161,9 @@ hipError_t launch_rational_combine(const double* x, const double* xp, int32_t n_
                                    const double* coef, double* y, int64_t n_reals, double* partials,
                                    hipStream_t s) {
   if (n_rhs == 0) return hipSuccess;
-  dim3 grid(elem_num_blocks(n_reals), n_rhs);
-  hipLaunchKernelGGL(k_rational_combine, grid, dim3(kBlock), 0, s, x, xp, n_poles, coef, y, n_reals, partials);
+  dim3 grid(red_num_blocks(n_reals), n_rhs);
+  hipLaunchKernelGGL(k_rational_combine, grid, dim3(kBlock), 0, s, x, xp, n_poles, coef, y, n_reals,
+                     red_steps(n_reals), partials);
   return hipGetLastError();
 }
 

@@ -1,7 +1,7 @@
 // Stencil launch configuration cache.  Entries are keyed by lattice extents, dtype and
 // the number of link fields per launch; the autotuner (rmh_autotune_laplacian) fills
 // them from timed candidates, otherwise the defaults apply.  RMH_HOP_FORM (0 adjoint,
-// 1 matrix) and RMH_HOP_BLOCK override the defaults for experiments.
+// 1 matrix, 2 streamed adjoint) and RMH_HOP_BLOCK override the defaults for experiments.
 #include <stdlib.h>
 
 #include <cstdlib>
@@ -10,6 +10,7 @@
 #include <mutex>
 #include <tuple>
 
+#include "rmh.h"
 #include "rmh_tune.h"
 
 namespace rmh {
@@ -23,9 +24,38 @@ Key key_of(const Geom& g, int32_t dtype, int32_t n_rhs) {
   return Key(g.L0, g.L1, g.L2, g.L3, dtype, n_rhs);
 }
 
-HopConfig defaults() {
+// Untuned defaults, from the sweeps of the autotuner: on lattices of a million sites and more
+// the x3-walking kernel with four directions per thread (the streamed form in FP64, the
+// materialised adjoint matrix in FP32); on smaller ones two directions per thread in the
+// x3-fastest order, which keeps x3 neighbours in cache.
+HopConfig defaults(const Geom& g, int32_t dtype) {
   HopConfig c;
-  if (const char* e = getenv("RMH_HOP_FORM")) c.form = atoi(e) ? kFormMatrix : kFormAdjoint;
+  if (g.V >= (1 << 20)) {
+    c.form = dtype == RMH_F64 ? kFormStream : kFormAdjoint;
+    c.block = 128;
+    c.xcd_remap = 0;
+    c.nv = 4;
+    c.order = 0;
+    c.walk = 0;
+    const int32_t P = g.V / g.L3;
+    const int32_t cpb = c.block * c.nv / 4;
+    for (int k : {16, 8, 4, 2}) {
+      if (g.L3 % k) continue;
+      if ((int64_t)((P + cpb - 1) / cpb) * (g.L3 / k) >= 1024) {
+        c.walk = k;
+        break;
+      }
+    }
+  } else {
+    c.form = dtype == RMH_F64 ? kFormAdjoint : kFormMatrix;
+    c.block = 256;
+    c.xcd_remap = 1;
+    c.nv = 2;
+    c.walk = 0;
+    c.order = 1;
+    if (!hop_order_ok(g, c)) c.order = 0;
+  }
+  if (const char* e = getenv("RMH_HOP_FORM")) c.form = atoi(e);
   if (const char* e = getenv("RMH_HOP_BLOCK")) {
     const int b = atoi(e);
     if (b == 64 || b == 128 || b == 256) c.block = b;
@@ -52,7 +82,7 @@ HopConfig tune_hop(const Geom& g, int32_t dtype, int32_t n_rhs, int32_t /*purpos
       dist = d;
     }
   }
-  return best ? *best : defaults();
+  return best ? *best : defaults(g, dtype);
 }
 
 void tune_clear() {

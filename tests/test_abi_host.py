@@ -119,13 +119,13 @@ def test_validation_rational():
     r = np.array([1.0, 2.0])
     s_bad = np.array([0.5, -1.0])
     rat = _lib.RmhRational(0.0, 2, r.ctypes.data_as(_lib.P_f64), s_bad.ctypes.data_as(_lib.P_f64))
-    sv = _lib.RmhSolver(1e-10, 100, 0, 0.1, 8, 0.0)
+    sv = _lib.RmhSolver(1e-10, 100, 0, 0.1, 8, 0.0, 0)
     st = _lib.lib().rmh_rational_apply(L, FAKE, FAKE + 2**20, 1, ctypes.byref(rat), ctypes.byref(sv), FAKE + 2**21,
                                        None, None, None, FAKE + 2**22, 1 << 30, None)
     assert st == 4                                                                # RMH_E_POLES
     s_ok = np.array([0.5, 1.0])
     rat = _lib.RmhRational(0.0, 2, r.ctypes.data_as(_lib.P_f64), s_ok.ctypes.data_as(_lib.P_f64))
-    sv_bad = _lib.RmhSolver(0.0, 100, 0, 0.1, 8, 0.0)
+    sv_bad = _lib.RmhSolver(0.0, 100, 0, 0.1, 8, 0.0, 0)
     st = _lib.lib().rmh_rational_apply(L, FAKE, FAKE + 2**20, 1, ctypes.byref(rat), ctypes.byref(sv_bad),
                                        FAKE + 2**21, None, None, None, FAKE + 2**22, 1 << 30, None)
     assert st == 1

@@ -62,6 +62,34 @@ def test_rational_apply_parity(mode, which):
         assert out["stats"]["reliable_updates"] >= 1
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_rational_apply_segment_lengths(mode):
+    """The shift solutions do not depend on how often the stored seed residuals are folded into
+    them: segments of 1, 3 and 32 iterations against the default, and every shift's true residual
+    from the oracle."""
+    L = (4, 4, 4, 6)
+    announce(f"rational_apply segment lengths mode={mode}")
+    U, P, Ud, Pd = setup(L, "eps", 0.6, 12, n=2)
+    rat = _rat_kappa(0.9, 12)
+    tol = 1e-10
+    ref = api.rational_apply(L, Ud, Pd, rat, api.Solver(tol=tol, mode=mode), want_poles=True)
+    xr = ref["x_poles"].cpu().numpy()
+    for basis in (1, 3, 32):
+        out = api.rational_apply(L, Ud, Pd, rat, api.Solver(tol=tol, mode=mode, basis=basis), want_poles=True)
+        xp = out["x_poles"].cpu().numpy()
+        assert out["stats"]["iters"] == ref["stats"]["iters"]
+        for i in range(2):
+            bn = np.linalg.norm(P[i])
+            for j, sj in enumerate(rat.sigma):
+                # both solves satisfy the tolerance, so they differ by at most 2 tol ||b|| / sigma_j
+                assert np.linalg.norm(xp[i, j] - xr[i, j]) <= 2 * tol * bn / sj, (basis, i, j)
+                res = np.linalg.norm(P[i] - olap.laplacian(U, xp[i, j], L, sj)) / bn
+                assert res <= 1.01 * tol, (basis, i, j, res)
+        if mode == 0:
+            # same iterates, only the summation order of the shift updates differs
+            assert np.abs(xp - xr).max() <= 1e-12 * np.abs(xr).max()
+
+
 @pytest.mark.parametrize("kappa", [0.5, 0.9])
 @pytest.mark.parametrize("mode", [0, 1])
 def test_rational_apply_16_true_residuals(kappa, mode):
