@@ -71,6 +71,25 @@ def cpu_baseline(U, P, L, budget_s=12.0):
                       f"overstates the oracle's rate for the whole step"}
 
 
+def stencil_traffic(kernel_class):
+    """HBM bytes per stencil launch of this step from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE, scaled by a calibration copy), or None when the summary is
+    missing or the stencil sources have changed since it was taken."""
+    if kernel_class != "stencil":
+        return None, None
+    path = os.path.join(ROOT, "profiles", "stencil_traffic_16x16x16x16.json")
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None, None
+    from paper_2112_04556_amd.profiling import stencil_source_hash
+    rel = os.path.relpath(path, ROOT)
+    if t.get("stencil_source_sha256") != stencil_source_hash():
+        return None, rel + " (stale: stencil sources changed)"
+    return round(float(t["traffic_bytes_per_launch"])), rel
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -130,8 +149,10 @@ def main():
     # dominant kernel class of the step by event time
     dom = max(prof, key=lambda c: prof[c]["ms"])
     d = prof[dom]
+    traffic, traffic_src = stencil_traffic(dom)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(d["gbs"], 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(d["gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(d["gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "traffic_source": traffic_src,
                 "avg_launch_ms": d["avg_ms"], "bytes_per_launch": d["bytes"] / max(d["launches"], 1),
                 "launches": d["launches"]}
     shares = {c: round(prof[c]["ms"] / max(sum(p["ms"] for p in prof.values()), 1e-12), 4) for c in prof}
@@ -232,6 +253,27 @@ def run_extras(api, inputs, torch, np, dev, L, U_aos, Ud, Pd):
         log(f"stencil 32^3x64 {name}: {sten[name]}")
         del Ubd, Fbd, y
     out["laplacian_32x32x32x64"] = sten
+
+    # the rational solve where nothing is cache resident: 16 poles, one momentum field
+    rat16 = api.rational_kappa(0.9, 16)
+    Ubd = api.pack_links(Lb, inputs.random_links(Lb, "eps", 0.4, seed=2).to(dev))
+    Pb = inputs.gaussian_fields(Lb, 1, seed=2).to(dev)
+    row = {}
+    for mode, name in ((0, "fp64"), (1, "mixed")):
+        sv = api.Solver(tol=1e-10, mode=mode)
+        api.rational_apply(Lb, Ubd, Pb, rat16, sv)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        o = api.rational_apply(Lb, Ubd, Pb, rat16, sv)
+        torch.cuda.synchronize()
+        row[f"{name}_ms"] = round((time.perf_counter() - t0) * 1e3, 3)
+        st = o["stats"]
+        row[f"{name}_iters"] = st["iters"]
+        row[f"{name}_refine_iters"] = st["refine_iters"]
+        row[f"{name}_true_relres_max"] = st["true_relres_max"]
+    row["mixed_speedup"] = round(row["fp64_ms"] / row["mixed_ms"], 3)
+    out["rational_solve_32x32x32x64_kappa0.9_16poles"] = row
+    log(f"solve 32^3x64: {row}")
     return out
 
 

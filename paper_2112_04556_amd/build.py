@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librmh.so")
-SOURCES = ["rmh_kernels.hip", "rmh_api.hip", "rmh_host.cpp", "rmh_tune.cpp"]
+SOURCES = ["rmh_stencil.hip", "rmh_kernels.hip", "rmh_api.hip", "rmh_host.cpp", "rmh_tune.cpp"]
 ARCH = os.environ.get("RMH_OFFLOAD_ARCH", "gfx950")
 
 

@@ -181,10 +181,11 @@ struct ProfScope {
   }
 };
 
-void prof_add_bytes(int cls, double bytes) {
+void prof_add_bytes(int cls, double bytes, double items = 0.0) {
   if (!g_prof.on) return;
   std::lock_guard<std::mutex> lk(g_prof.mu);
   g_prof.bytes[cls] += bytes;
+  g_prof.items[cls] += items;
 }
 
 // algorithmic bytes of one stencil launch over n fields: links once, x, optional z, optional out
@@ -531,8 +532,11 @@ rmh_status engine_solve(Engine& e, const double* U64, const float* U32, const do
           HIP_TRY(launch_cg_p_update<float>(cg32, e.ring, e.p32, n, s));
         }
         // reliable update decided by this iteration's beta kernel (blocks of rhs without a
-        // pending update exit at once)
-        HIP_TRY(launch_hop<double>(hr, c64, s));
+        // pending update exit at once); its bytes are added once the update count is known
+        {
+          ProfScope ps(RMH_PROF_STENCIL, 0.0, s, 0.0);
+          HIP_TRY(launch_hop<double>(hr, c64, s));
+        }
       }
     }
     it += check_every;
@@ -570,6 +574,9 @@ rmh_status engine_solve(Engine& e, const double* U64, const float* U32, const do
   for (int v = 0; v < nr; ++v) {
     info->iters = std::max(info->iters, (int32_t)hsc[(size_t)v * kScN + kScIters]);
     info->ru += (int32_t)hsc[(size_t)v * kScN + kScRU];
+    // the reliable-update stencils that ran (links, x_seed, b and r64 of one field each)
+    prof_add_bytes(RMH_PROF_STENCIL, hsc[(size_t)v * kScN + kScRU] * hop_bytes(g, 1, 8, true, true),
+                   hsc[(size_t)v * kScN + kScRU]);
     const int32_t stv = hfl[(size_t)v * kFlN + kFlStatus];
     if (stv == kStBreakdown) info->status = kStBreakdown;
     else if (stv == kStNoConv && info->status == kStOk) info->status = kStNoConv;

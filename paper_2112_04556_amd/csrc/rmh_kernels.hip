@@ -1,402 +1,14 @@
-// HIP kernels for gfx950: the adjoint-Laplacian stencil with fused epilogues, layout
-// conversion, deterministic reductions, the multi-shift CG vector and scalar kernels,
-// mixed-precision reliable updates, and the link-derivative (force) kernel.
-//
-// Wave size is 64.  Every reduction is a fixed tree: per-thread FP64 sums, a wave
-// butterfly (__shfl_xor), a fixed-order sum of the waves of a block into one partial
-// per block, then a fixed-order strided sum of the partials in a later kernel, so
-// results are bitwise reproducible run to run.
+// HIP kernels for gfx950 besides the stencil: layout conversion, element-wise kernels with
+// deterministic reductions, the multi-shift CG vector and scalar kernels, mixed-precision
+// reliable updates, and the link-derivative (force) kernel.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "rmh_internal.h"
+#include "rmh_reduce.h"
 
 namespace rmh {
-
-// ------------------------------------------------------------------------------------------
-// reductions
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-  return v;
-}
-
-// Sum over the block (any multiple of 64 threads up to 1024); result valid in thread 0.
-template <int NQ>
-__device__ __forceinline__ void block_sum(double (&v)[NQ], double (*lds)[16]) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    double w = wave_sum(v[q]);
-    if (lane == 0) lds[q][wid] = w;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int nw = (blockDim.x + 63) >> 6;
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      double s = 0.0;
-      for (int i = 0; i < nw; ++i) s += lds[q][i];
-      v[q] = s;
-    }
-  }
-  __syncthreads();  // lds may be reused by the caller right away
-}
-
-// Strided fixed-order sum of n values by a whole block; result in thread 0.
-__device__ double block_sum_array(const double* p, int32_t n, double (*lds)[16]) {
-  double v[1] = {0.0};
-  for (int32_t i = threadIdx.x; i < n; i += blockDim.x) v[0] += p[i];
-  block_sum<1>(v, lds);
-  return v[0];
-}
-
-__device__ __forceinline__ int32_t remap_block(int32_t b, int32_t G, int32_t xcd) {
-  // Consecutive hardware block ids go round-robin over the 8 XCDs; give each XCD a
-  // contiguous range of the lattice so neighbouring sites share its L2.
-  if (xcd && (G & 7) == 0) return (b & 7) * (G >> 3) + (b >> 3);
-  return b;
-}
-
-// ------------------------------------------------------------------------------------------
-// the stencil
-
-// One hop's contribution to NV vectors: forward (kT = false, link U_mu(x), neighbour x+mu) or
-// backward (kT = true, link U_mu(x-mu), neighbour x-mu).
-template <typename T, int FORM, int NV, bool kT>
-__device__ __forceinline__ void hop_apply(const T* u, const T (*phi)[8], T (*acc)[8]) {
-  if (FORM == kFormAdjoint) {
-    T R[64];
-    adjoint_matrix<T>(u, R);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      if (!kT)
-        adj_apply<T>(R, phi[v], acc[v]);
-      else
-        adj_apply_t<T>(R, phi[v], acc[v]);
-    }
-  } else if (FORM == kFormMatrix) {
-#pragma unroll
-    for (int v = 0; v < NV; ++v) mat_hop<T, kT>(u, phi[v], acc[v]);
-  } else {
-    adj_stream<T, NV, kT>(u, phi, acc);
-  }
-}
-
-// out[v] = a (H x)[v] + b x[v] + c z[v]: a block of B threads covers B * NV / 4 sites; the
-// 4 / NV thread groups of a site (direction subsets) are wave-aligned slices of the block.
-// One backward hop: link and field both read at the neighbour site sb.
-template <typename T, int FORM, int NV, bool kT>
-__device__ __forceinline__ void hop_term(const T* __restrict__ Um, int32_t sb, const T* __restrict__ xf,
-                                         int nu0, int32_t V, T (&acc)[NV][8]) {
-  T u[18], phi[NV][8];
-#pragma unroll
-  for (int c = 0; c < 18; ++c) u[c] = (Um + (size_t)c * V)[sb];
-#pragma unroll
-  for (int i = 0; i < NV; ++i)
-#pragma unroll
-    for (int b = 0; b < 8; ++b) phi[i][b] = (xf + (size_t)((nu0 + i) * 8 + b) * V)[sb];
-  hop_apply<T, FORM, NV, kT>(u, phi, acc);
-}
-
-// One forward hop: link at s, field at the neighbour sf.
-template <typename T, int FORM, int NV>
-__device__ __forceinline__ void hop_term_fwd(const T* __restrict__ Um, int32_t s, int32_t sf,
-                                             const T* __restrict__ xf, int nu0, int32_t V,
-                                             T (&acc)[NV][8]) {
-  T u[18], phi[NV][8];
-#pragma unroll
-  for (int c = 0; c < 18; ++c) u[c] = (Um + (size_t)c * V)[s];
-#pragma unroll
-  for (int i = 0; i < NV; ++i)
-#pragma unroll
-    for (int b = 0; b < 8; ++b) phi[i][b] = (xf + (size_t)((nu0 + i) * 8 + b) * V)[sf];
-  hop_apply<T, FORM, NV, false>(u, phi, acc);
-}
-
-template <typename T, int FORM, int NV, bool DOTS, bool FILTER>
-__global__ void __launch_bounds__(256) k_hop(const HopArgs<T> A, int32_t xcd, int32_t order) {
-  constexpr int G = 4 / NV;  // thread groups per site
-  const int32_t v = blockIdx.y;
-  if (A.run && A.run[(int64_t)v * A.run_stride] == 0) return;
-  const int32_t V = A.g.V;
-  const int32_t lb = remap_block(blockIdx.x, gridDim.x, xcd);
-  const int32_t spb = blockDim.x / G;              // sites per block
-  // direction subset of this thread: wave-uniform (spb is a multiple of the wave size), so the
-  // per-component base addresses stay in scalar registers
-  const int32_t grp = __builtin_amdgcn_readfirstlane(threadIdx.x / spb);
-  int32_t blk = lb;
-  if (order) {
-    // lb = ((chunk * L2) + x2) * L3 + x3  ->  lexicographic block of that (x0 x1 chunk, x2, x3)
-    const int32_t x3 = lb % A.g.L3;
-    const int32_t t = lb / A.g.L3;
-    const int32_t x2 = t % A.g.L2;
-    const int32_t chunk = t / A.g.L2;
-    const int32_t cpp = (A.g.L0 * A.g.L1) / spb;   // chunks per (x2, x3) plane
-    blk = (x3 * A.g.L2 + x2) * cpp + chunk;
-  }
-  const int32_t s = blk * spb + (threadIdx.x - grp * spb);
-  const int nu0 = grp * NV;
-  double dsum[3] = {0.0, 0.0, 0.0};
-  if (s < V) {
-    const int64_t FV = 32 * (int64_t)V;
-    const T* __restrict__ xf = A.x + ((int64_t)v * A.x_mul + A.x_add) * FV;
-    const T* __restrict__ U = A.U;
-    T acc[NV][8];
-#pragma unroll
-    for (int i = 0; i < NV; ++i)
-#pragma unroll
-      for (int a = 0; a < 8; ++a) acc[i][a] = T(0);
-    int32_t xc[4];
-    site_coords(A.g, s, xc);
-    // term order (shared with k_hop_walk, so every launch shape rounds alike): the x3
-    // backward hop, the x0, x1, x2 forward and backward hops, the x3 forward hop
-#pragma unroll 1
-    for (int mu = 0; mu < 4; ++mu) {
-      const int mb = (mu + 3) & 3;   // backward hop of the previous direction, x3 first
-      hop_term<T, FORM, NV, true>(U + (int64_t)mb * 18 * V, site_shift(A.g, s, xc, mb, -1), xf, nu0, V, acc);
-      hop_term_fwd<T, FORM, NV>(U + (int64_t)mu * 18 * V, s, site_shift(A.g, s, xc, mu, +1), xf, nu0, V, acc);
-    }
-    // epilogue: out = a H x + b x + c z
-    const T ca = T(A.a);
-    const T cb = T(A.b_rhs ? A.b_rhs[v] : A.b);
-    const T cc = T(A.c);
-    const T* zf = A.z ? A.z + (int64_t)(v / A.z_div) * FV : nullptr;  // may alias out
-    T* outf = A.out + (int64_t)v * FV;
-#pragma unroll
-    for (int i = 0; i < NV; ++i)
-#pragma unroll
-      for (int a = 0; a < 8; ++a) {
-        const int64_t e = (int64_t)((nu0 + i) * 8 + a) * V + s;
-        const T xv = xf[e];
-        T o = fmadd(ca, acc[i][a], cb * xv);
-        if (zf) o = fmadd(cc, zf[e], o);
-        if (A.store) outf[e] = o;
-        if (DOTS) {
-          const double xd = (double)xv, od = (double)o;
-          dsum[0] = fma(xd, xd, dsum[0]);
-          dsum[1] = fma(od, xd, dsum[1]);
-          dsum[2] = fma(od, od, dsum[2]);
-        }
-        if (FILTER) {
-          T* y = A.yacc + (int64_t)v * FV + e;
-          for (int w = 0; w < A.n_w; ++w) {
-            T* yw = y + w * A.yacc_stride;
-            if (A.filter_first)
-              *yw = fmadd(T(A.wcoef[w]), o, T(A.wcoef0[w]) * xv);
-            else
-              *yw = fmadd(T(A.wcoef[w]), o, *yw);
-          }
-        }
-      }
-  }
-  if (DOTS) {
-    __shared__ double lds[3][16];
-    block_sum<3>(dsum, lds);
-    if (threadIdx.x == 0) {
-      const int32_t nblk = gridDim.x;
-      double* p = A.partials + (int64_t)v * 3 * nblk + blockIdx.x;
-      if (A.dot_mask & 1) p[0] = dsum[0];
-      if (A.dot_mask & 2) p[nblk] = dsum[1];
-      if (A.dot_mask & 4) p[2 * nblk] = dsum[2];
-    }
-  }
-}
-
-// Walking variant of k_hop: a block of B threads covers B * NV / 4 columns (x0, x1, x2) of the
-// lattice; each thread walks K consecutive x3 values of its column.  Per step the x0, x1, x2
-// hops load their links and neighbours as in k_hop; the x3 forward hop loads U_3(x) and
-// phi(x+3), which become the backward link and the centre field of the next step.
-template <typename T, int FORM, int NV, bool DOTS, bool FILTER>
-__global__ void __launch_bounds__(256) k_hop_walk(const HopArgs<T> A, int32_t xcd, int32_t K) {
-  constexpr int G = 4 / NV;
-  const int32_t v = blockIdx.y;
-  if (A.run && A.run[(int64_t)v * A.run_stride] == 0) return;
-  const int32_t V = A.g.V;
-  const int32_t P = A.g.L0 * A.g.L1 * A.g.L2;            // sites per x3 plane
-  const int32_t cpb = blockDim.x / G;                    // columns per block
-  const int32_t nchunk = (P + cpb - 1) / cpb;
-  const int32_t lb = remap_block(blockIdx.x, gridDim.x, xcd);
-  const int32_t chunk = lb % nchunk;
-  const int32_t x3_0 = (lb / nchunk) * K;
-  const int32_t grp = __builtin_amdgcn_readfirstlane(threadIdx.x / cpb);  // wave-uniform
-  const int32_t col = chunk * cpb + (threadIdx.x - grp * cpb);
-  const int nu0 = grp * NV;
-  double dsum[3] = {0.0, 0.0, 0.0};
-  if (col < P) {
-    const int64_t FV = 32 * (int64_t)V;
-    const T* __restrict__ xf = A.x + ((int64_t)v * A.x_mul + A.x_add) * FV;
-    const T* __restrict__ U = A.U;
-    const T* __restrict__ U3 = U + (int64_t)3 * 18 * V;
-    const T ca = T(A.a);
-    const T cb = T(A.b_rhs ? A.b_rhs[v] : A.b);
-    const T cc = T(A.c);
-    const T* zf = A.z ? A.z + (int64_t)(v / A.z_div) * FV : nullptr;  // may alias out
-    T* outf = A.out + (int64_t)v * FV;
-    int32_t xc[4];
-    site_coords(A.g, col + x3_0 * P, xc);
-    // carried state: the centre field and the x-3 field (the link U_3(x-3), loaded by this
-    // thread one step earlier, is read again from the cache)
-    T cen[NV][8], bwd[NV][8];
-    {
-      const int32_t s0 = col + x3_0 * P;
-      const int32_t sb = (x3_0 == 0) ? s0 + (A.g.L3 - 1) * P : s0 - P;
-#pragma unroll
-      for (int i = 0; i < NV; ++i)
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-          cen[i][b] = (xf + (size_t)((nu0 + i) * 8 + b) * V)[s0];
-          bwd[i][b] = (xf + (size_t)((nu0 + i) * 8 + b) * V)[sb];
-        }
-    }
-#pragma unroll 1
-    for (int32_t t = 0; t < K; ++t) {
-      const int32_t x3 = x3_0 + t;
-      const int32_t s = col + x3 * P;
-      xc[3] = x3;
-      T acc[NV][8];
-#pragma unroll
-      for (int i = 0; i < NV; ++i)
-#pragma unroll
-        for (int a = 0; a < 8; ++a) acc[i][a] = T(0);
-      // x3 backward hop: carried field, link U_3(x - 3)
-      {
-        const int32_t sb = (x3 == 0) ? s + (A.g.L3 - 1) * P : s - P;
-        T u[18];
-#pragma unroll
-        for (int c = 0; c < 18; ++c) u[c] = (U3 + (size_t)c * V)[sb];
-        hop_apply<T, FORM, NV, true>(u, bwd, acc);
-      }
-#pragma unroll 1
-      for (int mu = 0; mu < 3; ++mu) {
-        const T* __restrict__ Um = U + (int64_t)mu * 18 * V;
-        hop_term_fwd<T, FORM, NV>(Um, s, site_shift(A.g, s, xc, mu, +1), xf, nu0, V, acc);
-        hop_term<T, FORM, NV, true>(Um, site_shift(A.g, s, xc, mu, -1), xf, nu0, V, acc);
-      }
-      // x3 forward hop: phi(x + 3) becomes the centre of the next step
-      T fwd[NV][8];
-      {
-        const int32_t sf = (x3 == A.g.L3 - 1) ? s - (A.g.L3 - 1) * P : s + P;
-        T u[18];
-#pragma unroll
-        for (int c = 0; c < 18; ++c) u[c] = (U3 + (size_t)c * V)[s];
-#pragma unroll
-        for (int i = 0; i < NV; ++i)
-#pragma unroll
-          for (int b = 0; b < 8; ++b) fwd[i][b] = (xf + (size_t)((nu0 + i) * 8 + b) * V)[sf];
-        hop_apply<T, FORM, NV, false>(u, fwd, acc);
-      }
-      // epilogue
-#pragma unroll
-      for (int i = 0; i < NV; ++i)
-#pragma unroll
-        for (int a = 0; a < 8; ++a) {
-          const int64_t e = (int64_t)((nu0 + i) * 8 + a) * V + s;
-          const T xv = cen[i][a];
-          T o = fmadd(ca, acc[i][a], cb * xv);
-          if (zf) o = fmadd(cc, zf[e], o);
-          if (A.store) outf[e] = o;
-          if (DOTS) {
-            const double xd = (double)xv, od = (double)o;
-            dsum[0] = fma(xd, xd, dsum[0]);
-            dsum[1] = fma(od, xd, dsum[1]);
-            dsum[2] = fma(od, od, dsum[2]);
-          }
-          if (FILTER) {
-            T* y = A.yacc + (int64_t)v * FV + e;
-            for (int w = 0; w < A.n_w; ++w) {
-              T* yw = y + w * A.yacc_stride;
-              if (A.filter_first)
-                *yw = fmadd(T(A.wcoef[w]), o, T(A.wcoef0[w]) * xv);
-              else
-                *yw = fmadd(T(A.wcoef[w]), o, *yw);
-            }
-          }
-        }
-#pragma unroll
-      for (int i = 0; i < NV; ++i)
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-          bwd[i][b] = cen[i][b];
-          cen[i][b] = fwd[i][b];
-        }
-    }
-  }
-  if (DOTS) {
-    __shared__ double lds[3][16];
-    block_sum<3>(dsum, lds);
-    if (threadIdx.x == 0) {
-      const int32_t nblk = gridDim.x;
-      double* p = A.partials + (int64_t)v * 3 * nblk + blockIdx.x;
-      if (A.dot_mask & 1) p[0] = dsum[0];
-      if (A.dot_mask & 2) p[nblk] = dsum[1];
-      if (A.dot_mask & 4) p[2 * nblk] = dsum[2];
-    }
-  }
-}
-
-int hop_walk_ok(const Geom& g, const HopConfig& cfg) {
-  return (cfg.walk > 0 && (g.L3 % cfg.walk) == 0) ? 1 : 0;
-}
-
-int hop_num_blocks(const Geom& g, const HopConfig& cfg) {
-  const int spb = cfg.block * cfg.nv / 4;
-  if (hop_walk_ok(g, cfg)) {
-    const int P = g.L0 * g.L1 * g.L2;
-    return ((P + spb - 1) / spb) * (g.L3 / cfg.walk);
-  }
-  return (g.V + spb - 1) / spb;
-}
-
-int hop_order_ok(const Geom& g, const HopConfig& cfg) {
-  const int spb = cfg.block * cfg.nv / 4;
-  return ((g.L0 * g.L1) % spb) == 0 ? 1 : 0;
-}
-
-template <typename T, int FORM, int NV>
-static hipError_t launch_hop_form(const HopArgs<T>& A, const HopConfig& cfg, hipStream_t s) {
-  dim3 grid(hop_num_blocks(A.g, cfg), A.n_rhs), block(cfg.block);
-  const bool dots = A.partials && A.dot_mask;
-  const bool filt = A.yacc && A.n_w > 0;
-  const int32_t order = (cfg.order && hop_order_ok(A.g, cfg)) ? 1 : 0;
-  if (hop_walk_ok(A.g, cfg)) {
-    const int32_t K = cfg.walk;
-    if (dots && filt)
-      hipLaunchKernelGGL((k_hop_walk<T, FORM, NV, true, true>), grid, block, 0, s, A, cfg.xcd_remap, K);
-    else if (dots)
-      hipLaunchKernelGGL((k_hop_walk<T, FORM, NV, true, false>), grid, block, 0, s, A, cfg.xcd_remap, K);
-    else if (filt)
-      hipLaunchKernelGGL((k_hop_walk<T, FORM, NV, false, true>), grid, block, 0, s, A, cfg.xcd_remap, K);
-    else
-      hipLaunchKernelGGL((k_hop_walk<T, FORM, NV, false, false>), grid, block, 0, s, A, cfg.xcd_remap, K);
-    return hipGetLastError();
-  }
-  if (dots && filt)
-    hipLaunchKernelGGL((k_hop<T, FORM, NV, true, true>), grid, block, 0, s, A, cfg.xcd_remap, order);
-  else if (dots)
-    hipLaunchKernelGGL((k_hop<T, FORM, NV, true, false>), grid, block, 0, s, A, cfg.xcd_remap, order);
-  else if (filt)
-    hipLaunchKernelGGL((k_hop<T, FORM, NV, false, true>), grid, block, 0, s, A, cfg.xcd_remap, order);
-  else
-    hipLaunchKernelGGL((k_hop<T, FORM, NV, false, false>), grid, block, 0, s, A, cfg.xcd_remap, order);
-  return hipGetLastError();
-}
-
-template <typename T, int FORM>
-static hipError_t launch_hop_nv(const HopArgs<T>& A, const HopConfig& cfg, hipStream_t s) {
-  if (cfg.nv == 2) return launch_hop_form<T, FORM, 2>(A, cfg, s);
-  return launch_hop_form<T, FORM, 4>(A, cfg, s);
-}
-
-template <typename T>
-hipError_t launch_hop(const HopArgs<T>& A, const HopConfig& cfg, hipStream_t s) {
-  if (A.n_rhs == 0 || A.g.V == 0) return hipSuccess;
-  if (cfg.form == kFormMatrix) return launch_hop_nv<T, kFormMatrix>(A, cfg, s);
-  if (cfg.form == kFormAdjoint) return launch_hop_nv<T, kFormAdjoint>(A, cfg, s);
-  return launch_hop_nv<T, kFormStream>(A, cfg, s);
-}
-template hipError_t launch_hop<double>(const HopArgs<double>&, const HopConfig&, hipStream_t);
-template hipError_t launch_hop<float>(const HopArgs<float>&, const HopConfig&, hipStream_t);
 
 // ------------------------------------------------------------------------------------------
 // element-wise helpers
