@@ -15,9 +15,19 @@ the rational-solve workload, kappa = 0.9), through every stage of the path:
 
 `value` is the Laplacian throughput of the whole step: lattice sites times link fields
 passed through Delta, divided by the step time (every other kernel of the step counts
-against it).  Extra fields report the time to 1e-10 of the rational solve alone, FP64
-against mixed precision, for one and eight momentum fields, and the stencil on the
-32^3 x 64 lattice, where the working set exceeds every cache.
+against it).  The step time comes from a pass without instrumentation; `roofline` and
+`kernel_time_share` from a second pass of the same steps with HIP events around every launch.
+
+Extra fields (skipped with --no-extras):
+  D1  the Laplacian alone at 16^4, 24^4 and 32^3 x 64, FP64 and FP32 (working sets under the
+      256 MB Infinity Cache timed over rotating buffer sets of >= 1 GiB), against 8 TB/s and
+      against a measured 1 GiB copy;
+  D2  the rational solve alone, time to FP64 true residual 1e-10, FP64 against mixed precision,
+      12 poles, kappa 0.9 and 0.5, one and eight momentum fields (median of 5);
+  D3  the batched power spectrum at 24^4 (32 sources, degree 256, 64 windows), Haar and U = 1;
+  D4  the 8-pole kinetic force at 16^4;
+  D5  the full force step at 32^3 x 64: 16-pole kinetic force of 8 momentum fields, then the
+      128-window degree-256 power spectrum of the 8 forces, FP64 against mixed precision.
 """
 from __future__ import annotations
 
@@ -132,16 +142,23 @@ def main():
     for _ in range(args.warmup):
         last = step()
     torch.cuda.synchronize()
-    api.profile_enable(True)
     log(f"timing {args.steps} steps")
     t0 = time.perf_counter()
     for _ in range(args.steps):
         last = step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    ms_step = (t1 - t0) / args.steps * 1e3
+    # the same steps again with HIP events around every launch of the instrumented kernel classes
+    # (the events add launch gaps, so the step time above is taken without them)
+    api.profile_enable(True)
+    tp0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms_step_profiled = (time.perf_counter() - tp0) / args.steps * 1e3
     prof = {c: api.profile_read(c) for c in api.PROF_CLASSES}
     api.profile_enable(False)
-    ms_step = (t1 - t0) / args.steps * 1e3
     fields_per_step = prof["stencil"]["items"] / args.steps
     value = V * fields_per_step / (ms_step * 1e-3) / 1e9
     log(f"{ms_step:.2f} ms/step, {fields_per_step:.0f} link-field stencil applications per step")
@@ -154,7 +171,9 @@ def main():
                 "unit": "GB/s", "frac": round(d["gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "traffic_source": traffic_src,
                 "avg_launch_ms": d["avg_ms"], "bytes_per_launch": d["bytes"] / max(d["launches"], 1),
-                "launches": d["launches"]}
+                "launches": d["launches"],
+                "measured_over": f"a second pass of the {args.steps} timed steps with HIP events "
+                                 f"({ms_step_profiled:.3f} ms/step with the events)"}
     shares = {c: round(prof[c]["ms"] / max(sum(p["ms"] for p in prof.values()), 1e-12), 4) for c in prof}
 
     extras = {}
@@ -191,9 +210,73 @@ def main():
     print(json.dumps(result), flush=True)
 
 
-def run_extras(api, inputs, torch, np, dev, L, U_aos, Ud, Pd):
+def _median_ms(fn, torch, reps=5):
+    """Median wall time of reps calls after one warm-up (each call synchronized)."""
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    out = None
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t0) * 1e3)
+    ts.sort()
+    return ts[len(ts) // 2], out
+
+
+def copy_bandwidth(torch, dev):
+    """Plain 1 GiB device copy: the bandwidth the memory system delivers to a streaming kernel."""
+    a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    ms, _ = _median_ms(lambda: b.copy_(a), torch, reps=5)
+    del a, b
+    return {"bytes": 2 * (1 << 30), "ms": round(ms, 4), "GBs": round(2 * (1 << 30) / (ms * 1e-3) / 1e9, 1)}
+
+
+def d1_laplacian(api, inputs, torch, dev, copy_gbs):
+    """Laplacian on one link field: 16^4, 24^4, 32^3x64, FP64 and FP32, eps=0.4 links.  A working
+    set under 256 MB (the Infinity Cache) is timed over rotating buffer sets of >= 1 GiB."""
     out = {}
-    # rational solve alone: time to 1e-10, FP64 against mixed, 1 and 8 momentum fields
+    for L in ((16, 16, 16, 16), (24, 24, 24, 24), (32, 32, 32, 64)):
+        V = api.volume(L)
+        U = inputs.random_links(L, "eps", 0.4, seed=1).to(dev)
+        F = inputs.gaussian_fields(L, 1, seed=1).to(dev)
+        for dt, name, ts in ((torch.float64, "fp64", 8), (torch.float32, "fp32", 4)):
+            Ud = api.pack_links(L, U, dt)
+            Fd = F.to(dt)
+            cfg, _ = api.autotune_laplacian(L, Ud, Fd, reps=3)
+            set_bytes = 136 * ts * V
+            nset = 1 if set_bytes >= (256 << 20) else -(-(1 << 30) // set_bytes)
+            sets = [(Ud, Fd, torch.empty_like(Fd))]
+            for _ in range(nset - 1):
+                sets.append((Ud.clone(), Fd.clone(), torch.empty_like(Fd)))
+            reps = max(20, 2 * nset)
+            for k in range(nset):
+                api.laplacian_apply(L, sets[k][0], sets[k][1], out=sets[k][2])
+            torch.cuda.synchronize()
+            api.profile_enable(True)
+            for r in range(reps):
+                u, x, y = sets[r % nset]
+                api.laplacian_apply(L, u, x, out=y)
+            torch.cuda.synchronize()
+            p = api.profile_read("stencil")
+            api.profile_enable(False)
+            gsite = V / (p["avg_ms"] * 1e-3) / 1e9
+            key = "x".join(map(str, L))
+            out.setdefault(key, {})[name] = {
+                "gsite_s": round(gsite, 3), "avg_ms": round(p["avg_ms"], 4), "achieved_GBs": round(p["gbs"], 1),
+                "hbm_frac": round(p["gbs"] / HBM_PEAK_GBS, 4), "copy_frac": round(p["gbs"] / copy_gbs, 4),
+                "bytes_per_site": 136 * ts, "rotating_sets": nset,
+                "config": dict(zip(("form", "block", "xcd_remap", "nv", "order", "walk"), cfg))}
+            log(f"D-1 {key} {name}: {out[key][name]}")
+            del sets, Ud, Fd
+        del U, F
+    return out
+
+
+def d2_solves(api, inputs, torch, dev, L, Ud, Pd):
+    """Rational solve alone, time to FP64 true residual 1e-10: FP64 against mixed precision."""
     solves = {}
     P8 = inputs.gaussian_fields(L, 8, seed=22).to(dev)
     for kappa in (0.9, 0.5):
@@ -202,78 +285,119 @@ def run_extras(api, inputs, torch, np, dev, L, U_aos, Ud, Pd):
             row = {}
             for mode, name in ((0, "fp64"), (1, "mixed")):
                 sv = api.Solver(tol=1e-10, mode=mode)
-                api.rational_apply(L, Ud, src, rat, sv)          # warm-up (workspace, tuner)
-                torch.cuda.synchronize()
-                reps = 3
-                t0 = time.perf_counter()
-                for _ in range(reps):
-                    o = api.rational_apply(L, Ud, src, rat, sv)
-                torch.cuda.synchronize()
-                row[f"{name}_ms"] = round((time.perf_counter() - t0) / reps * 1e3, 3)
+                ms, o = _median_ms(lambda: api.rational_apply(L, Ud, src, rat, sv), torch)
                 st = o["stats"]
+                row[f"{name}_ms"] = round(ms, 3)
                 row[f"{name}_iters"] = st["iters"]
+                row[f"{name}_fp64_iters"] = st["fp64_iters"]
                 row[f"{name}_refine_iters"] = st["refine_iters"]
                 row[f"{name}_true_relres_max"] = st["true_relres_max"]
                 if mode == 1:
                     row["mixed_reliable_updates"] = st["reliable_updates"]
             row["mixed_speedup"] = round(row["fp64_ms"] / row["mixed_ms"], 3)
             solves[f"kappa{kappa}_nrhs{n}"] = row
-            log(f"solve kappa={kappa} n={n}: {row}")
-    out["rational_solve_time_to_1e-10"] = solves
-    del P8
+            log(f"D-2 solve kappa={kappa} n={n}: {row}")
+    return solves
 
-    # the stencil where nothing is cache resident: 32^3 x 64, FP64 and FP32
-    Lb = (32, 32, 32, 64)
-    Vb = api.volume(Lb)
-    log("generating 32^3x64 inputs")
-    Ub = inputs.random_links(Lb, "haar", seed=5).to(dev)
-    Fb = inputs.gaussian_fields(Lb, 1, seed=5).to(dev)
-    sten = {}
-    for dt, name, ts in ((torch.float64, "fp64", 8), (torch.float32, "fp32", 4)):
-        Ubd = api.pack_links(Lb, Ub, dt)
-        Fbd = Fb.to(dt)
-        cfg, _ = api.autotune_laplacian(Lb, Ubd, Fbd, reps=3)
-        y = torch.empty_like(Fbd)
-        for _ in range(3):
-            api.laplacian_apply(Lb, Ubd, Fbd, out=y)
+
+def d3_spectrum(api, inputs, torch, dev):
+    """Batched power spectrum at 24^4: 32 Gaussian sources, degree 256, 64 windows, FP32 stencil
+    with FP64 moments; Haar links and the U = 1 control."""
+    L = (24, 24, 24, 24)
+    out = {}
+    F = inputs.gaussian_fields(L, 32, seed=3).to(dev).float()
+    for kind in ("haar", "unit"):
+        U32 = api.pack_links(L, inputs.random_links(L, kind, seed=3).to(dev), torch.float32)
+        api.autotune_laplacian(L, U32, F, reps=2)
+        api.power_spectrum(L, U32, F, 256, 64)
         torch.cuda.synchronize()
         api.profile_enable(True)
-        reps = 20
-        for _ in range(reps):
-            api.laplacian_apply(Lb, Ubd, Fbd, out=y)
+        t0 = time.perf_counter()
+        api.power_spectrum(L, U32, F, 256, 64)
         torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
         p = api.profile_read("stencil")
         api.profile_enable(False)
-        gsite = Vb / (p["avg_ms"] * 1e-3) / 1e9
-        sten[name] = {"gsite_s": round(gsite, 3), "avg_ms": round(p["avg_ms"], 4),
-                      "achieved_GBs": round(p["gbs"], 1), "hbm_frac": round(p["gbs"] / HBM_PEAK_GBS, 4),
-                      "bytes_per_site": 136 * ts,
-                      "config": {"form": cfg[0], "block": cfg[1], "xcd_remap": cfg[2], "nv": cfg[3],
-                                 "order": cfg[4], "walk": cfg[5]}}
-        log(f"stencil 32^3x64 {name}: {sten[name]}")
-        del Ubd, Fbd, y
-    out["laplacian_32x32x32x64"] = sten
+        out[kind] = {"ms": round(ms, 3), "sweeps": p["launches"], "stencil_ms": round(p["ms"], 3),
+                     "stencil_GBs": round(p["gbs"], 1), "hbm_frac": round(p["gbs"] / HBM_PEAK_GBS, 4),
+                     "gsite_rhs_s": round(api.volume(L) * p["items"] / (ms * 1e-3) / 1e9, 3)}
+        log(f"D-3 spectrum 24^4 {kind}: {out[kind]}")
+        del U32
+    return out
 
-    # the rational solve where nothing is cache resident: 16 poles, one momentum field
-    rat16 = api.rational_kappa(0.9, 16)
-    Ubd = api.pack_links(Lb, inputs.random_links(Lb, "eps", 0.4, seed=2).to(dev))
-    Pb = inputs.gaussian_fields(Lb, 1, seed=2).to(dev)
+
+def d4_force(api, inputs, torch, dev):
+    """Kinetic force at 16^4, eps=0.4: 8 poles kappa=0.9, both solves to 1e-10, link derivative."""
+    L = (16, 16, 16, 16)
+    Ud = api.pack_links(L, inputs.random_links(L, "eps", 0.4, seed=4).to(dev))
+    P = inputs.gaussian_fields(L, 1, seed=4).to(dev)
+    rat = api.rational_kappa(0.9, 8)
     row = {}
     for mode, name in ((0, "fp64"), (1, "mixed")):
         sv = api.Solver(tol=1e-10, mode=mode)
-        api.rational_apply(Lb, Ubd, Pb, rat16, sv)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        o = api.rational_apply(Lb, Ubd, Pb, rat16, sv)
-        torch.cuda.synchronize()
-        row[f"{name}_ms"] = round((time.perf_counter() - t0) * 1e3, 3)
-        st = o["stats"]
-        row[f"{name}_iters"] = st["iters"]
-        row[f"{name}_refine_iters"] = st["refine_iters"]
-        row[f"{name}_true_relres_max"] = st["true_relres_max"]
+        ms, o = _median_ms(lambda: api.kinetic_force(L, Ud, P, rat, sv), torch)
+        row[f"{name}_ms"] = round(ms, 3)
+        row[f"{name}_iters"] = o["stats"]["iters"]
     row["mixed_speedup"] = round(row["fp64_ms"] / row["mixed_ms"], 3)
-    out["rational_solve_32x32x32x64_kappa0.9_16poles"] = row
-    log(f"solve 32^3x64: {row}")
+    log(f"D-4 force 16^4: {row}")
+    return row
+
+
+def d5_force_step(api, inputs, torch, dev):
+    """Full force step at 32^3 x 64, eps=0.4: for 8 momentum fields (two per call), the 16-pole
+    kappa=0.9 kinetic force (two multi-shift solves to 1e-10 and the link derivative), then the
+    128-window degree-256 power spectrum of the 8 forces (FP32 stencil, FP64 moments)."""
+    L = (32, 32, 32, 64)
+    V = api.volume(L)
+    U = inputs.random_links(L, "eps", 0.4, seed=5).to(dev)
+    Ud = api.pack_links(L, U)
+    U32 = api.pack_links(L, U, torch.float32)
+    del U
+    P = inputs.gaussian_fields(L, 8, seed=5).to(dev)
+    rat = api.rational_kappa(0.9, 16)
+    need = max(api.workspace_bytes(6, L, 0, 2, 16, 0, m) for m in (0, 1))
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    row = {"workspace_GiB": round(need / 2**30, 1)}
+    for mode, name in ((0, "fp64"), (1, "mixed")):
+        sv = api.Solver(tol=1e-10, mode=mode)
+        forces = torch.empty((8, 4, 8, V), dtype=torch.float32, device=dev)
+        torch.cuda.synchronize()
+        api.profile_enable(True)
+        t0 = time.perf_counter()
+        iters = 0
+        for c in range(4):
+            o = api.kinetic_force(L, Ud, P[2 * c:2 * c + 2], rat, sv, per_rhs=True, ws=ws)
+            forces[2 * c:2 * c + 2] = o["dK"].float()
+            iters += o["stats"]["iters"]
+            del o
+        t1 = time.perf_counter()
+        api.power_spectrum(L, U32, forces, 256, 128)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        prof = {c: api.profile_read(c) for c in api.PROF_CLASSES}
+        api.profile_enable(False)
+        row[name] = {"ms_per_force": round((t1 - t0) * 1e3 / 8, 3), "spectrum_ms": round((t2 - t1) * 1e3, 3),
+                     "total_ms": round((t2 - t0) * 1e3, 3), "solver_iters": iters,
+                     "stencil_GBs": round(prof["stencil"]["gbs"], 1),
+                     "stencil_hbm_frac": round(prof["stencil"]["gbs"] / HBM_PEAK_GBS, 4),
+                     "kernel_ms": {c: round(prof[c]["ms"], 2) for c in prof}}
+        log(f"D-5 force step 32^3x64 {name}: {row[name]}")
+        del forces
+    row["mixed_speedup"] = round(row["fp64"]["total_ms"] / row["mixed"]["total_ms"], 3)
+    del ws
+    return row
+
+
+def run_extras(api, inputs, torch, np, dev, L, U_aos, Ud, Pd):
+    out = {}
+    cp = copy_bandwidth(torch, dev)
+    out["copy_1GiB"] = cp
+    log(f"copy: {cp}")
+    out["D1_laplacian"] = d1_laplacian(api, inputs, torch, dev, cp["GBs"])
+    out["D2_rational_solve_time_to_1e-10"] = d2_solves(api, inputs, torch, dev, L, Ud, Pd)
+    out["D3_power_spectrum_24x24x24x24"] = d3_spectrum(api, inputs, torch, dev)
+    out["D4_kinetic_force_16x16x16x16"] = d4_force(api, inputs, torch, dev)
+    out["D5_force_step_32x32x32x64"] = d5_force_step(api, inputs, torch, dev)
     return out
 
 

@@ -266,7 +266,8 @@ rmh_status rmh_kinetic_force(const int32_t L[4], const double* U, const double* 
 /* Fix the stencil launch configuration used for lattice L, dtype and launches over n_rhs link
  * fields: form 0 = adjoint 8x8 action R(U) built per hop, 1 = 3x3 matrix products U phi U^dag,
  * 2 = R(U) built and applied two columns at a time; block = 64, 128 or 256 threads; xcd_remap = 1
- * maps consecutive lattice blocks onto one XCD (L2 locality); nv = 4 or 2 directions per thread;
+ * maps consecutive lattice blocks onto one XCD (L2 locality); nv = 4, 2 or 1 directions per thread
+ * (1 with form 1 only, and block * nv / 4 a multiple of the 64-wide wave; else RMH_E_ARG);
  * order = 1 visits the blocks with x3 fastest (x2/x3 neighbours resident together; used when
  * L0*L1 is a multiple of the sites per block); walk = K > 0 makes each thread walk K consecutive
  * x3 sites carrying the x3 neighbours in registers (used when K divides L3).  Every configuration

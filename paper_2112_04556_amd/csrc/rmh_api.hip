@@ -232,6 +232,7 @@ struct Engine {
   float* p32 = nullptr;
   float* Ap32 = nullptr;
   double* r64 = nullptr;   // [n_rhs] FP64 residual of a reliable update (mixed)
+  float* x_lo = nullptr;   // [n_rhs] FP32 increment of the seed's solution since the last reliable update
   char* ring = nullptr;    // [n_rhs][nslot] seed residuals, FP64-sized slots
   double* pj = nullptr;    // [n_rhs][n_shift] shift directions at the segment start (n_shift > 1)
   double* coef = nullptr;  // [n_rhs][n_shift][2 + 2 nslot]
@@ -284,6 +285,7 @@ void plan_engine(Carver& c, Engine& e, const Geom& g, int32_t n_rhs, int32_t n_s
     e.p32 = c.take<float>(nr * n);
     e.Ap32 = c.take<float>(nr * n);
     e.r64 = c.take<double>(nr * n);
+    e.x_lo = c.take<float>(nr * n);
   }
   e.ring = c.take<char>(nr * e.nslot * n * 8);
   if (n_shift > 1) e.pj = c.take<double>(np * n);
@@ -407,11 +409,12 @@ rmh_status engine_solve(Engine& e, const double* U64, const float* U32, const do
   cg32.nblk_ru = nblk_64;
 
   bool fp32_phase = mixed && !(switch_rel > 0.0);
-  // a seed updated each iteration starts from zero; the flushes write x of the other shifts
+  // a seed solution kept outside the ring starts from zero; the flushes write x of the others
   if (ns == 1)
     HIP_TRY(launch_zero(x_hi, (size_t)nr * n * 8, s));
   else if (fp32_phase)
     for (int v = 0; v < nr; ++v) HIP_TRY(launch_zero(x_hi + ((size_t)v * ns + seed[v]) * n, (size_t)n * 8, s));
+  if (fp32_phase) HIP_TRY(launch_zero(e.x_lo, (size_t)nr * n * 4, s));
   if (fp32_phase)
     HIP_TRY(launch_cg_start<float>(b, e.ring, e.p32, nr, cg32.ring_rhs_bytes, n, s));
   else
@@ -514,7 +517,7 @@ rmh_status engine_solve(Engine& e, const double* U64, const float* U32, const do
         HIP_TRY(launch_cg_beta(cg64, 0, s));
         {
           ProfScope ps(RMH_PROF_CG_RESIDUAL, (double)nr * n * 3 * 8.0, s, nr);
-          HIP_TRY(launch_cg_p_update<double>(cg64, e.ring, e.p64, n, s));
+          HIP_TRY(launch_cg_p_update<double>(cg64, e.ring, e.p64, nullptr, n, s));
         }
       } else {
         {
@@ -523,16 +526,18 @@ rmh_status engine_solve(Engine& e, const double* U64, const float* U32, const do
         }
         HIP_TRY(launch_cg_alpha(cg32, s));
         {
-          ProfScope ps(RMH_PROF_CG_RESIDUAL, (double)nr * n * (3 * 4.0 + 20.0), s, nr);
-          HIP_TRY(launch_cg_r_update<float>(cg32, e.ring, e.Ap32, e.p32, x_hi, e.r64, n, s));
+          ProfScope ps(RMH_PROF_CG_RESIDUAL, (double)nr * n * 3 * 4.0, s, nr);
+          HIP_TRY(launch_cg_r_update<float>(cg32, e.ring, e.Ap32, e.p32, nullptr, e.r64, n, s));
         }
         HIP_TRY(launch_cg_beta(cg32, 1, s));
         {
-          ProfScope ps(RMH_PROF_CG_RESIDUAL, (double)nr * n * 3 * 4.0, s, nr);
-          HIP_TRY(launch_cg_p_update<float>(cg32, e.ring, e.p32, n, s));
+          ProfScope ps(RMH_PROF_CG_RESIDUAL, (double)nr * n * 5 * 4.0, s, nr);
+          HIP_TRY(launch_cg_p_update<float>(cg32, e.ring, e.p32, e.x_lo, n, s));
         }
         // reliable update decided by this iteration's beta kernel (blocks of rhs without a
-        // pending update exit at once); its bytes are added once the update count is known
+        // pending update exit at once): the seed solution into FP64, then its FP64 residual;
+        // the stencil's bytes are added once the update count is known
+        HIP_TRY(launch_cg_xfold(cg32, e.x_lo, x_hi, 0, n, s));
         {
           ProfScope ps(RMH_PROF_STENCIL, 0.0, s, 0.0);
           HIP_TRY(launch_hop<double>(hr, c64, s));
@@ -555,11 +560,13 @@ rmh_status engine_solve(Engine& e, const double* U64, const float* U32, const do
       // switch to FP32: the remaining increments are small, so their rounding no longer matters
       RMH_TRY(flush(false));
       HIP_TRY(launch_cg_to_f32(cg64, e.ring, e.p64, e.p32, n, s));
+      HIP_TRY(launch_zero(e.x_lo, (size_t)nr * n * 4, s));
       fp32_phase = true;
     }
     if (it > maxiter + 2 * check_every) break;  // safety net; the device sets NoConv first
   }
   RMH_TRY(flush(true));
+  if (fp32_phase) HIP_TRY(launch_cg_xfold(cg32, e.x_lo, x_hi, 1, n, s));
   RMH_TRY(d2h(st.data(), e.sc, e.state_bytes, s));
   if (log_level() > 0) {
     for (int v = 0; v < nr; ++v)
@@ -636,9 +643,8 @@ struct RefinePlan {
   int32_t nb;
 };
 
-int32_t refine_batch(int32_t n_rhs, int32_t n_shift) {
-  return std::max(1, std::min(n_rhs * n_shift, std::max(n_rhs, n_shift)));
-}
+// pairs refined together (a refinement is rare; its buffers cost some 11 link fields a pair)
+int32_t refine_batch(int32_t n_rhs, int32_t n_shift) { return std::max(1, std::min(n_rhs * n_shift, 4)); }
 
 void plan_refine(Carver& c, RefinePlan& rp, const Geom& g, int32_t nb, int32_t mode) {
   const int64_t n = field_reals(g);
@@ -1442,7 +1448,8 @@ rmh_status rmh_tune_set(const int32_t L[4], int32_t dtype, int32_t n_rhs, int32_
   RMH_TRY(check_dtype(dtype));
   if (form < kFormAdjoint || form > kFormStream) return fail(RMH_E_ARG, "form must be 0, 1 or 2");
   if (block != 64 && block != 128 && block != 256) return fail(RMH_E_ARG, "block must be 64, 128 or 256");
-  if (nv != 2 && nv != 4) return fail(RMH_E_ARG, "nv must be 2 or 4");
+  if (nv != 1 && nv != 2 && nv != 4) return fail(RMH_E_ARG, "nv must be 1, 2 or 4");
+  if (nv == 1 && form != kFormMatrix) return fail(RMH_E_ARG, "nv = 1 needs form 1 (3x3 products)");
   if ((block * nv / 4) % 64) return fail(RMH_E_ARG, "block * nv / 4 must be a multiple of 64");
   HopConfig c;
   c.form = form;
@@ -1475,7 +1482,7 @@ rmh_status rmh_autotune_laplacian(const int32_t L[4], const void* U, int32_t dty
   float bt = 1e30f;
   rmh_status st = RMH_OK;
   for (int form = 0; form < 3 && st == RMH_OK; ++form)
-    for (int nv : {4, 2})
+    for (int nv : {4, 2, 1})
     for (int block : {64, 128, 256})
     for (int walk : {0, 4, 8, 16})
     for (int order = 0; order < 2 && st == RMH_OK; ++order) {
@@ -1490,6 +1497,7 @@ rmh_status rmh_autotune_laplacian(const int32_t L[4], const void* U, int32_t dty
         if (order && !hop_order_ok(g, c)) continue;
         if (walk && (order || !hop_walk_ok(g, c))) continue;
         if ((block * nv / 4) % 64) continue;  // direction groups must be whole waves
+        if (nv == 1 && form != kFormMatrix) continue;
         tune_store(g, dtype, n_rhs, c);
         st = rmh_laplacian_apply(L, U, dtype, x, y, n_rhs, 0.0, stream);  // warm-up
         if (st != RMH_OK) break;

@@ -113,8 +113,9 @@ hipError_t launch_dot(const T* a, const T* b, int64_t n_reals, int32_t n, double
 //   x_j = x_j0 + a_j p_j0 + sum_i d_ji r_i,   p_j = b_j p_j0 + sum_i e_ji r_i,
 // with the scalar coefficients updated each iteration on the device and the combination folded
 // into x_j, p_j (flush) when the ring is full, at a precision switch and at the end.  The seed's
-// own solution is updated each iteration instead where reliable updates need it (FP32 phase)
-// and in single-shift engines.
+// own solution is kept outside the ring where reliable updates read it: in FP32 phases it
+// accumulates in an FP32 vector that each reliable update moves into FP64; single-shift engines
+// update it each iteration in FP64 phases.
 struct CgDev {
   int32_t n_rhs, n_shift;
   double* sc;            // [n_rhs][kScN]
@@ -132,7 +133,7 @@ struct CgDev {
   int64_t ring_rhs_bytes;  // ring bytes per rhs (FP32 slots are half as long, twice as many)
   int32_t ring_on;       // shift solutions through the ring (n_shift > 1); else the seed's
                          // solution is updated each iteration and nslot = 2
-  int32_t seed_explicit; // the seed's solution is updated each iteration (single shift, FP32 phase)
+  int32_t seed_explicit; // the seed's solution is kept outside the ring (single shift, FP32 phase)
   int32_t nblk_hop, nblk_e, nblk_ru;
 };
 // the residual ring: per rhs ring_rhs_bytes holding nslot FP64 slots of n_reals, or in FP32
@@ -164,9 +165,13 @@ hipError_t launch_cg_start(const double* b, void* ring, T* p, int32_t nr, int64_
 template <typename T>
 hipError_t launch_cg_r_update(const CgDev& cg, void* ring, const T* Ap, const T* p, double* x_hi,
                               const double* r64, int64_t n_reals, hipStream_t s);
-// seed direction p = r' + beta p
+// seed direction p = r' + beta p (while the rhs runs); with x_lo non-null also x_lo += alpha p
+// (the FP32 increment of the seed's solution, FP32 phase)
 template <typename T>
-hipError_t launch_cg_p_update(const CgDev& cg, const void* ring, T* p, int64_t n_reals, hipStream_t s);
+hipError_t launch_cg_p_update(const CgDev& cg, const void* ring, T* p, float* x_lo, int64_t n_reals,
+                              hipStream_t s);
+// x_hi[seed] += x_lo, x_lo = 0 for the rhs with a pending reliable update (all: every rhs)
+hipError_t launch_cg_xfold(const CgDev& cg, float* x_lo, double* x_hi, int32_t all, int64_t n_reals, hipStream_t s);
 // fold the segment into x_j (and p_j unless final) of every shift updated in it (p_j0 is read
 // only where its coefficient is nonzero: before the first flush it holds nothing), then reset
 // the coefficients and restart the ring at the current residual

@@ -537,27 +537,64 @@ template hipError_t launch_cg_r_update<float>(const CgDev&, void*, const float*,
                                               const double*, int64_t, hipStream_t);
 
 template <typename T>
-__global__ void k_cg_p(CgDev cg, const void* ring, T* __restrict__ p, int64_t n) {
+__global__ void k_cg_p(CgDev cg, const void* ring, T* __restrict__ p, float* __restrict__ x_lo, int64_t n) {
   const int32_t v = blockIdx.y;
   const int32_t* fl = cg.flags + (int64_t)v * kFlN;
-  if (fl[kFlLive] == 0 || fl[kFlRun] == 0) return;
+  if (fl[kFlLive] == 0) return;
+  const int32_t upd_p = fl[kFlRun];
+  if (!upd_p && !x_lo) return;
   const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
   if (i0 >= n) return;
   const T* r = ring_slot<T>(ring, cg.ring_rhs_bytes, v, (fl[kFlBase] + fl[kFlM]) % cg.nslot, n);
   const T beta = (T)cg.sc[(int64_t)v * kScN + kScBetaPrev];
+  const float alpha = (float)cg.sc[(int64_t)v * kScN + kScAlpha];
   T* pv = p + (int64_t)v * n;
+  float* xv = x_lo ? x_lo + (int64_t)v * n : nullptr;
+  T pold[4];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) pv[i0 + k] = fmadd(beta, pv[i0 + k], r[i0 + k]);
+  for (int k = 0; k < 4; ++k) pold[k] = pv[i0 + k];
+  if (xv) {
+    // the seed's increment of this iteration, alpha p, in FP32 until the next reliable update
+#pragma unroll
+    for (int k = 0; k < 4; ++k) xv[i0 + k] = fmaf(alpha, (float)pold[k], xv[i0 + k]);
+  }
+  if (upd_p) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pv[i0 + k] = fmadd(beta, pold[k], r[i0 + k]);
+  }
 }
 
 template <typename T>
-hipError_t launch_cg_p_update(const CgDev& cg, const void* ring, T* p, int64_t n_reals, hipStream_t s) {
+hipError_t launch_cg_p_update(const CgDev& cg, const void* ring, T* p, float* x_lo, int64_t n_reals,
+                              hipStream_t s) {
   dim3 grid(elem_num_blocks(n_reals), cg.n_rhs);
-  hipLaunchKernelGGL((k_cg_p<T>), grid, dim3(kBlock), 0, s, cg, ring, p, n_reals);
+  hipLaunchKernelGGL((k_cg_p<T>), grid, dim3(kBlock), 0, s, cg, ring, p, x_lo, n_reals);
   return hipGetLastError();
 }
-template hipError_t launch_cg_p_update<double>(const CgDev&, const void*, double*, int64_t, hipStream_t);
-template hipError_t launch_cg_p_update<float>(const CgDev&, const void*, float*, int64_t, hipStream_t);
+
+// x_hi[seed] += x_lo, x_lo = 0: for the rhs with a pending reliable update, or for all
+__global__ void k_cg_xfold(CgDev cg, float* __restrict__ x_lo, double* __restrict__ x_hi, int32_t all, int64_t n) {
+  const int32_t v = blockIdx.y;
+  if (!all && cg.flags[(int64_t)v * kFlN + kFlNeedRU] == 0) return;
+  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  if (i0 >= n) return;
+  float* xl = x_lo + (int64_t)v * n;
+  double* xh = x_hi + ((int64_t)v * cg.n_shift + cg.seed[v]) * n;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    xh[i0 + k] += (double)xl[i0 + k];
+    xl[i0 + k] = 0.0f;
+  }
+}
+
+hipError_t launch_cg_xfold(const CgDev& cg, float* x_lo, double* x_hi, int32_t all, int64_t n_reals, hipStream_t s) {
+  dim3 grid(elem_num_blocks(n_reals), cg.n_rhs);
+  hipLaunchKernelGGL(k_cg_xfold, grid, dim3(kBlock), 0, s, cg, x_lo, x_hi, all, n_reals);
+  return hipGetLastError();
+}
+
+template hipError_t launch_cg_p_update<double>(const CgDev&, const void*, double*, float*, int64_t, hipStream_t);
+template hipError_t launch_cg_p_update<float>(const CgDev&, const void*, float*, float*, int64_t, hipStream_t);
 
 // One element per thread: the segment's residuals at this element are loaded once and every
 // non-seed shift touched in the segment is folded from registers.

@@ -336,8 +336,14 @@ static hipError_t launch_hop_form(const HopArgs<T>& A, const HopConfig& cfg, hip
 
 template <typename T, int FORM>
 static hipError_t launch_hop_nv(const HopArgs<T>& A, const HopConfig& cfg, hipStream_t s) {
+  if (cfg.nv == 1) {
+    // one direction per thread: only the 3x3 form, whose work does not repeat across directions
+    if constexpr (FORM == kFormMatrix) return launch_hop_form<T, FORM, 1>(A, cfg, s);
+    return hipErrorInvalidValue;
+  }
   if (cfg.nv == 2) return launch_hop_form<T, FORM, 2>(A, cfg, s);
-  return launch_hop_form<T, FORM, 4>(A, cfg, s);
+  if (cfg.nv == 4) return launch_hop_form<T, FORM, 4>(A, cfg, s);
+  return hipErrorInvalidValue;
 }
 
 template <typename T>

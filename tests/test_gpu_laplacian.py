@@ -55,8 +55,11 @@ def test_laplacian_fp64_parity(L, kind, seed, shift):
     U, P, Ud, Pd = setup(L, kind, 0.5, seed, n=2)
     ref = olap.laplacian(U, P, L, shift)
     for form in (0, 1, 2):
-        for nv, walk in ((4, 0), (2, 0), (2, L[3]), (4, 1)):
-            api.tune_set(L, torch.float64, 2, form, 128, 1, nv, 1, walk)
+        shapes = ((4, 0, 128), (2, 0, 128), (2, L[3], 128), (4, 1, 128))
+        if form == 1:
+            shapes += ((1, 0, 256), (1, L[3], 256))
+        for nv, walk, block in shapes:
+            api.tune_set(L, torch.float64, 2, form, block, 1, nv, 1, walk)
             y = api.laplacian_apply(L, Ud, Pd, shift).cpu().numpy()
             assert rel_max(y, ref) <= 1e-12, (form, nv, walk)
     api.tune_clear()
@@ -88,7 +91,7 @@ def test_laplacian_configs_batched_and_deterministic(dtype):
         outs = []
         for block in (64, 128, 256):
             for xcd, order, walk in ((0, 0, 0), (1, 1, 0), (0, 1, 0), (1, 0, 2), (0, 0, 3), (0, 0, 6)):
-                for nv in (4, 2):
+                for nv in ((4, 2, 1) if form == 1 else (4, 2)):
                     if (block * nv // 4) % 64:
                         # a direction group must span whole wavefronts
                         with pytest.raises(RmhError):
@@ -114,7 +117,8 @@ def test_laplacian_empty_batch_and_autotune():
     empty = torch.empty((0, 4, 8, api.volume(L)), dtype=torch.float64, device=dev())
     api.laplacian_apply(L, Ud, empty)
     (form, block, xcd, nv, order, walk), ms = api.autotune_laplacian(L, Ud, Pd, reps=2)
-    assert form in (0, 1, 2) and block in (64, 128, 256) and nv in (2, 4) and ms > 0
+    assert form in (0, 1, 2) and block in (64, 128, 256) and nv in (1, 2, 4) and ms > 0
+    assert nv != 1 or form == 1
     U, P, _, _ = setup(L, "eps", 0.3, 1, n=1)
     assert rel_max(api.laplacian_apply(L, Ud, Pd).cpu().numpy(), olap.laplacian(U, P, L)) <= 1e-12
     api.tune_clear()
