@@ -128,7 +128,9 @@ typedef enum {
   RMH_OP_CHEB_FILTER = 3,
   RMH_OP_RATIONAL_APPLY = 4,
   RMH_OP_RATIONAL_APPLY_BWD = 5,
-  RMH_OP_KINETIC_FORCE = 6
+  RMH_OP_KINETIC_FORCE = 6,
+  RMH_OP_CHEB_FILTER_BWD = 7,
+  RMH_OP_POWER_SPECTRUM_BWD = 8
 } rmh_op;
 
 /* ---------------------------------------------------------------------------------------- */
@@ -211,9 +213,26 @@ rmh_status rmh_trace_moments_free(const int32_t L[4], int32_t degree, double* tr
 rmh_status rmh_cheb_filter(const int32_t L[4], const void* U, int32_t dtype, const void* x, int32_t n_rhs,
                            const rmh_cheb* cheb, void* y, void* ws, size_t ws_bytes, rmh_stream stream);
 
-/* Backward calls of the Chebyshev filters: not built. */
-rmh_status rmh_cheb_filter_bwd(void);
-rmh_status rmh_power_spectrum_bwd(void);
+/* Vector-Jacobian product of the filters y_w = B_w x (section 2, the bandpass of Eq. 4) with
+ * cotangents gy (device FP64 [n_windows][n_rhs][4][8][V]):
+ * grad_x (optional, device FP64 [n_rhs][4][8][V]) = sum_w B_w gy_w (B_w is symmetric);
+ * grad_omega (optional, device FP64 [n_out][4][8][V], n_out = per_rhs ? n_rhs : 1)
+ *   = d(sum_w <gy_w, y_w>)/d omega^c_mu(x) for U_mu(x) -> exp(i omega^c T^c) U_mu(x).
+ * U, x: device FP64.  At least one output.  Reverse Chebyshev sweep: 3 degree stencil sweeps and
+ * degree link-derivative passes; workspace: 4 link fields per source (RMH_OP_CHEB_FILTER_BWD,
+ * aux = n_windows).  Outputs are overwritten and must not overlap an input or the workspace. */
+rmh_status rmh_cheb_filter_bwd(const int32_t L[4], const double* U, const double* x, const double* gy, int32_t n_rhs,
+                               const rmh_cheb* cheb, double* grad_x, double* grad_omega, int32_t per_rhs, void* ws,
+                               size_t ws_bytes, rmh_stream stream);
+/* Vector-Jacobian product of power[n][w] = <F_n, B_w F_n> (Eq. 4 numerator) with host cotangent
+ * gamma[n_rhs][n_windows]:
+ * grad_F (optional, device FP64 [n_rhs][4][8][V]) = 2 sum_w gamma[n][w] B_w F_n;
+ * grad_omega (optional, as above) = d(sum_{n,w} gamma[n][w] power[n][w])/d omega.
+ * U, F: device FP64.  Workspace: RMH_OP_POWER_SPECTRUM_BWD.  Same conventions as
+ * rmh_cheb_filter_bwd. */
+rmh_status rmh_power_spectrum_bwd(const int32_t L[4], const double* U, const double* F, int32_t n_rhs,
+                                  const rmh_cheb* cheb, const double* gamma, double* grad_F, double* grad_omega,
+                                  int32_t per_rhs, void* ws, size_t ws_bytes, rmh_stream stream);
 
 /* ---------------------------------------------------------------------------------------- */
 /* rational mass term (section 3, Eq. 5 and Eq. 6) */
@@ -290,8 +309,8 @@ rmh_status rmh_tune_clear(void);
 /* Kernel classes of rmh_profile_read. */
 typedef enum {
   RMH_PROF_STENCIL = 0,      /* every Delta application (all drivers) */
-  RMH_PROF_CG_RESIDUAL = 1,  /* r -= alpha A p with <r, r> */
-  RMH_PROF_CG_SHIFTS = 2,    /* x_j += a_j p_j, p_j = z_j r + b_j p_j over the active shifts */
+  RMH_PROF_CG_RESIDUAL = 1,  /* the seed's vector updates: r -= alpha A p with <r, r>, p = r + beta p */
+  RMH_PROF_CG_SHIFTS = 2,    /* folds of the shift solutions and directions over the residual ring */
   RMH_PROF_FORCE = 3,        /* link derivative */
   RMH_PROF_N = 4
 } rmh_prof_class;

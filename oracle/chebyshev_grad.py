@@ -70,19 +70,16 @@ def poly_link_derivative(U, L, left, right, beta, spec=None) -> np.ndarray:
     V = volume(L)
     left = np.asarray(left, np.float64).reshape(-1, 4, 8 * V)
     right = np.asarray(right, np.float64).reshape(-1, 4, 8 * V)
-    out = np.zeros((4, 8, V))
     n = Q.shape[0]
+    # the pairs (q_i, sum_j M_ij q_j) of every direction nu and field are site fields (8, V); the
+    # bilinear derivative sums over all leading axes, so they go in one batch
+    As, Bs = [], []
     for m in range(left.shape[0]):
         for nu in range(4):
-            fl = Q.T @ left[m, nu]
-            fr = Q.T @ right[m, nu]
-            M = G * np.outer(fl, fr)
-            A = np.zeros((n, 4, 8 * V))
-            B = np.zeros((n, 4, 8 * V))
-            A[:, nu, :] = Q.T                 # q_i
-            B[:, nu, :] = (Q @ M.T).T         # sum_j M_ij q_j
-            out += bilinear_link_derivative(U, A.reshape(n, 4, 8, V), B.reshape(n, 4, 8, V), L) / 8.0
-    return out
+            M = G * np.outer(Q.T @ left[m, nu], Q.T @ right[m, nu])
+            As.append(Q.T.reshape(n, 8, V))                 # q_i
+            Bs.append((M @ Q.T).reshape(n, 8, V))           # sum_j M_ij q_j
+    return bilinear_link_derivative(U, np.concatenate(As), np.concatenate(Bs), L) / 8.0
 
 
 def power_spectrum_link_derivative(U, F, L, degree: int, edges, gamma, kernel: str = "jackson",

@@ -228,6 +228,51 @@ def cheb_filter(L, U, x, degree: int, n_windows: int, edges=None, kernel: int = 
     return y
 
 
+def _require_f64(*ts):
+    for t in ts:
+        if t.dtype != torch.float64:
+            raise TypeError("the Chebyshev backward calls take FP64 links and fields")
+
+
+def cheb_filter_bwd(L, U, x, gy, degree: int, n_windows: int, edges=None, kernel: int = 1,
+                    grad_x: bool = True, grad_omega: bool = True, per_rhs: bool = False):
+    """VJP of y_w = B_w x with cotangents gy (n_windows, n, 4, 8, V), all FP64:
+    (grad_x = sum_w B_w gy_w, grad_omega = d sum_w <gy_w, y_w> / d omega), None where not requested."""
+    n = x.shape[0]
+    V = volume(L)
+    _require_f64(U, x, gy)
+    if tuple(gy.shape) != (n_windows,) + tuple(x.shape):
+        raise ValueError(f"gy must have shape {(n_windows,) + tuple(x.shape)}")
+    st, keep = _cheb(degree, n_windows, edges, kernel)
+    gx = torch.empty_like(x) if grad_x else None
+    go = torch.empty((n if per_rhs else 1, 4, 8, V), dtype=torch.float64, device=x.device) if grad_omega else None
+    ws = _workspace(workspace_bytes(L_.OP_CHEB_FILTER_BWD, L, RMH_F64, n, n_windows, degree), x.device)
+    check(lib().rmh_cheb_filter_bwd(lattice_arg(L), _dev(U, "U"), _dev(x, "x"), _dev(gy, "gy"), n, ctypes.byref(st),
+                                    gx.data_ptr() if gx is not None else None,
+                                    go.data_ptr() if go is not None else None, int(per_rhs), ws.data_ptr(),
+                                    ws.numel(), _stream(x.device)), "rmh_cheb_filter_bwd")
+    return gx, go
+
+
+def power_spectrum_bwd(L, U, F, gamma, degree: int, n_windows: int, edges=None, kernel: int = 1,
+                       grad_F: bool = True, grad_omega: bool = True, per_rhs: bool = False):
+    """VJP of power[n, w] = <F_n, B_w F_n> with host cotangent gamma (n, n_windows), all FP64:
+    (grad_F = 2 sum_w gamma_w B_w F, grad_omega = d sum gamma * power / d omega)."""
+    n = F.shape[0]
+    V = volume(L)
+    _require_f64(U, F)
+    st, keep = _cheb(degree, n_windows, edges, kernel)
+    gam = np.ascontiguousarray(np.asarray(gamma, np.float64).reshape(n, n_windows))
+    gF = torch.empty_like(F) if grad_F else None
+    go = torch.empty((n if per_rhs else 1, 4, 8, V), dtype=torch.float64, device=F.device) if grad_omega else None
+    ws = _workspace(workspace_bytes(L_.OP_POWER_SPECTRUM_BWD, L, RMH_F64, n, n_windows, degree), F.device)
+    check(lib().rmh_power_spectrum_bwd(lattice_arg(L), _dev(U, "U"), _dev(F, "F"), n, ctypes.byref(st), _f64p(gam),
+                                       gF.data_ptr() if gF is not None else None,
+                                       go.data_ptr() if go is not None else None, int(per_rhs), ws.data_ptr(),
+                                       ws.numel(), _stream(F.device)), "rmh_power_spectrum_bwd")
+    return gF, go
+
+
 # ------------------------------------------------------------------------------------------
 # rational mass term
 

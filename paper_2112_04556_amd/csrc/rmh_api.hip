@@ -946,6 +946,118 @@ rmh_status cheb_filter_t(const Geom& g, const T* U, const T* x, int32_t n_rhs, i
   return RMH_OK;
 }
 
+// Reverse sweep of the Chebyshev recursion (FP64).  For L = sum_v sum_k <G_k[v], T_k(A) x[v]> with
+// A = Delta/8 - 1 and G_k[v] = sum_y c[v][y][k] Y[y][v], the adjoint vectors of t_k = T_k(A) x obey
+//   tb_k = G_k + 2A tb_{k+1} - tb_{k+2}  (tb_{D+1} = tb_{D+2} = 0),
+// and, since t_1 = A t_0 and t_k = 2A t_{k-1} - t_{k-2},
+//   dL/d omega = (1/8) <tb_1, dDelta t_0> + (1/4) sum_{k=2..D} <tb_k, dDelta t_{k-1}>,
+//   dL/dx      = tb_0 = G_0 + A tb_1 - tb_2  (through the recursion only).
+// t_D, t_{D-1} come from a forward sweep; the reverse sweep then runs the recursion backwards,
+// t_{k-2} = 2A t_{k-1} - t_k, so only two t and two tb vectors are held.  2A = -H/4.
+struct ChebBwdPlan {
+  double* T[2];
+  double* B[2];
+  double* coef;   // [n_rhs][n_y][D+1], then [n_rhs][n_y] scaled k = 0 coefficients
+};
+
+ChebBwdPlan plan_cheb_bwd(Carver& c, const Geom& g, int32_t n_rhs, int32_t n_y, int32_t D) {
+  ChebBwdPlan p{};
+  const size_t fr = (size_t)n_rhs * 32 * g.V;
+  p.T[0] = c.take<double>(fr);
+  p.T[1] = c.take<double>(fr);
+  p.B[0] = c.take<double>(fr);
+  p.B[1] = c.take<double>(fr);
+  p.coef = c.take<double>((size_t)n_rhs * n_y * (D + 2));
+  return p;
+}
+
+rmh_status cheb_bwd(const Geom& g, const double* U, const double* x, int32_t n_rhs, int32_t D, const double* Y,
+                    int32_t n_y, const std::vector<double>& coef_h, const ChebBwdPlan& p, double* grad_x,
+                    double xscale, double* grad_omega, int32_t per_rhs, hipStream_t s) {
+  const int64_t n = field_reals(g);
+  const int32_t nk = D + 1;
+  {
+    std::vector<double> up(coef_h);
+    up.resize((size_t)n_rhs * n_y * (D + 2));
+    for (size_t i = 0; i < (size_t)n_rhs * n_y; ++i) up[(size_t)n_rhs * n_y * nk + i] = xscale * coef_h[i * nk];
+    RMH_TRY(h2d(p.coef, up.data(), up.size() * 8, s));
+  }
+  const double* coef_x = p.coef + (size_t)n_rhs * n_y * nk;
+  const HopConfig cfg = hop_config(g, RMH_F64, n_rhs, 5);
+  auto hop = [&](const double* in, const double* z, double* out, double a, double c) -> rmh_status {
+    HopArgs<double> h{};
+    h.g = g;
+    h.U = U;
+    h.x = in;
+    h.x_mul = 1;
+    h.z = z;
+    h.z_div = 1;
+    h.out = out;
+    h.a = a;
+    h.c = c;
+    h.n_rhs = n_rhs;
+    h.store = 1;
+    ProfScope ps(RMH_PROF_STENCIL, hop_bytes(g, n_rhs, 8, z != nullptr, true), s, n_rhs);
+    HIP_TRY(launch_hop<double>(h, cfg, s));
+    return RMH_OK;
+  };
+  // forward: prv = t_{D-1}, cur = t_D
+  const double* prv = x;
+  double* cur = p.T[0];
+  RMH_TRY(hop(x, nullptr, cur, -0.125, 0.0));
+  for (int32_t k = 2; k <= D; ++k) {
+    double* out = (k == 2) ? p.T[1] : (double*)prv;   // t_{k-2}'s buffer (x itself is never written)
+    RMH_TRY(hop(cur, prv, out, -0.25, -1.0));
+    prv = cur;
+    cur = out;
+  }
+  // reverse
+  double* nb = p.B[0];    // tb_{k+1}
+  double* nb2 = p.B[1];   // tb_{k+2}
+  HIP_TRY(launch_zero(nb, (size_t)n * n_rhs * 8, s));
+  HIP_TRY(launch_zero(nb2, (size_t)n * n_rhs * 8, s));
+  for (int32_t k = D; k >= 1; --k) {
+    // tb_k into tb_{k+2}'s buffer
+    if (k < D) RMH_TRY(hop(nb, k + 1 < D ? nb2 : nullptr, nb2, -0.25, k + 1 < D ? -1.0 : 0.0));
+    HIP_TRY(launch_cheb_source(nb2, Y, p.coef, n_rhs, n_y, nk, k, n, s));
+    std::swap(nb, nb2);   // nb = tb_k, nb2 = tb_{k+1}
+    if (grad_omega) {
+      ForceArgs fa{};
+      fa.g = g;
+      fa.U = U;
+      fa.A = nb;
+      fa.B = prv;     // t_{k-1}
+      fa.n_rhs = n_rhs;
+      fa.n_pair = 1;
+      fa.w[0] = (k == 1) ? 0.125 : 0.25;
+      fa.grad = grad_omega;
+      fa.per_rhs = per_rhs ? 1 : 0;
+      fa.accumulate = (k == D) ? 0 : 1;
+      const double fbytes = (double)g.V * 8.0 * (72.0 + 64.0 * n_rhs + 32.0 * (per_rhs ? n_rhs : 1) * (k == D ? 1.0 : 2.0));
+      ProfScope ps(RMH_PROF_FORCE, fbytes, s, n_rhs);
+      HIP_TRY(launch_force(fa, s));
+    }
+    if (k >= 2) {
+      // t_{k-2} = 2A t_{k-1} - t_k into t_k's buffer; t_0 is x itself
+      if (k >= 3) {
+        RMH_TRY(hop(prv, cur, cur, -0.25, -1.0));
+        const double* t_km2 = cur;
+        cur = (double*)prv;
+        prv = t_km2;
+      } else {
+        cur = (double*)prv;
+        prv = x;
+      }
+    }
+  }
+  if (grad_x) {
+    // tb_0 = G_0 + A tb_1 - tb_2, scaled by xscale (nb = tb_1, nb2 = tb_2, zero when D = 1)
+    RMH_TRY(hop(nb, D >= 2 ? nb2 : nullptr, grad_x, -0.125 * xscale, D >= 2 ? -xscale : 0.0));
+    HIP_TRY(launch_cheb_source(grad_x, Y, coef_x, n_rhs, n_y, 1, 0, n, s));
+  }
+  return RMH_OK;
+}
+
 }  // namespace
 
 // =============================================================================================
@@ -975,6 +1087,12 @@ size_t rmh_workspace_bytes(int32_t op, const int32_t L[4], int32_t dtype, int32_
       break;
     case RMH_OP_CHEB_FILTER:
       plan_cheb(c, g, dtype, n_rhs, std::max(1, degree), false);
+      break;
+    case RMH_OP_CHEB_FILTER_BWD:
+      plan_cheb_bwd(c, g, n_rhs, std::max(1, aux), std::max(1, degree));
+      break;
+    case RMH_OP_POWER_SPECTRUM_BWD:
+      plan_cheb_bwd(c, g, n_rhs, 1, std::max(1, degree));
       break;
     case RMH_OP_RATIONAL_APPLY:
     case RMH_OP_RATIONAL_APPLY_BWD:
@@ -1258,8 +1376,88 @@ rmh_status rmh_cheb_filter(const int32_t L[4], const void* U, int32_t dtype, con
   return cheb_filter_t<float>(g, (const float*)U, (const float*)x, n_rhs, D, nw, coef, cp, (float*)y, s);
 }
 
-rmh_status rmh_cheb_filter_bwd(void) { return fail(RMH_E_UNIMPLEMENTED, "rmh_cheb_filter_bwd is not built"); }
-rmh_status rmh_power_spectrum_bwd(void) { return fail(RMH_E_UNIMPLEMENTED, "rmh_power_spectrum_bwd is not built"); }
+static rmh_status cheb_bwd_common(const int32_t L[4], const double* U, const double* x, int32_t n_rhs,
+                                  const rmh_cheb* cheb, const void* grad_x, const double* grad_omega, Geom* g,
+                                  std::vector<double>* coef) {
+  RMH_TRY(make_geom(L, g));
+  if (!cheb) return fail(RMH_E_ARG, "cheb is NULL");
+  if (n_rhs < 0) return fail(RMH_E_ARG, "n_rhs < 0");
+  const int32_t D = cheb->degree, nw = cheb->n_windows;
+  if (D < 1 || D > 100000) return fail(RMH_E_ARG, "degree = %d must be in [1, 100000]", D);
+  coef->resize((size_t)nw * (D + 1));
+  RMH_TRY(rmh_cheb_coefficients(cheb, coef->data()));
+  if (!grad_x && !grad_omega) return fail(RMH_E_ARG, "neither grad_x nor grad_omega requested");
+  if (n_rhs == 0) return RMH_OK;
+  RMH_TRY(check_ptr(U, "U"));
+  RMH_TRY(check_ptr(x, "x"));
+  if (grad_x) RMH_TRY(check_ptr(grad_x, "grad_x"));
+  if (grad_omega) RMH_TRY(check_ptr(grad_omega, "grad_omega"));
+  return RMH_OK;
+}
+
+rmh_status rmh_cheb_filter_bwd(const int32_t L[4], const double* U, const double* x, const double* gy, int32_t n_rhs,
+                               const rmh_cheb* cheb, double* grad_x, double* grad_omega, int32_t per_rhs, void* ws,
+                               size_t ws_bytes, rmh_stream stream) {
+  Geom g;
+  std::vector<double> coef;
+  RMH_TRY(cheb_bwd_common(L, U, x, n_rhs, cheb, grad_x, grad_omega, &g, &coef));
+  if (n_rhs == 0) return RMH_OK;
+  RMH_TRY(check_ptr(gy, "gy"));
+  RMH_TRY(check_ptr(ws, "ws"));
+  const int32_t D = cheb->degree, nw = cheb->n_windows;
+  Carver c(ws);
+  ChebBwdPlan p = plan_cheb_bwd(c, g, n_rhs, nw, D);
+  if (c.off > ws_bytes) return fail(RMH_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, c.off);
+  const size_t fb = (size_t)n_rhs * 32 * g.V * 8, gb = (size_t)(per_rhs ? n_rhs : 1) * 32 * g.V * 8;
+  const void* ins[4] = {U, x, gy, ws};
+  const size_t insz[4] = {(size_t)72 * g.V * 8, fb, fb * nw, c.off};
+  for (int i = 0; i < 4; ++i) {
+    if (grad_x && overlap(grad_x, fb, ins[i], insz[i])) return fail(RMH_E_ARG, "grad_x overlaps an input or the workspace");
+    if (grad_omega && overlap(grad_omega, gb, ins[i], insz[i]))
+      return fail(RMH_E_ARG, "grad_omega overlaps an input or the workspace");
+  }
+  if (grad_x && grad_omega && overlap(grad_x, fb, grad_omega, gb)) return fail(RMH_E_ARG, "grad_x overlaps grad_omega");
+  // G_k[v] = sum_w coef[w][k] gy[w][v]
+  std::vector<double> ch((size_t)n_rhs * nw * (D + 1));
+  for (int32_t v = 0; v < n_rhs; ++v)
+    for (int32_t w = 0; w < nw; ++w)
+      for (int32_t k = 0; k <= D; ++k) ch[((size_t)v * nw + w) * (D + 1) + k] = coef[(size_t)w * (D + 1) + k];
+  return cheb_bwd(g, U, x, n_rhs, D, gy, nw, ch, p, grad_x, 1.0, grad_omega, per_rhs, (hipStream_t)stream);
+}
+
+rmh_status rmh_power_spectrum_bwd(const int32_t L[4], const double* U, const double* F, int32_t n_rhs,
+                                  const rmh_cheb* cheb, const double* gamma, double* grad_F, double* grad_omega,
+                                  int32_t per_rhs, void* ws, size_t ws_bytes, rmh_stream stream) {
+  Geom g;
+  std::vector<double> coef;
+  RMH_TRY(cheb_bwd_common(L, U, F, n_rhs, cheb, grad_F, grad_omega, &g, &coef));
+  if (n_rhs == 0) return RMH_OK;
+  if (!gamma) return fail(RMH_E_ARG, "gamma is NULL");
+  RMH_TRY(check_ptr(ws, "ws"));
+  const int32_t D = cheb->degree, nw = cheb->n_windows;
+  for (size_t i = 0; i < (size_t)n_rhs * nw; ++i)
+    if (!isfinite(gamma[i])) return fail(RMH_E_ARG, "gamma[%zu] is not finite", i);
+  Carver c(ws);
+  ChebBwdPlan p = plan_cheb_bwd(c, g, n_rhs, 1, D);
+  if (c.off > ws_bytes) return fail(RMH_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, c.off);
+  const size_t fb = (size_t)n_rhs * 32 * g.V * 8, gb = (size_t)(per_rhs ? n_rhs : 1) * 32 * g.V * 8;
+  const void* ins[3] = {U, F, ws};
+  const size_t insz[3] = {(size_t)72 * g.V * 8, fb, c.off};
+  for (int i = 0; i < 3; ++i) {
+    if (grad_F && overlap(grad_F, fb, ins[i], insz[i])) return fail(RMH_E_ARG, "grad_F overlaps an input or the workspace");
+    if (grad_omega && overlap(grad_omega, gb, ins[i], insz[i]))
+      return fail(RMH_E_ARG, "grad_omega overlaps an input or the workspace");
+  }
+  if (grad_F && grad_omega && overlap(grad_F, fb, grad_omega, gb)) return fail(RMH_E_ARG, "grad_F overlaps grad_omega");
+  // one source vector per field, G_k = beta_k F with beta_k = sum_w gamma_w coef[w][k]
+  std::vector<double> ch((size_t)n_rhs * (D + 1), 0.0);
+  for (int32_t v = 0; v < n_rhs; ++v)
+    for (int32_t w = 0; w < nw; ++w)
+      for (int32_t k = 0; k <= D; ++k)
+        ch[(size_t)v * (D + 1) + k] += gamma[(size_t)v * nw + w] * coef[(size_t)w * (D + 1) + k];
+  // F enters both slots of <F, p(A) F>: grad_F = tb_0 + p(A) F = 2 tb_0 (p(A) symmetric)
+  return cheb_bwd(g, U, F, n_rhs, D, F, 1, ch, p, grad_F, 2.0, grad_omega, per_rhs, (hipStream_t)stream);
+}
 
 rmh_status rmh_rational_from_quadratics(int32_t n_terms, const double* a0, const double* a1, const double* b0,
                                         const double* b1, double* r, double* sigma) {

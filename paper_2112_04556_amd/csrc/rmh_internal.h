@@ -210,7 +210,13 @@ struct ForceArgs {
   double w[64];      // weight of each pair
   double* grad;      // [n_out][4][8][V]
   int32_t per_rhs;
+  int32_t accumulate;  // grad += (else grad =)
 };
 hipError_t launch_force(const ForceArgs& a, hipStream_t s);
+
+// Chebyshev reverse sweep source term: tb[v] += sum_y coef[(v * n_y + y) * n_k + k] Y[y][v] (FP64;
+// Y laid out [n_y][n_rhs][n_reals], coef on the device)
+hipError_t launch_cheb_source(double* tb, const double* Y, const double* coef, int32_t n_rhs, int32_t n_y,
+                              int32_t n_k, int32_t k, int64_t n_reals, hipStream_t s);
 
 }  // namespace rmh

@@ -908,9 +908,41 @@ __global__ void __launch_bounds__(256) k_force(const ForceArgs F, int32_t xcd) {
       G[b] += f * (RC[c * 8 + a] - RC[a * 8 + c]);
     }
     double* go = F.grad + ((int64_t)o * 4 + mu) * 8 * V;
+    if (F.accumulate) {
 #pragma unroll
-    for (int c = 0; c < 8; ++c) go[(int64_t)c * V + s] = G[c];
+      for (int c = 0; c < 8; ++c) go[(int64_t)c * V + s] += G[c];
+    } else {
+#pragma unroll
+      for (int c = 0; c < 8; ++c) go[(int64_t)c * V + s] = G[c];
+    }
   }
+}
+
+__global__ void k_cheb_source(double* __restrict__ tb, const double* __restrict__ Y, const double* __restrict__ coef,
+                              int32_t n_rhs, int32_t n_y, int32_t n_k, int32_t k, int64_t n) {
+  const int32_t v = blockIdx.y;
+  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  if (i0 >= n) return;
+  double acc[4];
+  double* t = tb + (int64_t)v * n + i0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[q] = t[q];
+  for (int32_t y = 0; y < n_y; ++y) {
+    const double c = coef[((int64_t)v * n_y + y) * n_k + k];
+    const double* yv = Y + ((int64_t)y * n_rhs + v) * n + i0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = fma(c, yv[q], acc[q]);
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) t[q] = acc[q];
+}
+
+hipError_t launch_cheb_source(double* tb, const double* Y, const double* coef, int32_t n_rhs, int32_t n_y,
+                              int32_t n_k, int32_t k, int64_t n_reals, hipStream_t s) {
+  if (n_rhs == 0 || n_y == 0) return hipSuccess;
+  dim3 grid(elem_num_blocks(n_reals), n_rhs);
+  hipLaunchKernelGGL(k_cheb_source, grid, dim3(kBlock), 0, s, tb, Y, coef, n_rhs, n_y, n_k, k, n_reals);
+  return hipGetLastError();
 }
 
 hipError_t launch_force(const ForceArgs& a, hipStream_t s) {

@@ -142,4 +142,32 @@ def test_workspace_query():
     m1 = _lib.lib().rmh_workspace_bytes(4, L, 0, 1, 12, 0, 1)
     assert 0 < n1 < n2 and m1 > 0
     assert _lib.lib().rmh_workspace_bytes(99, L, 0, 1, 1, 0, 0) == 0
-    assert _lib.lib().rmh_cheb_filter_bwd() == 8 and _lib.lib().rmh_power_spectrum_bwd() == 8
+    # Chebyshev backward: four link fields per source plus the coefficients
+    fb = 32 * 256 * 8
+    b7 = _lib.lib().rmh_workspace_bytes(7, L, 0, 2, 3, 10, 0)
+    b8 = _lib.lib().rmh_workspace_bytes(8, L, 0, 2, 3, 10, 0)
+    assert 4 * 2 * fb <= b8 <= b7 < 4 * 2 * fb + 4096
+
+
+def test_validation_cheb_bwd():
+    L = _lib.lattice_arg((4, 4, 4, 4))
+    fb = 32 * 256 * 8
+    st = _lib.RmhCheb(10, 3, None, 1)
+    bad = _lib.RmhCheb(0, 3, None, 1)
+    gam = np.ones(3)
+    args = lambda cheb, gx, go, wsb: (L, FAKE, FAKE + 2**20, FAKE + 2**21, 1, ctypes.byref(cheb), gx, go, 0,
+                                      FAKE + 2**22, wsb, None)
+    f = _lib.lib().rmh_cheb_filter_bwd
+    assert f(*args(bad, FAKE + 2**23, None, 1 << 30)) == 1                 # degree 0
+    assert f(*args(st, None, None, 1 << 30)) == 1                           # nothing requested
+    assert f(*args(st, FAKE + 2**23, None, 1024)) == 3                      # workspace too small
+    assert f(*args(st, FAKE + 2**20, None, 1 << 30)) == 1                   # grad_x aliases x
+    g = _lib.lib().rmh_power_spectrum_bwd
+    gp = gam.ctypes.data_as(_lib.P_f64)
+    assert g(L, FAKE, FAKE + 2**20, 1, ctypes.byref(st), None, FAKE + 2**23, None, 0, FAKE + 2**22, 1 << 30,
+             None) == 1                                                       # gamma NULL
+    assert g(L, FAKE, FAKE + 2**20, 1, ctypes.byref(st), gp, FAKE + 2**20 + fb // 2, None, 0, FAKE + 2**22,
+             1 << 30, None) == 1                                              # grad_F overlaps F
+    nan = np.array([1.0, np.nan, 0.0])
+    assert g(L, FAKE, FAKE + 2**20, 1, ctypes.byref(st), nan.ctypes.data_as(_lib.P_f64), FAKE + 2**23, None, 0,
+             FAKE + 2**22, 1 << 30, None) == 1                                # non-finite gamma
