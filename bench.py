@@ -27,7 +27,9 @@ Extra fields (skipped with --no-extras):
   D3  the batched power spectrum at 24^4 (32 sources, degree 256, 64 windows), Haar and U = 1;
   D4  the 8-pole kinetic force at 16^4;
   D5  the full force step at 32^3 x 64: 16-pole kinetic force of 8 momentum fields, then the
-      128-window degree-256 power spectrum of the 8 forces, FP64 against mixed precision.
+      128-window degree-256 power spectrum of the 8 forces, FP64 against mixed precision;
+  D6  the backward of the degree-64, 16-window power spectrum at 16^4 (link derivative and source
+      gradient) beside its forward.
 """
 from __future__ import annotations
 
@@ -130,8 +132,8 @@ def main():
     # stencil launch configurations for the shapes of the step (outside the timed region)
     Ud = api.pack_links(L, U_aos)
     U32 = api.pack_links(L, U_aos, torch.float32)
-    api.autotune_laplacian(L, Ud, Pd, reps=3)
-    api.autotune_laplacian(L, U32, Pd.float(), reps=3)
+    api.autotune_laplacian(L, Ud, Pd, reps=10)
+    api.autotune_laplacian(L, U32, Pd.float(), reps=10)
     ws = torch.empty(api.workspace_bytes(6, L, 0, 1, 12, 0, 1), dtype=torch.uint8, device=dev)
 
     def step():
@@ -391,6 +393,27 @@ def d5_force_step(api, inputs, torch, dev):
     return row
 
 
+def d6_spectrum_bwd(api, inputs, torch, np, dev):
+    """Backward of the power spectrum (link derivative and source gradient) at 16^4, eps=0.5,
+    degree 64, 16 windows: the reverse Chebyshev sweep (3 x 64 stencil sweeps, 64 derivative passes)."""
+    L = (16, 16, 16, 16)
+    Ud = api.pack_links(L, inputs.random_links(L, "eps", 0.5, seed=6).to(dev))
+    F = inputs.gaussian_fields(L, 1, seed=6).to(dev)
+    gamma = np.ones((1, 16))
+    fwd_ms, _ = _median_ms(lambda: api.power_spectrum(L, Ud, F, 64, 16), torch)
+    bwd_ms, _ = _median_ms(lambda: api.power_spectrum_bwd(L, Ud, F, gamma, 64, 16), torch)
+    api.profile_enable(True)
+    api.power_spectrum_bwd(L, Ud, F, gamma, 64, 16)
+    torch.cuda.synchronize()
+    prof = {c: api.profile_read(c) for c in ("stencil", "force")}
+    api.profile_enable(False)
+    row = {"forward_ms": round(fwd_ms, 3), "backward_ms": round(bwd_ms, 3),
+           "stencil": {"launches": prof["stencil"]["launches"], "GBs": round(prof["stencil"]["gbs"], 1)},
+           "force": {"launches": prof["force"]["launches"], "GBs": round(prof["force"]["gbs"], 1)}}
+    log(f"D6 power spectrum backward 16^4: {row}")
+    return row
+
+
 def run_extras(api, inputs, torch, np, dev, L, U_aos, Ud, Pd):
     out = {}
     cp = copy_bandwidth(torch, dev)
@@ -401,6 +424,7 @@ def run_extras(api, inputs, torch, np, dev, L, U_aos, Ud, Pd):
     out["D3_power_spectrum_24x24x24x24"] = d3_spectrum(api, inputs, torch, dev)
     out["D4_kinetic_force_16x16x16x16"] = d4_force(api, inputs, torch, dev)
     out["D5_force_step_32x32x32x64"] = d5_force_step(api, inputs, torch, dev)
+    out["D6_power_spectrum_bwd_16x16x16x16"] = d6_spectrum_bwd(api, inputs, torch, np, dev)
     return out
 
 

@@ -1,4 +1,5 @@
-"""torch.autograd wrapper of the RMHMC kinetic energy (section 3, Eq. 5 with Eq. 6).
+"""torch.autograd wrappers of the RMHMC kinetic energy (section 3, Eq. 5 with Eq. 6) and of the
+Chebyshev power spectrum (section 2, Eq. 4).
 
 K(omega, P) = 1/2 sum_n <Y_n, Y_n>,  Y = R(Delta[exp(i omega.T) U]) P,  evaluated at
 omega = 0.  ``omega`` is the (4, 8, V) Lie-algebra displacement of every link under
@@ -37,3 +38,32 @@ class KineticEnergy(torch.autograd.Function):
 
 def kinetic_energy(omega, P, U, L, rat, solver=api.Solver()):
     return KineticEnergy.apply(omega, P, U, L, rat, solver)
+
+
+class PowerSpectrum(torch.autograd.Function):
+    """power[n, w] = <F_n, B_w(Delta[exp(i omega.T) U]) F_n> at omega = 0 (FP64).  The backward
+    runs the reverse Chebyshev sweep in the HIP library: gradients for omega and F."""
+
+    @staticmethod
+    def forward(ctx, omega, F, U, L, degree, n_windows, edges, kernel):
+        if omega.shape != (4, 8, api.volume(L)):
+            raise ValueError("omega must have shape (4, 8, V)")
+        if bool(torch.any(omega != 0)):
+            raise ValueError("the power spectrum is differentiated at omega = 0; pass a zero displacement")
+        _, pw = api.power_spectrum(L, U, F, degree, n_windows, edges, kernel)
+        ctx.save_for_backward(F, U)
+        ctx.args = (L, degree, n_windows, edges, kernel)
+        return torch.from_numpy(pw).to(F.device)
+
+    @staticmethod
+    def backward(ctx, gp):
+        F, U = ctx.saved_tensors
+        L, degree, n_windows, edges, kernel = ctx.args
+        gF, go = api.power_spectrum_bwd(L, U, F, gp.detach().cpu().double().numpy(), degree, n_windows, edges,
+                                        kernel, grad_F=ctx.needs_input_grad[1],
+                                        grad_omega=ctx.needs_input_grad[0])
+        return (go[0] if go is not None else None), gF, None, None, None, None, None, None
+
+
+def power_spectrum(omega, F, U, L, degree, n_windows, edges=None, kernel=1):
+    return PowerSpectrum.apply(omega, F, U, L, degree, n_windows, edges, kernel)

@@ -124,3 +124,21 @@ def test_power_spectrum_bwd_finite_differences(L, D, nw, n_pert, rtol):
         worst = max(worst, abs(fd - go[mu, c, s]) / scale)
     announce(f"  FD worst relative deviation {worst:.3e}")
     assert worst <= rtol
+
+
+def test_autograd_power_spectrum():
+    """torch.autograd through the library's forward and backward: gradients for omega and F against
+    the oracle's dense derivative."""
+    from paper_2112_04556_amd import autograd
+    L = (2, 3, 2, 2)
+    U, F, Ud, Fd = setup(L, "eps", 0.6, 47, n=2)
+    D, nw = 10, 3
+    gamma = np.random.default_rng(47).normal(size=(2, nw))
+    omega = torch.zeros((4, 8, api.volume(L)), dtype=torch.float64, device=dev(), requires_grad=True)
+    Fg = Fd.clone().requires_grad_(True)
+    pw = autograd.power_spectrum(omega, Fg, Ud, L, D, nw)
+    loss = torch.sum(pw * torch.from_numpy(gamma).to(dev()))
+    loss.backward()
+    edges = och.equal_windows(nw)
+    assert rel_max(omega.grad.cpu().numpy(), ocg.power_spectrum_link_derivative(U, F, L, D, edges, gamma)) <= 1e-12
+    assert rel_max(Fg.grad.cpu().numpy(), ocg.power_spectrum_source_gradient(U, F, L, D, edges, gamma)) <= 1e-12
