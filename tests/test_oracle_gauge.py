@@ -1,0 +1,70 @@
+"""Pins for the oracle's Wilson action and gauge force, CPU only: finite differences of the action
+(the force is derived by hand), a closed form for one rotated link, gauge invariance of the action
+and covariance of the force, and U = 1."""
+import numpy as np
+import pytest
+from scipy.linalg import expm
+
+from oracle import gauge, lattice, su3
+from paper_2112_04556_amd import inputs
+
+L = (3, 4, 2, 5)   # anisotropic; L = 2 in one direction keeps both staples of that plane
+
+
+def _perturb(U, mu, s, c, eps):
+    U2 = U.copy()
+    U2[mu, s] = expm(1j * eps * su3.T[c]) @ U[mu, s]
+    return U2
+
+
+@pytest.mark.parametrize("kind", ["eps", "haar"])
+def test_force_is_minus_action_derivative(kind):
+    U = inputs.random_links(L, kind, 0.7, seed=51).numpy()
+    beta = 5.7
+    G = gauge.action_gradient(U, L, beta)
+    assert np.allclose(gauge.gauge_force(U, L, beta), -G)
+    rng = np.random.default_rng(0)
+    h = 1e-5
+    for _ in range(10):
+        mu, c, s = rng.integers(4), rng.integers(8), rng.integers(lattice.volume(L))
+        fd = (gauge.wilson_action(_perturb(U, mu, s, c, h), L, beta)
+              - gauge.wilson_action(_perturb(U, mu, s, c, -h), L, beta)) / (2 * h)
+        # rounding of S (~1e-16 x 4e3 terms) over 2h dominates: ~5e-8 absolute
+        assert abs(fd - G[mu, c, s]) <= 1e-6 * max(1.0, np.abs(G).max())
+
+
+def test_unit_links_and_one_rotated_link():
+    U = inputs.random_links(L, "unit").numpy()
+    assert gauge.wilson_action(U, L, 6.0) == 0.0
+    assert np.abs(gauge.gauge_force(U, L, 6.0)).max() == 0.0
+    # one link rotated by exp(i eps T^3): its 6 plaquettes have Re Tr = 2 cos(eps/2) + 1
+    eps, beta = 0.37, 2.5
+    U1 = _perturb(U, 2, 7, 2, eps)
+    assert np.isclose(gauge.wilson_action(U1, L, beta), 4 * beta * (1 - np.cos(eps / 2)), rtol=1e-13)
+    # and the force on it: (beta/3) * 6 * d/d eps Re Tr exp(i eps T^3) = -beta sin(eps/2)
+    F = gauge.gauge_force(U1, L, beta)
+    assert np.isclose(F[2, 2, 7], -beta * np.sin(eps / 2), rtol=1e-13)
+
+
+def test_gauge_invariance_and_covariance():
+    U = inputs.random_links(L, "haar", seed=52).numpy()
+    Om = inputs.gauge_transform(L, seed=52).numpy()
+    nb = lattice.neighbour_table(L)
+    UO = np.empty_like(U)
+    for mu in range(4):
+        UO[mu] = Om @ U[mu] @ su3.dagger(Om[nb[:, 2 * mu]])
+    beta = 4.0
+    assert np.isclose(gauge.wilson_action(UO, L, beta), gauge.wilson_action(U, L, beta), rtol=1e-12)
+    F = gauge.gauge_force(U, L, beta)
+    FO = gauge.gauge_force(UO, L, beta)
+    for mu in range(4):
+        M = su3.to_matrix(F[mu].T)                                       # (V, 3, 3)
+        MO = su3.to_matrix(FO[mu].T)
+        assert np.allclose(MO, Om @ M @ su3.dagger(Om), atol=1e-12)
+
+
+def test_plaquette_count():
+    U = inputs.random_links(L, "haar", seed=53).numpy()
+    # every plaquette is seen by the staples of its four links
+    lhs = np.einsum("mxii->", np.asarray(U) @ gauge.staples(U, L)).real
+    assert np.isclose(lhs, 4 * gauge.plaquette_traces(U, L).sum(), rtol=1e-12)
