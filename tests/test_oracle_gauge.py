@@ -41,9 +41,9 @@ def test_unit_links_and_one_rotated_link():
     eps, beta = 0.37, 2.5
     U1 = _perturb(U, 2, 7, 2, eps)
     assert np.isclose(gauge.wilson_action(U1, L, beta), 4 * beta * (1 - np.cos(eps / 2)), rtol=1e-13)
-    # and the force on it: (beta/3) * 6 * d/d eps Re Tr exp(i eps T^3) = -beta sin(eps/2)
+    # and the force on it: -dS/d eps of the closed form above, -2 beta sin(eps/2)
     F = gauge.gauge_force(U1, L, beta)
-    assert np.isclose(F[2, 2, 7], -beta * np.sin(eps / 2), rtol=1e-13)
+    assert np.isclose(F[2, 2, 7], -2 * beta * np.sin(eps / 2), rtol=1e-13)
 
 
 def test_gauge_invariance_and_covariance():
