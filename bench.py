@@ -29,7 +29,9 @@ Extra fields (skipped with --no-extras):
   D5  the full force step at 32^3 x 64: 16-pole kinetic force of 8 momentum fields, then the
       128-window degree-256 power spectrum of the 8 forces, FP64 against mixed precision;
   D6  the backward of the degree-64, 16-window power spectrum at 16^4 (link derivative and source
-      gradient) beside its forward.
+      gradient) beside its forward;
+  D7  the Wilson gauge force and its degree-128, 32-window power spectrum (the gauge-force spectra
+      of section 2) at 16^4 and 32^3 x 64.
 """
 from __future__ import annotations
 
@@ -414,6 +416,24 @@ def d6_spectrum_bwd(api, inputs, torch, np, dev):
     return row
 
 
+def d7_gauge_force_spectrum(api, inputs, torch, dev):
+    """The gauge-force spectra of section 2 (Fig. 1 workload) on synthetic links: Wilson force
+    (beta = 6.4) and its power spectrum, degree 128 and 32 windows, at 16^4 and 32^3 x 64."""
+    out = {}
+    for L in ((16, 16, 16, 16), (32, 32, 32, 64)):
+        V = api.volume(L)
+        Ud = api.pack_links(L, inputs.random_links(L, "eps", 0.4, seed=7).to(dev))
+        f_ms, (F, _) = _median_ms(lambda: api.wilson_gauge_force(L, Ud, 6.4, want_action=False), torch)
+        Fb = F[None].contiguous()
+        s_ms, _ = _median_ms(lambda: api.power_spectrum(L, Ud, Fb, 128, 32), torch, reps=3)
+        key = "x".join(map(str, L))
+        out[key] = {"force_ms": round(f_ms, 4), "force_GBs": round(V * 104 * 8 / (f_ms * 1e-3) / 1e9, 1),
+                    "spectrum_ms": round(s_ms, 3)}
+        log(f"D7 gauge force + spectrum {key}: {out[key]}")
+        del Ud, F, Fb
+    return out
+
+
 def run_extras(api, inputs, torch, np, dev, L, U_aos, Ud, Pd):
     out = {}
     cp = copy_bandwidth(torch, dev)
@@ -425,6 +445,7 @@ def run_extras(api, inputs, torch, np, dev, L, U_aos, Ud, Pd):
     out["D4_kinetic_force_16x16x16x16"] = d4_force(api, inputs, torch, dev)
     out["D5_force_step_32x32x32x64"] = d5_force_step(api, inputs, torch, dev)
     out["D6_power_spectrum_bwd_16x16x16x16"] = d6_spectrum_bwd(api, inputs, torch, np, dev)
+    out["D7_gauge_force_spectrum"] = d7_gauge_force_spectrum(api, inputs, torch, dev)
     return out
 
 

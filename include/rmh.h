@@ -130,7 +130,8 @@ typedef enum {
   RMH_OP_RATIONAL_APPLY_BWD = 5,
   RMH_OP_KINETIC_FORCE = 6,
   RMH_OP_CHEB_FILTER_BWD = 7,
-  RMH_OP_POWER_SPECTRUM_BWD = 8
+  RMH_OP_POWER_SPECTRUM_BWD = 8,
+  RMH_OP_GAUGE_FORCE = 9
 } rmh_op;
 
 /* ---------------------------------------------------------------------------------------- */
@@ -278,6 +279,18 @@ rmh_status rmh_kinetic_force(const int32_t L[4], const double* U, const double* 
                              const rmh_rational* rat, const rmh_solver* solver, double* Y, double* K,
                              double* dK_domega, int32_t per_rhs, rmh_stats* stats, void* ws, size_t ws_bytes,
                              rmh_stream stream);
+
+/* ---------------------------------------------------------------------------------------- */
+/* gauge force (the force whose power spectra section 2 measures, Fig. 1) */
+
+/* Wilson plaquette action S_W = beta sum_x sum_{mu<nu} (1 - Re Tr U_{mu nu}(x) / 3) and its gauge
+ * force F_G = -dS_W / d omega^c_mu(x) for U_mu(x) -> exp(i omega^c T^c) U_mu(x) (the
+ * left-multiplication derivative of section 2): F^c_mu(x) = -(beta/3) Im Tr(T^c U_mu(x) A_mu(x)),
+ * A_mu(x) the sum of the six staples.  U: device FP64 SoA links.  F (optional): device FP64
+ * [4][8][V], a link field ready for rmh_power_spectrum.  S (optional): host, the action; needs a
+ * workspace (RMH_OP_GAUGE_FORCE) and synchronizes the stream.  At least one of F, S. */
+rmh_status rmh_wilson_gauge_force(const int32_t L[4], const double* U, double beta, double* F, double* S, void* ws,
+                                  size_t ws_bytes, rmh_stream stream);
 
 /* ---------------------------------------------------------------------------------------- */
 /* stencil launch tuning */

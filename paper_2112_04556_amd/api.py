@@ -273,6 +273,18 @@ def power_spectrum_bwd(L, U, F, gamma, degree: int, n_windows: int, edges=None, 
     return gF, go
 
 
+def wilson_gauge_force(L, U, beta: float, want_action: bool = True):
+    """(F_G (4, 8, V) FP64 on the device, S_W or None) for FP64 SoA links U."""
+    _require_f64(U)
+    F = torch.empty((4, 8, volume(L)), dtype=torch.float64, device=U.device)
+    S = np.zeros(1)
+    ws = _workspace(workspace_bytes(L_.OP_GAUGE_FORCE, L, RMH_F64, 1), U.device)
+    check(lib().rmh_wilson_gauge_force(lattice_arg(L), _dev(U, "U"), float(beta), F.data_ptr(),
+                                       _f64p(S) if want_action else None, ws.data_ptr(), ws.numel(),
+                                       _stream(U.device)), "rmh_wilson_gauge_force")
+    return F, (float(S[0]) if want_action else None)
+
+
 # ------------------------------------------------------------------------------------------
 # rational mass term
 

@@ -1094,6 +1094,10 @@ size_t rmh_workspace_bytes(int32_t op, const int32_t L[4], int32_t dtype, int32_
     case RMH_OP_POWER_SPECTRUM_BWD:
       plan_cheb_bwd(c, g, n_rhs, 1, std::max(1, degree));
       break;
+    case RMH_OP_GAUGE_FORCE:
+      c.take<double>(gauge_force_blocks(g));   // the same carve as rmh_wilson_gauge_force
+      c.take<double>(1);
+      break;
     case RMH_OP_RATIONAL_APPLY:
     case RMH_OP_RATIONAL_APPLY_BWD:
     case RMH_OP_KINETIC_FORCE: {
@@ -1457,6 +1461,40 @@ rmh_status rmh_power_spectrum_bwd(const int32_t L[4], const double* U, const dou
         ch[(size_t)v * (D + 1) + k] += gamma[(size_t)v * nw + w] * coef[(size_t)w * (D + 1) + k];
   // F enters both slots of <F, p(A) F>: grad_F = tb_0 + p(A) F = 2 tb_0 (p(A) symmetric)
   return cheb_bwd(g, U, F, n_rhs, D, F, 1, ch, p, grad_F, 2.0, grad_omega, per_rhs, (hipStream_t)stream);
+}
+
+rmh_status rmh_wilson_gauge_force(const int32_t L[4], const double* U, double beta, double* F, double* S, void* ws,
+                                  size_t ws_bytes, rmh_stream stream) {
+  Geom g;
+  RMH_TRY(make_geom(L, &g));
+  if (!isfinite(beta)) return fail(RMH_E_ARG, "beta is not finite");
+  if (!F && !S) return fail(RMH_E_ARG, "neither F nor S requested");
+  RMH_TRY(check_ptr(U, "U"));
+  if (F) RMH_TRY(check_ptr(F, "F"));
+  if (F && overlap(F, (size_t)32 * g.V * 8, U, (size_t)72 * g.V * 8)) return fail(RMH_E_ARG, "F overlaps U");
+  hipStream_t s = (hipStream_t)stream;
+  double* part = nullptr;
+  double* sum = nullptr;
+  if (S) {
+    RMH_TRY(check_ptr(ws, "ws"));
+    Carver c(ws);
+    part = c.take<double>(gauge_force_blocks(g));
+    sum = c.take<double>(1);
+    if (c.off > ws_bytes) return fail(RMH_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, c.off);
+    if (F && overlap(F, (size_t)32 * g.V * 8, ws, c.off)) return fail(RMH_E_ARG, "F overlaps the workspace");
+  }
+  {
+    ProfScope ps(RMH_PROF_FORCE, (double)g.V * 8.0 * (72.0 + (F ? 32.0 : 0.0)), s, 1.0);
+    HIP_TRY(launch_gauge_force(g, U, beta, F, part, s));
+  }
+  if (S) {
+    HIP_TRY(launch_reduce_rows(part, gauge_force_blocks(g), 1, sum, s));
+    double tr = 0.0;
+    RMH_TRY(d2h(&tr, sum, 8, s));
+    // every plaquette enters the staple sums of its four links
+    *S = beta * (6.0 * g.V - tr / 12.0);
+  }
+  return RMH_OK;
 }
 
 rmh_status rmh_rational_from_quadratics(int32_t n_terms, const double* a0, const double* a1, const double* b0,

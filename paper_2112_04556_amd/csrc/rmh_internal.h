@@ -214,6 +214,12 @@ struct ForceArgs {
 };
 hipError_t launch_force(const ForceArgs& a, hipStream_t s);
 
+// Wilson gauge force F = -dS_W/d omega ([4][8][V], optional) and per-block partials of
+// sum_mu Re Tr(U_mu A_mu) (gauge_force_blocks of them, optional).
+int gauge_force_blocks(const Geom& g);
+hipError_t launch_gauge_force(const Geom& g, const double* U, double beta, double* F, double* partials,
+                              hipStream_t s);
+
 // Chebyshev reverse sweep source term: tb[v] += sum_y coef[(v * n_y + y) * n_k + k] Y[y][v] (FP64;
 // Y laid out [n_y][n_rhs][n_reals], coef on the device)
 hipError_t launch_cheb_source(double* tb, const double* Y, const double* coef, int32_t n_rhs, int32_t n_y,

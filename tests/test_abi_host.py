@@ -149,6 +149,17 @@ def test_workspace_query():
     assert 4 * 2 * fb <= b8 <= b7 < 4 * 2 * fb + 4096
 
 
+def test_gauge_force_workspace_and_validation():
+    L = _lib.lattice_arg((4, 4, 4, 4))
+    assert _lib.lib().rmh_workspace_bytes(9, L, 0, 1, 0, 0, 0) == 512      # block partials + the sum
+    S = np.zeros(1)
+    f = _lib.lib().rmh_wilson_gauge_force
+    assert f(L, FAKE, 6.0, None, None, None, 0, None) == 1                  # nothing requested
+    assert f(L, FAKE, float("nan"), FAKE + 2**20, None, None, 0, None) == 1
+    assert f(L, FAKE, 6.0, FAKE + 2**20, S.ctypes.data_as(_lib.P_f64), FAKE + 2**22, 256, None) == 3
+    assert f(L, FAKE, 6.0, FAKE + 4096, None, None, 0, None) == 1           # F overlaps U
+
+
 def test_validation_cheb_bwd():
     L = _lib.lattice_arg((4, 4, 4, 4))
     fb = 32 * 256 * 8
