@@ -127,3 +127,11 @@ def kinetic_energy(U, P, L, c, r, sigma, tol: float = 1e-13):
     """K[n] = 1/2 <Y_n, Y_n> with Y = R(Delta) P (Eq. 5 with M^{-1} = R^2, Eq. 6)."""
     Y, _ = rational_apply(U, P, L, c, r, sigma, tol)
     return 0.5 * np.sum((Y * Y).reshape(Y.shape[0], -1), axis=1), Y
+
+
+def heatbath_momenta(U, xi, L, kappa: float, c, r, sigma, tol: float = 1e-13):
+    """Heat-bath momenta for the kinetic term 1/2 P M^{-1} P with M = R^{-2} (section 3):
+    P = M^{1/2} xi = R(Delta)^{-1} xi.  For the pole sets with R^2 ~ y^{-1}, y = 1 - kappa + kappa
+    Delta, R^{-1} ~ y^{1/2} = y R, so P = (1 - kappa) R xi + kappa Delta (R xi)."""
+    y, _ = rational_apply(U, xi, L, c, r, sigma, tol)
+    return (1.0 - kappa) * y + kappa * laplacian(U, y, L)
