@@ -131,7 +131,8 @@ typedef enum {
   RMH_OP_KINETIC_FORCE = 6,
   RMH_OP_CHEB_FILTER_BWD = 7,
   RMH_OP_POWER_SPECTRUM_BWD = 8,
-  RMH_OP_GAUGE_FORCE = 9
+  RMH_OP_GAUGE_FORCE = 9,
+  RMH_OP_HEATBATH = 10
 } rmh_op;
 
 /* ---------------------------------------------------------------------------------------- */
@@ -259,6 +260,17 @@ rmh_status rmh_rational_kappa(double kappa, int32_t n, double* c, double* r, dou
 rmh_status rmh_rational_apply(const int32_t L[4], const double* U, const double* x, int32_t n_rhs,
                               const rmh_rational* rat, const rmh_solver* solver, double* y, double* x_poles,
                               double* K, rmh_stats* stats, void* ws, size_t ws_bytes, rmh_stream stream);
+
+/* RMHMC heat-bath momenta for the kinetic term 1/2 P M^{-1} P with M = R(Delta)^{-2} (section 3):
+ * P = M^{1/2} xi = R(Delta)^{-1} xi for Gaussian xi.  rat must be a pole set with
+ * R(Delta)^2 ~ (1 - kappa + kappa Delta)^{-1} (rmh_rational_kappa(kappa, n)), so that
+ * R^{-1} ~ (1 - kappa + kappa Delta) R: one multi-shift solve (to the solver's true residual)
+ * and one stencil.  xi, P: device FP64 [n_rhs][4][8][V]; U: device FP64.  kappa in (0, 1].
+ * Workspace: RMH_OP_HEATBATH (aux = n_poles, degree = solver basis, mode).  Synchronizes the
+ * stream.  Projection onto a spectral window (section 3) is rmh_cheb_filter of P. */
+rmh_status rmh_heatbath_momenta(const int32_t L[4], const double* U, const double* xi, int32_t n_rhs, double kappa,
+                                const rmh_rational* rat, const rmh_solver* solver, double* P, rmh_stats* stats,
+                                void* ws, size_t ws_bytes, rmh_stream stream);
 
 /* Vector-Jacobian product of y = R(Delta[U]) x with cotangent g (both FP64 [n_rhs][4][8][V]):
  * grad_x (optional, device FP64) = R(Delta) g;

@@ -19,7 +19,7 @@ STATUS_NAMES = {
 RMH_F64, RMH_F32 = 0, 1
 OP_LAPLACIAN, OP_LAPLACIAN_BWD, OP_POWER_SPECTRUM, OP_CHEB_FILTER = 0, 1, 2, 3
 OP_RATIONAL_APPLY, OP_RATIONAL_APPLY_BWD, OP_KINETIC_FORCE = 4, 5, 6
-OP_CHEB_FILTER_BWD, OP_POWER_SPECTRUM_BWD, OP_GAUGE_FORCE = 7, 8, 9
+OP_CHEB_FILTER_BWD, OP_POWER_SPECTRUM_BWD, OP_GAUGE_FORCE, OP_HEATBATH = 7, 8, 9, 10
 
 c_i32, c_i64, c_f64, c_sz, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t, ctypes.c_void_p
 P_i32 = ctypes.POINTER(c_i32)
@@ -68,6 +68,8 @@ SIGNATURES = {
     "rmh_cheb_filter": (c_i32, [P_i32, c_vp, c_i32, c_vp, c_i32, ctypes.POINTER(RmhCheb), c_vp, c_vp, c_sz, c_vp]),
     "rmh_cheb_filter_bwd": (c_i32, [P_i32, c_vp, c_vp, c_vp, c_i32, ctypes.POINTER(RmhCheb), c_vp, c_vp, c_i32,
                                     c_vp, c_sz, c_vp]),
+    "rmh_heatbath_momenta": (c_i32, [P_i32, c_vp, c_vp, c_i32, c_f64, ctypes.POINTER(RmhRational),
+                                     ctypes.POINTER(RmhSolver), c_vp, ctypes.POINTER(RmhStats), c_vp, c_sz, c_vp]),
     "rmh_wilson_gauge_force": (c_i32, [P_i32, c_vp, c_f64, c_vp, P_f64, c_vp, c_sz, c_vp]),
     "rmh_power_spectrum_bwd": (c_i32, [P_i32, c_vp, c_vp, c_i32, ctypes.POINTER(RmhCheb), P_f64, c_vp, c_vp,
                                        c_i32, c_vp, c_sz, c_vp]),

@@ -273,6 +273,21 @@ def power_spectrum_bwd(L, U, F, gamma, degree: int, n_windows: int, edges=None, 
     return gF, go
 
 
+def heatbath_momenta(L, U, xi, kappa: float, rat: Rational, solver: Solver = Solver()):
+    """dict(P, stats): P = R(Delta)^{-1} xi for a pole set with R^2 ~ (1 - kappa + kappa Delta)^{-1}."""
+    _require_f64(U, xi)
+    n = xi.shape[0]
+    P = torch.empty_like(xi)
+    stats = L_.RmhStats()
+    ws = _workspace(workspace_bytes(L_.OP_HEATBATH, L, RMH_F64, n, len(rat.r), solver.basis, solver.mode),
+                    xi.device)
+    rs, ss = rat.c_struct(), solver.c_struct()
+    check(lib().rmh_heatbath_momenta(lattice_arg(L), _dev(U, "U"), _dev(xi, "xi"), n, float(kappa),
+                                     ctypes.byref(rs), ctypes.byref(ss), P.data_ptr(), ctypes.byref(stats),
+                                     ws.data_ptr(), ws.numel(), _stream(xi.device)), "rmh_heatbath_momenta")
+    return {"P": P, "stats": stats.as_dict()}
+
+
 def wilson_gauge_force(L, U, beta: float, want_action: bool = True):
     """(F_G (4, 8, V) FP64 on the device, S_W or None) for FP64 SoA links U."""
     _require_f64(U)

@@ -842,10 +842,9 @@ void plan_rational(Carver& c, RationalPlan& rp, const Geom& g, int32_t n_rhs, in
   const int64_t n = field_reals(g);
   plan_solve(c, rp.sp, g, n_rhs, n_poles, mode, basis);
   rp.X = c.take<double>((size_t)n_rhs * n_poles * n);
-  if (op != RMH_OP_RATIONAL_APPLY) {
+  if (op == RMH_OP_RATIONAL_APPLY_BWD || op == RMH_OP_KINETIC_FORCE)
     rp.Z = c.take<double>((size_t)n_rhs * n_poles * n);
-    rp.Y = c.take<double>((size_t)n_rhs * n);
-  }
+  if (op != RMH_OP_RATIONAL_APPLY) rp.Y = c.take<double>((size_t)n_rhs * n);
   rp.coef = c.take<double>(n_poles + 1);
   rp.partK = c.take<double>((size_t)n_rhs * red_num_blocks(n));
   rp.sumsK = c.take<double>(n_rhs);
@@ -1100,7 +1099,8 @@ size_t rmh_workspace_bytes(int32_t op, const int32_t L[4], int32_t dtype, int32_
       break;
     case RMH_OP_RATIONAL_APPLY:
     case RMH_OP_RATIONAL_APPLY_BWD:
-    case RMH_OP_KINETIC_FORCE: {
+    case RMH_OP_KINETIC_FORCE:
+    case RMH_OP_HEATBATH: {
       if (aux < 1) {
         fail(RMH_E_ARG, "n_poles < 1");
         return 0;
@@ -1564,6 +1564,57 @@ rmh_status rmh_rational_apply(const int32_t L[4], const double* U, const double*
   }
   fill_stats(stats, &res, 1, now_s() - t0);
   return status_of(res, "rational_apply");
+}
+
+rmh_status rmh_heatbath_momenta(const int32_t L[4], const double* U, const double* xi, int32_t n_rhs, double kappa,
+                                const rmh_rational* rat, const rmh_solver* solver, double* P, rmh_stats* stats,
+                                void* ws, size_t ws_bytes, rmh_stream stream) {
+  const double t0 = now_s();
+  Geom g;
+  RMH_TRY(rational_common(L, U, n_rhs, rat, solver, &g));
+  if (!(kappa > 0.0 && kappa <= 1.0)) return fail(RMH_E_ARG, "kappa = %g must lie in (0, 1]", kappa);
+  if (n_rhs == 0) return RMH_OK;
+  RMH_TRY(check_ptr(xi, "xi"));
+  RMH_TRY(check_ptr(P, "P"));
+  RMH_TRY(check_ptr(ws, "ws"));
+  const int32_t np = rat->n_poles;
+  Carver c(ws);
+  RationalPlan rp;
+  plan_rational(c, rp, g, n_rhs, np, solver->mode, solver->basis, RMH_OP_HEATBATH);
+  if (c.off > ws_bytes) return fail(RMH_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, c.off);
+  const int64_t n = field_reals(g);
+  const size_t fb = (size_t)n_rhs * n * 8;
+  if (overlap(P, fb, xi, fb) || overlap(P, fb, ws, c.off) || overlap(P, fb, U, (size_t)72 * g.V * 8) ||
+      overlap(ws, c.off, xi, fb) || overlap(ws, c.off, U, (size_t)72 * g.V * 8))
+    return fail(RMH_E_ARG, "overlapping buffers");
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<double> sig(rat->sigma, rat->sigma + np);
+  SolveResult res;
+  RMH_TRY(solve_all(rp.sp, U, xi, rp.X, sig, *solver, s, &res));
+  std::vector<double> coef(np + 1);
+  coef[0] = rat->c;
+  for (int j = 0; j < np; ++j) coef[1 + j] = rat->r[j];
+  RMH_TRY(h2d(rp.coef, coef.data(), coef.size() * 8, s));
+  HIP_TRY(launch_rational_combine(xi, rp.X, n_rhs, np, rp.coef, rp.Y, n, nullptr, s));
+  // P = (1 - kappa) y + kappa Delta y = -kappa H y + (1 + 7 kappa) y,  y = R(Delta) xi
+  HopArgs<double> h{};
+  h.g = g;
+  h.U = U;
+  h.x = rp.Y;
+  h.x_mul = 1;
+  h.z_div = 1;
+  h.out = P;
+  h.a = -kappa;
+  h.b = 1.0 + 7.0 * kappa;
+  h.n_rhs = n_rhs;
+  h.store = 1;
+  {
+    ProfScope ps(RMH_PROF_STENCIL, hop_bytes(g, n_rhs, 8, false, true), s, n_rhs);
+    HIP_TRY(launch_hop<double>(h, hop_config(g, RMH_F64, n_rhs, 6), s));
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  fill_stats(stats, &res, 1, now_s() - t0);
+  return status_of(res, "heatbath_momenta");
 }
 
 // second solve (source g) and the force; X holds the pole solutions of the first solve

@@ -149,6 +149,22 @@ def test_workspace_query():
     assert 4 * 2 * fb <= b8 <= b7 < 4 * 2 * fb + 4096
 
 
+def test_heatbath_validation():
+    L = _lib.lattice_arg((2, 2, 2, 2))
+    r = np.array([1.0, 2.0])
+    sg = np.array([0.5, 1.0])
+    rat = _lib.RmhRational(0.0, 2, r.ctypes.data_as(_lib.P_f64), sg.ctypes.data_as(_lib.P_f64))
+    sv = _lib.RmhSolver(1e-10, 100, 0, 0.1, 8, 0.0, 0)
+    f = _lib.lib().rmh_heatbath_momenta
+    for kappa in (0.0, 1.5, float("nan")):
+        assert f(L, FAKE, FAKE + 2**20, 1, kappa, ctypes.byref(rat), ctypes.byref(sv), FAKE + 2**21, None,
+                 FAKE + 2**22, 1 << 30, None) == 1
+    assert f(L, FAKE, FAKE + 2**20, 1, 0.5, ctypes.byref(rat), ctypes.byref(sv), FAKE + 2**21, None,
+             FAKE + 2**22, 1024, None) == 3                                   # workspace too small
+    assert f(L, FAKE, FAKE + 2**20, 1, 0.5, ctypes.byref(rat), ctypes.byref(sv), FAKE + 2**20, None,
+             FAKE + 2**22, 1 << 30, None) == 1                                # P aliases xi
+
+
 def test_gauge_force_workspace_and_validation():
     L = _lib.lattice_arg((4, 4, 4, 4))
     assert _lib.lib().rmh_workspace_bytes(9, L, 0, 1, 0, 0, 0) == 512      # block partials + the sum

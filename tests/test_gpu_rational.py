@@ -12,7 +12,7 @@ import pytest
 import torch
 from scipy.linalg import expm
 
-from gpu_helpers import announce, dev, setup
+from gpu_helpers import announce, dev, rel_max, setup
 from oracle import force as oforce
 from oracle import lattice, su3
 from oracle import laplacian as olap
@@ -252,3 +252,52 @@ def test_solver_error_paths():
     zero = torch.zeros_like(Pd)
     out = api.rational_apply(L, Ud, zero, rat, api.Solver(tol=1e-10))
     assert bool(torch.all(out["y"] == 0)) and out["K"][0] == 0.0
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_heatbath_momenta_parity(mode):
+    """P = R(Delta)^{-1} xi against the oracle's composition (its own solves and Laplacian): both
+    solve to tol, so they differ by at most (1 + 15 kappa) sum_j |r_j| (tol_g + tol_o) ||xi|| / sigma_j
+    (the factor bounds ||1 - kappa + kappa Delta|| on [0, 16])."""
+    L = (4, 4, 4, 6)
+    announce(f"heatbath parity mode={mode}")
+    U, xi, Ud, xid = setup(L, "eps", 0.5, 83, n=2)
+    kappa = 0.9
+    rat = _rat_kappa(kappa, 12)
+    tol = 1e-10
+    out = api.heatbath_momenta(L, Ud, xid, kappa, rat, api.Solver(tol=tol, mode=mode))
+    ref = orat.heatbath_momenta(U, xi, L, kappa, rat.c, rat.r, rat.sigma, tol=1e-13)
+    P = out["P"].cpu().numpy()
+    for i in range(2):
+        bound = (1 + 15 * kappa) * _y_bound(rat, tol, 1e-13, np.linalg.norm(xi[i]))
+        assert np.linalg.norm(P[i] - ref[i]) <= bound
+    assert out["stats"]["true_relres_max"] <= tol
+
+
+def test_heatbath_momenta_16_properties():
+    """16^4: at U = 1 the momenta are the exact square root (1 - kappa + kappa k^2)^{1/2} up to the
+    pole set's accuracy (FFT, per plane wave); on eps links R(Delta) P = xi to that accuracy; and
+    a window projection of P through the filter sums back to P."""
+    L = (16, 16, 16, 16)
+    kappa = 0.5
+    rat = _rat_kappa(kappa, 12)           # R^2 y accurate to 2.3e-11 on [0, 16]
+    sv = api.Solver(tol=1e-12)
+    announce("heatbath 16^4 U=1")
+    U, xi, Ud, xid = setup(L, "unit", 0.0, 84, n=1)
+    P = api.heatbath_momenta(L, Ud, xid, kappa, rat, sv)["P"].cpu().numpy()[0]
+    shp = (16, 16, 16, 16)
+    ks = np.meshgrid(*[2 * np.pi * np.fft.fftfreq(n) for n in shp], indexing="ij")
+    lam = sum(4 * np.sin(k / 2) ** 2 for k in ks)
+    Xl = xi[0].reshape((4, 8) + shp)
+    exact = np.fft.ifftn(np.fft.fftn(Xl, axes=(2, 3, 4, 5)) * np.sqrt(1 - kappa + kappa * lam),
+                         axes=(2, 3, 4, 5)).real.reshape(P.shape)
+    assert np.abs(P - exact).max() <= 1e-9 * np.abs(exact).max()
+    announce("heatbath 16^4 eps links")
+    U, xi, Ud, xid = setup(L, "eps", 0.5, 85, n=1)
+    Pd = api.heatbath_momenta(L, Ud, xid, kappa, rat, sv)["P"]
+    back = api.rational_apply(L, Ud, Pd, rat, sv)["y"].cpu().numpy()
+    assert np.abs(back - xi).max() <= 1e-9 * np.abs(xi).max()
+    # projection onto four windows (section 3's window-projected momenta) sums back to P (partition
+    # of unity of the undamped windows holds for any degree)
+    yw = api.cheb_filter(L, Ud, Pd, 32, 4, kernel=0).sum(dim=0)
+    assert rel_max(yw.cpu().numpy(), Pd.cpu().numpy()) <= 1e-12
