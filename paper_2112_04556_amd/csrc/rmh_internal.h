@@ -26,6 +26,9 @@ enum HopForm : int32_t { kFormAdjoint = 0, kFormMatrix = 1, kFormStream = 2 };
 // order = 1 walks the blocks with x3 fastest, then x2, then the (x0, x1) chunks, so the blocks
 // holding a site's x2 and x3 neighbours are resident at the same time and share the L2; it needs
 // L0 * L1 to be a multiple of the sites per block (else the lexicographic order 0 is used).
+// order = 2 (hop split) gives each site four lanes of one wave, lane group mu doing the two hops
+// along mu, summed by wave shuffles: four times the threads of order 0, for lattices too small to
+// fill the chip (walk is then ignored).
 // walk = K > 0: each thread walks K consecutive sites along x3 (K divides L3), carrying the
 // centre field, the x-3 field and the x-3 link in registers, so every x3-direction field and
 // link is fetched once per column instead of being re-read from the caches.
@@ -70,6 +73,8 @@ struct HopArgs {
 int hop_num_blocks(const Geom& g, const HopConfig& cfg);
 // whether the x3-fastest block order applies to this lattice and configuration
 int hop_order_ok(const Geom& g, const HopConfig& cfg);
+// whether the hop-split shape applies (order 2)
+int hop_split_ok(const HopConfig& cfg);
 // whether the x3 walk applies (K divides L3)
 int hop_walk_ok(const Geom& g, const HopConfig& cfg);
 // upper bound of hop_num_blocks over every configuration (32 sites per block at least)

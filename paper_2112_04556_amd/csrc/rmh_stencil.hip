@@ -155,6 +155,97 @@ __global__ void __launch_bounds__(256) k_hop(const HopArgs<T> A, int32_t xcd, in
   }
 }
 
+// Hop-split variant of k_hop for lattices too small to fill the chip with one thread per site:
+// the four lanes l, l+16, l+32, l+48 of a wave share a site, lane group mu doing the forward and the
+// backward hop along mu; two butterfly shuffles sum the four partial results (in the fixed order
+// (mu0 + mu1) + (mu2 + mu3)), and each of the four lanes stores a quarter of the components.  A wave
+// covers 16 consecutive sites for one direction group; a block of B threads has B/64 waves.
+template <typename T, int FORM, int NV, bool DOTS, bool FILTER>
+__global__ void __launch_bounds__(256) k_hop_split(const HopArgs<T> A, int32_t xcd) {
+  constexpr int G = 4 / NV;
+  const int32_t v = blockIdx.y;
+  if (A.run && A.run[(int64_t)v * A.run_stride] == 0) return;
+  const int32_t V = A.g.V;
+  const int32_t lb = remap_block(blockIdx.x, gridDim.x, xcd);
+  const int32_t wi = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int32_t W = blockDim.x >> 6;
+  const int32_t grp = wi % G;   // wave-uniform direction group
+  const int32_t spb = (W / G) * 16;
+  const int32_t lane = threadIdx.x & 63;
+  const int32_t mu = lane >> 4;
+  const int32_t s = lb * spb + (wi / G) * 16 + (lane & 15);
+  const int nu0 = grp * NV;
+  const bool live = s < V;
+  const int64_t FV = 32 * (int64_t)V;
+  const T* __restrict__ xf = A.x + ((int64_t)v * A.x_mul + A.x_add) * FV;
+  T acc[NV][8];
+#pragma unroll
+  for (int i = 0; i < NV; ++i)
+#pragma unroll
+    for (int a = 0; a < 8; ++a) acc[i][a] = T(0);
+  if (live) {
+    int32_t xc[4];
+    site_coords(A.g, s, xc);
+    const T* __restrict__ Um = A.U + (int64_t)mu * 18 * V;
+    hop_term<T, FORM, NV, true>(Um, site_shift(A.g, s, xc, mu, -1), xf, nu0, V, acc);
+    hop_term_fwd<T, FORM, NV>(Um, s, site_shift(A.g, s, xc, mu, +1), xf, nu0, V, acc);
+  }
+#pragma unroll
+  for (int i = 0; i < NV; ++i)
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      acc[i][a] += __shfl_xor(acc[i][a], 16, 64);
+      acc[i][a] += __shfl_xor(acc[i][a], 32, 64);
+    }
+  // lane group mu keeps the components 4q + mu of its direction group (q < 2 NV): a 4-way select
+  // with compile-time register indices, then one full-wave load/store per q
+  double dsum[3] = {0.0, 0.0, 0.0};
+  if (live) {
+    const T ca = T(A.a);
+    const T cb = T(A.b_rhs ? A.b_rhs[v] : A.b);
+    const T cc = T(A.c);
+    const T* zf = A.z ? A.z + (int64_t)(v / A.z_div) * FV : nullptr;  // may alias out
+    T* outf = A.out + (int64_t)v * FV;
+#pragma unroll
+    for (int q = 0; q < 2 * NV; ++q) {
+      const int i = q >> 1, a0 = (q & 1) * 4;
+      const T h = mu == 0 ? acc[i][a0] : mu == 1 ? acc[i][a0 + 1] : mu == 2 ? acc[i][a0 + 2] : acc[i][a0 + 3];
+      const int64_t e = (int64_t)(nu0 * 8 + 4 * q + mu) * V + s;
+      const T xv = xf[e];
+      T o = fmadd(ca, h, cb * xv);
+      if (zf) o = fmadd(cc, zf[e], o);
+      if (A.store) outf[e] = o;
+      if (DOTS) {
+        const double xd = (double)xv, od = (double)o;
+        dsum[0] = fma(xd, xd, dsum[0]);
+        dsum[1] = fma(od, xd, dsum[1]);
+        dsum[2] = fma(od, od, dsum[2]);
+      }
+      if (FILTER) {
+        T* y = A.yacc + (int64_t)v * FV + e;
+        for (int w = 0; w < A.n_w; ++w) {
+          T* yw = y + w * A.yacc_stride;
+          if (A.filter_first)
+            *yw = fmadd(T(A.wcoef[w]), o, T(A.wcoef0[w]) * xv);
+          else
+            *yw = fmadd(T(A.wcoef[w]), o, *yw);
+        }
+      }
+    }
+  }
+  if (DOTS) {
+    __shared__ double lds[3][16];
+    block_sum<3>(dsum, lds);
+    if (threadIdx.x == 0) {
+      const int32_t nblk = gridDim.x;
+      double* p = A.partials + (int64_t)v * 3 * nblk + blockIdx.x;
+      if (A.dot_mask & 1) p[0] = dsum[0];
+      if (A.dot_mask & 2) p[nblk] = dsum[1];
+      if (A.dot_mask & 4) p[2 * nblk] = dsum[2];
+    }
+  }
+}
+
 // Walking variant of k_hop: a block of B threads covers B * NV / 4 columns (x0, x1, x2) of the
 // lattice; each thread walks K consecutive x3 values of its column.  Per step the x0, x1, x2
 // hops load their links and neighbours as in k_hop; the x3 forward hop loads U_3(x) and
@@ -291,7 +382,14 @@ int hop_walk_ok(const Geom& g, const HopConfig& cfg) {
   return (cfg.walk > 0 && (g.L3 % cfg.walk) == 0) ? 1 : 0;
 }
 
+// hop-split shape (order 2): each wave covers 16 sites of one direction group
+int hop_split_ok(const HopConfig& cfg) { return (cfg.order == 2 && (cfg.block / 64) % (4 / cfg.nv) == 0) ? 1 : 0; }
+
 int hop_num_blocks(const Geom& g, const HopConfig& cfg) {
+  if (hop_split_ok(cfg)) {
+    const int spb = (cfg.block / 64) / (4 / cfg.nv) * 16;
+    return (g.V + spb - 1) / spb;
+  }
   const int spb = cfg.block * cfg.nv / 4;
   if (hop_walk_ok(g, cfg)) {
     const int P = g.L0 * g.L1 * g.L2;
@@ -310,7 +408,18 @@ static hipError_t launch_hop_form(const HopArgs<T>& A, const HopConfig& cfg, hip
   dim3 grid(hop_num_blocks(A.g, cfg), A.n_rhs), block(cfg.block);
   const bool dots = A.partials && A.dot_mask;
   const bool filt = A.yacc && A.n_w > 0;
-  const int32_t order = (cfg.order && hop_order_ok(A.g, cfg)) ? 1 : 0;
+  if (hop_split_ok(cfg)) {
+    if (dots && filt)
+      hipLaunchKernelGGL((k_hop_split<T, FORM, NV, true, true>), grid, block, 0, s, A, cfg.xcd_remap);
+    else if (dots)
+      hipLaunchKernelGGL((k_hop_split<T, FORM, NV, true, false>), grid, block, 0, s, A, cfg.xcd_remap);
+    else if (filt)
+      hipLaunchKernelGGL((k_hop_split<T, FORM, NV, false, true>), grid, block, 0, s, A, cfg.xcd_remap);
+    else
+      hipLaunchKernelGGL((k_hop_split<T, FORM, NV, false, false>), grid, block, 0, s, A, cfg.xcd_remap);
+    return hipGetLastError();
+  }
+  const int32_t order = (cfg.order == 1 && hop_order_ok(A.g, cfg)) ? 1 : 0;
   if (hop_walk_ok(A.g, cfg)) {
     const int32_t K = cfg.walk;
     if (dots && filt)

@@ -26,8 +26,9 @@ Key key_of(const Geom& g, int32_t dtype, int32_t n_rhs) {
 
 // Untuned defaults, from the sweeps of the autotuner: on lattices of a million sites and more
 // the x3-walking kernel with four directions per thread (the streamed form in FP64, the
-// materialised adjoint matrix in FP32); on smaller ones two directions per thread in the
-// x3-fastest order, which keeps x3 neighbours in cache.
+// materialised adjoint matrix in FP32); on smaller ones the hop-split shape (four lanes per
+// site, one per direction), whose four times as many waves hide the memory latency that one
+// thread per site leaves exposed when the lattice gives only a few waves per SIMD.
 HopConfig defaults(const Geom& g, int32_t dtype) {
   HopConfig c;
   if (g.V >= (1 << 20)) {
@@ -47,13 +48,13 @@ HopConfig defaults(const Geom& g, int32_t dtype) {
       }
     }
   } else {
-    c.form = dtype == RMH_F64 ? kFormAdjoint : kFormMatrix;
-    c.block = 256;
-    c.xcd_remap = 1;
-    c.nv = 2;
+    // the hop-split shape: four lanes per site
+    c.form = dtype == RMH_F64 ? kFormMatrix : kFormStream;
+    c.block = dtype == RMH_F64 ? 128 : 256;
+    c.xcd_remap = dtype == RMH_F64 ? 0 : 1;
+    c.nv = dtype == RMH_F64 ? 2 : 4;
     c.walk = 0;
-    c.order = 1;
-    if (!hop_order_ok(g, c)) c.order = 0;
+    c.order = 2;
   }
   if (const char* e = getenv("RMH_HOP_FORM")) c.form = atoi(e);
   if (const char* e = getenv("RMH_HOP_BLOCK")) {

@@ -198,3 +198,24 @@ def test_validation_cheb_bwd():
     nan = np.array([1.0, np.nan, 0.0])
     assert g(L, FAKE, FAKE + 2**20, 1, ctypes.byref(st), nan.ctypes.data_as(_lib.P_f64), FAKE + 2**23, None, 0,
              FAKE + 2**22, 1 << 30, None) == 1                                # non-finite gamma
+
+
+def test_tune_set_validation():
+    """The launch cache is host state: every accepted and rejected configuration, no GPU."""
+    f = _lib.lib().rmh_tune_set
+    L = _lib.lattice_arg((4, 4, 4, 4))
+    ok = [(0, 256, 1, 4, 0, 0), (1, 64, 0, 4, 1, 0), (2, 128, 1, 2, 2, 0), (1, 256, 1, 1, 2, 0),
+          (2, 128, 0, 4, 0, 4)]
+    for form, block, xcd, nv, order, walk in ok:
+        assert f(L, 0, 1, form, block, xcd, nv, order, walk) == 0, (form, block, nv, order, walk)
+    bad = [(3, 256, 1, 4, 0, 0),     # form
+           (0, 96, 1, 4, 0, 0),      # block
+           (0, 256, 1, 3, 0, 0),     # nv
+           (0, 256, 1, 1, 0, 0),     # nv = 1 needs form 1
+           (0, 64, 1, 2, 2, 0),      # half a wave per direction group
+           (0, 256, 1, 4, 3, 0),     # order
+           (0, 256, 1, 4, -1, 0),
+           (0, 256, 1, 4, 0, 65)]    # walk
+    for form, block, xcd, nv, order, walk in bad:
+        assert f(L, 0, 1, form, block, xcd, nv, order, walk) == 1, (form, block, nv, order, walk)   # RMH_E_ARG
+    assert _lib.lib().rmh_tune_clear() == 0

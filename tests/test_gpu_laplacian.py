@@ -111,6 +111,51 @@ def test_laplacian_configs_batched_and_deterministic(dtype):
     assert torch.equal(y_a, y_b)
 
 
+@pytest.mark.parametrize("L,kind,seed", CASES)
+def test_laplacian_hop_split_parity(L, kind, seed):
+    """order = 2: four lanes per site, one per direction, summed by wave shuffles."""
+    announce(f"laplacian hop split {L} {kind}")
+    U, P, Ud, Pd = setup(L, kind, 0.5, seed, n=2)
+    ref = olap.laplacian(U, P, L, 0.4)
+    U32, P32 = Ud.float(), Pd.float()
+    for form in (0, 1, 2):
+        for nv, block in ((4, 64), (4, 256), (2, 128), (2, 256)) + (((1, 256),) if form == 1 else ()):
+            api.tune_set(L, torch.float64, 2, form, block, 1, nv, 2, 0)
+            y = api.laplacian_apply(L, Ud, Pd, 0.4).cpu().numpy()
+            assert rel_max(y, ref) <= 1e-12, (form, nv, block)
+            api.tune_set(L, torch.float32, 2, form, block, 0, nv, 2, 0)
+            y32 = api.laplacian_apply(L, U32, P32, 0.4).cpu().numpy().astype(np.float64)
+            assert np.abs(y32 - ref).max() <= 1e-5 * np.abs(ref).max(), (form, nv, block)
+    with pytest.raises(RmhError):
+        api.tune_set(L, torch.float64, 2, 0, 64, 1, 2, 2, 0)    # two direction groups need two waves
+    with pytest.raises(RmhError):
+        api.tune_set(L, torch.float64, 2, 0, 256, 1, 4, 3, 0)   # no order 3
+    api.tune_clear()
+
+
+def test_hop_split_fused_epilogues():
+    """The hop-split kernel's dot products (spectrum moments, CG) and filter accumulation give the
+    site-per-thread kernel's results to rounding."""
+    L = (4, 3, 2, 5)    # V = 120: two waves' worth of split sites and a ragged tail
+    announce(f"hop split fused epilogues {L}")
+    U, F, Ud, Fd = setup(L, "eps", 0.5, 9, n=2)
+    rat = api.rational_kappa(0.8, 8)
+    runs = []
+    for order in (0, 2):
+        api.tune_set(L, torch.float64, 1, 1, 256, 1, 2, order, 0)   # nearest-batch entry: every launch
+        mom, pw = api.power_spectrum(L, Ud, Fd, 30, 6)
+        yf = api.cheb_filter(L, Ud, Fd, 30, 6).cpu().numpy()
+        out = api.rational_apply(L, Ud, Fd, rat, api.Solver(tol=1e-12))
+        runs.append((mom, pw, yf, out["y"].cpu().numpy(), out["stats"]["true_relres_max"]))
+    api.tune_clear()
+    (m0, p0, f0, y0, r0), (m1, p1, f1, y1, r1) = runs
+    assert np.all(np.abs(m1 - m0) <= 1e-12 * m0[:, :1])
+    assert np.all(np.abs(p1 - p0) <= 1e-12 * m0[:, :1])
+    assert rel_max(f1, f0) <= 1e-12
+    assert r0 <= 1e-12 and r1 <= 1e-12
+    assert rel_max(y1, y0) <= 1e-10
+
+
 def test_laplacian_empty_batch_and_autotune():
     L = (4, 4, 4, 4)
     _, _, Ud, Pd = setup(L, "eps", 0.3, 1, n=1)
