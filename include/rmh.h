@@ -211,7 +211,10 @@ rmh_status rmh_power_ratio(const rmh_cheb* cheb, const double* trace_moments, co
 rmh_status rmh_trace_moments_free(const int32_t L[4], int32_t degree, double* trace_moments);
 
 /* y[w][n] = B_w x_n for every window (vector output).  x: device [n_rhs][4][8][V]; y: device
- * [n_windows][n_rhs][4][8][V]; dtype for both.  At most 64 windows.  Runs degree sweeps. */
+ * [n_windows][n_rhs][4][8][V]; dtype for both.  At most 64 windows.  Runs degree sweeps; the
+ * recursion vectors go into a workspace ring of min(16, max(3, degree)) fields and are folded
+ * into y once per ring (sums in FP64), so y is read and written once per 16 sweeps.  The
+ * window coefficients are copied to the workspace first (the stream is synchronized once). */
 rmh_status rmh_cheb_filter(const int32_t L[4], const void* U, int32_t dtype, const void* x, int32_t n_rhs,
                            const rmh_cheb* cheb, void* y, void* ws, size_t ws_bytes, rmh_stream stream);
 
@@ -340,7 +343,8 @@ typedef enum {
   RMH_PROF_CG_RESIDUAL = 1,  /* the seed's vector updates: r -= alpha A p with <r, r>, p = r + beta p */
   RMH_PROF_CG_SHIFTS = 2,    /* folds of the shift solutions and directions over the residual ring */
   RMH_PROF_FORCE = 3,        /* link derivative */
-  RMH_PROF_N = 4
+  RMH_PROF_CHEB_FOLD = 4,    /* folds of the Chebyshev filter's recursion vectors into its window outputs */
+  RMH_PROF_N = 5
 } rmh_prof_class;
 
 /* enable != 0: record a HIP event pair on the call's stream around every launch of the classes

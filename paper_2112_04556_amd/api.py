@@ -405,7 +405,7 @@ def autotune_laplacian(L, U, x, reps: int = 5):
 # ------------------------------------------------------------------------------------------
 # kernel timing
 
-PROF_CLASSES = {"stencil": 0, "cg_residual": 1, "cg_shifts": 2, "force": 3}
+PROF_CLASSES = {"stencil": 0, "cg_residual": 1, "cg_shifts": 2, "force": 3, "cheb_fold": 4}
 
 
 def profile_enable(on: bool = True) -> None:

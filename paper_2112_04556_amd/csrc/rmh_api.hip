@@ -220,6 +220,25 @@ ChebPlan plan_cheb(Carver& c, const Geom& g, int32_t dtype, int32_t n_rhs, int32
   return p;
 }
 
+// The filter keeps its recursion vectors in a ring of R slots and folds them into the window
+// outputs every R sweeps (and at the end): each output is read and written once per R sweeps
+// instead of once per sweep.
+struct FilterPlan {
+  void* ring;     // [R][n_rhs][4][8][V]
+  double* coef;   // [nw][D + 1]
+  int32_t R;
+};
+
+int32_t filter_ring_slots(int32_t D) { return std::min(kMaxFold, std::max(3, D)); }
+
+FilterPlan plan_filter(Carver& c, const Geom& g, int32_t dtype, int32_t n_rhs, int32_t D, int32_t nw) {
+  FilterPlan p{};
+  p.R = filter_ring_slots(D);
+  p.ring = c.take<char>((size_t)p.R * n_rhs * 32 * g.V * dsize(dtype));
+  p.coef = c.take<double>((size_t)std::max(1, nw) * (D + 1));
+  return p;
+}
+
 // ------------------------------------------------------------------------------------------
 // multi-shift CG engine
 
@@ -899,48 +918,50 @@ rmh_status power_spectrum_t(const Geom& g, const T* U, const T* F, int32_t n_rhs
 
 template <typename T>
 rmh_status cheb_filter_t(const Geom& g, const T* U, const T* x, int32_t n_rhs, int32_t D, int32_t nw,
-                                const std::vector<double>& coef, const ChebPlan& cp, T* y, hipStream_t s) {
+                         const std::vector<double>& coef, const FilterPlan& fp, T* y, hipStream_t s) {
   const HopConfig cfg = hop_config(g, sizeof(T) == 8 ? RMH_F64 : RMH_F32, n_rhs, 4);
-  T* A = (T*)cp.bufA;
-  T* B = (T*)cp.bufB;
-  const T* cur = x;
-  const T* prev = nullptr;
+  const int64_t n = (int64_t)n_rhs * 32 * g.V;
+  RMH_TRY(h2d(fp.coef, coef.data(), coef.size() * sizeof(double), s));
+  T* ring = (T*)fp.ring;
+  const int32_t R = fp.R;
+  const T* cur = x;       // t_k
+  const T* prev = nullptr;  // t_{k-1}
+  int32_t pending = 1;    // first t_k not yet folded
   for (int32_t k = 0; k < D; ++k) {
+    // t_{k+1} into slot (k+1) % R: that slot held t_{k+1-R}, folded already, and R >= 3 keeps it
+    // apart from t_k and t_{k-1}
+    T* out = ring + (int64_t)((k + 1) % R) * n;
     HopArgs<T> h{};
     h.g = g;
     h.U = U;
     h.x_mul = 1;
     h.z_div = 1;
     h.n_rhs = n_rhs;
-    h.store = (k + 1 < D) ? 1 : 0;
+    h.store = 1;
     h.x = cur;
-    h.yacc = y;
-    h.n_w = nw;
-    h.yacc_stride = (int64_t)n_rhs * 32 * g.V;
-    for (int w = 0; w < nw; ++w) {
-      h.wcoef[w] = coef[(size_t)w * (D + 1) + k + 1];
-      h.wcoef0[w] = coef[(size_t)w * (D + 1)];
-    }
-    h.filter_first = (k == 0) ? 1 : 0;
-    T* out;
+    h.out = out;
     if (k == 0) {
-      out = A;
-      h.a = -0.125;
+      h.a = -0.125;      // t_1 = A t_0 = -H t_0 / 8
     } else {
-      out = (k & 1) ? B : A;
-      h.a = -0.25;
+      h.a = -0.25;       // t_{k+1} = 2 A t_k - t_{k-1} = -H t_k / 4 - t_{k-1}
       h.c = -1.0;
       h.z = prev;
     }
-    h.out = out;
     {
-      // the filter also reads (after the first sweep) and writes every window output
-      const double yb = (double)nw * n_rhs * 32.0 * g.V * sizeof(T) * (k == 0 ? 1.0 : 2.0);
-      ProfScope ps(RMH_PROF_STENCIL, hop_bytes(g, n_rhs, sizeof(T), k > 0, h.store != 0) + yb, s, n_rhs);
+      ProfScope ps(RMH_PROF_STENCIL, hop_bytes(g, n_rhs, sizeof(T), k > 0, true), s, n_rhs);
       HIP_TRY(launch_hop<T>(h, cfg, s));
     }
     prev = cur;
     cur = out;
+    const int32_t cnt = k + 2 - pending;   // t_pending .. t_{k+1}
+    if (cnt == R || k + 1 == D) {
+      const int32_t first = pending == 1 ? 1 : 0;
+      // reads cnt vectors (and x on the first fold), reads (after the first) and writes nw outputs
+      const double fb = (double)n * sizeof(T);
+      ProfScope ps(RMH_PROF_CHEB_FOLD, fb * (cnt + first + (double)nw * (first ? 1.0 : 2.0)), s, n_rhs);
+      HIP_TRY(launch_cheb_fold<T>(x, ring, R, pending, cnt, first, fp.coef, D, nw, y, n, s));
+      pending = k + 2;
+    }
   }
   return RMH_OK;
 }
@@ -1085,7 +1106,7 @@ size_t rmh_workspace_bytes(int32_t op, const int32_t L[4], int32_t dtype, int32_
       plan_cheb(c, g, dtype, n_rhs, std::max(1, (degree + 1) / 2), true);
       break;
     case RMH_OP_CHEB_FILTER:
-      plan_cheb(c, g, dtype, n_rhs, std::max(1, degree), false);
+      plan_filter(c, g, dtype, n_rhs, std::max(1, degree), std::min(std::max(aux, 1), kMaxFilterWindows));
       break;
     case RMH_OP_CHEB_FILTER_BWD:
       plan_cheb_bwd(c, g, n_rhs, std::max(1, aux), std::max(1, degree));
@@ -1369,15 +1390,15 @@ rmh_status rmh_cheb_filter(const int32_t L[4], const void* U, int32_t dtype, con
   RMH_TRY(check_ptr(y, "y"));
   RMH_TRY(check_ptr(ws, "ws"));
   Carver c(ws);
-  ChebPlan cp = plan_cheb(c, g, dtype, n_rhs, D, false);
+  FilterPlan fp = plan_filter(c, g, dtype, n_rhs, D, nw);
   if (c.off > ws_bytes) return fail(RMH_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, c.off);
   const size_t fb = (size_t)n_rhs * 32 * g.V * dsize(dtype);
   if (overlap(y, fb * nw, x, fb) || overlap(y, fb * nw, ws, c.off) || overlap(y, fb * nw, U, (size_t)72 * g.V * dsize(dtype)))
     return fail(RMH_E_ARG, "y overlaps an input or the workspace");
   hipStream_t s = (hipStream_t)stream;
   if (dtype == RMH_F64)
-    return cheb_filter_t<double>(g, (const double*)U, (const double*)x, n_rhs, D, nw, coef, cp, (double*)y, s);
-  return cheb_filter_t<float>(g, (const float*)U, (const float*)x, n_rhs, D, nw, coef, cp, (float*)y, s);
+    return cheb_filter_t<double>(g, (const double*)U, (const double*)x, n_rhs, D, nw, coef, fp, (double*)y, s);
+  return cheb_filter_t<float>(g, (const float*)U, (const float*)x, n_rhs, D, nw, coef, fp, (float*)y, s);
 }
 
 static rmh_status cheb_bwd_common(const int32_t L[4], const double* U, const double* x, int32_t n_rhs,

@@ -43,7 +43,7 @@ struct HopConfig {
 
 // out[v] = a * (H x)[v] + b_v * x[v] + c * z[v / z_div]   for v in [0, n_rhs) link fields,
 // where H = sum_mu (forward hop + backward hop), so Delta = 8 - H.
-// Optional: per-block partial dot products, filter accumulation into yacc.
+// Optional: per-block partial dot products.
 template <typename T>
 struct HopArgs {
   Geom g;
@@ -61,13 +61,6 @@ struct HopArgs {
   int32_t store;            // write out
   double* partials;         // [n_rhs][3][nblk]: <x,x>, <out,x>, <out,out>
   int32_t dot_mask;         // bit q set -> compute dot q
-  // filter accumulation: yacc[w][v] (= y_w) += wcoef[w] * out   (first: y_w = wcoef0[w] x + wcoef[w] out)
-  T* yacc;
-  int32_t n_w;
-  int64_t yacc_stride;      // elements between consecutive windows
-  double wcoef[kMaxFilterWindows];
-  double wcoef0[kMaxFilterWindows];
-  int32_t filter_first;
 };
 
 int hop_num_blocks(const Geom& g, const HopConfig& cfg);
@@ -77,8 +70,10 @@ int hop_order_ok(const Geom& g, const HopConfig& cfg);
 int hop_split_ok(const HopConfig& cfg);
 // whether the x3 walk applies (K divides L3)
 int hop_walk_ok(const Geom& g, const HopConfig& cfg);
-// upper bound of hop_num_blocks over every configuration (32 sites per block at least)
-inline int hop_max_blocks(const Geom& g) { return (g.V + 31) / 32 + g.L3; }
+// upper bound of hop_num_blocks over every configuration: 16 sites per block at least (the
+// hop-split shape with one direction group per block), plus one partial block per x3 slice of
+// the walking shape; every per-block partial-sum buffer is sized with it
+inline int hop_max_blocks(const Geom& g) { return (g.V + 15) / 16 + g.L3; }
 
 template <typename T>
 hipError_t launch_hop(const HopArgs<T>& args, const HopConfig& cfg, hipStream_t s);
@@ -227,6 +222,14 @@ hipError_t launch_gauge_force(const Geom& g, const double* U, double beta, doubl
 
 // Chebyshev reverse sweep source term: tb[v] += sum_y coef[(v * n_y + y) * n_k + k] Y[y][v] (FP64;
 // Y laid out [n_y][n_rhs][n_reals], coef on the device)
+// Chebyshev filter fold over a ring of R recursion vectors of n elements each (t_k in slot k % R):
+//   y_w = (first ? coef[w][0] x : y_w) + sum_{j < cnt} coef[w][k0 + j] t_{k0 + j},   w < nw,
+// coef [nw][D + 1] on the device, y_w = y + w * n; accumulated in FP64.  cnt <= kMaxFold.
+constexpr int kMaxFold = 16;
+template <typename T>
+hipError_t launch_cheb_fold(const T* x, const T* ring, int32_t R, int32_t k0, int32_t cnt, int32_t first,
+                            const double* coef, int32_t D, int32_t nw, T* y, int64_t n, hipStream_t s);
+
 hipError_t launch_cheb_source(double* tb, const double* Y, const double* coef, int32_t n_rhs, int32_t n_y,
                               int32_t n_k, int32_t k, int64_t n_reals, hipStream_t s);
 

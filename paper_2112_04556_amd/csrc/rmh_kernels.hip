@@ -945,6 +945,67 @@ hipError_t launch_cheb_source(double* tb, const double* Y, const double* coef, i
   return hipGetLastError();
 }
 
+// Chebyshev filter fold: two consecutive elements per thread; the block's t_k are loaded once
+// into registers and every window output is read, updated and written once per fold.
+template <typename T>
+__global__ void __launch_bounds__(256) k_cheb_fold(const T* __restrict__ x, const T* __restrict__ ring, int32_t R,
+                                                   int32_t k0, int32_t cnt, int32_t first,
+                                                   const double* __restrict__ coef, int32_t D1, int32_t nw,
+                                                   T* __restrict__ y, int64_t n) {
+  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 2;
+  if (i0 >= n) return;
+  double tv[kMaxFold][2];
+#pragma unroll
+  for (int j = 0; j < kMaxFold; ++j) {
+    if (j < cnt) {
+      const T* t = ring + (int64_t)((k0 + j) % R) * n + i0;
+      tv[j][0] = (double)t[0];
+      tv[j][1] = (double)t[1];
+    }
+  }
+  double x0 = 0.0, x1 = 0.0;
+  if (first) {
+    x0 = (double)x[i0];
+    x1 = (double)x[i0 + 1];
+  }
+  for (int32_t w = 0; w < nw; ++w) {
+    const double* cw = coef + (int64_t)w * D1;
+    T* yw = y + (int64_t)w * n + i0;
+    double a0, a1;
+    if (first) {
+      a0 = cw[0] * x0;
+      a1 = cw[0] * x1;
+    } else {
+      a0 = (double)yw[0];
+      a1 = (double)yw[1];
+    }
+#pragma unroll
+    for (int j = 0; j < kMaxFold; ++j) {
+      if (j < cnt) {
+        const double c = cw[k0 + j];
+        a0 = fma(c, tv[j][0], a0);
+        a1 = fma(c, tv[j][1], a1);
+      }
+    }
+    yw[0] = (T)a0;
+    yw[1] = (T)a1;
+  }
+}
+
+template <typename T>
+hipError_t launch_cheb_fold(const T* x, const T* ring, int32_t R, int32_t k0, int32_t cnt, int32_t first,
+                            const double* coef, int32_t D, int32_t nw, T* y, int64_t n, hipStream_t s) {
+  if (n == 0 || nw == 0 || cnt < 0 || cnt > kMaxFold || (n & 1)) return n == 0 || nw == 0 ? hipSuccess : hipErrorInvalidValue;
+  const int64_t nb = (n / 2 + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_cheb_fold<T>, dim3((uint32_t)nb), dim3(kBlock), 0, s, x, ring, R, k0, cnt, first, coef, D + 1,
+                     nw, y, n);
+  return hipGetLastError();
+}
+template hipError_t launch_cheb_fold<double>(const double*, const double*, int32_t, int32_t, int32_t, int32_t,
+                                             const double*, int32_t, int32_t, double*, int64_t, hipStream_t);
+template hipError_t launch_cheb_fold<float>(const float*, const float*, int32_t, int32_t, int32_t, int32_t,
+                                            const double*, int32_t, int32_t, float*, int64_t, hipStream_t);
+
 hipError_t launch_force(const ForceArgs& a, hipStream_t s) {
   const int32_t n_out = a.per_rhs ? a.n_rhs : 1;
   if (n_out == 0) return hipSuccess;

@@ -1,5 +1,5 @@
 // The adjoint-Laplacian stencil for gfx950: one hop per direction and sign, fused epilogues
-// (axpby, dot products, Chebyshev filter accumulation), the site-per-thread kernel and the
+// (axpby, dot products), the site-per-thread kernel, the hop-split kernel and the
 // x3-walking kernel, and their launch dispatch.
 #include <hip/hip_runtime.h>
 
@@ -66,7 +66,7 @@ __device__ __forceinline__ void hop_term_fwd(const T* __restrict__ Um, int32_t s
   hop_apply<T, FORM, NV, false>(u, phi, acc);
 }
 
-template <typename T, int FORM, int NV, bool DOTS, bool FILTER>
+template <typename T, int FORM, int NV, bool DOTS>
 __global__ void __launch_bounds__(256) k_hop(const HopArgs<T> A, int32_t xcd, int32_t order) {
   constexpr int G = 4 / NV;  // thread groups per site
   const int32_t v = blockIdx.y;
@@ -130,16 +130,6 @@ __global__ void __launch_bounds__(256) k_hop(const HopArgs<T> A, int32_t xcd, in
           dsum[1] = fma(od, xd, dsum[1]);
           dsum[2] = fma(od, od, dsum[2]);
         }
-        if (FILTER) {
-          T* y = A.yacc + (int64_t)v * FV + e;
-          for (int w = 0; w < A.n_w; ++w) {
-            T* yw = y + w * A.yacc_stride;
-            if (A.filter_first)
-              *yw = fmadd(T(A.wcoef[w]), o, T(A.wcoef0[w]) * xv);
-            else
-              *yw = fmadd(T(A.wcoef[w]), o, *yw);
-          }
-        }
       }
   }
   if (DOTS) {
@@ -160,7 +150,7 @@ __global__ void __launch_bounds__(256) k_hop(const HopArgs<T> A, int32_t xcd, in
 // backward hop along mu; two butterfly shuffles sum the four partial results (in the fixed order
 // (mu0 + mu1) + (mu2 + mu3)), and each of the four lanes stores a quarter of the components.  A wave
 // covers 16 consecutive sites for one direction group; a block of B threads has B/64 waves.
-template <typename T, int FORM, int NV, bool DOTS, bool FILTER>
+template <typename T, int FORM, int NV, bool DOTS>
 __global__ void __launch_bounds__(256) k_hop_split(const HopArgs<T> A, int32_t xcd) {
   constexpr int G = 4 / NV;
   const int32_t v = blockIdx.y;
@@ -221,16 +211,6 @@ __global__ void __launch_bounds__(256) k_hop_split(const HopArgs<T> A, int32_t x
         dsum[1] = fma(od, xd, dsum[1]);
         dsum[2] = fma(od, od, dsum[2]);
       }
-      if (FILTER) {
-        T* y = A.yacc + (int64_t)v * FV + e;
-        for (int w = 0; w < A.n_w; ++w) {
-          T* yw = y + w * A.yacc_stride;
-          if (A.filter_first)
-            *yw = fmadd(T(A.wcoef[w]), o, T(A.wcoef0[w]) * xv);
-          else
-            *yw = fmadd(T(A.wcoef[w]), o, *yw);
-        }
-      }
     }
   }
   if (DOTS) {
@@ -250,7 +230,7 @@ __global__ void __launch_bounds__(256) k_hop_split(const HopArgs<T> A, int32_t x
 // lattice; each thread walks K consecutive x3 values of its column.  Per step the x0, x1, x2
 // hops load their links and neighbours as in k_hop; the x3 forward hop loads U_3(x) and
 // phi(x+3), which become the backward link and the centre field of the next step.
-template <typename T, int FORM, int NV, bool DOTS, bool FILTER>
+template <typename T, int FORM, int NV, bool DOTS>
 __global__ void __launch_bounds__(256) k_hop_walk(const HopArgs<T> A, int32_t xcd, int32_t K) {
   constexpr int G = 4 / NV;
   const int32_t v = blockIdx.y;
@@ -345,16 +325,6 @@ __global__ void __launch_bounds__(256) k_hop_walk(const HopArgs<T> A, int32_t xc
             dsum[1] = fma(od, xd, dsum[1]);
             dsum[2] = fma(od, od, dsum[2]);
           }
-          if (FILTER) {
-            T* y = A.yacc + (int64_t)v * FV + e;
-            for (int w = 0; w < A.n_w; ++w) {
-              T* yw = y + w * A.yacc_stride;
-              if (A.filter_first)
-                *yw = fmadd(T(A.wcoef[w]), o, T(A.wcoef0[w]) * xv);
-              else
-                *yw = fmadd(T(A.wcoef[w]), o, *yw);
-            }
-          }
         }
 #pragma unroll
       for (int i = 0; i < NV; ++i)
@@ -407,39 +377,28 @@ template <typename T, int FORM, int NV>
 static hipError_t launch_hop_form(const HopArgs<T>& A, const HopConfig& cfg, hipStream_t s) {
   dim3 grid(hop_num_blocks(A.g, cfg), A.n_rhs), block(cfg.block);
   const bool dots = A.partials && A.dot_mask;
-  const bool filt = A.yacc && A.n_w > 0;
+  // the partial-sum buffers hold hop_max_blocks entries per field and dot product
+  if (dots && (int)grid.x > hop_max_blocks(A.g)) return hipErrorInvalidValue;
   if (hop_split_ok(cfg)) {
-    if (dots && filt)
-      hipLaunchKernelGGL((k_hop_split<T, FORM, NV, true, true>), grid, block, 0, s, A, cfg.xcd_remap);
-    else if (dots)
-      hipLaunchKernelGGL((k_hop_split<T, FORM, NV, true, false>), grid, block, 0, s, A, cfg.xcd_remap);
-    else if (filt)
-      hipLaunchKernelGGL((k_hop_split<T, FORM, NV, false, true>), grid, block, 0, s, A, cfg.xcd_remap);
+    if (dots)
+      hipLaunchKernelGGL((k_hop_split<T, FORM, NV, true>), grid, block, 0, s, A, cfg.xcd_remap);
     else
-      hipLaunchKernelGGL((k_hop_split<T, FORM, NV, false, false>), grid, block, 0, s, A, cfg.xcd_remap);
+      hipLaunchKernelGGL((k_hop_split<T, FORM, NV, false>), grid, block, 0, s, A, cfg.xcd_remap);
     return hipGetLastError();
   }
   const int32_t order = (cfg.order == 1 && hop_order_ok(A.g, cfg)) ? 1 : 0;
   if (hop_walk_ok(A.g, cfg)) {
     const int32_t K = cfg.walk;
-    if (dots && filt)
-      hipLaunchKernelGGL((k_hop_walk<T, FORM, NV, true, true>), grid, block, 0, s, A, cfg.xcd_remap, K);
-    else if (dots)
-      hipLaunchKernelGGL((k_hop_walk<T, FORM, NV, true, false>), grid, block, 0, s, A, cfg.xcd_remap, K);
-    else if (filt)
-      hipLaunchKernelGGL((k_hop_walk<T, FORM, NV, false, true>), grid, block, 0, s, A, cfg.xcd_remap, K);
+    if (dots)
+      hipLaunchKernelGGL((k_hop_walk<T, FORM, NV, true>), grid, block, 0, s, A, cfg.xcd_remap, K);
     else
-      hipLaunchKernelGGL((k_hop_walk<T, FORM, NV, false, false>), grid, block, 0, s, A, cfg.xcd_remap, K);
+      hipLaunchKernelGGL((k_hop_walk<T, FORM, NV, false>), grid, block, 0, s, A, cfg.xcd_remap, K);
     return hipGetLastError();
   }
-  if (dots && filt)
-    hipLaunchKernelGGL((k_hop<T, FORM, NV, true, true>), grid, block, 0, s, A, cfg.xcd_remap, order);
-  else if (dots)
-    hipLaunchKernelGGL((k_hop<T, FORM, NV, true, false>), grid, block, 0, s, A, cfg.xcd_remap, order);
-  else if (filt)
-    hipLaunchKernelGGL((k_hop<T, FORM, NV, false, true>), grid, block, 0, s, A, cfg.xcd_remap, order);
+  if (dots)
+    hipLaunchKernelGGL((k_hop<T, FORM, NV, true>), grid, block, 0, s, A, cfg.xcd_remap, order);
   else
-    hipLaunchKernelGGL((k_hop<T, FORM, NV, false, false>), grid, block, 0, s, A, cfg.xcd_remap, order);
+    hipLaunchKernelGGL((k_hop<T, FORM, NV, false>), grid, block, 0, s, A, cfg.xcd_remap, order);
   return hipGetLastError();
 }
 

@@ -63,12 +63,15 @@ def test_power_ratio_free_field():
     assert abs(ratio.mean() - 1.0) < 0.1
 
 
-@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-def test_cheb_filter(dtype):
+# degrees around the fold ring of 16 recursion vectors: one short ring (D < 3), exactly one
+# ring, one ring and a partial one, two rings and a one-vector remainder
+@pytest.mark.parametrize("dtype,D", [(torch.float64, 1), (torch.float64, 2), (torch.float64, 16),
+                                     (torch.float64, 24), (torch.float64, 33), (torch.float32, 24)])
+def test_cheb_filter(dtype, D):
     L = (3, 5, 2, 7)
-    announce(f"cheb_filter {dtype}")
+    announce(f"cheb_filter {dtype} D={D}")
     U, x, Ud, xd = setup(L, "eps", 0.5, 6, n=2, dtype=dtype)
-    D, nw = 24, 5
+    nw = 5
     edges = np.array([0.0, 2.0, 5.0, 9.5, 12.0, 16.0])
     y = api.cheb_filter(L, Ud, xd, D, nw, edges).cpu().numpy().astype(np.float64)
     if dtype == torch.float64:

@@ -133,16 +133,18 @@ def test_laplacian_hop_split_parity(L, kind, seed):
     api.tune_clear()
 
 
-def test_hop_split_fused_epilogues():
-    """The hop-split kernel's dot products (spectrum moments, CG) and filter accumulation give the
-    site-per-thread kernel's results to rounding."""
-    L = (4, 3, 2, 5)    # V = 120: two waves' worth of split sites and a ragged tail
-    announce(f"hop split fused epilogues {L}")
+@pytest.mark.parametrize("form,block,nv", [(1, 256, 2), (1, 128, 2), (0, 64, 4), (1, 256, 1), (2, 128, 4)])
+def test_hop_split_fused_epilogues(form, block, nv):
+    """The hop-split kernel's dot products (spectrum moments, CG) give the site-per-thread kernel's
+    results to rounding, also in the shapes with 16 sites per block (block 64 / nv 4, block 128 /
+    nv 2, block 256 / nv 1), whose block count is the largest any shape launches."""
+    L = (4, 3, 2, 5)    # V = 120: 16-site blocks with a ragged tail
+    announce(f"hop split fused epilogues {L} form={form} block={block} nv={nv}")
     U, F, Ud, Fd = setup(L, "eps", 0.5, 9, n=2)
     rat = api.rational_kappa(0.8, 8)
     runs = []
-    for order in (0, 2):
-        api.tune_set(L, torch.float64, 1, 1, 256, 1, 2, order, 0)   # nearest-batch entry: every launch
+    for cfg in ((1, 256, 1, 2, 0, 0), (form, block, 1, nv, 2, 0)):
+        api.tune_set(L, torch.float64, 1, *cfg)   # nearest-batch entry: every launch on L
         mom, pw = api.power_spectrum(L, Ud, Fd, 30, 6)
         yf = api.cheb_filter(L, Ud, Fd, 30, 6).cpu().numpy()
         out = api.rational_apply(L, Ud, Fd, rat, api.Solver(tol=1e-12))
