@@ -14,6 +14,7 @@ namespace rmh {
 constexpr int kBlock = 256;        // threads per block for site and element kernels
 constexpr int kRedBlock = 256;     // threads of the per-rhs scalar kernels
 constexpr int kMaxFilterWindows = 64;
+constexpr int kMaxShifts = 64;      // poles of one rational (shifts of one multi-shift solve)
 
 // Stencil variants chosen by the tuner.
 // kFormAdjoint: the 8x8 adjoint matrix R(U) built once per hop and applied to every vector;
@@ -220,8 +221,6 @@ int gauge_force_blocks(const Geom& g);
 hipError_t launch_gauge_force(const Geom& g, const double* U, double beta, double* F, double* partials,
                               hipStream_t s);
 
-// Chebyshev reverse sweep source term: tb[v] += sum_y coef[(v * n_y + y) * n_k + k] Y[y][v] (FP64;
-// Y laid out [n_y][n_rhs][n_reals], coef on the device)
 // Chebyshev filter fold over a ring of R recursion vectors of n elements each (t_k in slot k % R):
 //   y_w = (first ? coef[w][0] x : y_w) + sum_{j < cnt} coef[w][k0 + j] t_{k0 + j},   w < nw,
 // coef [nw][D + 1] on the device, y_w = y + w * n; accumulated in FP64.  cnt <= kMaxFold.
@@ -230,6 +229,8 @@ template <typename T>
 hipError_t launch_cheb_fold(const T* x, const T* ring, int32_t R, int32_t k0, int32_t cnt, int32_t first,
                             const double* coef, int32_t D, int32_t nw, T* y, int64_t n, hipStream_t s);
 
+// Chebyshev reverse sweep source term: tb[v] += sum_y coef[(v * n_y + y) * n_k + k] Y[y][v] (FP64;
+// Y laid out [n_y][n_rhs][n_reals], coef on the device)
 hipError_t launch_cheb_source(double* tb, const double* Y, const double* coef, int32_t n_rhs, int32_t n_y,
                               int32_t n_k, int32_t k, int64_t n_reals, hipStream_t s);
 

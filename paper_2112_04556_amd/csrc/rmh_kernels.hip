@@ -321,11 +321,15 @@ __global__ void k_cg_alpha(CgDev cg) {
   const double s0 = cg.sigma[(int64_t)v * cg.n_shift + seed];
   const int32_t m = fl[kFlM];
   const int32_t nc = 2 + 2 * cg.cslots;
+  __shared__ double s_cx[kMaxShifts];
+  __shared__ int s_upd[kMaxShifts];
+  // per shift: zeta_{k+1} and the x coefficient
   for (int j = threadIdx.x; j < cg.n_shift; j += blockDim.x) {
     const int64_t vj = (int64_t)v * cg.n_shift + j;
     const int32_t on = cg.act_next[vj];
     cg.act[vj] = on;
     double* sh = cg.sh + vj * kShN;
+    int upd = 0;
     if (on) {
       const double z = sh[kShZeta], zp = sh[kShZetaPrev];
       const double ds = cg.sigma[vj] - s0;
@@ -334,21 +338,31 @@ __global__ void k_cg_alpha(CgDev cg) {
       sh[kShZetaNext] = zn;
       sh[kShCx] = cx;
       sh[kShUpd] += 1.0;
-      if (cg.ring_on && m < cg.nslot && !(cg.seed_explicit && j == seed)) {
-        double* cf = cg.coef + vj * nc;
-        const double* e = cf + 2 + cg.cslots;
-        double* d = cf + 2;
-        cf[0] = fma(cx, cf[1], cf[0]);
-        for (int i = 0; i <= m; ++i) d[i] = fma(cx, e[i], d[i]);
-        sh[kShSeg] = 1.0;
-      }
+      upd = (cg.ring_on && m < cg.nslot && !(cg.seed_explicit && j == seed)) ? 1 : 0;
+      if (upd) sh[kShSeg] = 1.0;
+      s_cx[j] = cx;
     } else {
       sh[kShCx] = 0.0;
     }
+    s_upd[j] = upd;
+  }
+  __syncthreads();
+  // x_j += cx_j p_j on the segment coefficients, one (shift, coefficient) per thread:
+  // q = 0 the p_j0 coefficient, q = 1 + i the ring entry i <= m
+  const int32_t per = m + 2;
+  for (int t = threadIdx.x; t < cg.n_shift * per; t += blockDim.x) {
+    const int32_t j = t / per, q = t - j * per;
+    if (!s_upd[j]) continue;
+    double* cf = cg.coef + ((int64_t)v * cg.n_shift + j) * nc;
+    if (q == 0)
+      cf[0] = fma(s_cx[j], cf[1], cf[0]);
+    else
+      cf[1 + q] = fma(s_cx[j], cf[1 + q + cg.cslots], cf[1 + q]);
   }
 }
 
 hipError_t launch_cg_alpha(const CgDev& cg, hipStream_t s) {
+  if (cg.n_shift > kMaxShifts) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_cg_alpha, dim3(cg.n_rhs), dim3(kRedBlock), 0, s, cg);
   return hipGetLastError();
 }
@@ -375,33 +389,32 @@ __global__ void k_cg_beta(CgDev cg, int32_t mixed) {
   const int32_t seed = cg.seed[v];
   const int32_t m = fl[kFlM];
   const int32_t nc = 2 + 2 * cg.cslots;
+  __shared__ double s_cp[kMaxShifts], s_cr[kMaxShifts];
+  __shared__ int s_upd[kMaxShifts];
   int any_other = 0;
+  // per shift: beta_j, the p coefficients, convergence
   for (int j = threadIdx.x; j < cg.n_shift; j += blockDim.x) {
     const int64_t vj = (int64_t)v * cg.n_shift + j;
     double* sh = cg.sh + vj * kShN;
+    int upd = 0;
     if (cg.act[vj]) {
       const double z = sh[kShZeta], zn = sh[kShZetaNext];
       const double ratio = zn / z;
       const double cr = zn, cp = beta * ratio * ratio;
       sh[kShCr] = cr;
       sh[kShCp] = cp;
+      s_cr[j] = cr;
+      s_cp[j] = cp;
       const int32_t keep = (fabs(zn) * rnorm > tolabs) ? 1 : 0;
       cg.act_next[vj] = keep;
       if (j != seed) any_other |= keep;
-      if (!(cg.seed_explicit && j == seed)) {
-        if (cg.ring_on && keep && m + 1 < cg.nslot) {
-          double* cf = cg.coef + vj * nc;
-          double* e = cf + 2 + cg.cslots;
-          cf[1] *= cp;
-          for (int i = 0; i <= m; ++i) e[i] *= cp;
-          e[m + 1] = cr;
-        }
-      }
+      upd = (!(cg.seed_explicit && j == seed) && cg.ring_on && keep && m + 1 < cg.nslot) ? 1 : 0;
       sh[kShZetaPrev] = z;
       sh[kShZeta] = zn;
     } else {
       cg.act_next[vj] = 0;
     }
+    s_upd[j] = upd;
   }
   any_other = __syncthreads_or(any_other);
   if (threadIdx.x == 0) {
@@ -409,14 +422,7 @@ __global__ void k_cg_beta(CgDev cg, int32_t mixed) {
     if (any_other && !cg.act_next[vs] && cg.act[vs]) {
       // the seed carries the Krylov space for the others: its direction keeps being updated
       cg.act_next[vs] = 1;
-      if (cg.ring_on && !cg.seed_explicit && m + 1 < cg.nslot) {
-        double* cf = cg.coef + vs * nc;
-        double* e = cf + 2 + cg.cslots;
-        const double cp = cg.sh[vs * kShN + kShCp];
-        cf[1] *= cp;
-        for (int i = 0; i <= m; ++i) e[i] *= cp;
-        e[m + 1] = cg.sh[vs * kShN + kShCr];
-      }
+      if (cg.ring_on && !cg.seed_explicit && m + 1 < cg.nslot) s_upd[seed] = 1;
     }
     if (any_other) cg.act_next[vs] = 1;
     const int32_t any = any_other | cg.act_next[vs];
@@ -440,9 +446,26 @@ __global__ void k_cg_beta(CgDev cg, int32_t mixed) {
       if (rnorm < sc[kScDelta] * sc[kScMaxR]) fl[kFlNeedRU] = 1;
     }
   }
+  __syncthreads();
+  // p_j = cr_j r' + cp_j p_j on the segment coefficients, one (shift, coefficient) per thread:
+  // q = 0 the p_j0 coefficient, q = 1 + i the ring entry i <= m, q = m + 2 the new entry m + 1
+  const int32_t per = m + 3;
+  for (int t = threadIdx.x; t < cg.n_shift * per; t += blockDim.x) {
+    const int32_t j = t / per, q = t - j * per;
+    if (!s_upd[j]) continue;
+    double* cf = cg.coef + ((int64_t)v * cg.n_shift + j) * nc;
+    double* e = cf + 2 + cg.cslots;
+    if (q == 0)
+      cf[1] *= s_cp[j];
+    else if (q <= m + 1)
+      e[q - 1] *= s_cp[j];
+    else
+      e[m + 1] = s_cr[j];
+  }
 }
 
 hipError_t launch_cg_beta(const CgDev& cg, int32_t mixed, hipStream_t s) {
+  if (cg.n_shift > kMaxShifts) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_cg_beta, dim3(cg.n_rhs), dim3(kRedBlock), 0, s, cg, mixed);
   return hipGetLastError();
 }
@@ -829,29 +852,49 @@ struct FTriple {
   int a, b, c;
   double f;
 };
-__constant__ FTriple kF[9] = {{0, 1, 2, 1.0},
-                              {0, 3, 6, 0.5},
-                              {0, 4, 5, -0.5},
-                              {1, 3, 5, 0.5},
-                              {1, 4, 6, 0.5},
-                              {2, 3, 4, 0.5},
-                              {2, 5, 6, -0.5},
-                              {3, 4, 7, 0.86602540378443864676},
-                              {5, 6, 7, 0.86602540378443864676}};
+// compile-time table: with the loop over it unrolled every index is a constant, so the 8x8
+// products stay in registers
+constexpr FTriple kF[9] = {{0, 1, 2, 1.0},
+                           {0, 3, 6, 0.5},
+                           {0, 4, 5, -0.5},
+                           {1, 3, 5, 0.5},
+                           {1, 4, 6, 0.5},
+                           {2, 3, 4, 0.5},
+                           {2, 5, 6, -0.5},
+                           {3, 4, 7, 0.86602540378443864676},
+                           {5, 6, 7, 0.86602540378443864676}};
 
+// G += R[:, b1] x C[b1, :] + R[:, b2] x C[b2, :] for the column group q of R(U) (columns b1, b2)
+template <int q, int b1, int b2>
+__device__ __forceinline__ void force_cross_cols(const double* u, const double* C, double* G) {
+  double c1[8], c2[8];
+  adjoint_columns<double, q>(u, c1, c2);
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    const int a = kF[t].a, b = kF[t].b, c = kF[t].c;
+    const double f = kF[t].f;
+    // (p x q)_c += f (p_a q_b - p_b q_a), cyclically in (a, b, c)
+    G[c] += f * ((c1[a] * C[b1 * 8 + b] - c1[b] * C[b1 * 8 + a]) + (c2[a] * C[b2 * 8 + b] - c2[b] * C[b2 * 8 + a]));
+    G[a] += f * ((c1[b] * C[b1 * 8 + c] - c1[c] * C[b1 * 8 + b]) + (c2[b] * C[b2 * 8 + c] - c2[c] * C[b2 * 8 + b]));
+    G[b] += f * ((c1[c] * C[b1 * 8 + a] - c1[a] * C[b1 * 8 + c]) + (c2[c] * C[b2 * 8 + a] - c2[a] * C[b2 * 8 + c]));
+  }
+}
+
+// One thread per (site, mu): a block of 256 threads is four waves, wave w taking direction mu = w
+// for 64 consecutive sites, so every link and field base address is wave-uniform.
 __global__ void __launch_bounds__(256) k_force(const ForceArgs F, int32_t xcd) {
   const int32_t o = blockIdx.y;
   const int32_t V = F.g.V;
   const int32_t blk = remap_block(blockIdx.x, gridDim.x, xcd);
-  const int32_t s = blk * blockDim.x + threadIdx.x;
+  const int32_t mu = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int32_t s = blk * 64 + (threadIdx.x & 63);
   if (s >= V) return;
   const int64_t FV = 32 * (int64_t)V;
   int32_t xc[4];
   site_coords(F.g, s, xc);
   const int32_t r0 = F.per_rhs ? o : 0;
   const int32_t r1 = F.per_rhs ? o + 1 : F.n_rhs;
-#pragma unroll 1
-  for (int mu = 0; mu < 4; ++mu) {
+  {
     const int32_t sf = site_shift(F.g, s, xc, mu, +1);
     double C[64];
 #pragma unroll
@@ -884,29 +927,15 @@ __global__ void __launch_bounds__(256) k_force(const ForceArgs F, int32_t xcd) {
     const double* Um = F.U + (int64_t)mu * 18 * V;
 #pragma unroll
     for (int c = 0; c < 18; ++c) u[c] = (Um + (size_t)c * V)[s];
-    double R[64];
-    adjoint_matrix<double>(u, R);
-    double RC[64];
-#pragma unroll
-    for (int d = 0; d < 8; ++d)
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        double t = 0.0;
-#pragma unroll
-        for (int b = 0; b < 8; ++b) t = fma(R[d * 8 + b], C[b * 8 + e], t);
-        RC[d * 8 + e] = t;
-      }
+    // G = sum_b R[:, b] x C[b, :], x the su(3) product (p x q)_c = sum_{a,e} f^{aec} p_a q_e, with
+    // the columns of R(U) formed two at a time (the whole of R is never held)
     double G[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c) G[c] = 0.0;
-#pragma unroll
-    for (int t = 0; t < 9; ++t) {
-      const int a = kF[t].a, b = kF[t].b, c = kF[t].c;
-      const double f = kF[t].f;
-      G[c] += f * (RC[a * 8 + b] - RC[b * 8 + a]);
-      G[a] += f * (RC[b * 8 + c] - RC[c * 8 + b]);
-      G[b] += f * (RC[c * 8 + a] - RC[a * 8 + c]);
-    }
+    force_cross_cols<0, 0, 1>(u, C, G);
+    force_cross_cols<1, 3, 4>(u, C, G);
+    force_cross_cols<2, 5, 6>(u, C, G);
+    force_cross_cols<3, 2, 7>(u, C, G);
     double* go = F.grad + ((int64_t)o * 4 + mu) * 8 * V;
     if (F.accumulate) {
 #pragma unroll
@@ -1009,8 +1038,8 @@ template hipError_t launch_cheb_fold<float>(const float*, const float*, int32_t,
 hipError_t launch_force(const ForceArgs& a, hipStream_t s) {
   const int32_t n_out = a.per_rhs ? a.n_rhs : 1;
   if (n_out == 0) return hipSuccess;
-  dim3 grid((a.g.V + kBlock - 1) / kBlock, n_out);
-  hipLaunchKernelGGL(k_force, grid, dim3(kBlock), 0, s, a, 1);
+  dim3 grid((a.g.V + 63) / 64, n_out);
+  hipLaunchKernelGGL(k_force, grid, dim3(256), 0, s, a, 1);
   return hipGetLastError();
 }
 

@@ -44,9 +44,19 @@ __device__ __forceinline__ void block_sum(double (&v)[NQ], double (*lds)[16]) {
 }
 
 // Strided fixed-order sum of n values by a whole block; result in thread 0.
+// Fixed-order sum of p[0, n): four independent loads in flight per thread, then the block tree.
 __device__ __forceinline__ double block_sum_array(const double* p, int32_t n, double (*lds)[16]) {
-  double v[1] = {0.0};
-  for (int32_t i = threadIdx.x; i < n; i += blockDim.x) v[0] += p[i];
+  const int32_t B = blockDim.x;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int32_t i = threadIdx.x;
+  for (; i + 3 * B < n; i += 4 * B) {
+    a0 += p[i];
+    a1 += p[i + B];
+    a2 += p[i + 2 * B];
+    a3 += p[i + 3 * B];
+  }
+  for (; i < n; i += B) a0 += p[i];
+  double v[1] = {(a0 + a1) + (a2 + a3)};
   block_sum<1>(v, lds);
   return v[0];
 }
