@@ -318,11 +318,12 @@ rmh_status rmh_wilson_gauge_force(const int32_t L[4], const double* U, double be
  * order = 1 visits the blocks with x3 fastest (x2/x3 neighbours resident together; used when
  * L0*L1 is a multiple of the sites per block); order = 2 splits each site over four lanes, one per
  * direction mu, summed by wave shuffles (four times the threads, for small lattices; walk is then
- * ignored); walk = K > 0 makes each thread walk K consecutive x3 sites carrying the x3 neighbours
- * in registers (used when K divides L3); order outside [0, 2] is RMH_E_ARG.  Every configuration
+ * ignored), and order = 3 is that shape visiting its blocks with x3 fastest (as order 1); walk =
+ * K > 0 makes each thread walk K consecutive x3 sites carrying the x3 neighbours in registers
+ * (used when K divides L3); order outside [0, 3] is RMH_E_ARG.  Every configuration
  * computes the same operator; a form fixes the per-site arithmetic, so results are bitwise
- * identical across block sizes, remaps, nv, orders 0 and 1 and walks of one form (order 2 sums the
- * eight hops in another order: equal to rounding). */
+ * identical across block sizes, remaps, nv, orders 0 and 1 and walks of one form (orders 2 and 3
+ * sum the eight hops in another order: equal to rounding). */
 rmh_status rmh_tune_set(const int32_t L[4], int32_t dtype, int32_t n_rhs, int32_t form, int32_t block,
                         int32_t xcd_remap, int32_t nv, int32_t order, int32_t walk);
 /* Time every configuration of rmh_laplacian_apply on the caller's buffers (y is overwritten;

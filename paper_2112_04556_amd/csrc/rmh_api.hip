@@ -1764,7 +1764,7 @@ rmh_status rmh_tune_set(const int32_t L[4], int32_t dtype, int32_t n_rhs, int32_
   c.block = block;
   c.xcd_remap = xcd_remap ? 1 : 0;
   c.nv = nv;
-  if (order < 0 || order > 2) return fail(RMH_E_ARG, "order must be 0, 1 or 2");
+  if (order < 0 || order > 3) return fail(RMH_E_ARG, "order must be 0, 1, 2 or 3");
   c.order = order;
   if (walk < 0 || walk > 64) return fail(RMH_E_ARG, "walk must be in [0, 64]");
   c.walk = walk;
@@ -1794,7 +1794,7 @@ rmh_status rmh_autotune_laplacian(const int32_t L[4], const void* U, int32_t dty
     for (int nv : {4, 2, 1})
     for (int block : {64, 128, 256})
     for (int walk : {0, 4, 8, 16})
-    for (int order = 0; order < 3 && st == RMH_OK; ++order) {
+    for (int order = 0; order < 4 && st == RMH_OK; ++order) {
       for (int xcd = 0; xcd < 2 && st == RMH_OK; ++xcd) {
         HopConfig c;
         c.form = form;
@@ -1803,7 +1803,7 @@ rmh_status rmh_autotune_laplacian(const int32_t L[4], const void* U, int32_t dty
         c.nv = nv;
         c.order = order;
         c.walk = walk;
-        if (order == 1 && !hop_order_ok(g, c)) continue;
+        if ((order == 1 || order == 3) && !hop_order_ok(g, c)) continue;
         if (walk && (order || !hop_walk_ok(g, c))) continue;
         if ((block * nv / 4) % 64) continue;  // direction groups must be whole waves
         if (nv == 1 && form != kFormMatrix) continue;

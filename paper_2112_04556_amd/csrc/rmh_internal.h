@@ -29,7 +29,8 @@ enum HopForm : int32_t { kFormAdjoint = 0, kFormMatrix = 1, kFormStream = 2 };
 // L0 * L1 to be a multiple of the sites per block (else the lexicographic order 0 is used).
 // order = 2 (hop split) gives each site four lanes of one wave, lane group mu doing the two hops
 // along mu, summed by wave shuffles: four times the threads of order 0, for lattices too small to
-// fill the chip (walk is then ignored).
+// fill the chip (walk is then ignored); order = 3 is the same shape with the x3-fastest block
+// order of order 1.
 // walk = K > 0: each thread walks K consecutive sites along x3 (K divides L3), carrying the
 // centre field, the x-3 field and the x-3 link in registers, so every x3-direction field and
 // link is fetched once per column instead of being re-read from the caches.

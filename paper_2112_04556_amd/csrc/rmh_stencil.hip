@@ -151,7 +151,7 @@ __global__ void __launch_bounds__(256) k_hop(const HopArgs<T> A, int32_t xcd, in
 // (mu0 + mu1) + (mu2 + mu3)), and each of the four lanes stores a quarter of the components.  A wave
 // covers 16 consecutive sites for one direction group; a block of B threads has B/64 waves.
 template <typename T, int FORM, int NV, bool DOTS>
-__global__ void __launch_bounds__(256) k_hop_split(const HopArgs<T> A, int32_t xcd) {
+__global__ void __launch_bounds__(256) k_hop_split(const HopArgs<T> A, int32_t xcd, int32_t order) {
   constexpr int G = 4 / NV;
   const int32_t v = blockIdx.y;
   if (A.run && A.run[(int64_t)v * A.run_stride] == 0) return;
@@ -163,7 +163,19 @@ __global__ void __launch_bounds__(256) k_hop_split(const HopArgs<T> A, int32_t x
   const int32_t spb = (W / G) * 16;
   const int32_t lane = threadIdx.x & 63;
   const int32_t mu = lane >> 4;
-  const int32_t s = lb * spb + (wi / G) * 16 + (lane & 15);
+  int32_t blk = lb;
+  if (order) {
+    // x3 fastest, then x2, then the (x0, x1) chunks: a contiguous range of blocks (one XCD's,
+    // with the remap) sweeps whole x3 columns of a few chunks, so the x3 and x2 neighbours of a
+    // block were loaded moments before by the same XCD
+    const int32_t x3 = lb % A.g.L3;
+    const int32_t t = lb / A.g.L3;
+    const int32_t x2 = t % A.g.L2;
+    const int32_t chunk = t / A.g.L2;
+    const int32_t cpp = (A.g.L0 * A.g.L1) / spb;
+    blk = (x3 * A.g.L2 + x2) * cpp + chunk;
+  }
+  const int32_t s = blk * spb + (wi / G) * 16 + (lane & 15);
   const int nu0 = grp * NV;
   const bool live = s < V;
   const int64_t FV = 32 * (int64_t)V;
@@ -352,12 +364,16 @@ int hop_walk_ok(const Geom& g, const HopConfig& cfg) {
   return (cfg.walk > 0 && (g.L3 % cfg.walk) == 0) ? 1 : 0;
 }
 
-// hop-split shape (order 2): each wave covers 16 sites of one direction group
-int hop_split_ok(const HopConfig& cfg) { return (cfg.order == 2 && (cfg.block / 64) % (4 / cfg.nv) == 0) ? 1 : 0; }
+// hop-split shape (order 2, or 3 with the x3-fastest block order): each wave covers 16 sites
+// of one direction group
+int hop_split_ok(const HopConfig& cfg) {
+  return ((cfg.order == 2 || cfg.order == 3) && (cfg.block / 64) % (4 / cfg.nv) == 0) ? 1 : 0;
+}
+static int hop_split_spb(const HopConfig& cfg) { return (cfg.block / 64) / (4 / cfg.nv) * 16; }
 
 int hop_num_blocks(const Geom& g, const HopConfig& cfg) {
   if (hop_split_ok(cfg)) {
-    const int spb = (cfg.block / 64) / (4 / cfg.nv) * 16;
+    const int spb = hop_split_spb(cfg);
     return (g.V + spb - 1) / spb;
   }
   const int spb = cfg.block * cfg.nv / 4;
@@ -369,7 +385,7 @@ int hop_num_blocks(const Geom& g, const HopConfig& cfg) {
 }
 
 int hop_order_ok(const Geom& g, const HopConfig& cfg) {
-  const int spb = cfg.block * cfg.nv / 4;
+  const int spb = hop_split_ok(cfg) ? hop_split_spb(cfg) : cfg.block * cfg.nv / 4;
   return ((g.L0 * g.L1) % spb) == 0 ? 1 : 0;
 }
 
@@ -380,10 +396,11 @@ static hipError_t launch_hop_form(const HopArgs<T>& A, const HopConfig& cfg, hip
   // the partial-sum buffers hold hop_max_blocks entries per field and dot product
   if (dots && (int)grid.x > hop_max_blocks(A.g)) return hipErrorInvalidValue;
   if (hop_split_ok(cfg)) {
+    const int32_t ord = (cfg.order == 3 && hop_order_ok(A.g, cfg)) ? 1 : 0;
     if (dots)
-      hipLaunchKernelGGL((k_hop_split<T, FORM, NV, true>), grid, block, 0, s, A, cfg.xcd_remap);
+      hipLaunchKernelGGL((k_hop_split<T, FORM, NV, true>), grid, block, 0, s, A, cfg.xcd_remap, ord);
     else
-      hipLaunchKernelGGL((k_hop_split<T, FORM, NV, false>), grid, block, 0, s, A, cfg.xcd_remap);
+      hipLaunchKernelGGL((k_hop_split<T, FORM, NV, false>), grid, block, 0, s, A, cfg.xcd_remap, ord);
     return hipGetLastError();
   }
   const int32_t order = (cfg.order == 1 && hop_order_ok(A.g, cfg)) ? 1 : 0;

@@ -26,9 +26,10 @@ Key key_of(const Geom& g, int32_t dtype, int32_t n_rhs) {
 
 // Untuned defaults, from the sweeps of the autotuner: on lattices of a million sites and more
 // the x3-walking kernel with four directions per thread (the streamed form in FP64, the
-// materialised adjoint matrix in FP32); on smaller ones the hop-split shape (four lanes per
-// site, one per direction), whose four times as many waves hide the memory latency that one
-// thread per site leaves exposed when the lattice gives only a few waves per SIMD.
+// materialised adjoint matrix in FP32); below that the hop-split shape (four lanes per site, one
+// per direction), whose four times as many waves hide the memory latency that one thread per
+// site leaves exposed when the lattice gives only a few waves per SIMD, except FP64 from 2^18
+// sites on, where one thread per site and direction pair in the x3-fastest order is as fast.
 HopConfig defaults(const Geom& g, int32_t dtype) {
   HopConfig c;
   if (g.V >= (1 << 20)) {
@@ -47,6 +48,15 @@ HopConfig defaults(const Geom& g, int32_t dtype) {
         break;
       }
     }
+  } else if (dtype == RMH_F64 && g.V >= (1 << 18)) {
+    // one thread per site and direction pair, 3x3 products, x3-fastest block order
+    c.form = kFormMatrix;
+    c.block = 256;
+    c.xcd_remap = 1;
+    c.nv = 2;
+    c.walk = 0;
+    c.order = 1;
+    if (!hop_order_ok(g, c)) c.order = 0;
   } else {
     // the hop-split shape: four lanes per site
     c.form = dtype == RMH_F64 ? kFormMatrix : kFormStream;

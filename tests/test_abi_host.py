@@ -205,7 +205,7 @@ def test_tune_set_validation():
     f = _lib.lib().rmh_tune_set
     L = _lib.lattice_arg((4, 4, 4, 4))
     ok = [(0, 256, 1, 4, 0, 0), (1, 64, 0, 4, 1, 0), (2, 128, 1, 2, 2, 0), (1, 256, 1, 1, 2, 0),
-          (2, 128, 0, 4, 0, 4)]
+          (2, 128, 0, 4, 0, 4), (1, 128, 1, 2, 3, 0)]
     for form, block, xcd, nv, order, walk in ok:
         assert f(L, 0, 1, form, block, xcd, nv, order, walk) == 0, (form, block, nv, order, walk)
     bad = [(3, 256, 1, 4, 0, 0),     # form
@@ -213,7 +213,7 @@ def test_tune_set_validation():
            (0, 256, 1, 3, 0, 0),     # nv
            (0, 256, 1, 1, 0, 0),     # nv = 1 needs form 1
            (0, 64, 1, 2, 2, 0),      # half a wave per direction group
-           (0, 256, 1, 4, 3, 0),     # order
+           (0, 256, 1, 4, 4, 0),     # order
            (0, 256, 1, 4, -1, 0),
            (0, 256, 1, 4, 0, 65)]    # walk
     for form, block, xcd, nv, order, walk in bad:

@@ -118,18 +118,23 @@ def test_laplacian_hop_split_parity(L, kind, seed):
     U, P, Ud, Pd = setup(L, kind, 0.5, seed, n=2)
     ref = olap.laplacian(U, P, L, 0.4)
     U32, P32 = Ud.float(), Pd.float()
+    outs = {}
     for form in (0, 1, 2):
         for nv, block in ((4, 64), (4, 256), (2, 128), (2, 256)) + (((1, 256),) if form == 1 else ()):
-            api.tune_set(L, torch.float64, 2, form, block, 1, nv, 2, 0)
-            y = api.laplacian_apply(L, Ud, Pd, 0.4).cpu().numpy()
-            assert rel_max(y, ref) <= 1e-12, (form, nv, block)
+            # order 3: the x3-fastest block order (when L0 * L1 holds whole blocks)
+            for order, xcd in ((2, 1), (3, 1), (3, 0)):
+                api.tune_set(L, torch.float64, 2, form, block, xcd, nv, order, 0)
+                y = api.laplacian_apply(L, Ud, Pd, 0.4).cpu().numpy()
+                assert rel_max(y, ref) <= 1e-12, (form, nv, block, order)
+                # the block order does not change any site's arithmetic
+                assert np.array_equal(outs.setdefault((form, nv), y), y), (form, nv, block, order)
             api.tune_set(L, torch.float32, 2, form, block, 0, nv, 2, 0)
             y32 = api.laplacian_apply(L, U32, P32, 0.4).cpu().numpy().astype(np.float64)
             assert np.abs(y32 - ref).max() <= 1e-5 * np.abs(ref).max(), (form, nv, block)
     with pytest.raises(RmhError):
         api.tune_set(L, torch.float64, 2, 0, 64, 1, 2, 2, 0)    # two direction groups need two waves
     with pytest.raises(RmhError):
-        api.tune_set(L, torch.float64, 2, 0, 256, 1, 4, 3, 0)   # no order 3
+        api.tune_set(L, torch.float64, 2, 0, 256, 1, 4, 4, 0)   # no order 4
     api.tune_clear()
 
 
