@@ -536,7 +536,7 @@ rmh_status engine_solve(Engine& e, const double* U64, const float* U32, const do
         HIP_TRY(launch_cg_beta(cg64, 0, s));
         {
           ProfScope ps(RMH_PROF_CG_RESIDUAL, (double)nr * n * 3 * 8.0, s, nr);
-          HIP_TRY(launch_cg_p_update<double>(cg64, e.ring, e.p64, nullptr, n, s));
+          HIP_TRY(launch_cg_p_update<double>(cg64, e.ring, e.p64, nullptr, nullptr, n, s));
         }
       } else {
         {
@@ -551,12 +551,11 @@ rmh_status engine_solve(Engine& e, const double* U64, const float* U32, const do
         HIP_TRY(launch_cg_beta(cg32, 1, s));
         {
           ProfScope ps(RMH_PROF_CG_RESIDUAL, (double)nr * n * 5 * 4.0, s, nr);
-          HIP_TRY(launch_cg_p_update<float>(cg32, e.ring, e.p32, e.x_lo, n, s));
+          HIP_TRY(launch_cg_p_update<float>(cg32, e.ring, e.p32, e.x_lo, x_hi, n, s));
         }
         // reliable update decided by this iteration's beta kernel (blocks of rhs without a
-        // pending update exit at once): the seed solution into FP64, then its FP64 residual;
-        // the stencil's bytes are added once the update count is known
-        HIP_TRY(launch_cg_xfold(cg32, e.x_lo, x_hi, 0, n, s));
+        // pending update exit at once): the p update has folded the seed solution into FP64,
+        // now its FP64 residual; the stencil's bytes are added once the update count is known
         {
           ProfScope ps(RMH_PROF_STENCIL, 0.0, s, 0.0);
           HIP_TRY(launch_hop<double>(hr, c64, s));

@@ -168,11 +168,13 @@ template <typename T>
 hipError_t launch_cg_r_update(const CgDev& cg, void* ring, const T* Ap, const T* p, double* x_hi,
                               const double* r64, int64_t n_reals, hipStream_t s);
 // seed direction p = r' + beta p (while the rhs runs); with x_lo non-null also x_lo += alpha p
-// (the FP32 increment of the seed's solution, FP32 phase)
+// (the FP32 increment of the seed's solution, FP32 phase), and with x_hi non-null, for the rhs
+// with a pending reliable update, x_hi[seed] += x_lo, x_lo = 0 in the same pass
 template <typename T>
-hipError_t launch_cg_p_update(const CgDev& cg, const void* ring, T* p, float* x_lo, int64_t n_reals,
-                              hipStream_t s);
-// x_hi[seed] += x_lo, x_lo = 0 for the rhs with a pending reliable update (all: every rhs)
+hipError_t launch_cg_p_update(const CgDev& cg, const void* ring, T* p, float* x_lo, double* x_hi,
+                              int64_t n_reals, hipStream_t s);
+// x_hi[seed] += x_lo, x_lo = 0 for every rhs (all, the end of a mixed solve) or those with a
+// pending reliable update
 hipError_t launch_cg_xfold(const CgDev& cg, float* x_lo, double* x_hi, int32_t all, int64_t n_reals, hipStream_t s);
 // fold the segment into x_j (and p_j unless final) of every shift updated in it (p_j0 is read
 // only where its coefficient is nonzero: before the first flush it holds nothing), then reset

@@ -560,7 +560,8 @@ template hipError_t launch_cg_r_update<float>(const CgDev&, void*, const float*,
                                               const double*, int64_t, hipStream_t);
 
 template <typename T>
-__global__ void k_cg_p(CgDev cg, const void* ring, T* __restrict__ p, float* __restrict__ x_lo, int64_t n) {
+__global__ void k_cg_p(CgDev cg, const void* ring, T* __restrict__ p, float* __restrict__ x_lo,
+                       double* __restrict__ x_hi, int64_t n) {
   const int32_t v = blockIdx.y;
   const int32_t* fl = cg.flags + (int64_t)v * kFlN;
   if (fl[kFlLive] == 0) return;
@@ -577,9 +578,21 @@ __global__ void k_cg_p(CgDev cg, const void* ring, T* __restrict__ p, float* __r
 #pragma unroll
   for (int k = 0; k < 4; ++k) pold[k] = pv[i0 + k];
   if (xv) {
-    // the seed's increment of this iteration, alpha p, in FP32 until the next reliable update
+    // the seed's increment of this iteration, alpha p, in FP32 until the next reliable update;
+    // when this iteration's beta kernel asked for one, the increment goes into the FP64 seed
+    // solution now (x_hi[seed] += x_lo, x_lo = 0), ahead of the update's FP64 residual stencil
+    const bool fold = x_hi && fl[kFlNeedRU];
+    double* xh = fold ? x_hi + ((int64_t)v * cg.n_shift + cg.seed[v]) * n : nullptr;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) xv[i0 + k] = fmaf(alpha, (float)pold[k], xv[i0 + k]);
+    for (int k = 0; k < 4; ++k) {
+      const float xn = fmaf(alpha, (float)pold[k], xv[i0 + k]);
+      if (fold) {
+        xh[i0 + k] += (double)xn;
+        xv[i0 + k] = 0.0f;
+      } else {
+        xv[i0 + k] = xn;
+      }
+    }
   }
   if (upd_p) {
 #pragma unroll
@@ -588,10 +601,10 @@ __global__ void k_cg_p(CgDev cg, const void* ring, T* __restrict__ p, float* __r
 }
 
 template <typename T>
-hipError_t launch_cg_p_update(const CgDev& cg, const void* ring, T* p, float* x_lo, int64_t n_reals,
-                              hipStream_t s) {
+hipError_t launch_cg_p_update(const CgDev& cg, const void* ring, T* p, float* x_lo, double* x_hi,
+                              int64_t n_reals, hipStream_t s) {
   dim3 grid(elem_num_blocks(n_reals), cg.n_rhs);
-  hipLaunchKernelGGL((k_cg_p<T>), grid, dim3(kBlock), 0, s, cg, ring, p, x_lo, n_reals);
+  hipLaunchKernelGGL((k_cg_p<T>), grid, dim3(kBlock), 0, s, cg, ring, p, x_lo, x_hi, n_reals);
   return hipGetLastError();
 }
 
@@ -616,8 +629,10 @@ hipError_t launch_cg_xfold(const CgDev& cg, float* x_lo, double* x_hi, int32_t a
   return hipGetLastError();
 }
 
-template hipError_t launch_cg_p_update<double>(const CgDev&, const void*, double*, float*, int64_t, hipStream_t);
-template hipError_t launch_cg_p_update<float>(const CgDev&, const void*, float*, float*, int64_t, hipStream_t);
+template hipError_t launch_cg_p_update<double>(const CgDev&, const void*, double*, float*, double*, int64_t,
+                                               hipStream_t);
+template hipError_t launch_cg_p_update<float>(const CgDev&, const void*, float*, float*, double*, int64_t,
+                                              hipStream_t);
 
 // One element per thread: the segment's residuals at this element are loaded once and every
 // non-seed shift touched in the segment is folded from registers.
