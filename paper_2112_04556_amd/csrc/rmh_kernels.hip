@@ -278,21 +278,54 @@ hipError_t launch_cg_init(const CgDev& cg, const double* bn2_partials, int32_t n
 __global__ void k_cg_alpha(CgDev cg) {
   const int32_t v = blockIdx.x;
   int32_t* fl = cg.flags + (int64_t)v * kFlN;
-  if (fl[kFlRun] == 0) {
-    if (threadIdx.x == 0) fl[kFlLive] = 0;
+  double* sc = cg.sc + (int64_t)v * kScN;
+  const int32_t ns = cg.n_shift;
+  const int32_t nc = 2 + 2 * cg.cslots;
+  const int32_t tid = threadIdx.x;
+  // Every load that does not need alpha is issued first (each address is valid whatever the
+  // flags hold), so the block waits on memory a few times instead of once per dependent step.
+  const int32_t run = fl[kFlRun];
+  const int32_t m = fl[kFlM];
+  const int32_t ru = cg.part_ru ? fl[kFlNeedRU] : 0;
+  const int32_t seed = cg.seed[v];
+  const double rr_sc = sc[kScRR], ap = sc[kScAlphaPrev], bp = sc[kScBetaPrev];
+  // this thread's shift (n_shift <= blockDim)
+  int32_t on = 0;
+  double z = 0.0, zp = 0.0, sig = 0.0;
+  if (tid < ns) {
+    const int64_t vj = (int64_t)v * ns + tid;
+    on = cg.act_next[vj];
+    z = cg.sh[vj * kShN + kShZeta];
+    zp = cg.sh[vj * kShN + kShZetaPrev];
+    sig = cg.sigma[vj];
+  }
+  const double s0 = cg.sigma[(int64_t)v * ns + seed];
+  // this thread's (shift, coefficient) pair when they all fit in the block: q = 0 the p_j0
+  // coefficient (x_j0 += cx p_j0), q = 1 + i the ring entry i <= m (d_ji += cx e_ji)
+  const int32_t per = m + 2;
+  const bool one_pass = ns * per <= (int32_t)blockDim.x;
+  int32_t pj = 0, pq = 0;
+  double c_dst = 0.0, c_src = 0.0;
+  if (one_pass && tid < ns * per) {
+    pj = tid / per;
+    pq = tid - pj * per;
+    const double* cf = cg.coef + ((int64_t)v * ns + pj) * nc;
+    c_dst = pq == 0 ? cf[0] : cf[1 + pq];
+    c_src = pq == 0 ? cf[1] : cf[1 + pq + cg.cslots];
+  }
+  if (run == 0) {
+    if (tid == 0) fl[kFlLive] = 0;
     return;
   }
   __shared__ double lds[1][16];
-  double* sc = cg.sc + (int64_t)v * kScN;
   // a reliable update issued at the end of the previous iteration: its FP64 residual
   // r64 = b - (Delta + sigma0) x_seed replaces the recursive residual from now on
-  const int32_t ru = cg.part_ru ? fl[kFlNeedRU] : 0;
   double rr_true = 0.0;
   if (ru) rr_true = block_sum_array(cg.part_ru + ((int64_t)v * 3 + 2) * cg.nblk_ru, cg.nblk_ru, lds);
   const double pAp = block_sum_array(cg.part + ((int64_t)v * 3 + 1) * cg.nblk_hop, cg.nblk_hop, lds);
   __shared__ double s_alpha;
   __shared__ int s_ok;
-  if (threadIdx.x == 0) {
+  if (tid == 0) {
     if (ru) {
       sc[kScRR] = rr_true;
       sc[kScMaxR] = sqrt(rr_true);
@@ -300,7 +333,7 @@ __global__ void k_cg_alpha(CgDev cg) {
       fl[kFlNeedRU] = 0;
       fl[kFlRUMask] = 1;
     }
-    const double rr = sc[kScRR];
+    const double rr = ru ? rr_true : rr_sc;
     const double alpha = rr / pAp;
     s_ok = (pAp > 0.0 && alpha == alpha && alpha < 1e300) ? 1 : 0;
     s_alpha = alpha;
@@ -316,48 +349,46 @@ __global__ void k_cg_alpha(CgDev cg) {
   __syncthreads();
   if (!s_ok) return;
   const double alpha = s_alpha;
-  const double ap = sc[kScAlphaPrev], bp = sc[kScBetaPrev];
-  const int32_t seed = cg.seed[v];
-  const double s0 = cg.sigma[(int64_t)v * cg.n_shift + seed];
-  const int32_t m = fl[kFlM];
-  const int32_t nc = 2 + 2 * cg.cslots;
   __shared__ double s_cx[kMaxShifts];
   __shared__ int s_upd[kMaxShifts];
   // per shift: zeta_{k+1} and the x coefficient
-  for (int j = threadIdx.x; j < cg.n_shift; j += blockDim.x) {
-    const int64_t vj = (int64_t)v * cg.n_shift + j;
-    const int32_t on = cg.act_next[vj];
+  if (tid < ns) {
+    const int64_t vj = (int64_t)v * ns + tid;
     cg.act[vj] = on;
     double* sh = cg.sh + vj * kShN;
     int upd = 0;
     if (on) {
-      const double z = sh[kShZeta], zp = sh[kShZetaPrev];
-      const double ds = cg.sigma[vj] - s0;
+      const double ds = sig - s0;
       const double zn = z * zp * ap / (ap * zp * (1.0 + alpha * ds) + alpha * bp * (zp - z));
       const double cx = alpha * zn / z;
       sh[kShZetaNext] = zn;
       sh[kShCx] = cx;
       sh[kShUpd] += 1.0;
-      upd = (cg.ring_on && m < cg.nslot && !(cg.seed_explicit && j == seed)) ? 1 : 0;
+      upd = (cg.ring_on && m < cg.nslot && !(cg.seed_explicit && tid == seed)) ? 1 : 0;
       if (upd) sh[kShSeg] = 1.0;
-      s_cx[j] = cx;
+      s_cx[tid] = cx;
     } else {
       sh[kShCx] = 0.0;
     }
-    s_upd[j] = upd;
+    s_upd[tid] = upd;
   }
   __syncthreads();
-  // x_j += cx_j p_j on the segment coefficients, one (shift, coefficient) per thread:
-  // q = 0 the p_j0 coefficient, q = 1 + i the ring entry i <= m
-  const int32_t per = m + 2;
-  for (int t = threadIdx.x; t < cg.n_shift * per; t += blockDim.x) {
-    const int32_t j = t / per, q = t - j * per;
-    if (!s_upd[j]) continue;
-    double* cf = cg.coef + ((int64_t)v * cg.n_shift + j) * nc;
-    if (q == 0)
-      cf[0] = fma(s_cx[j], cf[1], cf[0]);
-    else
-      cf[1 + q] = fma(s_cx[j], cf[1 + q + cg.cslots], cf[1 + q]);
+  // x_j += cx_j p_j on the segment coefficients, one (shift, coefficient) pair per thread
+  if (one_pass) {
+    if (tid < ns * per && s_upd[pj]) {
+      double* cf = cg.coef + ((int64_t)v * ns + pj) * nc;
+      cf[pq == 0 ? 0 : 1 + pq] = fma(s_cx[pj], c_src, c_dst);
+    }
+  } else {
+    for (int t = tid; t < ns * per; t += blockDim.x) {
+      const int32_t jj = t / per, q = t - jj * per;
+      if (!s_upd[jj]) continue;
+      double* cf = cg.coef + ((int64_t)v * ns + jj) * nc;
+      if (q == 0)
+        cf[0] = fma(s_cx[jj], cf[1], cf[0]);
+      else
+        cf[1 + q] = fma(s_cx[jj], cf[1 + q + cg.cslots], cf[1 + q]);
+    }
   }
 }
 
@@ -373,52 +404,80 @@ hipError_t launch_cg_alpha(const CgDev& cg, hipStream_t s) {
 __global__ void k_cg_beta(CgDev cg, int32_t mixed) {
   const int32_t v = blockIdx.x;
   int32_t* fl = cg.flags + (int64_t)v * kFlN;
-  if (fl[kFlLive] == 0) return;
+  double* sc = cg.sc + (int64_t)v * kScN;
+  const int32_t ns = cg.n_shift;
+  const int32_t nc = 2 + 2 * cg.cslots;
+  const int32_t tid = threadIdx.x;
+  // loads that do not need the new residual norm go out first (valid addresses whatever the
+  // flags hold)
+  const int32_t live = fl[kFlLive];
+  const int32_t m = fl[kFlM];
+  const int32_t seed = cg.seed[v];
+  const double rr_old = sc[kScRR], tolabs = sc[kScTolAbs];
+  int32_t act = 0;
+  double z = 0.0, zn = 0.0;
+  if (tid < ns) {
+    const int64_t vj = (int64_t)v * ns + tid;
+    act = cg.act[vj];
+    z = cg.sh[vj * kShN + kShZeta];
+    zn = cg.sh[vj * kShN + kShZetaNext];
+  }
+  // this thread's (shift, coefficient) pair when they all fit in the block: q = 0 the p_j0
+  // coefficient, q = 1 + i the ring entry i <= m (both scaled by cp_j), q = m + 2 the new
+  // entry m + 1 (set to cr_j)
+  const int32_t per = m + 3;
+  const bool one_pass = ns * per <= (int32_t)blockDim.x;
+  int32_t pj = 0, pq = 0;
+  double c_old = 0.0;
+  if (one_pass && tid < ns * per) {
+    pj = tid / per;
+    pq = tid - pj * per;
+    const double* cf = cg.coef + ((int64_t)v * ns + pj) * nc;
+    if (pq == 0)
+      c_old = cf[1];
+    else if (pq <= m + 1)
+      c_old = cf[2 + cg.cslots + pq - 1];
+  }
+  if (live == 0) return;
   __shared__ double lds[1][16];
   __shared__ double s_rrn;
   {
     const double t = block_sum_array(cg.part + (int64_t)v * cg.nblk_e, cg.nblk_e, lds);
-    if (threadIdx.x == 0) s_rrn = t;  // the block sum is valid in thread 0 only
+    if (tid == 0) s_rrn = t;  // the block sum is valid in thread 0 only
     __syncthreads();
   }
   const double rrn = s_rrn;
-  double* sc = cg.sc + (int64_t)v * kScN;
-  const double beta = rrn / sc[kScRR];
+  const double beta = rrn / rr_old;
   const double rnorm = sqrt(rrn);
-  const double tolabs = sc[kScTolAbs];
-  const int32_t seed = cg.seed[v];
-  const int32_t m = fl[kFlM];
-  const int32_t nc = 2 + 2 * cg.cslots;
   __shared__ double s_cp[kMaxShifts], s_cr[kMaxShifts];
   __shared__ int s_upd[kMaxShifts];
   int any_other = 0;
   // per shift: beta_j, the p coefficients, convergence
-  for (int j = threadIdx.x; j < cg.n_shift; j += blockDim.x) {
-    const int64_t vj = (int64_t)v * cg.n_shift + j;
+  if (tid < ns) {
+    const int64_t vj = (int64_t)v * ns + tid;
     double* sh = cg.sh + vj * kShN;
     int upd = 0;
-    if (cg.act[vj]) {
-      const double z = sh[kShZeta], zn = sh[kShZetaNext];
+    if (act) {
       const double ratio = zn / z;
       const double cr = zn, cp = beta * ratio * ratio;
       sh[kShCr] = cr;
       sh[kShCp] = cp;
-      s_cr[j] = cr;
-      s_cp[j] = cp;
+      s_cr[tid] = cr;
+      s_cp[tid] = cp;
       const int32_t keep = (fabs(zn) * rnorm > tolabs) ? 1 : 0;
       cg.act_next[vj] = keep;
-      if (j != seed) any_other |= keep;
-      upd = (!(cg.seed_explicit && j == seed) && cg.ring_on && keep && m + 1 < cg.nslot) ? 1 : 0;
+      if (tid != seed) any_other |= keep;
+      upd = (!(cg.seed_explicit && tid == seed) && cg.ring_on && keep && m + 1 < cg.nslot) ? 1 : 0;
       sh[kShZetaPrev] = z;
       sh[kShZeta] = zn;
     } else {
       cg.act_next[vj] = 0;
     }
-    s_upd[j] = upd;
+    s_upd[tid] = upd;
   }
   any_other = __syncthreads_or(any_other);
-  if (threadIdx.x == 0) {
-    const int64_t vs = (int64_t)v * cg.n_shift + seed;
+  if (tid == 0) {
+    const int64_t vs = (int64_t)v * ns + seed;
     if (any_other && !cg.act_next[vs] && cg.act[vs]) {
       // the seed carries the Krylov space for the others: its direction keeps being updated
       cg.act_next[vs] = 1;
@@ -447,20 +506,30 @@ __global__ void k_cg_beta(CgDev cg, int32_t mixed) {
     }
   }
   __syncthreads();
-  // p_j = cr_j r' + cp_j p_j on the segment coefficients, one (shift, coefficient) per thread:
-  // q = 0 the p_j0 coefficient, q = 1 + i the ring entry i <= m, q = m + 2 the new entry m + 1
-  const int32_t per = m + 3;
-  for (int t = threadIdx.x; t < cg.n_shift * per; t += blockDim.x) {
-    const int32_t j = t / per, q = t - j * per;
-    if (!s_upd[j]) continue;
-    double* cf = cg.coef + ((int64_t)v * cg.n_shift + j) * nc;
-    double* e = cf + 2 + cg.cslots;
-    if (q == 0)
-      cf[1] *= s_cp[j];
-    else if (q <= m + 1)
-      e[q - 1] *= s_cp[j];
-    else
-      e[m + 1] = s_cr[j];
+  // p_j = cr_j r' + cp_j p_j on the segment coefficients, one (shift, coefficient) pair per thread
+  if (one_pass) {
+    if (tid < ns * per && s_upd[pj]) {
+      double* cf = cg.coef + ((int64_t)v * ns + pj) * nc;
+      if (pq == 0)
+        cf[1] = c_old * s_cp[pj];
+      else if (pq <= m + 1)
+        cf[2 + cg.cslots + pq - 1] = c_old * s_cp[pj];
+      else
+        cf[2 + cg.cslots + m + 1] = s_cr[pj];
+    }
+  } else {
+    for (int t = tid; t < ns * per; t += blockDim.x) {
+      const int32_t jj = t / per, q = t - jj * per;
+      if (!s_upd[jj]) continue;
+      double* cf = cg.coef + ((int64_t)v * ns + jj) * nc;
+      double* e = cf + 2 + cg.cslots;
+      if (q == 0)
+        cf[1] *= s_cp[jj];
+      else if (q <= m + 1)
+        e[q - 1] *= s_cp[jj];
+      else
+        e[m + 1] = s_cr[jj];
+    }
   }
 }
 
@@ -507,27 +576,38 @@ __global__ void k_cg_r(CgDev cg, void* ring, const T* __restrict__ Ap, const T* 
                        double* __restrict__ x_hi, const double* __restrict__ r64, int64_t n, int32_t steps) {
   const int32_t v = blockIdx.y;
   const int32_t* fl = cg.flags + (int64_t)v * kFlN;
-  if (fl[kFlLive] == 0) return;
-  const int32_t from64 = r64 ? fl[kFlRUMask] : 0;
+  // the per-rhs state in one batch of independent loads, ahead of any branch on it
+  const int32_t live = fl[kFlLive], ru_mask = fl[kFlRUMask];
   const int32_t m = fl[kFlM], base = fl[kFlBase];
+  const int32_t seed = cg.seed[v];
+  const double alpha_d = cg.sc[(int64_t)v * kScN + kScAlpha];
+  if (live == 0) return;
+  const int32_t from64 = r64 ? ru_mask : 0;
   const T* rc = ring_slot<T>(ring, cg.ring_rhs_bytes, v, (base + m) % cg.nslot, n);
   T* rn = ring_slot<T>(ring, cg.ring_rhs_bytes, v, (base + m + 1) % cg.nslot, n);
-  const double alpha_d = cg.sc[(int64_t)v * kScN + kScAlpha];
   const T alpha = (T)alpha_d;
   const T* av = Ap + (int64_t)v * n;
   const T* pv = p + (int64_t)v * n;
-  double* xs = x_hi ? x_hi + ((int64_t)v * cg.n_shift + cg.seed[v]) * n : nullptr;
+  double* xs = x_hi ? x_hi + ((int64_t)v * cg.n_shift + seed) * n : nullptr;
   const double* r64v = r64 ? r64 + (int64_t)v * n : nullptr;
   double d[1] = {0.0};
   for (int32_t t = 0; t < steps; ++t) {
     const int64_t i0 = (((int64_t)blockIdx.x * steps + t) * blockDim.x + threadIdx.x) * 4;
     if (i0 < n) {
+      // (the residual source is uniform per field: one branch around whole vector loads)
       T r0[4], a4[4];
+      if (from64) {
+        double rd[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        r0[k] = from64 ? (T)r64v[i0 + k] : rc[i0 + k];
-        a4[k] = av[i0 + k];
+        for (int k = 0; k < 4; ++k) rd[k] = r64v[i0 + k];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) r0[k] = (T)rd[k];
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) r0[k] = rc[i0 + k];
       }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) a4[k] = av[i0 + k];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const T r1 = fmadd(-alpha, a4[k], r0[k]);
@@ -564,34 +644,44 @@ __global__ void k_cg_p(CgDev cg, const void* ring, T* __restrict__ p, float* __r
                        double* __restrict__ x_hi, int64_t n) {
   const int32_t v = blockIdx.y;
   const int32_t* fl = cg.flags + (int64_t)v * kFlN;
-  if (fl[kFlLive] == 0) return;
-  const int32_t upd_p = fl[kFlRun];
+  const double* scv = cg.sc + (int64_t)v * kScN;
+  // the per-rhs state in one batch of independent loads, ahead of any branch on it
+  const int32_t live = fl[kFlLive], upd_p = fl[kFlRun], need_ru = fl[kFlNeedRU];
+  const int32_t cur = fl[kFlBase] + fl[kFlM];
+  const int32_t seed = cg.seed[v];
+  const double beta_d = scv[kScBetaPrev], alpha_d = scv[kScAlpha];
+  if (live == 0) return;
   if (!upd_p && !x_lo) return;
   const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
   if (i0 >= n) return;
-  const T* r = ring_slot<T>(ring, cg.ring_rhs_bytes, v, (fl[kFlBase] + fl[kFlM]) % cg.nslot, n);
-  const T beta = (T)cg.sc[(int64_t)v * kScN + kScBetaPrev];
-  const float alpha = (float)cg.sc[(int64_t)v * kScN + kScAlpha];
+  const T* r = ring_slot<T>(ring, cg.ring_rhs_bytes, v, cur % cg.nslot, n);
+  const T beta = (T)beta_d;
+  const float alpha = (float)alpha_d;
   T* pv = p + (int64_t)v * n;
-  float* xv = x_lo ? x_lo + (int64_t)v * n : nullptr;
   T pold[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) pold[k] = pv[i0 + k];
-  if (xv) {
+  if (x_lo) {
     // the seed's increment of this iteration, alpha p, in FP32 until the next reliable update;
     // when this iteration's beta kernel asked for one, the increment goes into the FP64 seed
     // solution now (x_hi[seed] += x_lo, x_lo = 0), ahead of the update's FP64 residual stencil
-    const bool fold = x_hi && fl[kFlNeedRU];
-    double* xh = fold ? x_hi + ((int64_t)v * cg.n_shift + cg.seed[v]) * n : nullptr;
+    float* xv = x_lo + (int64_t)v * n + i0;
+    float xl[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const float xn = fmaf(alpha, (float)pold[k], xv[i0 + k]);
-      if (fold) {
-        xh[i0 + k] += (double)xn;
-        xv[i0 + k] = 0.0f;
-      } else {
-        xv[i0 + k] = xn;
+    for (int k = 0; k < 4; ++k) xl[k] = xv[k];
+    if (x_hi && need_ru) {
+      double* xh = x_hi + ((int64_t)v * cg.n_shift + seed) * n + i0;
+      double xo[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) xo[k] = xh[k];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        xh[k] = xo[k] + (double)fmaf(alpha, (float)pold[k], xl[k]);
+        xv[k] = 0.0f;
       }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) xv[k] = fmaf(alpha, (float)pold[k], xl[k]);
     }
   }
   if (upd_p) {
@@ -658,12 +748,15 @@ __global__ void __launch_bounds__(256) k_cg_flush(CgDev cg, const void* ring, do
   __syncthreads();
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
+  // every slot load is issued unconditionally so they overlap: entries past m re-read slot m
+  // (a cache hit) and are never used
+  T rt[kMaxSlots];
+#pragma unroll
+  for (int i = 0; i < kMaxSlots; ++i)
+    rt[i] = ring_slot<T>(ring, cg.ring_rhs_bytes, v, (base + min(i, m)) % cg.nslot, n)[e];
   double rv[kMaxSlots];
 #pragma unroll
-  for (int i = 0; i < kMaxSlots; ++i) {
-    rv[i] = 0.0;
-    if (i <= m) rv[i] = (double)ring_slot<T>(ring, cg.ring_rhs_bytes, v, (base + i) % cg.nslot, n)[e];
-  }
+  for (int i = 0; i < kMaxSlots; ++i) rv[i] = (double)rt[i];
   for (int j = 0; j < ns; ++j) {
     if (cg.seed_explicit && j == seed) continue;   // kept current by the residual update
     const int64_t vj = (int64_t)v * ns + j;
@@ -996,50 +1089,83 @@ __global__ void __launch_bounds__(256) k_cheb_fold(const T* __restrict__ x, cons
                                                    int32_t k0, int32_t cnt, int32_t first,
                                                    const double* __restrict__ coef, int32_t D1, int32_t nw,
                                                    T* __restrict__ y, int64_t n) {
+  // this fold's coefficients (window w, vector j: coef[w][k0 + j]; column 0 for x on the first
+  // fold) staged in LDS by the whole block, so the window loop reads no global scalars
+  __shared__ double s_c[kMaxFilterWindows][kMaxFold + 1];
+  for (int t = threadIdx.x; t < nw * (kMaxFold + 1); t += blockDim.x) {
+    const int w = t / (kMaxFold + 1), j = t - w * (kMaxFold + 1);
+    double c = 0.0;
+    if (j == 0)
+      c = first ? coef[(int64_t)w * D1] : 0.0;
+    else if (j <= cnt)
+      c = coef[(int64_t)w * D1 + k0 + j - 1];
+    s_c[w][j] = c;
+  }
+  __syncthreads();
   const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 2;
   if (i0 >= n) return;
+  // every load is issued unconditionally so they overlap: entries past cnt re-read the last
+  // vector of the fold (a cache hit) and are never used
+  T tt[kMaxFold][2];
+#pragma unroll
+  for (int j = 0; j < kMaxFold; ++j) {
+    const T* t = ring + (int64_t)((k0 + min(j, cnt - 1)) % R) * n + i0;
+    tt[j][0] = t[0];
+    tt[j][1] = t[1];
+  }
   double tv[kMaxFold][2];
 #pragma unroll
   for (int j = 0; j < kMaxFold; ++j) {
-    if (j < cnt) {
-      const T* t = ring + (int64_t)((k0 + j) % R) * n + i0;
-      tv[j][0] = (double)t[0];
-      tv[j][1] = (double)t[1];
-    }
+    tv[j][0] = (double)tt[j][0];
+    tv[j][1] = (double)tt[j][1];
   }
   double x0 = 0.0, x1 = 0.0;
   if (first) {
     x0 = (double)x[i0];
     x1 = (double)x[i0 + 1];
   }
-  for (int32_t w = 0; w < nw; ++w) {
-    const double* cw = coef + (int64_t)w * D1;
-    T* yw = y + (int64_t)w * n + i0;
-    double a0, a1;
-    if (first) {
-      a0 = cw[0] * x0;
-      a1 = cw[0] * x1;
-    } else {
-      a0 = (double)yw[0];
-      a1 = (double)yw[1];
-    }
+  // windows four at a time: their outputs are loaded together
+  for (int32_t w0 = 0; w0 < nw; w0 += 4) {
+    double a[4][2];
 #pragma unroll
-    for (int j = 0; j < kMaxFold; ++j) {
-      if (j < cnt) {
-        const double c = cw[k0 + j];
-        a0 = fma(c, tv[j][0], a0);
-        a1 = fma(c, tv[j][1], a1);
+    for (int u = 0; u < 4; ++u) {
+      const int32_t w = w0 + u;
+      if (w < nw && !first) {
+        const T* yw = y + (int64_t)w * n + i0;
+        a[u][0] = (double)yw[0];
+        a[u][1] = (double)yw[1];
+      } else {
+        a[u][0] = 0.0;
+        a[u][1] = 0.0;
       }
     }
-    yw[0] = (T)a0;
-    yw[1] = (T)a1;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int32_t w = w0 + u;
+      if (w >= nw) break;
+      const double* c = s_c[w];
+      if (first) {
+        a[u][0] = c[0] * x0;
+        a[u][1] = c[0] * x1;
+      }
+      // branch-free: the coefficients past cnt are zero (their vectors are finite re-reads)
+#pragma unroll
+      for (int j = 0; j < kMaxFold; ++j) {
+        a[u][0] = fma(c[1 + j], tv[j][0], a[u][0]);
+        a[u][1] = fma(c[1 + j], tv[j][1], a[u][1]);
+      }
+      T* yw = y + (int64_t)w * n + i0;
+      yw[0] = (T)a[u][0];
+      yw[1] = (T)a[u][1];
+    }
   }
 }
 
 template <typename T>
 hipError_t launch_cheb_fold(const T* x, const T* ring, int32_t R, int32_t k0, int32_t cnt, int32_t first,
                             const double* coef, int32_t D, int32_t nw, T* y, int64_t n, hipStream_t s) {
-  if (n == 0 || nw == 0 || cnt < 0 || cnt > kMaxFold || (n & 1)) return n == 0 || nw == 0 ? hipSuccess : hipErrorInvalidValue;
+  if (n == 0 || nw == 0) return hipSuccess;
+  if (cnt < 1 || cnt > kMaxFold || nw > kMaxFilterWindows || (n & 1)) return hipErrorInvalidValue;
   const int64_t nb = (n / 2 + kBlock - 1) / kBlock;
   hipLaunchKernelGGL(k_cheb_fold<T>, dim3((uint32_t)nb), dim3(kBlock), 0, s, x, ring, R, k0, cnt, first, coef, D + 1,
                      nw, y, n);
