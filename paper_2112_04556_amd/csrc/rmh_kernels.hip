@@ -748,15 +748,23 @@ __global__ void __launch_bounds__(256) k_cg_flush(CgDev cg, const void* ring, do
   __syncthreads();
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
-  // every slot load is issued unconditionally so they overlap: entries past m re-read slot m
-  // (a cache hit) and are never used
-  T rt[kMaxSlots];
-#pragma unroll
-  for (int i = 0; i < kMaxSlots; ++i)
-    rt[i] = ring_slot<T>(ring, cg.ring_rhs_bytes, v, (base + min(i, m)) % cg.nslot, n)[e];
   double rv[kMaxSlots];
+  if constexpr (sizeof(T) == 8) {
 #pragma unroll
-  for (int i = 0; i < kMaxSlots; ++i) rv[i] = (double)rt[i];
+    for (int i = 0; i < kMaxSlots; ++i) {
+      rv[i] = 0.0;
+      if (i <= m) rv[i] = ring_slot<T>(ring, cg.ring_rhs_bytes, v, (base + i) % cg.nslot, n)[e];
+    }
+  } else {
+    // FP32 slots: every load is issued unconditionally so they overlap (the conditional form
+    // waits on each); entries past m re-read slot m (a cache hit) and are never used
+    T rt[kMaxSlots];
+#pragma unroll
+    for (int i = 0; i < kMaxSlots; ++i)
+      rt[i] = ring_slot<T>(ring, cg.ring_rhs_bytes, v, (base + min(i, m)) % cg.nslot, n)[e];
+#pragma unroll
+    for (int i = 0; i < kMaxSlots; ++i) rv[i] = (double)rt[i];
+  }
   for (int j = 0; j < ns; ++j) {
     if (cg.seed_explicit && j == seed) continue;   // kept current by the residual update
     const int64_t vj = (int64_t)v * ns + j;
