@@ -10,7 +10,8 @@ the rational-solve workload, kappa = 0.9), through every stage of the path:
      FP32 stencil and vectors with FP64 reliable updates, Y = R(Delta) P, K = 1/2 <Y, Y>;
   3. backward: second multi-shift solve z_j = (Delta + sigma_j)^-1 Y and the link
      derivative dK/d omega (the mass-term force, section 3);
-  4. the Chebyshev power spectrum of the force (degree 64, 16 windows, FP64 moments);
+  4. the Chebyshev power spectrum of the force (degree 64, 16 windows): FP32 stencil sweeps
+     with the moments summed in FP64, as for the batched spectra;
   5. a Chebyshev vector filter of the momentum onto 4 windows (degree 32), on a second
      stream beside stages 2-4 (it depends only on the momentum and the links).
 
@@ -153,7 +154,8 @@ def main():
             with torch.cuda.stream(side):
                 api.cheb_filter(L, Uw, Pd, 32, 4)
         out = api.kinetic_force(L, Uw, Pd, rat, solver, ws=ws)
-        api.power_spectrum(L, Uw, out["dK"], 64, 16)
+        # spectrum: FP32 stencil sweeps, FP64 moment sums (as the batched spectra)
+        api.power_spectrum(L, api.convert_f64_f32(Uw), api.convert_f64_f32(out["dK"]), 64, 16)
         if overlap:
             main.wait_stream(side)
         else:
@@ -219,7 +221,8 @@ def main():
         "config": {"workload": "RMHMC kinetic-force evaluation, 16^4 lattice, eps=0.5 links (seed 2), "
                                f"one Gaussian momentum field, 12-pole kappa={args.kappa} rational to FP64 true "
                                "residual 1e-10 (FP32 + FP64 reliable updates), force, degree-64/16-window power "
-                               "spectrum, degree-32/4-window filter of the momentum on a second stream",
+                               "spectrum (FP32 sweeps, FP64 moments), degree-32/4-window FP64 filter of the "
+                               "momentum on a second stream",
                    "lattice": list(L), "n_rhs": 1, "poles": 12, "kappa": args.kappa,
                    "value_definition": "sites x link fields through Delta per second, whole step"},
         "roofline": roofline,
