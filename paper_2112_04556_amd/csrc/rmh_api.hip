@@ -99,17 +99,48 @@ struct Carver {
   }
 };
 
-// copies host -> device on the stream and waits (host buffers may be pageable)
+// Pinned host staging for the drivers' small transfers (coefficient tables, solver state): one
+// buffer per calling thread, allocated with hipHostMalloc, grown on demand and freed when the
+// thread ends, so the copies skip the runtime's bounce through pageable memory.
+struct PinnedStage {
+  void* p = nullptr;
+  size_t cap = 0;
+  ~PinnedStage() {
+    if (p) (void)hipHostFree(p);
+  }
+};
+static thread_local PinnedStage t_stage;
+
+static rmh_status pinned(size_t bytes, void** out) {
+  if (t_stage.cap < bytes) {
+    if (t_stage.p) HIP_TRY(hipHostFree(t_stage.p));   // no copy is in flight: every user waits
+    t_stage.p = nullptr;
+    t_stage.cap = 0;
+    const size_t cap = std::max<size_t>(bytes, (size_t)1 << 16);
+    HIP_TRY(hipHostMalloc(&t_stage.p, cap, hipHostMallocDefault));
+    t_stage.cap = cap;
+  }
+  *out = t_stage.p;
+  return RMH_OK;
+}
+
+// copies host -> device on the stream through the pinned stage and waits
 rmh_status h2d(void* dst, const void* src, size_t bytes, hipStream_t s) {
   if (bytes == 0) return RMH_OK;
-  HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
+  void* st = nullptr;
+  RMH_TRY(pinned(bytes, &st));
+  memcpy(st, src, bytes);
+  HIP_TRY(hipMemcpyAsync(dst, st, bytes, hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
   return RMH_OK;
 }
 rmh_status d2h(void* dst, const void* src, size_t bytes, hipStream_t s) {
   if (bytes == 0) return RMH_OK;
-  HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
+  void* st = nullptr;
+  RMH_TRY(pinned(bytes, &st));
+  HIP_TRY(hipMemcpyAsync(st, src, bytes, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
+  memcpy(dst, st, bytes);
   return RMH_OK;
 }
 

@@ -301,3 +301,31 @@ def test_heatbath_momenta_16_properties():
     # of unity of the undamped windows holds for any degree)
     yw = api.cheb_filter(L, Ud, Pd, 32, 4, kernel=0).sum(dim=0)
     assert rel_max(yw.cpu().numpy(), Pd.cpu().numpy()) <= 1e-12
+
+
+def test_concurrent_streams_match_serial():
+    """A filter on a second stream while a rational solve and a spectrum run on the first (as the
+    benchmark step does): every result equals the serial one bit for bit (each call's workspace
+    is its own and every reduction has a fixed order)."""
+    L = (8, 8, 6, 4)
+    announce(f"concurrent streams {L}")
+    _, _, Ud, Pd = setup(L, "eps", 0.5, 21, n=1)
+    rat = _rat_kappa(0.9, 12)
+    sv = api.Solver(tol=1e-10, mode=1)
+    y_ser = api.rational_apply(L, Ud, Pd, rat, sv)["y"]
+    mom_ser, _ = api.power_spectrum(L, Ud, Pd, 40, 8)
+    f_ser = api.cheb_filter(L, Ud, Pd, 32, 4)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    main = torch.cuda.current_stream()
+    for _ in range(3):
+        side.wait_stream(main)
+        with torch.cuda.stream(side):
+            f_con = api.cheb_filter(L, Ud, Pd, 32, 4)
+        y_con = api.rational_apply(L, Ud, Pd, rat, sv)["y"]
+        mom_con, _ = api.power_spectrum(L, Ud, Pd, 40, 8)
+        main.wait_stream(side)
+        torch.cuda.synchronize()
+        assert torch.equal(y_con, y_ser)
+        assert np.array_equal(mom_con, mom_ser)
+        assert torch.equal(f_con, f_ser)
