@@ -139,6 +139,8 @@ def main():
     U32 = api.pack_links(L, U_aos, torch.float32)
     api.autotune_laplacian(L, Ud, Pd, reps=10)
     api.autotune_laplacian(L, U32, Pd.float(), reps=10)
+    # the solver's FP64 true-residual check applies Delta to all 12 shift solutions in one launch
+    api.autotune_laplacian(L, Ud, Pd.expand(12, -1, -1, -1).contiguous(), reps=5)
     ws = torch.empty(api.workspace_bytes(6, L, 0, 1, 12, 0, 1), dtype=torch.uint8, device=dev)
 
     # the momentum filter needs only P and the links: it runs on a second stream (default

@@ -30,9 +30,19 @@ Key key_of(const Geom& g, int32_t dtype, int32_t n_rhs) {
 // per direction), whose four times as many waves hide the memory latency that one thread per
 // site leaves exposed when the lattice gives only a few waves per SIMD, except FP64 from 2^18
 // sites on, where one thread per site and direction pair in the x3-fastest order is as fast.
-HopConfig defaults(const Geom& g, int32_t dtype) {
+HopConfig defaults(const Geom& g, int32_t dtype, int32_t n_rhs) {
   HopConfig c;
-  if (g.V >= (1 << 20)) {
+  if (g.V < (1 << 20) && (int64_t)g.V * n_rhs >= (1 << 19)) {
+    // a batch of fields already gives every SIMD several waves: one thread per site and all four
+    // directions, the adjoint matrix streamed two columns at a time and shared by them
+    c.form = kFormStream;
+    c.block = 64;
+    c.xcd_remap = 1;
+    c.nv = 4;
+    c.walk = 0;
+    c.order = 1;
+    if (!hop_order_ok(g, c)) c.order = 0;
+  } else if (g.V >= (1 << 20)) {
     c.form = dtype == RMH_F64 ? kFormStream : kFormAdjoint;
     c.block = 128;
     c.xcd_remap = 0;
@@ -93,7 +103,7 @@ HopConfig tune_hop(const Geom& g, int32_t dtype, int32_t n_rhs, int32_t /*purpos
       dist = d;
     }
   }
-  return best ? *best : defaults(g, dtype);
+  return best ? *best : defaults(g, dtype, n_rhs);
 }
 
 void tune_clear() {
