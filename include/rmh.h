@@ -326,10 +326,12 @@ rmh_status rmh_wilson_gauge_force(const int32_t L[4], const double* U, double be
  * sum the eight hops in another order: equal to rounding). */
 rmh_status rmh_tune_set(const int32_t L[4], int32_t dtype, int32_t n_rhs, int32_t form, int32_t block,
                         int32_t xcd_remap, int32_t nv, int32_t order, int32_t walk);
-/* Time every configuration of rmh_laplacian_apply on the caller's buffers (y is overwritten;
- * reps timed launches each, HIP events on the stream) and keep the fastest for (L, dtype, n_rhs).
- * best (optional host int32[6]) receives (form, block, xcd_remap, nv, order, walk); best_ms
- * (optional) its mean time per launch.  Synchronizes the stream. */
+/* Time every stencil configuration on the caller's buffers and keep the fastest for (L, dtype,
+ * n_rhs).  One timing unit is the pair of launches the drivers use, the plain y = (8 - H) x (CG)
+ * and the recursion step y = -H x / 4 - x (Chebyshev sweeps), both writing y (overwritten); reps
+ * units each, HIP events on the stream.  best (optional host int32[6]) receives (form, block,
+ * xcd_remap, nv, order, walk); best_ms (optional) the mean time of one unit.  RMH_E_ARG for null
+ * pointers or y overlapping x or U.  Synchronizes the stream. */
 rmh_status rmh_autotune_laplacian(const int32_t L[4], const void* U, int32_t dtype, const void* x, void* y,
                                   int32_t n_rhs, int32_t reps, int32_t* best, double* best_ms, rmh_stream stream);
 /* Forget every stored configuration. */

@@ -392,7 +392,8 @@ def tune_clear() -> None:
 
 
 def autotune_laplacian(L, U, x, reps: int = 5):
-    """((form, block, xcd_remap, nv, order, walk), ms per launch) of the fastest configuration, now stored."""
+    """((form, block, xcd_remap, nv, order, walk), ms) of the fastest configuration, now stored; ms is
+    the mean time of one timing unit (a plain application and a Chebyshev recursion step)."""
     y = torch.empty_like(x)
     best = (L_.c_i32 * 6)()
     ms = ctypes.c_double()

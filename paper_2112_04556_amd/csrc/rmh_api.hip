@@ -1111,6 +1111,32 @@ rmh_status cheb_bwd(const Geom& g, const double* U, const double* x, int32_t n_r
 }  // namespace
 
 // =============================================================================================
+// One timing unit of the autotuner: the two stencil epilogues the drivers use, the plain
+// y = (8 - H) x of the CG and the Chebyshev recursion step y = -H x / 4 - z (z = x here), both
+// writing y, so the pick fits the solves and the spectra alike.
+template <typename T>
+static hipError_t tune_unit(const Geom& g, const T* U, const T* x, T* y, int32_t n_rhs, const HopConfig& cfg,
+                            hipStream_t s) {
+  HopArgs<T> h{};
+  h.g = g;
+  h.U = U;
+  h.x = x;
+  h.x_mul = 1;
+  h.out = y;
+  h.z_div = 1;
+  h.a = -1.0;
+  h.b = 8.0;
+  h.n_rhs = n_rhs;
+  h.store = 1;
+  hipError_t e = launch_hop<T>(h, cfg, s);
+  if (e != hipSuccess) return e;
+  h.a = -0.25;
+  h.b = 0.0;
+  h.c = -1.0;
+  h.z = x;
+  return launch_hop<T>(h, cfg, s);
+}
+
 extern "C" {
 
 const char* rmh_last_error(void) { return g_err.c_str(); }
@@ -1813,6 +1839,13 @@ rmh_status rmh_autotune_laplacian(const int32_t L[4], const void* U, int32_t dty
   RMH_TRY(make_geom(L, &g));
   RMH_TRY(check_dtype(dtype));
   if (n_rhs < 1 || reps < 1) return fail(RMH_E_ARG, "n_rhs and reps must be >= 1");
+  RMH_TRY(check_ptr(U, "U"));
+  RMH_TRY(check_ptr(x, "x"));
+  RMH_TRY(check_ptr(y, "y"));
+  {
+    const size_t fb = (size_t)n_rhs * 32 * g.V * dsize(dtype), ub = (size_t)72 * g.V * dsize(dtype);
+    if (overlap(x, fb, y, fb) || overlap(U, ub, y, fb)) return fail(RMH_E_ARG, "y overlaps x or U");
+  }
   hipStream_t s = (hipStream_t)stream;
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
@@ -1838,10 +1871,16 @@ rmh_status rmh_autotune_laplacian(const int32_t L[4], const void* U, int32_t dty
         if ((block * nv / 4) % 64) continue;  // direction groups must be whole waves
         if (nv == 1 && form != kFormMatrix) continue;
         tune_store(g, dtype, n_rhs, c);
-        st = rmh_laplacian_apply(L, U, dtype, x, y, n_rhs, 0.0, stream);  // warm-up
+        auto unit = [&]() -> rmh_status {
+          const hipError_t e = dtype == RMH_F64
+                                   ? tune_unit<double>(g, (const double*)U, (const double*)x, (double*)y, n_rhs, c, s)
+                                   : tune_unit<float>(g, (const float*)U, (const float*)x, (float*)y, n_rhs, c, s);
+          return e == hipSuccess ? RMH_OK : fail(RMH_E_HIP, "stencil launch: %s", hipGetErrorString(e));
+        };
+        st = unit();  // warm-up
         if (st != RMH_OK) break;
         if (hipEventRecord(e0, s) != hipSuccess) st = fail(RMH_E_HIP, "hipEventRecord");
-        for (int r = 0; r < reps && st == RMH_OK; ++r) st = rmh_laplacian_apply(L, U, dtype, x, y, n_rhs, 0.0, stream);
+        for (int r = 0; r < reps && st == RMH_OK; ++r) st = unit();
         if (st != RMH_OK) break;
         if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
           st = fail(RMH_E_HIP, "hipEventRecord/Synchronize");

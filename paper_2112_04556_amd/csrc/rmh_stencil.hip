@@ -13,6 +13,32 @@ namespace rmh {
 // ------------------------------------------------------------------------------------------
 // the stencil
 
+// Block -> (field v, lattice block lb). The grid is one-dimensional, nblk lattice blocks times
+// n_rhs fields, taken in groups of fg fields (the largest divisor of n_rhs up to 4): within a
+// group the fields are fastest, so consecutive blocks take the same sites of successive fields
+// and a link loaded for the first is an L2 hit for the others (with the XCD remap each XCD owns
+// a contiguous range); the groups are not interleaved, which keeps the neighbour fields of at
+// most fg fields in the L2 at a time.
+struct HopBlock {
+  int32_t v, lb, nblk;
+};
+__host__ __device__ __forceinline__ int32_t hop_field_group(int32_t n_rhs) {
+  for (int32_t f = 4; f > 1; --f)
+    if (n_rhs % f == 0) return f;
+  return 1;
+}
+__device__ __forceinline__ HopBlock hop_block(int32_t xcd, int32_t n_rhs) {
+  const int32_t b = remap_block(blockIdx.x, gridDim.x, xcd);
+  const int32_t fg = hop_field_group(n_rhs);
+  HopBlock h;
+  h.nblk = gridDim.x / n_rhs;
+  const int32_t gsize = h.nblk * fg;   // blocks per field group
+  const int32_t grp = b / gsize, r = b - grp * gsize;
+  h.v = grp * fg + r % fg;
+  h.lb = r / fg;
+  return h;
+}
+
 // One hop's contribution to NV vectors: forward (kT = false, link U_mu(x), neighbour x+mu) or
 // backward (kT = true, link U_mu(x-mu), neighbour x-mu).
 template <typename T, int FORM, int NV, bool kT>
@@ -69,10 +95,11 @@ __device__ __forceinline__ void hop_term_fwd(const T* __restrict__ Um, int32_t s
 template <typename T, int FORM, int NV, bool DOTS>
 __global__ void __launch_bounds__(256) k_hop(const HopArgs<T> A, int32_t xcd, int32_t order) {
   constexpr int G = 4 / NV;  // thread groups per site
-  const int32_t v = blockIdx.y;
+  const HopBlock hb = hop_block(xcd, A.n_rhs);
+  const int32_t v = hb.v;
   if (A.run && A.run[(int64_t)v * A.run_stride] == 0) return;
   const int32_t V = A.g.V;
-  const int32_t lb = remap_block(blockIdx.x, gridDim.x, xcd);
+  const int32_t lb = hb.lb;
   const int32_t spb = blockDim.x / G;              // sites per block
   // direction subset of this thread: wave-uniform (spb is a multiple of the wave size), so the
   // per-component base addresses stay in scalar registers
@@ -136,8 +163,8 @@ __global__ void __launch_bounds__(256) k_hop(const HopArgs<T> A, int32_t xcd, in
     __shared__ double lds[3][16];
     block_sum<3>(dsum, lds);
     if (threadIdx.x == 0) {
-      const int32_t nblk = gridDim.x;
-      double* p = A.partials + (int64_t)v * 3 * nblk + blockIdx.x;
+      const int32_t nblk = hb.nblk;
+      double* p = A.partials + (int64_t)v * 3 * nblk + lb;
       if (A.dot_mask & 1) p[0] = dsum[0];
       if (A.dot_mask & 2) p[nblk] = dsum[1];
       if (A.dot_mask & 4) p[2 * nblk] = dsum[2];
@@ -153,10 +180,11 @@ __global__ void __launch_bounds__(256) k_hop(const HopArgs<T> A, int32_t xcd, in
 template <typename T, int FORM, int NV, bool DOTS>
 __global__ void __launch_bounds__(256) k_hop_split(const HopArgs<T> A, int32_t xcd, int32_t order) {
   constexpr int G = 4 / NV;
-  const int32_t v = blockIdx.y;
+  const HopBlock hb = hop_block(xcd, A.n_rhs);
+  const int32_t v = hb.v;
   if (A.run && A.run[(int64_t)v * A.run_stride] == 0) return;
   const int32_t V = A.g.V;
-  const int32_t lb = remap_block(blockIdx.x, gridDim.x, xcd);
+  const int32_t lb = hb.lb;
   const int32_t wi = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int32_t W = blockDim.x >> 6;
   const int32_t grp = wi % G;   // wave-uniform direction group
@@ -229,8 +257,8 @@ __global__ void __launch_bounds__(256) k_hop_split(const HopArgs<T> A, int32_t x
     __shared__ double lds[3][16];
     block_sum<3>(dsum, lds);
     if (threadIdx.x == 0) {
-      const int32_t nblk = gridDim.x;
-      double* p = A.partials + (int64_t)v * 3 * nblk + blockIdx.x;
+      const int32_t nblk = hb.nblk;
+      double* p = A.partials + (int64_t)v * 3 * nblk + lb;
       if (A.dot_mask & 1) p[0] = dsum[0];
       if (A.dot_mask & 2) p[nblk] = dsum[1];
       if (A.dot_mask & 4) p[2 * nblk] = dsum[2];
@@ -245,13 +273,14 @@ __global__ void __launch_bounds__(256) k_hop_split(const HopArgs<T> A, int32_t x
 template <typename T, int FORM, int NV, bool DOTS>
 __global__ void __launch_bounds__(256) k_hop_walk(const HopArgs<T> A, int32_t xcd, int32_t K) {
   constexpr int G = 4 / NV;
-  const int32_t v = blockIdx.y;
+  const HopBlock hb = hop_block(xcd, A.n_rhs);
+  const int32_t v = hb.v;
   if (A.run && A.run[(int64_t)v * A.run_stride] == 0) return;
   const int32_t V = A.g.V;
   const int32_t P = A.g.L0 * A.g.L1 * A.g.L2;            // sites per x3 plane
   const int32_t cpb = blockDim.x / G;                    // columns per block
   const int32_t nchunk = (P + cpb - 1) / cpb;
-  const int32_t lb = remap_block(blockIdx.x, gridDim.x, xcd);
+  const int32_t lb = hb.lb;
   const int32_t chunk = lb % nchunk;
   const int32_t x3_0 = (lb / nchunk) * K;
   const int32_t grp = __builtin_amdgcn_readfirstlane(threadIdx.x / cpb);  // wave-uniform
@@ -351,8 +380,8 @@ __global__ void __launch_bounds__(256) k_hop_walk(const HopArgs<T> A, int32_t xc
     __shared__ double lds[3][16];
     block_sum<3>(dsum, lds);
     if (threadIdx.x == 0) {
-      const int32_t nblk = gridDim.x;
-      double* p = A.partials + (int64_t)v * 3 * nblk + blockIdx.x;
+      const int32_t nblk = hb.nblk;
+      double* p = A.partials + (int64_t)v * 3 * nblk + lb;
       if (A.dot_mask & 1) p[0] = dsum[0];
       if (A.dot_mask & 2) p[nblk] = dsum[1];
       if (A.dot_mask & 4) p[2 * nblk] = dsum[2];
@@ -391,10 +420,13 @@ int hop_order_ok(const Geom& g, const HopConfig& cfg) {
 
 template <typename T, int FORM, int NV>
 static hipError_t launch_hop_form(const HopArgs<T>& A, const HopConfig& cfg, hipStream_t s) {
-  dim3 grid(hop_num_blocks(A.g, cfg), A.n_rhs), block(cfg.block);
+  const int64_t nblk = hop_num_blocks(A.g, cfg);
+  // one-dimensional grid, fields fastest (hop_block)
+  if (nblk * A.n_rhs > 0x7fffffff) return hipErrorInvalidValue;
+  dim3 grid((uint32_t)(nblk * A.n_rhs)), block(cfg.block);
   const bool dots = A.partials && A.dot_mask;
   // the partial-sum buffers hold hop_max_blocks entries per field and dot product
-  if (dots && (int)grid.x > hop_max_blocks(A.g)) return hipErrorInvalidValue;
+  if (dots && nblk > hop_max_blocks(A.g)) return hipErrorInvalidValue;
   if (hop_split_ok(cfg)) {
     const int32_t ord = (cfg.order == 3 && hop_order_ok(A.g, cfg)) ? 1 : 0;
     if (dots)
