@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
+#include <type_traits>
 
 #include "rmh_internal.h"
 #include "rmh_reduce.h"
@@ -142,14 +144,23 @@ __global__ void __launch_bounds__(256) k_hop(const HopArgs<T> A, int32_t xcd, in
     const T cc = T(A.c);
     const T* zf = A.z ? A.z + (int64_t)(v / A.z_div) * FV : nullptr;  // may alias out
     T* outf = A.out + (int64_t)v * FV;
+    // per direction: the 8 z values are loaded before any of the 8 stores (z may be the output
+    // itself, each element read and written by this thread only), so those loads overlap
 #pragma unroll
-    for (int i = 0; i < NV; ++i)
+    for (int i = 0; i < NV; ++i) {
+      const int64_t e0 = (int64_t)((nu0 + i) * 8) * V + s;
+      T xs[8], zv[8];
 #pragma unroll
       for (int a = 0; a < 8; ++a) {
-        const int64_t e = (int64_t)((nu0 + i) * 8 + a) * V + s;
-        const T xv = xf[e];
+        xs[a] = xf[e0 + (int64_t)a * V];
+        zv[a] = zf ? zf[e0 + (int64_t)a * V] : T(0);
+      }
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        const int64_t e = e0 + (int64_t)a * V;
+        const T xv = xs[a];
         T o = fmadd(ca, acc[i][a], cb * xv);
-        if (zf) o = fmadd(cc, zf[e], o);
+        if (zf) o = fmadd(cc, zv[a], o);
         if (A.store) outf[e] = o;
         if (DOTS) {
           const double xd = (double)xv, od = (double)o;
@@ -158,6 +169,7 @@ __global__ void __launch_bounds__(256) k_hop(const HopArgs<T> A, int32_t xcd, in
           dsum[2] = fma(od, od, dsum[2]);
         }
       }
+    }
   }
   if (DOTS) {
     __shared__ double lds[3][16];
@@ -227,8 +239,10 @@ __global__ void __launch_bounds__(256) k_hop_split(const HopArgs<T> A, int32_t x
       acc[i][a] += __shfl_xor(acc[i][a], 16, 64);
       acc[i][a] += __shfl_xor(acc[i][a], 32, 64);
     }
-  // lane group mu keeps the components 4q + mu of its direction group (q < 2 NV): a 4-way select
-  // with compile-time register indices, then one full-wave load/store per q
+  // lane group mu keeps the components 4q + mu of its direction group (q < 2 NV), picked with
+  // bit masks (a select chain here tends to become a lane-indexed array in scratch), then one
+  // full-wave load/store per q; every z value is loaded before the first store (z may be the
+  // output itself, each element read and written by this lane only), so those loads overlap
   double dsum[3] = {0.0, 0.0, 0.0};
   if (live) {
     const T ca = T(A.a);
@@ -236,14 +250,27 @@ __global__ void __launch_bounds__(256) k_hop_split(const HopArgs<T> A, int32_t x
     const T cc = T(A.c);
     const T* zf = A.z ? A.z + (int64_t)(v / A.z_div) * FV : nullptr;  // may alias out
     T* outf = A.out + (int64_t)v * FV;
+    using Bits = typename std::conditional<sizeof(T) == 8, uint64_t, uint32_t>::type;
+    const Bits m0 = mu == 0 ? ~Bits(0) : Bits(0), m1 = mu == 1 ? ~Bits(0) : Bits(0);
+    const Bits m2 = mu == 2 ? ~Bits(0) : Bits(0), m3 = mu == 3 ? ~Bits(0) : Bits(0);
+    T hs[2 * NV], xs[2 * NV], zv[2 * NV];
 #pragma unroll
     for (int q = 0; q < 2 * NV; ++q) {
       const int i = q >> 1, a0 = (q & 1) * 4;
-      const T h = mu == 0 ? acc[i][a0] : mu == 1 ? acc[i][a0 + 1] : mu == 2 ? acc[i][a0 + 2] : acc[i][a0 + 3];
+      const Bits hb_ = (m0 & __builtin_bit_cast(Bits, acc[i][a0])) | (m1 & __builtin_bit_cast(Bits, acc[i][a0 + 1])) |
+                       (m2 & __builtin_bit_cast(Bits, acc[i][a0 + 2])) | (m3 & __builtin_bit_cast(Bits, acc[i][a0 + 3]));
+      hs[q] = __builtin_bit_cast(T, hb_);
       const int64_t e = (int64_t)(nu0 * 8 + 4 * q + mu) * V + s;
-      const T xv = xf[e];
+      xs[q] = xf[e];
+      zv[q] = zf ? zf[e] : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < 2 * NV; ++q) {
+      const T h = hs[q];
+      const int64_t e = (int64_t)(nu0 * 8 + 4 * q + mu) * V + s;
+      const T xv = xs[q];
       T o = fmadd(ca, h, cb * xv);
-      if (zf) o = fmadd(cc, zf[e], o);
+      if (zf) o = fmadd(cc, zv[q], o);
       if (A.store) outf[e] = o;
       if (DOTS) {
         const double xd = (double)xv, od = (double)o;
@@ -352,13 +379,18 @@ __global__ void __launch_bounds__(256) k_hop_walk(const HopArgs<T> A, int32_t xc
       }
       // epilogue
 #pragma unroll
-      for (int i = 0; i < NV; ++i)
+      for (int i = 0; i < NV; ++i) {
+        // the 8 z values before the 8 stores (z may be the output itself, element by element)
+        const int64_t e0 = (int64_t)((nu0 + i) * 8) * V + s;
+        T zv[8];
+#pragma unroll
+        for (int a = 0; a < 8; ++a) zv[a] = zf ? zf[e0 + (int64_t)a * V] : T(0);
 #pragma unroll
         for (int a = 0; a < 8; ++a) {
-          const int64_t e = (int64_t)((nu0 + i) * 8 + a) * V + s;
+          const int64_t e = e0 + (int64_t)a * V;
           const T xv = cen[i][a];
           T o = fmadd(ca, acc[i][a], cb * xv);
-          if (zf) o = fmadd(cc, zf[e], o);
+          if (zf) o = fmadd(cc, zv[a], o);
           if (A.store) outf[e] = o;
           if (DOTS) {
             const double xd = (double)xv, od = (double)o;
@@ -367,6 +399,7 @@ __global__ void __launch_bounds__(256) k_hop_walk(const HopArgs<T> A, int32_t xc
             dsum[2] = fma(od, od, dsum[2]);
           }
         }
+      }
 #pragma unroll
       for (int i = 0; i < NV; ++i)
 #pragma unroll
