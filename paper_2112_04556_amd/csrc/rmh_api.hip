@@ -275,7 +275,7 @@ FilterPlan plan_filter(Carver& c, const Geom& g, int32_t dtype, int32_t n_rhs, i
 
 struct Engine {
   Geom g;
-  int32_t n_rhs = 0, n_shift = 0, mode = 0, nslot = 2, nslot32 = 4;
+  int32_t n_rhs = 0, n_shift = 0, mode = 0, nslot = 2, nslot32 = 4;   // FP64 and FP32 ring slots
   // seed vectors: direction and its image, FP64 (FP64 phase) and FP32 (FP32 phase)
   double* p64 = nullptr;   // [n_rhs]
   double* Ap64 = nullptr;  // [n_rhs]
@@ -283,9 +283,10 @@ struct Engine {
   float* Ap32 = nullptr;
   double* r64 = nullptr;   // [n_rhs] FP64 residual of a reliable update (mixed)
   float* x_lo = nullptr;   // [n_rhs] FP32 increment of the seed's solution since the last reliable update
-  char* ring = nullptr;    // [n_rhs][nslot] seed residuals, FP64-sized slots
+  double* ring = nullptr;  // [n_rhs][nslot] seed residuals of the FP64 phase
+  float* ring32 = nullptr; // [n_rhs][nslot32] seed residuals of the FP32 phase (mixed)
   double* pj = nullptr;    // [n_rhs][n_shift] shift directions at the segment start (n_shift > 1)
-  double* coef = nullptr;  // [n_rhs][n_shift][2 + 2 nslot]
+  double* coef = nullptr;  // [n_rhs][n_shift][2 + 2 nslot32]
   // scalar state, contiguous so one copy brings it to the host: sc then flags
   double* sc = nullptr;
   int32_t* flags = nullptr;
@@ -337,7 +338,8 @@ void plan_engine(Carver& c, Engine& e, const Geom& g, int32_t n_rhs, int32_t n_s
     e.r64 = c.take<double>(nr * n);
     e.x_lo = c.take<float>(nr * n);
   }
-  e.ring = c.take<char>(nr * e.nslot * n * 8);
+  e.ring = c.take<double>(nr * e.nslot * n);
+  if (mode) e.ring32 = c.take<float>(nr * e.nslot32 * n);
   if (n_shift > 1) e.pj = c.take<double>(np * n);
   e.coef = c.take<double>(np * (2 + 2 * std::max(e.nslot, e.nslot32)));
   const size_t scb = rup(nr * kScN * 8), flb = rup(nr * kFlN * 4);
@@ -382,9 +384,14 @@ CgDev cg_view(const Engine& e, int32_t nblk_hop, bool fp32) {
   d.part = e.part;
   d.part_ru = e.part_ru;
   d.coef = e.coef;
-  d.nslot = fp32 ? e.nslot32 : e.nslot;
   d.cslots = std::max(e.nslot, e.nslot32);
-  d.ring_rhs_bytes = (int64_t)e.nslot * field_reals(e.g) * 8;
+  d.nslot = fp32 ? d.cslots : e.nslot;
+  d.ring64 = e.ring;
+  d.rb64 = (int64_t)e.nslot * field_reals(e.g) * 8;
+  d.nslot64 = e.nslot;
+  d.ring32 = e.ring32;
+  d.rb32 = (int64_t)e.nslot32 * field_reals(e.g) * 4;
+  d.nslot32 = e.nslot32;
   d.ring_on = e.n_shift > 1 ? 1 : 0;
   // the seed's solution is updated each iteration where reliable updates read it
   d.seed_explicit = (e.n_shift == 1 || fp32) ? 1 : 0;
@@ -466,11 +473,11 @@ rmh_status engine_solve(Engine& e, const double* U64, const float* U32, const do
     for (int v = 0; v < nr; ++v) HIP_TRY(launch_zero(x_hi + ((size_t)v * ns + seed[v]) * n, (size_t)n * 8, s));
   if (fp32_phase) HIP_TRY(launch_zero(e.x_lo, (size_t)nr * n * 4, s));
   if (fp32_phase)
-    HIP_TRY(launch_cg_start<float>(b, e.ring, e.p32, nr, cg32.ring_rhs_bytes, n, s));
+    HIP_TRY(launch_cg_start<float>(b, e.ring32, e.p32, nr, cg32.rb32, n, s));
   else
-    HIP_TRY(launch_cg_start<double>(b, e.ring, e.p64, nr, cg64.ring_rhs_bytes, n, s));
+    HIP_TRY(launch_cg_start<double>(b, e.ring, e.p64, nr, cg64.rb64, n, s));
   HIP_TRY(launch_dot<double>(b, b, n, nr, e.part, s));
-  HIP_TRY(launch_cg_init(cg64, e.part, e.nblk_e, e.tol_rhs, delta, maxiter, s));
+  HIP_TRY(launch_cg_init(cg64, e.part, e.nblk_e, e.tol_rhs, delta, maxiter, fp32_phase ? 1 : 0, s));
 
   // FP64 stencil on the seed direction: Ap = (8 + sigma0) p - H p, partial <p, Ap>
   HopArgs<double> h64{};
@@ -524,25 +531,29 @@ rmh_status engine_solve(Engine& e, const double* U64, const float* U32, const do
   hr.partials = e.part_ru;
   hr.dot_mask = 4;
 
-  // shift solutions through the residual ring (more than one shift): flush before the ring
-  // would overflow; a single shift updates its solution each iteration
+  // shift solutions through the residual ring (more than one shift): flush before a segment
+  // would outgrow its ring; a single shift updates its solution each iteration.  The segment
+  // open at the switch to FP32 goes on in the FP32 ring (its FP64 entries stay where they are),
+  // so the switch folds only the seed's solution, which the FP32 phase keeps explicitly.
   const bool multi = ns > 1;
-  const int32_t seg64 = e.nslot - 1, seg32 = e.nslot32 - 1;
+  const int32_t seg64 = cg64.nslot - 1, seg32 = cg32.nslot - 1;
   if (check_every <= 0) check_every = 8;
   if (multi) check_every = std::min(check_every, std::min(seg64, seg32));
-  int32_t since = 0;
+  int32_t since = 0;     // iterations in the open segment
+  int32_t k64 = 0;       // FP64 entries of the open FP32-phase segment
   bool first = true;
   auto flush = [&](bool fin) -> rmh_status {
     if (!multi) return RMH_OK;
-    const double ts = fp32_phase ? 4.0 : 8.0;
-    const double bytes = (double)nr * n * ((since + 1) * ts + ns * (16.0 + (first ? 0.0 : 8.0) + (fin ? 0.0 : 8.0)));
+    const double res = fp32_phase ? k64 * 8.0 + (since + 1 - k64) * 4.0 : (since + 1) * 8.0;
+    const double bytes = (double)nr * n * (res + ns * (16.0 + (first ? 0.0 : 8.0) + (fin ? 0.0 : 8.0)));
     ProfScope ps(RMH_PROF_CG_SHIFTS, bytes, s, nr);
     if (fp32_phase)
-      HIP_TRY(launch_cg_flush<float>(cg32, e.ring, x_hi, e.pj, fin ? 1 : 0, first ? 1 : 0, n, s));
+      HIP_TRY(launch_cg_flush(cg32, x_hi, e.pj, fin ? 1 : 0, first ? 1 : 0, 0, 1, n, s));
     else
-      HIP_TRY(launch_cg_flush<double>(cg64, e.ring, x_hi, e.pj, fin ? 1 : 0, first ? 1 : 0, n, s));
+      HIP_TRY(launch_cg_flush(cg64, x_hi, e.pj, fin ? 1 : 0, first ? 1 : 0, 0, 0, n, s));
     first = false;
     since = 0;
+    k64 = 0;
     return RMH_OK;
   };
 
@@ -562,12 +573,12 @@ rmh_status engine_solve(Engine& e, const double* U64, const float* U32, const do
         HIP_TRY(launch_cg_alpha(cg64, s));
         {
           ProfScope ps(RMH_PROF_CG_RESIDUAL, (double)nr * n * (3 * 8.0 + (multi ? 0.0 : 24.0)), s, nr);
-          HIP_TRY(launch_cg_r_update<double>(cg64, e.ring, e.Ap64, e.p64, multi ? nullptr : x_hi, nullptr, n, s));
+          HIP_TRY(launch_cg_r_update<double>(cg64, e.Ap64, e.p64, multi ? nullptr : x_hi, nullptr, n, s));
         }
         HIP_TRY(launch_cg_beta(cg64, 0, s));
         {
           ProfScope ps(RMH_PROF_CG_RESIDUAL, (double)nr * n * 3 * 8.0, s, nr);
-          HIP_TRY(launch_cg_p_update<double>(cg64, e.ring, e.p64, nullptr, nullptr, n, s));
+          HIP_TRY(launch_cg_p_update<double>(cg64, e.p64, nullptr, nullptr, n, s));
         }
       } else {
         {
@@ -577,12 +588,12 @@ rmh_status engine_solve(Engine& e, const double* U64, const float* U32, const do
         HIP_TRY(launch_cg_alpha(cg32, s));
         {
           ProfScope ps(RMH_PROF_CG_RESIDUAL, (double)nr * n * 3 * 4.0, s, nr);
-          HIP_TRY(launch_cg_r_update<float>(cg32, e.ring, e.Ap32, e.p32, nullptr, e.r64, n, s));
+          HIP_TRY(launch_cg_r_update<float>(cg32, e.Ap32, e.p32, nullptr, e.r64, n, s));
         }
         HIP_TRY(launch_cg_beta(cg32, 1, s));
         {
           ProfScope ps(RMH_PROF_CG_RESIDUAL, (double)nr * n * 5 * 4.0, s, nr);
-          HIP_TRY(launch_cg_p_update<float>(cg32, e.ring, e.p32, e.x_lo, x_hi, n, s));
+          HIP_TRY(launch_cg_p_update<float>(cg32, e.p32, e.x_lo, x_hi, n, s));
         }
         // reliable update decided by this iteration's beta kernel (blocks of rhs without a
         // pending update exit at once): the p update has folded the seed solution into FP64,
@@ -607,8 +618,12 @@ rmh_status engine_solve(Engine& e, const double* U64, const float* U32, const do
     if (!running) break;
     if (mixed && !fp32_phase && below) {
       // switch to FP32: the remaining increments are small, so their rounding no longer matters
-      RMH_TRY(flush(false));
-      HIP_TRY(launch_cg_to_f32(cg64, e.ring, e.p64, e.p32, n, s));
+      if (multi) {
+        ProfScope ps(RMH_PROF_CG_SHIFTS, (double)nr * n * ((since + 1) * 8.0 + (first ? 8.0 : 16.0)), s, nr);
+        HIP_TRY(launch_cg_flush(cg64, x_hi, e.pj, 0, first ? 1 : 0, 1, 0, n, s));
+        k64 = since + 1;
+      }
+      HIP_TRY(launch_cg_to_f32(cg64, e.p64, e.p32, n, s));
       HIP_TRY(launch_zero(e.x_lo, (size_t)nr * n * 4, s));
       fp32_phase = true;
     }

@@ -130,17 +130,28 @@ struct CgDev {
   double* part;          // partials scratch [n_rhs][nblk_max]
   double* part_ru;       // partials of the FP64 residual stencil [n_rhs][3][nblk_ru] (mixed precision)
   double* coef;          // [n_rhs][n_shift][2 + 2 cslots]: a, b, d[cslots], e[cslots]
-  int32_t nslot;         // residual ring length of this precision (segment of nslot - 1 iterations)
-  int32_t cslots;        // coefficient slots (the longer of the FP64 and FP32 rings)
-  int64_t ring_rhs_bytes;  // ring bytes per rhs (FP32 slots are half as long, twice as many)
+  int32_t nslot;         // segment capacity guard of this view: FP64 ring slots, or (FP32 view)
+                         // the coefficient slots
+  int32_t cslots;        // coefficient slots: entries a segment can hold
+  // the residual rings: FP64 slots (nslot64 per rhs, rb64 bytes per rhs) and, with mixed
+  // precision, FP32 slots (nslot32 per rhs, rb32 bytes per rhs) in a region of their own
+  void* ring64;
+  int64_t rb64;
+  int32_t nslot64;
+  void* ring32;
+  int64_t rb32;
+  int32_t nslot32;
   int32_t ring_on;       // shift solutions through the ring (n_shift > 1); else the seed's
                          // solution is updated each iteration and nslot = 2
   int32_t seed_explicit; // the seed's solution is kept outside the ring (single shift, FP32 phase)
   int32_t nblk_hop, nblk_e, nblk_ru;
 };
-// the residual ring: per rhs ring_rhs_bytes holding nslot FP64 slots of n_reals, or in FP32
-// phases twice as many FP32 slots (at most kMaxSlots)
+// Segment entries: entry i < K64 is FP64 slot (Base + i) % nslot64; entry i >= K64 is FP32 slot
+// (Base32 + i - K0) % nslot32 (K0: the entry held in FP32 slot Base32).  FP64 phases have
+// K64 = kAllFp64; at the switch to FP32 the segment goes on, K64 = M + 1 and the current FP64
+// residual is copied to FP32 slot Base32 as entry K0 = M; after an FP32-phase flush K64 = K0 = 0.
 constexpr int kMaxSlots = 33;
+constexpr int32_t kAllFp64 = 1 << 30;
 // scalar slots per rhs
 enum : int { kScRR = 0, kScAlpha, kScAlphaPrev, kScBetaPrev, kScBnorm2, kScMaxR, kScTolAbs, kScIters,
              kScRU, kScDelta, kScMaxIter, kScN };
@@ -150,44 +161,45 @@ enum : int { kShZeta = 0, kShZetaPrev, kShZetaNext, kShCx, kShCr, kShCp, kShUpd,
 // Run: the rhs still iterates (read by the stencil of the next iteration);
 // Live: the current iteration is being carried out (set by the alpha kernel), so the
 // update kernels of the iteration in which a rhs converges still run once.
-// Base, M: ring slot of the segment's first residual, index of the current residual in it.
-enum : int { kFlRun = 0, kFlLive, kFlStatus, kFlNeedRU, kFlRUMask, kFlBase, kFlM, kFlN };
+// Base, M: FP64 ring slot of the segment's first residual, index of the current residual in it;
+// K64, K0, Base32: the FP64 entries of the segment and the FP32 slot of entry K0 (above).
+enum : int { kFlRun = 0, kFlLive, kFlStatus, kFlNeedRU, kFlRUMask, kFlBase, kFlM, kFlK64, kFlK0, kFlBase32, kFlN };
 enum : int { kStOk = 0, kStNoConv = 1, kStBreakdown = 2 };
 
+// fp32_start: the solve runs in FP32 from its first iteration (its segment has no FP64 entries)
 hipError_t launch_cg_init(const CgDev& cg, const double* bn2_partials, int32_t nblk, const double* tol_rel,
-                          double delta, int32_t maxiter, hipStream_t s);
+                          double delta, int32_t maxiter, int32_t fp32_start, hipStream_t s);
 hipError_t launch_cg_alpha(const CgDev& cg, hipStream_t s);
 hipError_t launch_cg_beta(const CgDev& cg, int32_t mixed, hipStream_t s);
-// ring slot 0 = (T) b, p = (T) b for every rhs
+// slot 0 of the ring region (ring, rhs_bytes per rhs) = (T) b, p = (T) b for every rhs
 template <typename T>
 hipError_t launch_cg_start(const double* b, void* ring, T* p, int32_t nr, int64_t rhs_bytes, int64_t n_reals,
                            hipStream_t s);
-// next residual r' = r - alpha Ap into the next ring slot (r taken from r64 when a reliable
+// next residual r' = r - alpha Ap into the next segment entry (r taken from r64 when a reliable
 // update was consumed), partial <r', r'>; with x_hi non-null also x_hi[seed] += alpha p
 template <typename T>
-hipError_t launch_cg_r_update(const CgDev& cg, void* ring, const T* Ap, const T* p, double* x_hi,
-                              const double* r64, int64_t n_reals, hipStream_t s);
+hipError_t launch_cg_r_update(const CgDev& cg, const T* Ap, const T* p, double* x_hi, const double* r64,
+                              int64_t n_reals, hipStream_t s);
 // seed direction p = r' + beta p (while the rhs runs); with x_lo non-null also x_lo += alpha p
 // (the FP32 increment of the seed's solution, FP32 phase), and with x_hi non-null, for the rhs
 // with a pending reliable update, x_hi[seed] += x_lo, x_lo = 0 in the same pass
 template <typename T>
-hipError_t launch_cg_p_update(const CgDev& cg, const void* ring, T* p, float* x_lo, double* x_hi,
-                              int64_t n_reals, hipStream_t s);
+hipError_t launch_cg_p_update(const CgDev& cg, T* p, float* x_lo, double* x_hi, int64_t n_reals, hipStream_t s);
 // x_hi[seed] += x_lo, x_lo = 0 for every rhs (all, the end of a mixed solve) or those with a
 // pending reliable update
 hipError_t launch_cg_xfold(const CgDev& cg, float* x_lo, double* x_hi, int32_t all, int64_t n_reals, hipStream_t s);
-// fold the segment into x_j (and p_j unless final) of every shift updated in it (p_j0 is read
-// only where its coefficient is nonzero: before the first flush it holds nothing), then reset
-// the coefficients and restart the ring at the current residual
-// first: no flush yet in this solve (x_j holds nothing: written, not accumulated)
-template <typename T>
-hipError_t launch_cg_flush(const CgDev& cg, const void* ring, double* x_hi, double* pj, int32_t final_,
-                           int32_t first, int64_t n_reals, hipStream_t s);
-// precision switch (after a flush): current residual (FP64 slot) -> an FP32 slot outside it,
-// p64 -> p32; the FP32 ring (cg32 view) restarts there and the reliable-update reference
-// becomes the current residual norm
-hipError_t launch_cg_to_f32(const CgDev& cg64, void* ring, const double* p64, float* p32, int64_t n_reals,
-                            hipStream_t s);
+// fold the segment (FP64 and FP32 entries alike) into x_j (and p_j unless final) of every shift
+// updated in it (p_j0 is read only where its coefficient is nonzero: before the first flush it
+// holds nothing); then, unless seed_only, reset the coefficients and restart the segment at the
+// current residual (fp32: in the FP32 ring).  first: no flush yet in this solve (x_j holds
+// nothing: written, not accumulated).  seed_only: fold the seed's solution alone, nothing reset
+// (the switch to FP32, after which the seed's solution is kept explicitly).
+hipError_t launch_cg_flush(const CgDev& cg, double* x_hi, double* pj, int32_t final_, int32_t first,
+                           int32_t seed_only, int32_t fp32, int64_t n_reals, hipStream_t s);
+// precision switch (no flush: the segment goes on in FP32): the current FP64 residual -> FP32
+// slot 0, p64 -> p32, K64 = M + 1, K0 = M, Base32 = 0; the reliable-update reference becomes the
+// current residual norm
+hipError_t launch_cg_to_f32(const CgDev& cg64, const double* p64, float* p32, int64_t n_reals, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_gather_pairs(const double* x_hi, const double* b, const int32_t* idx, int32_t ns, double* X,
                                double* B, int32_t nb, int64_t n, hipStream_t s);

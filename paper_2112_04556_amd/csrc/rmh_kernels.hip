@@ -214,7 +214,7 @@ hipError_t launch_fields_soa_to_aos(const Geom& g, int32_t n, const void* soa, i
 // residual is zeta_j times the seed residual)
 
 __global__ void k_cg_init(CgDev cg, const double* bn2_part, int32_t nblk, const double* tol_rel, double delta,
-                          int32_t maxiter) {
+                          int32_t maxiter, int32_t fp32_start) {
   __shared__ double lds[1][16];
   const int32_t v = blockIdx.x;
   const double bn2 = block_sum_array(bn2_part + (int64_t)v * nblk, nblk, lds);
@@ -241,6 +241,9 @@ __global__ void k_cg_init(CgDev cg, const double* bn2_part, int32_t nblk, const 
     fl[kFlLive] = 0;
     fl[kFlBase] = 0;
     fl[kFlM] = 0;
+    fl[kFlK64] = fp32_start ? 0 : kAllFp64;
+    fl[kFlK0] = 0;
+    fl[kFlBase32] = 0;
     s_bn2 = bn2;
   }
   __syncthreads();
@@ -267,9 +270,9 @@ __global__ void k_cg_init(CgDev cg, const double* bn2_part, int32_t nblk, const 
 }
 
 hipError_t launch_cg_init(const CgDev& cg, const double* bn2_partials, int32_t nblk, const double* tol_rel,
-                          double delta, int32_t maxiter, hipStream_t s) {
+                          double delta, int32_t maxiter, int32_t fp32_start, hipStream_t s) {
   hipLaunchKernelGGL(k_cg_init, dim3(cg.n_rhs), dim3(kRedBlock), 0, s, cg, bn2_partials, nblk, tol_rel, delta,
-                     maxiter);
+                     maxiter, fp32_start);
   return hipGetLastError();
 }
 
@@ -301,8 +304,10 @@ __global__ void k_cg_alpha(CgDev cg) {
   }
   const double s0 = cg.sigma[(int64_t)v * ns + seed];
   // this thread's (shift, coefficient) pair when they all fit in the block: q = 0 the p_j0
-  // coefficient (x_j0 += cx p_j0), q = 1 + i the ring entry i <= m (d_ji += cx e_ji)
-  const int32_t per = m + 2;
+  // coefficient (x_j0 += cx p_j0), q = 1 + i the ring entry i <= m (d_ji += cx e_ji).  A shift is
+  // updated only while m < nslot <= cslots; past that (a single shift's segment index grows
+  // without flushes) the pairs stop at the last coefficient slot so every read stays in its row.
+  const int32_t per = min(m, cg.cslots - 1) + 2;
   const bool one_pass = ns * per <= (int32_t)blockDim.x;
   int32_t pj = 0, pq = 0;
   double c_dst = 0.0, c_src = 0.0;
@@ -424,8 +429,10 @@ __global__ void k_cg_beta(CgDev cg, int32_t mixed) {
   }
   // this thread's (shift, coefficient) pair when they all fit in the block: q = 0 the p_j0
   // coefficient, q = 1 + i the ring entry i <= m (both scaled by cp_j), q = m + 2 the new
-  // entry m + 1 (set to cr_j)
-  const int32_t per = m + 3;
+  // entry m + 1 (set to cr_j).  Updates need m + 1 < nslot <= cslots; the pairs stop at the
+  // last coefficient slot for larger m (reads in the row, nothing written).
+  const int32_t mc = min(m, cg.cslots - 2);
+  const int32_t per = mc + 3;
   const bool one_pass = ns * per <= (int32_t)blockDim.x;
   int32_t pj = 0, pq = 0;
   double c_old = 0.0;
@@ -435,7 +442,7 @@ __global__ void k_cg_beta(CgDev cg, int32_t mixed) {
     const double* cf = cg.coef + ((int64_t)v * ns + pj) * nc;
     if (pq == 0)
       c_old = cf[1];
-    else if (pq <= m + 1)
+    else if (pq <= mc + 1)
       c_old = cf[2 + cg.cslots + pq - 1];
   }
   if (live == 0) return;
@@ -539,10 +546,28 @@ hipError_t launch_cg_beta(const CgDev& cg, int32_t mixed, hipStream_t s) {
   return hipGetLastError();
 }
 
-// ring slot i of rhs v, viewed as T (FP32 slots are n_reals floats)
+// ring slot i of rhs v in a ring region of rhs_bytes per rhs, viewed as T (slots of n_reals)
 template <typename T>
 __device__ __forceinline__ T* ring_slot(const void* ring, int64_t rhs_bytes, int32_t v, int32_t i, int64_t n) {
   return (T*)((char*)ring + (int64_t)v * rhs_bytes + (int64_t)i * n * (int64_t)sizeof(T));
+}
+
+// segment entry i of rhs v: in the FP64 ring from the segment's FP64 base slot, or in the FP32
+// ring counted from entry k0, which sits in FP32 slot base32
+__device__ __forceinline__ double* entry64(const CgDev& cg, int32_t v, int32_t base, int32_t i, int64_t n) {
+  return ring_slot<double>(cg.ring64, cg.rb64, v, (base + i) % cg.nslot64, n);
+}
+__device__ __forceinline__ float* entry32(const CgDev& cg, int32_t v, int32_t base32, int32_t k0, int32_t i,
+                                          int64_t n) {
+  return ring_slot<float>(cg.ring32, cg.rb32, v, (base32 + i - k0) % cg.nslot32, n);
+}
+// entry i of the phase whose arithmetic type is T (the FP32 phase only touches entries >= k0)
+template <typename T>
+__device__ __forceinline__ T* entry(const CgDev& cg, int32_t v, const int32_t* st, int32_t i, int64_t n) {
+  if constexpr (sizeof(T) == 8)
+    return entry64(cg, v, st[0], i, n);
+  else
+    return entry32(cg, v, st[1], st[2], i, n);
 }
 
 template <typename T>
@@ -572,19 +597,20 @@ template hipError_t launch_cg_start<double>(const double*, void*, double*, int32
 template hipError_t launch_cg_start<float>(const double*, void*, float*, int32_t, int64_t, int64_t, hipStream_t);
 
 template <typename T>
-__global__ void k_cg_r(CgDev cg, void* ring, const T* __restrict__ Ap, const T* __restrict__ p,
-                       double* __restrict__ x_hi, const double* __restrict__ r64, int64_t n, int32_t steps) {
+__global__ void k_cg_r(CgDev cg, const T* __restrict__ Ap, const T* __restrict__ p, double* __restrict__ x_hi,
+                       const double* __restrict__ r64, int64_t n, int32_t steps) {
   const int32_t v = blockIdx.y;
   const int32_t* fl = cg.flags + (int64_t)v * kFlN;
   // the per-rhs state in one batch of independent loads, ahead of any branch on it
   const int32_t live = fl[kFlLive], ru_mask = fl[kFlRUMask];
-  const int32_t m = fl[kFlM], base = fl[kFlBase];
+  const int32_t m = fl[kFlM];
+  const int32_t st[3] = {fl[kFlBase], fl[kFlBase32], fl[kFlK0]};
   const int32_t seed = cg.seed[v];
   const double alpha_d = cg.sc[(int64_t)v * kScN + kScAlpha];
   if (live == 0) return;
   const int32_t from64 = r64 ? ru_mask : 0;
-  const T* rc = ring_slot<T>(ring, cg.ring_rhs_bytes, v, (base + m) % cg.nslot, n);
-  T* rn = ring_slot<T>(ring, cg.ring_rhs_bytes, v, (base + m + 1) % cg.nslot, n);
+  const T* rc = entry<T>(cg, v, st, m, n);
+  T* rn = entry<T>(cg, v, st, m + 1, n);
   const T alpha = (T)alpha_d;
   const T* av = Ap + (int64_t)v * n;
   const T* pv = p + (int64_t)v * n;
@@ -626,35 +652,35 @@ __global__ void k_cg_r(CgDev cg, void* ring, const T* __restrict__ Ap, const T* 
 }
 
 template <typename T>
-hipError_t launch_cg_r_update(const CgDev& cg, void* ring, const T* Ap, const T* p, double* x_hi,
-                              const double* r64, int64_t n_reals, hipStream_t s) {
+hipError_t launch_cg_r_update(const CgDev& cg, const T* Ap, const T* p, double* x_hi, const double* r64,
+                              int64_t n_reals, hipStream_t s) {
   if (cg.nblk_e != red_num_blocks(n_reals)) return hipErrorInvalidValue;
+  if (sizeof(T) == 4 && !cg.ring32) return hipErrorInvalidValue;
   dim3 grid(cg.nblk_e, cg.n_rhs);
-  hipLaunchKernelGGL((k_cg_r<T>), grid, dim3(kBlock), 0, s, cg, ring, Ap, p, x_hi, r64, n_reals,
-                     red_steps(n_reals));
+  hipLaunchKernelGGL((k_cg_r<T>), grid, dim3(kBlock), 0, s, cg, Ap, p, x_hi, r64, n_reals, red_steps(n_reals));
   return hipGetLastError();
 }
-template hipError_t launch_cg_r_update<double>(const CgDev&, void*, const double*, const double*, double*,
-                                               const double*, int64_t, hipStream_t);
-template hipError_t launch_cg_r_update<float>(const CgDev&, void*, const float*, const float*, double*,
-                                              const double*, int64_t, hipStream_t);
+template hipError_t launch_cg_r_update<double>(const CgDev&, const double*, const double*, double*, const double*,
+                                               int64_t, hipStream_t);
+template hipError_t launch_cg_r_update<float>(const CgDev&, const float*, const float*, double*, const double*,
+                                              int64_t, hipStream_t);
 
 template <typename T>
-__global__ void k_cg_p(CgDev cg, const void* ring, T* __restrict__ p, float* __restrict__ x_lo,
-                       double* __restrict__ x_hi, int64_t n) {
+__global__ void k_cg_p(CgDev cg, T* __restrict__ p, float* __restrict__ x_lo, double* __restrict__ x_hi, int64_t n) {
   const int32_t v = blockIdx.y;
   const int32_t* fl = cg.flags + (int64_t)v * kFlN;
   const double* scv = cg.sc + (int64_t)v * kScN;
   // the per-rhs state in one batch of independent loads, ahead of any branch on it
   const int32_t live = fl[kFlLive], upd_p = fl[kFlRun], need_ru = fl[kFlNeedRU];
-  const int32_t cur = fl[kFlBase] + fl[kFlM];
+  const int32_t m = fl[kFlM];
+  const int32_t st[3] = {fl[kFlBase], fl[kFlBase32], fl[kFlK0]};
   const int32_t seed = cg.seed[v];
   const double beta_d = scv[kScBetaPrev], alpha_d = scv[kScAlpha];
   if (live == 0) return;
   if (!upd_p && !x_lo) return;
   const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
   if (i0 >= n) return;
-  const T* r = ring_slot<T>(ring, cg.ring_rhs_bytes, v, cur % cg.nslot, n);
+  const T* r = entry<T>(cg, v, st, m, n);
   const T beta = (T)beta_d;
   const float alpha = (float)alpha_d;
   T* pv = p + (int64_t)v * n;
@@ -691,10 +717,10 @@ __global__ void k_cg_p(CgDev cg, const void* ring, T* __restrict__ p, float* __r
 }
 
 template <typename T>
-hipError_t launch_cg_p_update(const CgDev& cg, const void* ring, T* p, float* x_lo, double* x_hi,
-                              int64_t n_reals, hipStream_t s) {
+hipError_t launch_cg_p_update(const CgDev& cg, T* p, float* x_lo, double* x_hi, int64_t n_reals, hipStream_t s) {
+  if (sizeof(T) == 4 && !cg.ring32) return hipErrorInvalidValue;
   dim3 grid(elem_num_blocks(n_reals), cg.n_rhs);
-  hipLaunchKernelGGL((k_cg_p<T>), grid, dim3(kBlock), 0, s, cg, ring, p, x_lo, x_hi, n_reals);
+  hipLaunchKernelGGL((k_cg_p<T>), grid, dim3(kBlock), 0, s, cg, p, x_lo, x_hi, n_reals);
   return hipGetLastError();
 }
 
@@ -719,20 +745,20 @@ hipError_t launch_cg_xfold(const CgDev& cg, float* x_lo, double* x_hi, int32_t a
   return hipGetLastError();
 }
 
-template hipError_t launch_cg_p_update<double>(const CgDev&, const void*, double*, float*, double*, int64_t,
-                                               hipStream_t);
-template hipError_t launch_cg_p_update<float>(const CgDev&, const void*, float*, float*, double*, int64_t,
-                                              hipStream_t);
+template hipError_t launch_cg_p_update<double>(const CgDev&, double*, float*, double*, int64_t, hipStream_t);
+template hipError_t launch_cg_p_update<float>(const CgDev&, float*, float*, double*, int64_t, hipStream_t);
 
 // One element per thread: the segment's residuals at this element are loaded once and every
-// non-seed shift touched in the segment is folded from registers.
-template <typename T>
-__global__ void __launch_bounds__(256) k_cg_flush(CgDev cg, const void* ring, double* __restrict__ x_hi,
-                                                  double* __restrict__ pj, int32_t final_, int32_t first,
-                                                  int64_t n) {
+// non-seed shift touched in the segment is folded from registers (seed_only: the seed alone,
+// its solution only).  F32: an FP32-phase segment, whose entries from K64 on are FP32 (those
+// below K64, in the segment that spans the switch of precision, are FP64).
+template <bool F32>
+__global__ void __launch_bounds__(256) k_cg_flush(CgDev cg, double* __restrict__ x_hi, double* __restrict__ pj,
+                                                  int32_t final_, int32_t first, int32_t seed_only, int64_t n) {
   const int32_t v = blockIdx.y;
   const int32_t* fl = cg.flags + (int64_t)v * kFlN;
-  const int32_t m = min(fl[kFlM], cg.nslot - 1), base = fl[kFlBase];   // the host flushes before m passes nslot - 1
+  const int32_t m = min(fl[kFlM], cg.nslot - 1);   // the host flushes before m passes nslot - 1
+  const int32_t base = fl[kFlBase], base32 = fl[kFlBase32], k0 = fl[kFlK0], k64 = fl[kFlK64];
   const int32_t seed = cg.seed[v];
   const int32_t nc = 2 + 2 * cg.cslots;
   const int32_t ns = cg.n_shift;
@@ -749,24 +775,29 @@ __global__ void __launch_bounds__(256) k_cg_flush(CgDev cg, const void* ring, do
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
   double rv[kMaxSlots];
-  if constexpr (sizeof(T) == 8) {
+  if constexpr (!F32) {
 #pragma unroll
     for (int i = 0; i < kMaxSlots; ++i) {
       rv[i] = 0.0;
-      if (i <= m) rv[i] = ring_slot<T>(ring, cg.ring_rhs_bytes, v, (base + i) % cg.nslot, n)[e];
+      if (i <= m) rv[i] = entry64(cg, v, base, i, n)[e];
     }
   } else {
-    // FP32 slots: every load is issued unconditionally so they overlap (the conditional form
-    // waits on each); entries past m re-read slot m (a cache hit) and are never used
-    T rt[kMaxSlots];
+    // FP32 entries: every load is issued unconditionally so they overlap (the conditional form
+    // waits on each); indices outside [k0, m] re-read an end of that range (a cache hit) and are
+    // never used
+    float rt[kMaxSlots];
 #pragma unroll
-    for (int i = 0; i < kMaxSlots; ++i)
-      rt[i] = ring_slot<T>(ring, cg.ring_rhs_bytes, v, (base + min(i, m)) % cg.nslot, n)[e];
+    for (int i = 0; i < kMaxSlots; ++i) rt[i] = entry32(cg, v, base32, k0, min(max(i, k0), m), n)[e];
 #pragma unroll
     for (int i = 0; i < kMaxSlots; ++i) rv[i] = (double)rt[i];
+    if (k64 > 0) {   // uniform per rhs: only the segment that spans the switch
+#pragma unroll
+      for (int i = 0; i < kMaxSlots; ++i)
+        if (i < k64) rv[i] = entry64(cg, v, base, i, n)[e];
+    }
   }
   for (int j = 0; j < ns; ++j) {
-    if (cg.seed_explicit && j == seed) continue;   // kept current by the residual update
+    if (seed_only ? j != seed : (cg.seed_explicit && j == seed)) continue;   // kept current by the residual update
     const int64_t vj = (int64_t)v * ns + j;
     const double* cf = s_cf + (size_t)j * nc;
     const double* d = cf + 2;
@@ -784,7 +815,7 @@ __global__ void __launch_bounds__(256) k_cg_flush(CgDev cg, const void* ring, do
     for (int i = 0; i < kMaxSlots; ++i)
       if (i <= m) x = fma(d[i], rv[i], x);
     *xj = x;
-    if (!final_ && s_fl[2 * j + 1]) {
+    if (!final_ && !seed_only && s_fl[2 * j + 1]) {
       double q = cf[1] * p0;
 #pragma unroll
       for (int i = 0; i < kMaxSlots; ++i)
@@ -794,9 +825,9 @@ __global__ void __launch_bounds__(256) k_cg_flush(CgDev cg, const void* ring, do
   }
 }
 
-// after a flush: coefficients of the fresh segment (x_j = x_j0, p_j = p_j0) and the ring restarts
-// at the current residual
-__global__ void k_cg_flush_reset(CgDev cg) {
+// after a flush: coefficients of the fresh segment (x_j = x_j0, p_j = p_j0), which starts at the
+// current residual (fp32: in the FP32 ring, with no FP64 entries)
+__global__ void k_cg_flush_reset(CgDev cg, int32_t fp32) {
   const int32_t v = blockIdx.x;
   int32_t* fl = cg.flags + (int64_t)v * kFlN;
   const int32_t nc = 2 + 2 * cg.cslots;
@@ -809,7 +840,14 @@ __global__ void k_cg_flush_reset(CgDev cg) {
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    fl[kFlBase] = (fl[kFlBase] + fl[kFlM]) % cg.nslot;
+    const int32_t m = fl[kFlM];
+    if (fp32) {
+      fl[kFlBase32] = (fl[kFlBase32] + m - fl[kFlK0]) % cg.nslot32;
+      fl[kFlK0] = 0;
+      fl[kFlK64] = 0;
+    } else {
+      fl[kFlBase] = (fl[kFlBase] + m) % cg.nslot64;
+    }
     fl[kFlM] = 0;
   }
 }
@@ -818,30 +856,28 @@ size_t flush_lds_bytes(const CgDev& cg) {
   return (size_t)cg.n_shift * (2 + 2 * cg.cslots) * 8 + (size_t)cg.n_shift * 2 * 4;
 }
 
-template <typename T>
-hipError_t launch_cg_flush(const CgDev& cg, const void* ring, double* x_hi, double* pj, int32_t final_,
-                           int32_t first, int64_t n_reals, hipStream_t s) {
-  if (cg.nslot > kMaxSlots || cg.nslot > cg.cslots) return hipErrorInvalidValue;
+hipError_t launch_cg_flush(const CgDev& cg, double* x_hi, double* pj, int32_t final_, int32_t first,
+                           int32_t seed_only, int32_t fp32, int64_t n_reals, hipStream_t s) {
+  if (cg.nslot > kMaxSlots || cg.nslot > cg.cslots || cg.nslot64 > kMaxSlots) return hipErrorInvalidValue;
+  if (fp32 && (!cg.ring32 || cg.nslot32 < cg.nslot || seed_only)) return hipErrorInvalidValue;
   dim3 grid((unsigned)((n_reals + kBlock - 1) / kBlock), cg.n_rhs);
-  hipLaunchKernelGGL((k_cg_flush<T>), grid, dim3(kBlock), flush_lds_bytes(cg), s, cg, ring, x_hi, pj, final_,
-                     first, n_reals);
-  hipLaunchKernelGGL(k_cg_flush_reset, dim3(cg.n_rhs), dim3(kRedBlock), 0, s, cg);
+  if (fp32)
+    hipLaunchKernelGGL((k_cg_flush<true>), grid, dim3(kBlock), flush_lds_bytes(cg), s, cg, x_hi, pj, final_, first,
+                       0, n_reals);
+  else
+    hipLaunchKernelGGL((k_cg_flush<false>), grid, dim3(kBlock), flush_lds_bytes(cg), s, cg, x_hi, pj, final_,
+                       first, seed_only, n_reals);
+  if (!seed_only) hipLaunchKernelGGL(k_cg_flush_reset, dim3(cg.n_rhs), dim3(kRedBlock), 0, s, cg, fp32);
   return hipGetLastError();
 }
-template hipError_t launch_cg_flush<double>(const CgDev&, const void*, double*, double*, int32_t, int32_t,
-                                            int64_t, hipStream_t);
-template hipError_t launch_cg_flush<float>(const CgDev&, const void*, double*, double*, int32_t, int32_t,
-                                           int64_t, hipStream_t);
 
-// FP64 slot cur -> FP32 slot 0 (inside FP64 slot 0), or FP32 slot 2 (inside FP64 slot 1) when
-// cur is 0: the copy never overlaps its source and the FP32 ring restarts at that slot
-__global__ void k_cg_to_f32(CgDev cg, void* ring, const double* __restrict__ p64, float* __restrict__ p32,
-                            int64_t n) {
+// the switch of precision: the current FP64 entry M -> FP32 slot 0, which holds entry K0 = M from
+// now on; p64 -> p32
+__global__ void k_cg_to_f32(CgDev cg, const double* __restrict__ p64, float* __restrict__ p32, int64_t n) {
   const int32_t v = blockIdx.y;
   const int32_t* fl = cg.flags + (int64_t)v * kFlN;
-  const int32_t cur = (fl[kFlBase] + fl[kFlM]) % cg.nslot;
-  const double* r = ring_slot<double>(ring, cg.ring_rhs_bytes, v, cur, n);
-  float* r32 = ring_slot<float>(ring, cg.ring_rhs_bytes, v, cur == 0 ? 2 : 0, n);
+  const double* r = entry64(cg, v, fl[kFlBase], fl[kFlM], n);
+  float* r32 = ring_slot<float>(cg.ring32, cg.rb32, v, 0, n);
   const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
   if (i0 >= n) return;
 #pragma unroll
@@ -855,16 +891,17 @@ __global__ void k_cg_to_f32_scalars(CgDev cg) {
   for (int v = threadIdx.x; v < cg.n_rhs; v += blockDim.x) {
     int32_t* fl = cg.flags + (int64_t)v * kFlN;
     double* sc = cg.sc + (int64_t)v * kScN;
-    fl[kFlBase] = ((fl[kFlBase] + fl[kFlM]) % cg.nslot) == 0 ? 2 : 0;
-    fl[kFlM] = 0;
+    fl[kFlK64] = fl[kFlM] + 1;
+    fl[kFlK0] = fl[kFlM];
+    fl[kFlBase32] = 0;
     sc[kScMaxR] = sqrt(sc[kScRR]);
   }
 }
 
-hipError_t launch_cg_to_f32(const CgDev& cg64, void* ring, const double* p64, float* p32, int64_t n_reals,
-                            hipStream_t s) {
+hipError_t launch_cg_to_f32(const CgDev& cg64, const double* p64, float* p32, int64_t n_reals, hipStream_t s) {
+  if (!cg64.ring32) return hipErrorInvalidValue;
   dim3 grid(elem_num_blocks(n_reals), cg64.n_rhs);
-  hipLaunchKernelGGL(k_cg_to_f32, grid, dim3(kBlock), 0, s, cg64, ring, p64, p32, n_reals);
+  hipLaunchKernelGGL(k_cg_to_f32, grid, dim3(kBlock), 0, s, cg64, p64, p32, n_reals);
   hipLaunchKernelGGL(k_cg_to_f32_scalars, dim3(1), dim3(kRedBlock), 0, s, cg64);
   return hipGetLastError();
 }

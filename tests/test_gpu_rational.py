@@ -90,6 +90,32 @@ def test_rational_apply_segment_lengths(mode):
             assert np.abs(xp - xr).max() <= 1e-12 * np.abs(xr).max()
 
 
+@pytest.mark.parametrize("switch", [-1.0, 1e-2, 1e-4, 1e-7])
+@pytest.mark.parametrize("basis", [3, 16, 32])
+def test_mixed_switch_points(switch, basis):
+    """Mixed solves whose switch to FP32 falls at the first iteration (switch < 0), early, at the
+    default and late, with segments of 3, 16 and 32 iterations: the segment open at the switch
+    carries FP64 and FP32 entries in every proportion.  Every shift meets its FP64 true residual
+    and lies within the tolerance bound of the FP64 solve."""
+    L = (4, 4, 4, 6)
+    announce(f"mixed switch={switch} basis={basis}")
+    U, P, Ud, Pd = setup(L, "eps", 0.6, 12, n=2)
+    rat = _rat_kappa(0.9, 12)
+    tol = 1e-10
+    ref = api.rational_apply(L, Ud, Pd, rat, api.Solver(tol=tol, mode=0), want_poles=True)
+    xr = ref["x_poles"].cpu().numpy()
+    out = api.rational_apply(L, Ud, Pd, rat, api.Solver(tol=tol, mode=1, basis=basis, mixed_switch=switch),
+                             want_poles=True)
+    xp = out["x_poles"].cpu().numpy()
+    assert out["stats"]["true_relres_max"] <= tol
+    for i in range(2):
+        bn = np.linalg.norm(P[i])
+        for j, sj in enumerate(rat.sigma):
+            assert np.linalg.norm(xp[i, j] - xr[i, j]) <= 2 * tol * bn / sj, (i, j)
+            res = np.linalg.norm(P[i] - olap.laplacian(U, xp[i, j], L, sj)) / bn
+            assert res <= 1.01 * tol, (i, j, res)
+
+
 @pytest.mark.parametrize("kappa", [0.5, 0.9])
 @pytest.mark.parametrize("mode", [0, 1])
 def test_rational_apply_16_true_residuals(kappa, mode):
