@@ -274,7 +274,7 @@ def d1_laplacian(api, inputs, torch, dev, copy_gbs):
             Ud = api.pack_links(L, U, dt)
             Fd = F.to(dt)
             cfg, _ = api.autotune_laplacian(L, Ud, Fd, reps=3)
-            set_bytes = 136 * ts * V
+            set_bytes = 136 * ts * V   # buffers of one set: links (18 reals), input and output
             nset = 1 if set_bytes >= (256 << 20) else -(-(1 << 30) // set_bytes)
             sets = [(Ud, Fd, torch.empty_like(Fd))]
             for _ in range(nset - 1):
@@ -295,7 +295,7 @@ def d1_laplacian(api, inputs, torch, dev, copy_gbs):
             out.setdefault(key, {})[name] = {
                 "gsite_s": round(gsite, 3), "avg_ms": round(p["avg_ms"], 4), "achieved_GBs": round(p["gbs"], 1),
                 "hbm_frac": round(p["gbs"] / HBM_PEAK_GBS, 4), "copy_frac": round(p["gbs"] / copy_gbs, 4),
-                "bytes_per_site": 136 * ts, "rotating_sets": nset,
+                "bytes_per_site": 112 * ts, "rotating_sets": nset,
                 "config": dict(zip(("form", "block", "xcd_remap", "nv", "order", "walk"), cfg))}
             log(f"D-1 {key} {name}: {out[key][name]}")
             del sets, Ud, Fd

@@ -24,6 +24,10 @@
  *              phi = sum_a phi^a T^a, <phi, psi> = sum_a phi^a psi^a.
  * Links        "SoA" U[mu][18][V]: component 2*(3i+j) = Re U_ij, 2*(3i+j)+1 = Im U_ij.
  *              "AoS" U[mu][V][3][3] complex interleaved (re, im) doubles.
+ *              Links are SU(3) matrices (unitary, unit determinant, to rounding): the
+ *              Laplacian reads rows 0 and 1 of each link and rebuilds row 2 as the complex
+ *              conjugate of their cross product, U_2j = conj(U_0k U_1l - U_0l U_1k) for
+ *              (j, k, l) cyclic; components 12..17 of the SoA links are not read by it.
  * Link fields  "SoA" F[n][nu][a][V] = F[n][4][8][V] (n counts independent fields).
  *              "AoS" F[n][V][4][8].
  * dtype        RMH_F64 (double) or RMH_F32 (float) for links and fields where a call

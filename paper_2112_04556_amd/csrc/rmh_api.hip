@@ -221,7 +221,8 @@ void prof_add_bytes(int cls, double bytes, double items = 0.0) {
 
 // algorithmic bytes of one stencil launch over n fields: links once, x, optional z, optional out
 double hop_bytes(const Geom& g, int32_t n, size_t ts, bool z, bool store) {
-  return (double)g.V * ts * (72.0 + (double)n * 32.0 * (1.0 + (z ? 1.0 : 0.0) + (store ? 1.0 : 0.0)));
+  // links: the 12 reals of rows 0 and 1 per direction (row 2 is rebuilt in registers)
+  return (double)g.V * ts * (48.0 + (double)n * 32.0 * (1.0 + (z ? 1.0 : 0.0) + (store ? 1.0 : 0.0)));
 }
 
 HopConfig hop_config(const Geom& g, int32_t dtype, int32_t n_rhs, int32_t purpose) {

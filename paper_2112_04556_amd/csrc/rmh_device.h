@@ -210,6 +210,23 @@ RMH_HD void adjoint_columns(const T* u, T* c1, T* c2) {
 #undef UIM
 }
 
+// Row 2 of an SU(3) matrix from rows 0 and 1 (u as in adjoint_matrix): for a unitary matrix of
+// unit determinant each row is the complex conjugate of the cross product of the other two,
+// U_2j = conj(U_0k U_1l - U_0l U_1k) with (j, k, l) a cyclic permutation of (0, 1, 2).
+template <typename T>
+RMH_HD void su3_row2(T* u) {
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const int k = (j + 1) % 3, l = (j + 2) % 3;
+    const T ar = u[2 * k], ai = u[2 * k + 1];            // U_0k
+    const T br = u[6 + 2 * l], bi = u[6 + 2 * l + 1];    // U_1l
+    const T cr = u[2 * l], ci = u[2 * l + 1];            // U_0l
+    const T dr = u[6 + 2 * k], di = u[6 + 2 * k + 1];    // U_1k
+    u[12 + 2 * j] = (ar * br - ai * bi) - (cr * dr - ci * di);
+    u[12 + 2 * j + 1] = (cr * di + ci * dr) - (ar * bi + ai * br);
+  }
+}
+
 // Column indices of group q (see adjoint_columns).
 template <int q>
 struct ColPair {

@@ -63,6 +63,15 @@ __device__ __forceinline__ void hop_apply(const T* u, const T (*phi)[8], T (*acc
   }
 }
 
+// The link at site s (component c at Um[c V + s]): rows 0 and 1 are loaded, row 2 is rebuilt
+// from them (SU(3)), so a hop moves 12 link reals instead of 18.
+template <typename T>
+__device__ __forceinline__ void load_link(const T* __restrict__ Um, int32_t s, int32_t V, T (&u)[18]) {
+#pragma unroll
+  for (int c = 0; c < 12; ++c) u[c] = (Um + (size_t)c * V)[s];
+  su3_row2<T>(u);
+}
+
 // out[v] = a (H x)[v] + b x[v] + c z[v]: a block of B threads covers B * NV / 4 sites; the
 // 4 / NV thread groups of a site (direction subsets) are wave-aligned slices of the block.
 // One backward hop: link and field both read at the neighbour site sb.
@@ -70,8 +79,7 @@ template <typename T, int FORM, int NV, bool kT>
 __device__ __forceinline__ void hop_term(const T* __restrict__ Um, int32_t sb, const T* __restrict__ xf,
                                          int nu0, int32_t V, T (&acc)[NV][8]) {
   T u[18], phi[NV][8];
-#pragma unroll
-  for (int c = 0; c < 18; ++c) u[c] = (Um + (size_t)c * V)[sb];
+  load_link<T>(Um, sb, V, u);
 #pragma unroll
   for (int i = 0; i < NV; ++i)
 #pragma unroll
@@ -85,8 +93,7 @@ __device__ __forceinline__ void hop_term_fwd(const T* __restrict__ Um, int32_t s
                                              const T* __restrict__ xf, int nu0, int32_t V,
                                              T (&acc)[NV][8]) {
   T u[18], phi[NV][8];
-#pragma unroll
-  for (int c = 0; c < 18; ++c) u[c] = (Um + (size_t)c * V)[s];
+  load_link<T>(Um, s, V, u);
 #pragma unroll
   for (int i = 0; i < NV; ++i)
 #pragma unroll
@@ -354,8 +361,7 @@ __global__ void __launch_bounds__(256) k_hop_walk(const HopArgs<T> A, int32_t xc
       {
         const int32_t sb = (x3 == 0) ? s + (A.g.L3 - 1) * P : s - P;
         T u[18];
-#pragma unroll
-        for (int c = 0; c < 18; ++c) u[c] = (U3 + (size_t)c * V)[sb];
+        load_link<T>(U3, sb, V, u);
         hop_apply<T, FORM, NV, true>(u, bwd, acc);
       }
 #pragma unroll 1
@@ -369,8 +375,7 @@ __global__ void __launch_bounds__(256) k_hop_walk(const HopArgs<T> A, int32_t xc
       {
         const int32_t sf = (x3 == A.g.L3 - 1) ? s - (A.g.L3 - 1) * P : s + P;
         T u[18];
-#pragma unroll
-        for (int c = 0; c < 18; ++c) u[c] = (U3 + (size_t)c * V)[s];
+        load_link<T>(U3, s, V, u);
 #pragma unroll
         for (int i = 0; i < NV; ++i)
 #pragma unroll
