@@ -65,6 +65,26 @@ def test_laplacian_fp64_parity(L, kind, seed, shift):
     api.tune_clear()
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_laplacian_reads_rows_0_and_1_only(dtype):
+    """Every launch shape rebuilds row 2 of each link from rows 0 and 1: with components 12..17
+    of the SoA links overwritten by NaN the output is bitwise unchanged."""
+    L = (4, 4, 2, 6)
+    announce(f"laplacian row-2 rebuild {dtype}")
+    U, P, Ud, Pd = setup(L, "haar", 0.5, 3, n=2)
+    U2 = api.pack_links(L, inputs.random_links(L, "haar", seed=3).to(dev()), dtype)
+    x = Pd.to(dtype)
+    bad = U2.clone()
+    bad[:, 12:18, :] = float("nan")
+    shapes = [(0, 128, 4, 0, 0), (1, 256, 1, 0, 0), (2, 64, 2, L[3], 0), (2, 256, 4, 0, 2), (1, 128, 2, 0, 3)]
+    for form, block, nv, walk, order in shapes:
+        api.tune_set(L, dtype, 2, form, block, 1, nv, order, walk)
+        a = api.laplacian_apply(L, U2, x)
+        b = api.laplacian_apply(L, bad, x)
+        assert torch.equal(a, b), (form, block, nv, walk, order)
+    api.tune_clear()
+
+
 @pytest.mark.parametrize("form", [0, 1, 2])
 @pytest.mark.parametrize("L,kind,seed", CASES[:3])
 def test_laplacian_fp32_parity(L, kind, seed, form):

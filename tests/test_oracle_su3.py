@@ -111,3 +111,16 @@ def test_field_moments():
     # determinism
     Q = inputs.gaussian_fields((8, 8, 8, 8), 2, seed=7).numpy()
     assert np.array_equal(P, Q)
+
+
+@pytest.mark.parametrize("kind", ["eps", "haar", "unit"])
+def test_links_third_row_is_conjugate_cross_product(kind):
+    """The seeded links are SU(3): row 2 equals the complex conjugate of the cross product of rows
+    0 and 1 (what a reader of rows 0 and 1 alone relies on), and the matrices are unitary with unit
+    determinant."""
+    U = inputs.random_links((4, 4, 4, 4), kind, 0.5, seed=7).numpy()
+    r0, r1, r2 = U[..., 0, :], U[..., 1, :], U[..., 2, :]
+    assert np.abs(r2 - np.conj(np.cross(r0, r1))).max() <= 1e-14
+    assert np.abs(U @ np.conj(np.swapaxes(U, -1, -2)) - np.eye(3)).max() <= 1e-14
+    assert np.abs(np.linalg.det(U) - 1.0).max() <= 1e-14
+
