@@ -34,7 +34,11 @@ Extra fields (skipped with --no-extras):
   D6  the backward of the degree-64, 16-window power spectrum at 16^4 (link derivative and source
       gradient) beside its forward;
   D7  the Wilson gauge force and its degree-128, 32-window power spectrum (the gauge-force spectra
-      of section 2) at 16^4 and 32^3 x 64.
+      of section 2) at 16^4 and 32^3 x 64;
+  D8  one implicit leapfrog step of the non-separable Hamiltonian (kinetic term with the 12-pole
+      kappa = 0.9 mass term plus the Wilson action, beta = 5.5, eps = 0.02) at 16^4: time,
+      fixed-point iterations, solver iterations, the energy change of the step and the stencil
+      launches inside it.
 """
 from __future__ import annotations
 
@@ -455,6 +459,35 @@ def d7_gauge_force_spectrum(api, inputs, torch, dev):
     return out
 
 
+def d8_leapfrog(api, inputs, torch, dev):
+    """One implicit leapfrog step at 16^4 (eps-links 0.5, one Gaussian momentum field)."""
+    L = (16, 16, 16, 16)
+    Ud = api.pack_links(L, inputs.random_links(L, "eps", 0.5, seed=8).to(dev))
+    Pd = inputs.gaussian_fields(L, 1, seed=8)[0].to(dev)
+    rat = api.rational_kappa(0.9, 12)
+    sv = api.Solver(tol=1e-10)
+    beta, eps = 5.5, 0.02
+    ws = torch.empty(api.workspace_bytes(api.L_.OP_LEAPFROG, L, api.RMH_F64, 1, 12), dtype=torch.uint8, device=dev)
+    ms, (U1, P1, st) = _median_ms(lambda: api.leapfrog_step(L, Ud, Pd, rat, eps, beta, sv, fp_tol=1e-10, ws=ws),
+                                  torch, reps=3)
+    api.profile_enable(True)
+    api.leapfrog_step(L, Ud, Pd, rat, eps, beta, sv, fp_tol=1e-10, ws=ws)
+    torch.cuda.synchronize()
+    p = api.profile_read("stencil")
+    api.profile_enable(False)
+
+    def ham(U, P):
+        K = api.rational_apply(L, U, P[None], rat, api.Solver(tol=1e-12))["K"][0]
+        return float(K) + api.wilson_gauge_force(L, U, beta)[1]
+
+    out = {"ms_per_step": round(ms, 2), "p_iters": st["p_iters"], "u_iters": st["u_iters"],
+           "solver_iters": st["solver"]["iters"], "true_relres_max": st["solver"]["true_relres_max"],
+           "dH": ham(U1, P1) - ham(Ud, Pd), "stencil": {"launches": p["launches"], "ms": round(p["ms"], 2),
+                                                        "GBs": round(p["gbs"], 1)}}
+    log(f"D8 leapfrog step 16^4: {out}")
+    return out
+
+
 def run_extras(api, inputs, torch, np, dev, L, U_aos, Ud, Pd):
     out = {}
     cp = copy_bandwidth(torch, dev)
@@ -467,6 +500,7 @@ def run_extras(api, inputs, torch, np, dev, L, U_aos, Ud, Pd):
     out["D5_force_step_32x32x32x64"] = d5_force_step(api, inputs, torch, dev)
     out["D6_power_spectrum_bwd_16x16x16x16"] = d6_spectrum_bwd(api, inputs, torch, np, dev)
     out["D7_gauge_force_spectrum"] = d7_gauge_force_spectrum(api, inputs, torch, dev)
+    out["D8_leapfrog_step_16x16x16x16"] = d8_leapfrog(api, inputs, torch, dev)
     return out
 
 

@@ -136,7 +136,8 @@ typedef enum {
   RMH_OP_CHEB_FILTER_BWD = 7,
   RMH_OP_POWER_SPECTRUM_BWD = 8,
   RMH_OP_GAUGE_FORCE = 9,
-  RMH_OP_HEATBATH = 10
+  RMH_OP_HEATBATH = 10,
+  RMH_OP_LEAPFROG = 11
 } rmh_op;
 
 /* ---------------------------------------------------------------------------------------- */
@@ -310,6 +311,45 @@ rmh_status rmh_kinetic_force(const int32_t L[4], const double* U, const double* 
  * workspace (RMH_OP_GAUGE_FORCE) and synchronizes the stream.  At least one of F, S. */
 rmh_status rmh_wilson_gauge_force(const int32_t L[4], const double* U, double beta, double* F, double* S, void* ws,
                                   size_t ws_bytes, rmh_stream stream);
+
+/* ---------------------------------------------------------------------------------------- */
+/* molecular dynamics: the implicit leapfrog step of RMHMC (section 3) */
+
+/* Step controls: step size eps (molecular-dynamics time), Wilson coupling beta, and the
+ * fixed points' relative tolerance and iteration limit. */
+typedef struct {
+  double eps;
+  double beta;
+  double fp_tol;
+  int32_t fp_maxiter;
+} rmh_leapfrog;
+
+typedef struct {
+  int32_t p_iters;   /* fixed-point iterations of the half-step momentum */
+  int32_t u_iters;   /* fixed-point iterations of the link update */
+  double p_res;      /* last relative change of the half-step momentum */
+  double u_res;      /* last relative change of Pi(U', P_h) */
+  rmh_stats solver;  /* every multi-shift solve of the step, summed */
+} rmh_leapfrog_stats;
+
+/* One implicit (generalized) leapfrog step for the non-separable Hamiltonian of section 3,
+ * H(U, P) = 1/2 <R(Delta) P, R(Delta) P> + S_W(U) (Eq. 5 with M^-1 = R^2; the log|M| term is not
+ * included: the paper realises it with auxiliary fields it does not define).  Links move by left
+ * multiplication, dU/dt = i Pi^a T^a U with Pi = dH/dP = R(Delta)^2 P, and dP/dt = F = F_G - dK/d omega.
+ * With h = eps / 2:
+ *   P_h = P + h F(U, P_h)                               (fixed point, from P_h = P),
+ *   U'  = exp(i h (Pi(U, P_h) + Pi(U', P_h))^a T^a) U   (fixed point, from Pi(U') = Pi(U)),
+ *   P'  = P_h + h F(U', P_h).
+ * A fixed point stops when successive iterates (P_h, then Pi(U', P_h)) differ by at most fp_tol
+ * relative to the newer one; after fp_maxiter iterations the step goes on with the last iterate
+ * and returns RMH_E_NOCONV.  Every solve runs to solver->tol.  The step is time reversible:
+ * from (U', -P') it returns to (U, -P) up to the tolerances.
+ * U0, U1: device FP64 SoA links (distinct buffers); P0, P1: device FP64 [4][8][V] (distinct).
+ * Workspace: RMH_OP_LEAPFROG (n_rhs = 1, aux = n_poles, degree = solver basis, mode).
+ * stats: optional host.  Synchronizes the stream. */
+rmh_status rmh_leapfrog_step(const int32_t L[4], const double* U0, const double* P0, const rmh_rational* rat,
+                             const rmh_solver* solver, const rmh_leapfrog* lf, double* U1, double* P1,
+                             rmh_leapfrog_stats* stats, void* ws, size_t ws_bytes, rmh_stream stream);
 
 /* ---------------------------------------------------------------------------------------- */
 /* stencil launch tuning */

@@ -19,7 +19,7 @@ STATUS_NAMES = {
 RMH_F64, RMH_F32 = 0, 1
 OP_LAPLACIAN, OP_LAPLACIAN_BWD, OP_POWER_SPECTRUM, OP_CHEB_FILTER = 0, 1, 2, 3
 OP_RATIONAL_APPLY, OP_RATIONAL_APPLY_BWD, OP_KINETIC_FORCE = 4, 5, 6
-OP_CHEB_FILTER_BWD, OP_POWER_SPECTRUM_BWD, OP_GAUGE_FORCE, OP_HEATBATH = 7, 8, 9, 10
+OP_CHEB_FILTER_BWD, OP_POWER_SPECTRUM_BWD, OP_GAUGE_FORCE, OP_HEATBATH, OP_LEAPFROG = 7, 8, 9, 10, 11
 
 c_i32, c_i64, c_f64, c_sz, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t, ctypes.c_void_p
 P_i32 = ctypes.POINTER(c_i32)
@@ -49,6 +49,19 @@ class RmhStats(ctypes.Structure):
 
 
 # name -> (restype, argtypes)
+class RmhLeapfrog(ctypes.Structure):
+    _fields_ = [("eps", c_f64), ("beta", c_f64), ("fp_tol", c_f64), ("fp_maxiter", c_i32)]
+
+
+class RmhLeapfrogStats(ctypes.Structure):
+    _fields_ = [("p_iters", c_i32), ("u_iters", c_i32), ("p_res", c_f64), ("u_res", c_f64), ("solver", RmhStats)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "solver"}
+        d["solver"] = self.solver.as_dict()
+        return d
+
+
 SIGNATURES = {
     "rmh_last_error": (ctypes.c_char_p, []),
     "rmh_version": (c_i32, []),
@@ -89,6 +102,9 @@ SIGNATURES = {
     "rmh_kinetic_force": (c_i32, [P_i32, c_vp, c_vp, c_i32, ctypes.POINTER(RmhRational),
                                   ctypes.POINTER(RmhSolver), c_vp, P_f64, c_vp, c_i32,
                                   ctypes.POINTER(RmhStats), c_vp, c_sz, c_vp]),
+    "rmh_leapfrog_step": (c_i32, [P_i32, c_vp, c_vp, ctypes.POINTER(RmhRational), ctypes.POINTER(RmhSolver),
+                                  ctypes.POINTER(RmhLeapfrog), c_vp, c_vp, ctypes.POINTER(RmhLeapfrogStats),
+                                  c_vp, c_sz, c_vp]),
 }
 
 _lib = None

@@ -231,7 +231,7 @@ def cheb_filter(L, U, x, degree: int, n_windows: int, edges=None, kernel: int = 
 def _require_f64(*ts):
     for t in ts:
         if t.dtype != torch.float64:
-            raise TypeError("the Chebyshev backward calls take FP64 links and fields")
+            raise TypeError("this call takes FP64 links and fields")
 
 
 def cheb_filter_bwd(L, U, x, gy, degree: int, n_windows: int, edges=None, kernel: int = 1,
@@ -375,6 +375,26 @@ def kinetic_force(L, U, P, rat: Rational, solver: Solver = Solver(), per_rhs: bo
                                   _dev(dK, "dK"), int(per_rhs), ctypes.byref(stats), ws.data_ptr(), ws.numel(),
                                   _stream(P.device)), "rmh_kinetic_force")
     return {"Y": Y, "K": K, "dK": dK, "stats": stats.as_dict()}
+
+
+def leapfrog_step(L, U, P, rat: Rational, eps: float, beta: float, solver: Solver = Solver(),
+                  fp_tol: float = 1e-12, fp_maxiter: int = 50, ws: Optional[torch.Tensor] = None):
+    """(U', P', stats): one implicit leapfrog step of size eps for H = 1/2 <R(Delta) P, R(Delta) P> + S_W(U)
+    (rmh_leapfrog_step).  U: SoA FP64 links (4, 18, V); P: FP64 momentum field (4, 8, V) or (1, 4, 8, V)."""
+    _require_f64(U, P)
+    U1 = torch.empty_like(U)
+    P1 = torch.empty_like(P)
+    np_ = len(rat.r)
+    need = workspace_bytes(L_.OP_LEAPFROG, L, RMH_F64, 1, np_, solver.basis, solver.mode)
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, P.device)
+    lf = L_.RmhLeapfrog(float(eps), float(beta), float(fp_tol), int(fp_maxiter))
+    stats = L_.RmhLeapfrogStats()
+    rs, ss = rat.c_struct(), solver.c_struct()
+    check(lib().rmh_leapfrog_step(lattice_arg(L), _dev(U, "U"), _dev(P, "P"), ctypes.byref(rs), ctypes.byref(ss),
+                                  ctypes.byref(lf), _dev(U1, "U1"), _dev(P1, "P1"), ctypes.byref(stats),
+                                  ws.data_ptr(), ws.numel(), _stream(P.device)), "rmh_leapfrog_step")
+    return U1, P1, stats.as_dict()
 
 
 # ------------------------------------------------------------------------------------------

@@ -915,6 +915,32 @@ void plan_rational(Carver& c, RationalPlan& rp, const Geom& g, int32_t n_rhs, in
   rp.sumsK = c.take<double>(n_rhs);
 }
 
+// workspace of one implicit leapfrog step (one momentum field)
+struct LeapfrogPlan {
+  RationalPlan rp;       // solves of the kinetic term: X, Z, Y, coefficients
+  double* Fg = nullptr;  // gauge force
+  double* dK = nullptr;  // dK/d omega
+  double* Ph = nullptr;  // half-step momentum
+  double* Pi0 = nullptr; // Pi(U, P_h)
+  double* PiA = nullptr; // Pi(U', P_h), newest
+  double* PiB = nullptr; // Pi(U', P_h), previous
+  double* part = nullptr;  // [2][red_num_blocks] partials of the fixed-point norms
+  double* sums = nullptr;  // [2]
+};
+
+void plan_leapfrog(Carver& c, LeapfrogPlan& lp, const Geom& g, int32_t n_poles, int32_t mode, int32_t basis) {
+  const int64_t n = field_reals(g);
+  plan_rational(c, lp.rp, g, 1, n_poles, mode, basis, RMH_OP_KINETIC_FORCE);
+  lp.Fg = c.take<double>(n);
+  lp.dK = c.take<double>(n);
+  lp.Ph = c.take<double>(n);
+  lp.Pi0 = c.take<double>(n);
+  lp.PiA = c.take<double>(n);
+  lp.PiB = c.take<double>(n);
+  lp.part = c.take<double>(2 * (size_t)red_num_blocks(n));
+  lp.sums = c.take<double>(2);
+}
+
 template <typename T>
 rmh_status power_spectrum_t(const Geom& g, const T* U, const T* F, int32_t n_rhs, int32_t D,
                                    const ChebPlan& cp, std::vector<double>* sums_h, hipStream_t s) {
@@ -1200,6 +1226,15 @@ size_t rmh_workspace_bytes(int32_t op, const int32_t L[4], int32_t dtype, int32_
       }
       RationalPlan rp;
       plan_rational(c, rp, g, n_rhs, aux, mode ? 1 : 0, degree, op);
+      break;
+    }
+    case RMH_OP_LEAPFROG: {
+      if (aux < 1) {
+        fail(RMH_E_ARG, "n_poles < 1");
+        return 0;
+      }
+      LeapfrogPlan lp;
+      plan_leapfrog(c, lp, g, aux, mode ? 1 : 0, degree);
       break;
     }
     default:
@@ -1819,6 +1854,137 @@ rmh_status rmh_kinetic_force(const int32_t L[4], const double* U, const double* 
   fill_stats(stats, res, 2, now_s() - t0);
   RMH_TRY(status_of(res[0], "kinetic_force (solve of P)"));
   return status_of(res[1], "kinetic_force (solve of Y)");
+}
+
+// dK/d omega at (U, P) into lp.dK: the kinetic force's two solves and its link derivative
+static rmh_status lf_kinetic_grad(LeapfrogPlan& lp, const Geom& g, const double* U, const double* P,
+                                  const rmh_rational* rat, const rmh_solver* sv, hipStream_t s,
+                                  std::vector<SolveResult>& res) {
+  const int32_t np = rat->n_poles;
+  const int64_t n = field_reals(g);
+  std::vector<double> sig(rat->sigma, rat->sigma + np);
+  SolveResult r1, r2;
+  RMH_TRY(solve_all(lp.rp.sp, U, P, lp.rp.X, sig, *sv, s, &r1));
+  HIP_TRY(launch_rational_combine(P, lp.rp.X, 1, np, lp.rp.coef, lp.rp.Y, n, nullptr, s));
+  RMH_TRY(force_from_solves(lp.rp, g, U, lp.rp.X, lp.rp.Y, 1, rat, sv, nullptr, lp.dK, 0, s, &r2));
+  res.push_back(r1);
+  res.push_back(r2);
+  return RMH_OK;
+}
+
+// Pi = R(Delta[U])^2 P into out
+static rmh_status lf_velocity(LeapfrogPlan& lp, const Geom& g, const double* U, const double* P, double* out,
+                              const rmh_rational* rat, const rmh_solver* sv, hipStream_t s,
+                              std::vector<SolveResult>& res) {
+  const int32_t np = rat->n_poles;
+  const int64_t n = field_reals(g);
+  std::vector<double> sig(rat->sigma, rat->sigma + np);
+  SolveResult r1, r2;
+  RMH_TRY(solve_all(lp.rp.sp, U, P, lp.rp.X, sig, *sv, s, &r1));
+  HIP_TRY(launch_rational_combine(P, lp.rp.X, 1, np, lp.rp.coef, lp.rp.Y, n, nullptr, s));
+  RMH_TRY(solve_all(lp.rp.sp, U, lp.rp.Y, lp.rp.Z, sig, *sv, s, &r2));
+  HIP_TRY(launch_rational_combine(lp.rp.Y, lp.rp.Z, 1, np, lp.rp.coef, out, n, nullptr, s));
+  res.push_back(r1);
+  res.push_back(r2);
+  return RMH_OK;
+}
+
+// out = x + h (y - z); returns |out_new - out_old| and |out_new|
+static rmh_status lf_update(LeapfrogPlan& lp, const double* x, const double* y, const double* z, double h,
+                            double* out, int64_t n, hipStream_t s, double* diff, double* norm) {
+  HIP_TRY(launch_axpy_diff(x, y, z, h, out, n, lp.part, s));
+  if (!diff) return RMH_OK;
+  HIP_TRY(launch_reduce_rows(lp.part, red_num_blocks(n), 2, lp.sums, s));
+  double hs[2];
+  RMH_TRY(d2h(hs, lp.sums, sizeof(hs), s));
+  *diff = sqrt(hs[0]);
+  *norm = sqrt(hs[1]);
+  return RMH_OK;
+}
+
+rmh_status rmh_leapfrog_step(const int32_t L[4], const double* U0, const double* P0, const rmh_rational* rat,
+                             const rmh_solver* solver, const rmh_leapfrog* lf, double* U1, double* P1,
+                             rmh_leapfrog_stats* stats, void* ws, size_t ws_bytes, rmh_stream stream) {
+  const double t0 = now_s();
+  Geom g;
+  RMH_TRY(rational_common(L, U0, 1, rat, solver, &g));
+  if (!lf) return fail(RMH_E_ARG, "NULL step controls");
+  if (!(isfinite(lf->eps) && isfinite(lf->beta))) return fail(RMH_E_ARG, "eps and beta must be finite");
+  if (!(lf->fp_tol > 0.0) || lf->fp_maxiter < 1) return fail(RMH_E_ARG, "need fp_tol > 0 and fp_maxiter >= 1");
+  RMH_TRY(check_ptr(P0, "P0"));
+  RMH_TRY(check_ptr(U1, "U1"));
+  RMH_TRY(check_ptr(P1, "P1"));
+  RMH_TRY(check_ptr(ws, "ws"));
+  Carver c(ws);
+  LeapfrogPlan lp;
+  plan_leapfrog(c, lp, g, rat->n_poles, solver->mode, solver->basis);
+  if (c.off > ws_bytes) return fail(RMH_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, c.off);
+  const int64_t n = field_reals(g);
+  const size_t fb = (size_t)n * 8, ub = (size_t)72 * g.V * 8;
+  const void* bufs[5] = {U0, P0, U1, P1, ws};
+  const size_t lens[5] = {ub, fb, ub, fb, c.off};
+  for (int i = 0; i < 5; ++i)
+    for (int j = i + 1; j < 5; ++j)
+      if (overlap(bufs[i], lens[i], bufs[j], lens[j])) return fail(RMH_E_ARG, "overlapping buffers");
+  hipStream_t s = (hipStream_t)stream;
+  const int32_t np = rat->n_poles;
+  std::vector<double> coef(np + 1);
+  coef[0] = rat->c;
+  for (int j = 0; j < np; ++j) coef[1 + j] = rat->r[j];
+  RMH_TRY(h2d(lp.rp.coef, coef.data(), coef.size() * 8, s));
+  const double h = 0.5 * lf->eps, tol = lf->fp_tol;
+  std::vector<SolveResult> res;
+  bool noconv = false;
+  // (i) P_h = P0 + h F(U0, P_h), F = F_G - dK/d omega, from P_h = P0
+  HIP_TRY(launch_gauge_force(g, U0, lf->beta, lp.Fg, nullptr, s));
+  HIP_TRY(hipMemcpyAsync(lp.Ph, P0, fb, hipMemcpyDeviceToDevice, s));
+  int32_t ip = 0;
+  double dp = 0.0, np_ = 0.0;
+  while (true) {
+    ++ip;
+    RMH_TRY(lf_kinetic_grad(lp, g, U0, lp.Ph, rat, solver, s, res));
+    RMH_TRY(lf_update(lp, P0, lp.Fg, lp.dK, h, lp.Ph, n, s, &dp, &np_));
+    if (dp <= tol * np_) break;
+    if (ip >= lf->fp_maxiter || !(dp == dp)) {
+      noconv = true;
+      break;
+    }
+  }
+  // (ii) U1 = exp(i h (Pi(U0, P_h) + Pi(U1, P_h))) U0, from Pi(U1) = Pi(U0)
+  RMH_TRY(lf_velocity(lp, g, U0, lp.Ph, lp.Pi0, rat, solver, s, res));
+  HIP_TRY(launch_link_exp(g, U0, lp.Pi0, lp.Pi0, h, U1, s));
+  HIP_TRY(hipMemcpyAsync(lp.PiB, lp.Pi0, fb, hipMemcpyDeviceToDevice, s));
+  int32_t iu = 0;
+  double du = 0.0, nu = 0.0;
+  while (true) {
+    ++iu;
+    RMH_TRY(lf_velocity(lp, g, U1, lp.Ph, lp.PiA, rat, solver, s, res));
+    RMH_TRY(lf_update(lp, lp.PiA, lp.PiA, lp.PiA, 0.0, lp.PiB, n, s, &du, &nu));   // PiB = PiA, change
+    HIP_TRY(launch_link_exp(g, U0, lp.Pi0, lp.PiA, h, U1, s));
+    if (du <= tol * nu) break;
+    if (iu >= lf->fp_maxiter || !(du == du)) {
+      noconv = true;
+      break;
+    }
+  }
+  // (iii) P1 = P_h + h F(U1, P_h)
+  HIP_TRY(launch_gauge_force(g, U1, lf->beta, lp.Fg, nullptr, s));
+  RMH_TRY(lf_kinetic_grad(lp, g, U1, lp.Ph, rat, solver, s, res));
+  RMH_TRY(lf_update(lp, lp.Ph, lp.Fg, lp.dK, h, P1, n, s, nullptr, nullptr));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (stats) {
+    memset(stats, 0, sizeof(*stats));
+    stats->p_iters = ip;
+    stats->u_iters = iu;
+    stats->p_res = np_ > 0.0 ? dp / np_ : dp;
+    stats->u_res = nu > 0.0 ? du / nu : du;
+    fill_stats(&stats->solver, res.data(), (int)res.size(), now_s() - t0);
+  }
+  for (const SolveResult& r : res) RMH_TRY(status_of(r, "leapfrog_step (a shifted solve)"));
+  if (noconv)
+    return fail(RMH_E_NOCONV, "leapfrog_step: a fixed point did not reach fp_tol = %g in %d iterations (%d, %d)",
+                tol, lf->fp_maxiter, ip, iu);
+  return RMH_OK;
 }
 
 rmh_status rmh_tune_set(const int32_t L[4], int32_t dtype, int32_t n_rhs, int32_t form, int32_t block,

@@ -1357,4 +1357,159 @@ hipError_t launch_gauge_force(const Geom& g, const double* U, double beta, doubl
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------------------------------
+// molecular-dynamics updates of the implicit leapfrog
+
+// 3x3 complex matrices as separate real and imaginary parts, row major
+struct Cm3 {
+  double re[9], im[9];
+};
+
+__device__ __forceinline__ void cm3_mul(const Cm3& a, const Cm3& b, Cm3& c) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      double sr = 0.0, si = 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        sr = fma(a.re[3 * i + k], b.re[3 * k + j], fma(-a.im[3 * i + k], b.im[3 * k + j], sr));
+        si = fma(a.re[3 * i + k], b.im[3 * k + j], fma(a.im[3 * i + k], b.re[3 * k + j], si));
+      }
+      c.re[3 * i + j] = sr;
+      c.im[3 * i + j] = si;
+    }
+}
+
+// exp(i H) U per link, H = sum_c a^c T^c: scaling and squaring of the Taylor series.  X = i H is
+// scaled by 2^-q until its Frobenius norm is at most 1/4, the series is summed to degree 12 in
+// Horner form (remainder below 0.25^13 / 13! < 3e-18 relative), and the result is squared q
+// times.  The exponential of an anti-Hermitian traceless matrix is in SU(3), so U1 stays in SU(3)
+// to rounding.
+__global__ void k_link_exp(Geom g, const double* __restrict__ U0, const double* __restrict__ A,
+                           const double* __restrict__ B, double h, double* __restrict__ U1) {
+  const int32_t mu = blockIdx.y;
+  const int64_t V = g.V;
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= V) return;
+  double a[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int64_t e = ((int64_t)mu * 8 + c) * V + s;
+    a[c] = h * (A[e] + B[e]);
+  }
+  // H = sum_c a^c lambda^c / 2 (Gell-Mann), Hermitian traceless
+  const double r3 = 0.57735026918962576451;   // 1 / sqrt(3)
+  double hre[9], him[9];
+  hre[0] = 0.5 * (a[2] + r3 * a[7]);
+  hre[4] = 0.5 * (-a[2] + r3 * a[7]);
+  hre[8] = -r3 * a[7];
+  him[0] = him[4] = him[8] = 0.0;
+  hre[1] = 0.5 * a[0]; him[1] = -0.5 * a[1];
+  hre[2] = 0.5 * a[3]; him[2] = -0.5 * a[4];
+  hre[5] = 0.5 * a[5]; him[5] = -0.5 * a[6];
+  hre[3] = hre[1]; him[3] = -him[1];
+  hre[6] = hre[2]; him[6] = -him[2];
+  hre[7] = hre[5]; him[7] = -him[5];
+  double nrm2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) nrm2 += hre[k] * hre[k] + him[k] * him[k];
+  double nrm = sqrt(nrm2), scale = 1.0;
+  int q = 0;
+  while (nrm > 0.25 && q < 64) {   // false for NaN: a NaN momentum gives a NaN link
+    nrm *= 0.5;
+    scale *= 0.5;
+    ++q;
+  }
+  // Y = i H * scale
+  Cm3 Y, E, T;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    Y.re[k] = -him[k] * scale;
+    Y.im[k] = hre[k] * scale;
+  }
+  // E = I + Y/1 (I + Y/2 (I + ... (I + Y/12)))
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    E.re[k] = (k % 4 == 0) ? 1.0 : 0.0;
+    E.im[k] = 0.0;
+  }
+#pragma unroll 1
+  for (int m = 12; m >= 1; --m) {
+    cm3_mul(Y, E, T);
+    const double w = 1.0 / (double)m;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      E.re[k] = ((k % 4 == 0) ? 1.0 : 0.0) + w * T.re[k];
+      E.im[k] = w * T.im[k];
+    }
+  }
+#pragma unroll 1
+  for (int i = 0; i < q; ++i) {
+    cm3_mul(E, E, T);
+    E = T;
+  }
+  Cm3 u;
+  const double* um = U0 + (int64_t)mu * 18 * V + s;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    u.re[k] = um[(int64_t)(2 * k) * V];
+    u.im[k] = um[(int64_t)(2 * k + 1) * V];
+  }
+  cm3_mul(E, u, T);
+  double* uo = U1 + (int64_t)mu * 18 * V + s;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    uo[(int64_t)(2 * k) * V] = T.re[k];
+    uo[(int64_t)(2 * k + 1) * V] = T.im[k];
+  }
+}
+
+hipError_t launch_link_exp(const Geom& g, const double* U0, const double* A, const double* B, double h, double* U1,
+                           hipStream_t s) {
+  dim3 grid((unsigned)((g.V + kBlock - 1) / kBlock), 4);
+  hipLaunchKernelGGL(k_link_exp, grid, dim3(kBlock), 0, s, g, U0, A, B, h, U1);
+  return hipGetLastError();
+}
+
+__global__ void k_axpy_diff(const double* x, const double* __restrict__ y, const double* __restrict__ z, double h,
+                            double* out, int64_t n, int32_t steps, double* __restrict__ partials) {
+  double d[2] = {0.0, 0.0};
+  for (int32_t t = 0; t < steps; ++t) {
+    const int64_t i0 = (((int64_t)blockIdx.x * steps + t) * blockDim.x + threadIdx.x) * 4;
+    if (i0 < n) {
+      double xv[4], yv[4], zv[4], ov[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        xv[k] = x[i0 + k];
+        yv[k] = y[i0 + k];
+        zv[k] = z[i0 + k];
+        ov[k] = out[i0 + k];
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double o = fma(h, yv[k] - zv[k], xv[k]);
+        const double e = o - ov[k];
+        out[i0 + k] = o;
+        d[0] = fma(e, e, d[0]);
+        d[1] = fma(o, o, d[1]);
+      }
+    }
+  }
+  __shared__ double lds[2][16];
+  block_sum<2>(d, lds);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = d[0];
+    partials[gridDim.x + blockIdx.x] = d[1];
+  }
+}
+
+hipError_t launch_axpy_diff(const double* x, const double* y, const double* z, double h, double* out, int64_t n,
+                            double* partials, hipStream_t s) {
+  if (n % 4) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_axpy_diff, dim3(red_num_blocks(n)), dim3(kBlock), 0, s, x, y, z, h, out, n, red_steps(n),
+                     partials);
+  return hipGetLastError();
+}
+
 }  // namespace rmh

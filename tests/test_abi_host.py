@@ -219,3 +219,32 @@ def test_tune_set_validation():
     for form, block, xcd, nv, order, walk in bad:
         assert f(L, 0, 1, form, block, xcd, nv, order, walk) == 1, (form, block, nv, order, walk)   # RMH_E_ARG
     assert _lib.lib().rmh_tune_clear() == 0
+
+
+def test_leapfrog_validation():
+    """rmh_leapfrog_step rejects bad controls, a short workspace and aliased buffers before any
+    device work."""
+    Lt = (2, 2, 2, 2)
+    L = _lib.lattice_arg(Lt)
+    r = np.array([1.0, 2.0])
+    sg = np.array([0.5, 1.0])
+    rat = _lib.RmhRational(0.0, 2, r.ctypes.data_as(_lib.P_f64), sg.ctypes.data_as(_lib.P_f64))
+    sv = _lib.RmhSolver(1e-10, 100, 0, 0.1, 8, 0.0, 0)
+    f = _lib.lib().rmh_leapfrog_step
+    need = _lib.lib().rmh_workspace_bytes(_lib.OP_LEAPFROG, L, 0, 1, 2, 0, 0)
+    assert need > _lib.lib().rmh_workspace_bytes(_lib.OP_KINETIC_FORCE, L, 0, 1, 2, 0, 0)
+    U0, P0, U1, P1, WS = FAKE, FAKE + 2**20, FAKE + 2**21, FAKE + 2**22, FAKE + 2**23
+
+    def call(lf, u1=U1, p1=P1, ws_bytes=1 << 30):
+        return f(L, U0, P0, ctypes.byref(rat), ctypes.byref(sv), ctypes.byref(lf) if lf is not None else None,
+                 u1, p1, None, WS, ws_bytes, None)
+
+    ok = _lib.RmhLeapfrog(0.1, 5.0, 1e-12, 20)
+    assert call(None) == 1
+    assert call(_lib.RmhLeapfrog(float("inf"), 5.0, 1e-12, 20)) == 1
+    assert call(_lib.RmhLeapfrog(0.1, float("nan"), 1e-12, 20)) == 1
+    assert call(_lib.RmhLeapfrog(0.1, 5.0, 0.0, 20)) == 1
+    assert call(_lib.RmhLeapfrog(0.1, 5.0, 1e-12, 0)) == 1
+    assert call(ok, ws_bytes=need - 8) == 3                      # workspace too small
+    assert call(ok, u1=U0) == 1                                  # U1 aliases U0
+    assert call(ok, p1=P0 + 64) == 1                             # P1 overlaps P0

@@ -76,7 +76,7 @@ def test_laplacian_reads_rows_0_and_1_only(dtype):
     x = Pd.to(dtype)
     bad = U2.clone()
     bad[:, 12:18, :] = float("nan")
-    shapes = [(0, 128, 4, 0, 0), (1, 256, 1, 0, 0), (2, 64, 2, L[3], 0), (2, 256, 4, 0, 2), (1, 128, 2, 0, 3)]
+    shapes = [(0, 128, 4, 0, 0), (1, 256, 1, 0, 0), (2, 128, 2, L[3], 0), (2, 256, 4, 0, 2), (1, 128, 2, 0, 3)]
     for form, block, nv, walk, order in shapes:
         api.tune_set(L, dtype, 2, form, block, 1, nv, order, walk)
         a = api.laplacian_apply(L, U2, x)
