@@ -101,7 +101,9 @@ typedef struct {
  * check_every: iterations between host convergence checks (0 = 8).  basis: iterations per
  * segment of the shift solutions (0 = 16, at most 32): the shifts other than the seed are
  * carried as coefficients over the stored seed residuals of a segment and folded into their
- * FP64 vectors once per segment, so the workspace holds basis + 1 extra link fields per source. */
+ * FP64 vectors once per segment, so the workspace holds basis + 1 extra link fields per source
+ * (mode 1: plus min(2 (basis + 1), 33) FP32 residuals, where the FP32 phase, and the segment open
+ * at the switch of precision, go on). */
 typedef struct {
   double tol;
   int32_t maxiter;
