@@ -342,10 +342,12 @@ typedef struct {
  *   P_h = P + h F(U, P_h)                               (fixed point, from P_h = P),
  *   U'  = exp(i h (Pi(U, P_h) + Pi(U', P_h))^a T^a) U   (fixed point, from Pi(U') = Pi(U)),
  *   P'  = P_h + h F(U', P_h).
- * A fixed point stops when successive iterates (P_h, then Pi(U', P_h)) differ by at most fp_tol
- * relative to the newer one; after fp_maxiter iterations the step goes on with the last iterate
- * and returns RMH_E_NOCONV.  Every solve runs to solver->tol.  The step is time reversible:
- * from (U', -P') it returns to (U, -P) up to the tolerances.
+ * A fixed point keeps the first iterate whose successor differs from it by at most fp_tol relative
+ * to the successor (stage 1: P_h; stage 2: U', comparing Pi(U', P_h) with the Pi that built U'), so
+ * the solves of the kept iterate serve the next stage: 2 (n_1 + n_2) multi-shift solves for n_1, n_2
+ * iterations.  After fp_maxiter iterations the step goes on with the last iterate and returns
+ * RMH_E_NOCONV.  Every solve runs to solver->tol.  The step is time reversible: from (U', -P') it
+ * returns to (U, -P) up to the tolerances.
  * U0, U1: device FP64 SoA links (distinct buffers); P0, P1: device FP64 [4][8][V] (distinct).
  * Workspace: RMH_OP_LEAPFROG (n_rhs = 1, aux = n_poles, degree = solver basis, mode).
  * stats: optional host.  Synchronizes the stream. */

@@ -1889,10 +1889,27 @@ static rmh_status lf_velocity(LeapfrogPlan& lp, const Geom& g, const double* U, 
   return RMH_OK;
 }
 
-// out = x + h (y - z); returns |out_new - out_old| and |out_new|
+// -dK/d omega weights of the pole pairs at the solves held in lp.rp (X of P, Z of Y = R(Delta) P)
+static rmh_status lf_force_from_held(LeapfrogPlan& lp, const Geom& g, const double* U, const rmh_rational* rat,
+                                     hipStream_t s) {
+  ForceArgs fa{};
+  for (int j = 0; j < rat->n_poles; ++j) fa.w[j] = -rat->r[j];
+  fa.g = g;
+  fa.U = U;
+  fa.A = lp.rp.Z;
+  fa.B = lp.rp.X;
+  fa.n_rhs = 1;
+  fa.n_pair = rat->n_poles;
+  fa.grad = lp.dK;
+  ProfScope ps(RMH_PROF_FORCE, (double)g.V * 8.0 * (72.0 + 64.0 * rat->n_poles + 32.0), s, 1.0);
+  HIP_TRY(launch_force(fa, s));
+  return RMH_OK;
+}
+
+// out = x + h (y - z); returns |out - prev| and |out|
 static rmh_status lf_update(LeapfrogPlan& lp, const double* x, const double* y, const double* z, double h,
-                            double* out, int64_t n, hipStream_t s, double* diff, double* norm) {
-  HIP_TRY(launch_axpy_diff(x, y, z, h, out, n, lp.part, s));
+                            const double* prev, double* out, int64_t n, hipStream_t s, double* diff, double* norm) {
+  HIP_TRY(launch_axpy_diff(x, y, z, h, prev, out, n, lp.part, s));
   if (!diff) return RMH_OK;
   HIP_TRY(launch_reduce_rows(lp.part, red_num_blocks(n), 2, lp.sums, s));
   double hs[2];
@@ -1935,42 +1952,49 @@ rmh_status rmh_leapfrog_step(const int32_t L[4], const double* U0, const double*
   const double h = 0.5 * lf->eps, tol = lf->fp_tol;
   std::vector<SolveResult> res;
   bool noconv = false;
+  // Each fixed point keeps the first iterate whose successor changes it by at most tol: the solves
+  // of the kept iterate are then the ones in the workspace, and the next stage starts from them.
   // (i) P_h = P0 + h F(U0, P_h), F = F_G - dK/d omega, from P_h = P0
   HIP_TRY(launch_gauge_force(g, U0, lf->beta, lp.Fg, nullptr, s));
   HIP_TRY(hipMemcpyAsync(lp.Ph, P0, fb, hipMemcpyDeviceToDevice, s));
+  double* ph = lp.Ph;    // current iterate
+  double* pn = lp.PiB;   // its successor (PiB is free until stage ii)
   int32_t ip = 0;
   double dp = 0.0, np_ = 0.0;
   while (true) {
     ++ip;
-    RMH_TRY(lf_kinetic_grad(lp, g, U0, lp.Ph, rat, solver, s, res));
-    RMH_TRY(lf_update(lp, P0, lp.Fg, lp.dK, h, lp.Ph, n, s, &dp, &np_));
+    RMH_TRY(lf_kinetic_grad(lp, g, U0, ph, rat, solver, s, res));
+    RMH_TRY(lf_update(lp, P0, lp.Fg, lp.dK, h, ph, pn, n, s, &dp, &np_));
     if (dp <= tol * np_) break;
     if (ip >= lf->fp_maxiter || !(dp == dp)) {
       noconv = true;
       break;
     }
+    std::swap(ph, pn);
   }
-  // (ii) U1 = exp(i h (Pi(U0, P_h) + Pi(U1, P_h))) U0, from Pi(U1) = Pi(U0)
-  RMH_TRY(lf_velocity(lp, g, U0, lp.Ph, lp.Pi0, rat, solver, s, res));
-  HIP_TRY(launch_link_exp(g, U0, lp.Pi0, lp.Pi0, h, U1, s));
-  HIP_TRY(hipMemcpyAsync(lp.PiB, lp.Pi0, fb, hipMemcpyDeviceToDevice, s));
+  // (ii) U1 = exp(i h (Pi(U0, P_h) + Pi(U1, P_h))) U0, from Pi(U1) = Pi(U0).  Pi(U0, P_h) =
+  // R(Delta) Y from the held solves of P_h (X) and of Y = R(Delta) P_h (Z).
+  HIP_TRY(launch_rational_combine(lp.rp.Y, lp.rp.Z, 1, np, lp.rp.coef, lp.Pi0, n, nullptr, s));
+  double* pib = pn;   // the Pi that U1 was built from (in the buffer ph does not use)
+  HIP_TRY(hipMemcpyAsync(pib, lp.Pi0, fb, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(launch_link_exp(g, U0, lp.Pi0, pib, h, U1, s));
   int32_t iu = 0;
   double du = 0.0, nu = 0.0;
   while (true) {
     ++iu;
-    RMH_TRY(lf_velocity(lp, g, U1, lp.Ph, lp.PiA, rat, solver, s, res));
-    RMH_TRY(lf_update(lp, lp.PiA, lp.PiA, lp.PiA, 0.0, lp.PiB, n, s, &du, &nu));   // PiB = PiA, change
-    HIP_TRY(launch_link_exp(g, U0, lp.Pi0, lp.PiA, h, U1, s));
+    RMH_TRY(lf_velocity(lp, g, U1, ph, lp.PiA, rat, solver, s, res));
+    RMH_TRY(lf_update(lp, lp.PiA, lp.PiA, lp.PiA, 0.0, pib, pib, n, s, &du, &nu));   // change; pib = PiA
     if (du <= tol * nu) break;
     if (iu >= lf->fp_maxiter || !(du == du)) {
       noconv = true;
       break;
     }
+    HIP_TRY(launch_link_exp(g, U0, lp.Pi0, lp.PiA, h, U1, s));
   }
-  // (iii) P1 = P_h + h F(U1, P_h)
+  // (iii) P1 = P_h + h F(U1, P_h), the kinetic part from the solves at the kept U1
   HIP_TRY(launch_gauge_force(g, U1, lf->beta, lp.Fg, nullptr, s));
-  RMH_TRY(lf_kinetic_grad(lp, g, U1, lp.Ph, rat, solver, s, res));
-  RMH_TRY(lf_update(lp, lp.Ph, lp.Fg, lp.dK, h, P1, n, s, nullptr, nullptr));
+  RMH_TRY(lf_force_from_held(lp, g, U1, rat, s));
+  RMH_TRY(lf_update(lp, ph, lp.Fg, lp.dK, h, P1, P1, n, s, nullptr, nullptr));
   HIP_TRY(hipStreamSynchronize(s));
   if (stats) {
     memset(stats, 0, sizeof(*stats));

@@ -240,11 +240,11 @@ hipError_t launch_gauge_force(const Geom& g, const double* U, double beta, doubl
 // (FP64 SoA links, A and B FP64 [4][8][V]; U1 must not overlap U0)
 hipError_t launch_link_exp(const Geom& g, const double* U0, const double* A, const double* B, double h, double* U1,
                            hipStream_t s);
-// out_new = x + h (y - z) over n reals (FP64; out may alias x), with per-block partials of
-// |out_new - out_old|^2 and |out_new|^2 written to partials[0][nblk], partials[1][nblk],
-// nblk = red_num_blocks(n)
-hipError_t launch_axpy_diff(const double* x, const double* y, const double* z, double h, double* out, int64_t n,
-                            double* partials, hipStream_t s);
+// out = x + h (y - z) over n reals (FP64), with per-block partials of |out - prev|^2 and |out|^2
+// written to partials[0][nblk], partials[1][nblk], nblk = red_num_blocks(n); prev may be out itself
+// (each element is read before it is written, by the same thread)
+hipError_t launch_axpy_diff(const double* x, const double* y, const double* z, double h, const double* prev,
+                            double* out, int64_t n, double* partials, hipStream_t s);
 
 // Chebyshev filter fold over a ring of R recursion vectors of n elements each (t_k in slot k % R):
 //   y_w = (first ? coef[w][0] x : y_w) + sum_{j < cnt} coef[w][k0 + j] t_{k0 + j},   w < nw,

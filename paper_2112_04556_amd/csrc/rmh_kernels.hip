@@ -1473,7 +1473,8 @@ hipError_t launch_link_exp(const Geom& g, const double* U0, const double* A, con
 }
 
 __global__ void k_axpy_diff(const double* x, const double* __restrict__ y, const double* __restrict__ z, double h,
-                            double* out, int64_t n, int32_t steps, double* __restrict__ partials) {
+                            const double* prev, double* out, int64_t n, int32_t steps,
+                            double* __restrict__ partials) {
   double d[2] = {0.0, 0.0};
   for (int32_t t = 0; t < steps; ++t) {
     const int64_t i0 = (((int64_t)blockIdx.x * steps + t) * blockDim.x + threadIdx.x) * 4;
@@ -1484,7 +1485,7 @@ __global__ void k_axpy_diff(const double* x, const double* __restrict__ y, const
         xv[k] = x[i0 + k];
         yv[k] = y[i0 + k];
         zv[k] = z[i0 + k];
-        ov[k] = out[i0 + k];
+        ov[k] = prev[i0 + k];
       }
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
@@ -1504,11 +1505,11 @@ __global__ void k_axpy_diff(const double* x, const double* __restrict__ y, const
   }
 }
 
-hipError_t launch_axpy_diff(const double* x, const double* y, const double* z, double h, double* out, int64_t n,
-                            double* partials, hipStream_t s) {
+hipError_t launch_axpy_diff(const double* x, const double* y, const double* z, double h, const double* prev,
+                            double* out, int64_t n, double* partials, hipStream_t s) {
   if (n % 4) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_axpy_diff, dim3(red_num_blocks(n)), dim3(kBlock), 0, s, x, y, z, h, out, n, red_steps(n),
-                     partials);
+  hipLaunchKernelGGL(k_axpy_diff, dim3(red_num_blocks(n)), dim3(kBlock), 0, s, x, y, z, h, prev, out, n,
+                     red_steps(n), partials);
   return hipGetLastError();
 }
 
