@@ -419,6 +419,15 @@ __global__ void k_cg_beta(CgDev cg, int32_t mixed) {
   const int32_t m = fl[kFlM];
   const int32_t seed = cg.seed[v];
   const double rr_old = sc[kScRR], tolabs = sc[kScTolAbs];
+  // the scalars thread 0 updates after the shift pass, loaded now so that pass ends in no load
+  double alpha0 = 0.0, iters0 = 0.0, maxit0 = 0.0, maxr0 = 0.0, delta0 = 0.0;
+  if (tid == 0) {
+    alpha0 = sc[kScAlpha];
+    iters0 = sc[kScIters];
+    maxit0 = sc[kScMaxIter];
+    maxr0 = sc[kScMaxR];
+    delta0 = sc[kScDelta];
+  }
   int32_t act = 0;
   double z = 0.0, zn = 0.0;
   if (tid < ns) {
@@ -458,6 +467,7 @@ __global__ void k_cg_beta(CgDev cg, int32_t mixed) {
   const double rnorm = sqrt(rrn);
   __shared__ double s_cp[kMaxShifts], s_cr[kMaxShifts];
   __shared__ int s_upd[kMaxShifts];
+  __shared__ int s_seed_act, s_seed_keep;   // the seed's act and act_next, for thread 0
   int any_other = 0;
   // per shift: beta_j, the p coefficients, convergence
   if (tid < ns) {
@@ -474,28 +484,33 @@ __global__ void k_cg_beta(CgDev cg, int32_t mixed) {
       const int32_t keep = (fabs(zn) * rnorm > tolabs) ? 1 : 0;
       cg.act_next[vj] = keep;
       if (tid != seed) any_other |= keep;
+      if (tid == seed) s_seed_keep = keep;
       upd = (!(cg.seed_explicit && tid == seed) && cg.ring_on && keep && m + 1 < cg.nslot) ? 1 : 0;
       sh[kShZetaPrev] = z;
       sh[kShZeta] = zn;
     } else {
       cg.act_next[vj] = 0;
+      if (tid == seed) s_seed_keep = 0;
     }
+    if (tid == seed) s_seed_act = act;
     s_upd[tid] = upd;
   }
   any_other = __syncthreads_or(any_other);
   if (tid == 0) {
     const int64_t vs = (int64_t)v * ns + seed;
-    if (any_other && !cg.act_next[vs] && cg.act[vs]) {
+    int32_t seed_next = s_seed_keep;
+    if (any_other && !seed_next && s_seed_act) {
       // the seed carries the Krylov space for the others: its direction keeps being updated
-      cg.act_next[vs] = 1;
       if (cg.ring_on && !cg.seed_explicit && m + 1 < cg.nslot) s_upd[seed] = 1;
     }
-    if (any_other) cg.act_next[vs] = 1;
-    const int32_t any = any_other | cg.act_next[vs];
-    sc[kScAlphaPrev] = sc[kScAlpha];
+    if (any_other) seed_next = 1;
+    if (seed_next != s_seed_keep) cg.act_next[vs] = seed_next;
+    const int32_t any = any_other | seed_next;
+    const double iters = iters0 + 1.0;
+    sc[kScAlphaPrev] = alpha0;
     sc[kScBetaPrev] = beta;
     sc[kScRR] = rrn;
-    sc[kScIters] += 1.0;
+    sc[kScIters] = iters;
     fl[kFlRUMask] = 0;  // the residual update of this iteration has consumed it
     fl[kFlM] = m + 1;
     if (!(rrn == rrn)) {
@@ -503,13 +518,14 @@ __global__ void k_cg_beta(CgDev cg, int32_t mixed) {
       fl[kFlRun] = 0;
     } else if (!any) {
       fl[kFlRun] = 0;
-    } else if (sc[kScIters] >= sc[kScMaxIter]) {
+    } else if (iters >= maxit0) {
       fl[kFlStatus] = kStNoConv;
       fl[kFlRun] = 0;
     }
     if (mixed) {
-      if (rnorm > sc[kScMaxR]) sc[kScMaxR] = rnorm;
-      if (rnorm < sc[kScDelta] * sc[kScMaxR]) fl[kFlNeedRU] = 1;
+      const double maxr = rnorm > maxr0 ? rnorm : maxr0;
+      if (rnorm > maxr0) sc[kScMaxR] = rnorm;
+      if (rnorm < delta0 * maxr) fl[kFlNeedRU] = 1;
     }
   }
   __syncthreads();
