@@ -156,7 +156,7 @@ constexpr int32_t kAllFp64 = 1 << 30;
 enum : int { kScRR = 0, kScAlpha, kScAlphaPrev, kScBetaPrev, kScBnorm2, kScMaxR, kScTolAbs, kScIters,
              kScRU, kScDelta, kScMaxIter, kScN };
 // per (rhs, shift) slots; Seg: the shift was updated in the current segment
-enum : int { kShZeta = 0, kShZetaPrev, kShZetaNext, kShCx, kShCr, kShCp, kShUpd, kShSeg, kShN };
+enum : int { kShZeta = 0, kShZetaPrev, kShZetaNext, kShCx, kShCr, kShCp, kShSeg, kShN };
 // int flags per rhs
 // Run: the rhs still iterates (read by the stencil of the next iteration);
 // Live: the current iteration is being carried out (set by the alpha kernel), so the

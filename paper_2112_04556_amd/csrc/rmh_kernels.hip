@@ -257,7 +257,6 @@ __global__ void k_cg_init(CgDev cg, const double* bn2_part, int32_t nblk, const 
     sh[kShCx] = 0.0;
     sh[kShCr] = 0.0;
     sh[kShCp] = 0.0;
-    sh[kShUpd] = 0.0;
     sh[kShSeg] = 0.0;
     // x_j = 0, p_j = b = ring slot 0
     double* cf = cg.coef + vj * nc;
@@ -368,7 +367,6 @@ __global__ void k_cg_alpha(CgDev cg) {
       const double cx = alpha * zn / z;
       sh[kShZetaNext] = zn;
       sh[kShCx] = cx;
-      sh[kShUpd] += 1.0;
       upd = (cg.ring_on && m < cg.nslot && !(cg.seed_explicit && tid == seed)) ? 1 : 0;
       if (upd) sh[kShSeg] = 1.0;
       s_cx[tid] = cx;
