@@ -6,6 +6,9 @@ Workloads (run under ``rocprofv3``; each prints what it launched):
         a 1 GiB device-to-device copy (calibration: read and written bytes are known)
     python -m paper_2112_04556_amd.profiling stencil --L 32 32 32 64 --dtype f64 --reps 3
         the Laplacian on one link field, autotuned first, then ``reps`` timed launches
+    python -m paper_2112_04556_amd.profiling leapfrog --L 16 16 16 16 --reps 2
+        implicit leapfrog steps (12-pole kappa = 0.9 mass term, beta = 5.5, eps = 0.02) on one
+        momentum field, after one warm-up step
 
 Summaries (run on the host, over the CSV files rocprofv3 wrote):
 
@@ -119,6 +122,23 @@ def run_stencil(L, dtype_name: str, reps: int):
     print(f"stencil {L} {dtype_name}: config {cfg} (autotune {ms:.4f} ms), {reps} launches", flush=True)
 
 
+def run_leapfrog(L, reps: int):
+    import torch
+    from . import api, inputs
+    U = api.pack_links(L, inputs.random_links(L, "eps", 0.5, seed=8).to("cuda"))
+    P = inputs.gaussian_fields(L, 1, seed=8)[0].to("cuda")
+    rat = api.rational_kappa(0.9, 12)
+    sv = api.Solver(tol=1e-10)
+    ws = torch.empty(api.workspace_bytes(api.L_.OP_LEAPFROG, L, api.RMH_F64, 1, 12), dtype=torch.uint8,
+                     device="cuda")
+    st = None
+    for _ in range(reps + 1):
+        _, _, st = api.leapfrog_step(L, U, P, rat, 0.02, 5.5, sv, fp_tol=1e-10, ws=ws)
+    torch.cuda.synchronize()
+    print(f"leapfrog {L}: {reps + 1} steps, last {st['p_iters']} + {st['u_iters']} fixed-point iterations, "
+          f"{st['solver']['iters']} solver iterations", flush=True)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -127,6 +147,9 @@ def main(argv=None):
     p.add_argument("--L", type=int, nargs=4, default=[32, 32, 32, 64])
     p.add_argument("--dtype", choices=["f64", "f32"], default="f64")
     p.add_argument("--reps", type=int, default=3)
+    p = sub.add_parser("leapfrog")
+    p.add_argument("--L", type=int, nargs=4, default=[16, 16, 16, 16])
+    p.add_argument("--reps", type=int, default=2)
     p = sub.add_parser("summarize-trace")
     p.add_argument("dir")
     p.add_argument("--prefix", default="rmh::k_hop")
@@ -145,6 +168,8 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.cmd == "copy":
         run_copy()
+    elif a.cmd == "leapfrog":
+        run_leapfrog(tuple(a.L), a.reps)
     elif a.cmd == "stencil":
         run_stencil(tuple(a.L), a.dtype, a.reps)
     elif a.cmd == "summarize-trace":
