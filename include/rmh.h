@@ -99,9 +99,10 @@ typedef struct {
  * mixed_switch * ||x|| (0 = default 1e-4, negative = none), then FP32 stencil and vectors with
  * FP64 reliable updates of the seed residual (delta = reliable-update threshold, e.g. 0.1).
  * check_every: iterations between host convergence checks (0 = 8).  basis: iterations per
- * segment of the shift solutions (0 = 16, at most 32): the shifts other than the seed are
- * carried as coefficients over the stored seed residuals of a segment and folded into their
- * FP64 vectors once per segment, so the workspace holds basis + 1 extra link fields per source
+ * segment of the shift solutions (0 = 32 in mode 0, 16 in mode 1; at most 32): the shifts other
+ * than the seed are carried as coefficients over the stored seed residuals of a segment and
+ * folded into their FP64 vectors once per segment, so the workspace holds basis + 1 extra link
+ * fields per source
  * (mode 1: plus min(2 (basis + 1), 33) FP32 residuals, where the FP32 phase, and the segment open
  * at the switch of precision, go on). */
 typedef struct {

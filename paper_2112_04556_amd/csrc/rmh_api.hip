@@ -314,10 +314,12 @@ struct Engine {
 size_t rup(size_t b) { return ((b + 255) / 256) * 256; }
 
 // Residual ring length for a solver: basis iterations per segment + 1 (single-shift engines
-// keep only the current and the next residual).
-int32_t ring_slots(int32_t n_shift, int32_t basis) {
+// keep only the current and the next residual).  Default segments: 32 iterations in FP64 engines
+// (a solve of up to 32 iterations folds its shifts once), 16 in mixed ones (whose FP64 phase
+// ends near there; the open segment then goes on in the FP32 ring).
+int32_t ring_slots(int32_t n_shift, int32_t basis, int32_t mode) {
   if (n_shift <= 1) return 2;
-  const int32_t m = basis > 0 ? basis : 16;
+  const int32_t m = basis > 0 ? basis : (mode ? 16 : 32);
   return std::min<int32_t>(m, kMaxSlots - 1) + 1;
 }
 
@@ -327,7 +329,7 @@ void plan_engine(Carver& c, Engine& e, const Geom& g, int32_t n_rhs, int32_t n_s
   e.n_rhs = n_rhs;
   e.n_shift = n_shift;
   e.mode = mode;
-  e.nslot = ring_slots(n_shift, basis);
+  e.nslot = ring_slots(n_shift, basis, mode);
   e.nslot32 = std::min<int32_t>(2 * e.nslot, kMaxSlots);
   const int64_t n = field_reals(g);
   const size_t nr = n_rhs, np = (size_t)n_rhs * n_shift;

@@ -13,6 +13,8 @@ namespace rmh {
 
 constexpr int kBlock = 256;        // threads per block for site and element kernels
 constexpr int kRedBlock = 256;     // threads of the per-rhs scalar kernels
+constexpr int kCgBlock = 512;      // threads of the CG alpha and beta kernels: one (shift, coefficient)
+                                   // pair each for 12 shifts over segments of up to 40 iterations
 constexpr int kMaxFilterWindows = 64;
 constexpr int kMaxShifts = 64;      // poles of one rational (shifts of one multi-shift solve)
 

@@ -397,7 +397,7 @@ __global__ void k_cg_alpha(CgDev cg) {
 
 hipError_t launch_cg_alpha(const CgDev& cg, hipStream_t s) {
   if (cg.n_shift > kMaxShifts) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_cg_alpha, dim3(cg.n_rhs), dim3(kRedBlock), 0, s, cg);
+  hipLaunchKernelGGL(k_cg_alpha, dim3(cg.n_rhs), dim3(kCgBlock), 0, s, cg);
   return hipGetLastError();
 }
 
@@ -556,7 +556,7 @@ __global__ void k_cg_beta(CgDev cg, int32_t mixed) {
 
 hipError_t launch_cg_beta(const CgDev& cg, int32_t mixed, hipStream_t s) {
   if (cg.n_shift > kMaxShifts) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_cg_beta, dim3(cg.n_rhs), dim3(kRedBlock), 0, s, cg, mixed);
+  hipLaunchKernelGGL(k_cg_beta, dim3(cg.n_rhs), dim3(kCgBlock), 0, s, cg, mixed);
   return hipGetLastError();
 }
 
