@@ -65,7 +65,7 @@ def test_rational_apply_parity(mode, which):
 @pytest.mark.parametrize("mode", [0, 1])
 def test_rational_apply_segment_lengths(mode):
     """The shift solutions do not depend on how often the stored seed residuals are folded into
-    them: segments of 1, 3 and 32 iterations against the default, and every shift's true residual
+    them: segments of 1, 3, 16 and 32 iterations against the default, and every shift's true residual
     from the oracle."""
     L = (4, 4, 4, 6)
     announce(f"rational_apply segment lengths mode={mode}")
@@ -74,7 +74,7 @@ def test_rational_apply_segment_lengths(mode):
     tol = 1e-10
     ref = api.rational_apply(L, Ud, Pd, rat, api.Solver(tol=tol, mode=mode), want_poles=True)
     xr = ref["x_poles"].cpu().numpy()
-    for basis in (1, 3, 32):
+    for basis in (1, 3, 16, 32):
         out = api.rational_apply(L, Ud, Pd, rat, api.Solver(tol=tol, mode=mode, basis=basis), want_poles=True)
         xp = out["x_poles"].cpu().numpy()
         assert out["stats"]["iters"] == ref["stats"]["iters"]
