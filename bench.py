@@ -38,7 +38,10 @@ Extra fields (skipped with --no-extras):
   D8  one implicit leapfrog step of the non-separable Hamiltonian (kinetic term with the 12-pole
       kappa = 0.9 mass term plus the Wilson action, beta = 5.5, eps = 0.02) at 16^4: time,
       fixed-point iterations, solver iterations, the energy change of the step and the stencil
-      launches inside it.
+      launches inside it;
+  D9  RMHMC heat-bath momenta P = R(Delta)^-1 xi (12-pole kappa = 0.9 set) at 16^4 and their
+      projection onto 4 spectral windows (degree-32 filter), the input of the section-3 momentum
+      injection.
 """
 from __future__ import annotations
 
@@ -488,6 +491,22 @@ def d8_leapfrog(api, inputs, torch, dev):
     return out
 
 
+def d9_heatbath(api, inputs, torch, dev):
+    """Heat-bath momenta and their window projection at 16^4 (one Gaussian field)."""
+    L = (16, 16, 16, 16)
+    Ud = api.pack_links(L, inputs.random_links(L, "eps", 0.5, seed=9).to(dev))
+    xi = inputs.gaussian_fields(L, 1, seed=9).to(dev)
+    rat = api.rational_kappa(0.9, 12)
+    sv = api.Solver(tol=1e-10)
+    hb_ms, out = _median_ms(lambda: api.heatbath_momenta(L, Ud, xi, 0.9, rat, sv), torch)
+    P = out["P"]
+    f_ms, _ = _median_ms(lambda: api.cheb_filter(L, Ud, P, 32, 4), torch)
+    res = {"heatbath_ms": round(hb_ms, 3), "solver_iters": out["stats"]["iters"],
+           "true_relres_max": out["stats"]["true_relres_max"], "filter_ms": round(f_ms, 3)}
+    log(f"D9 heat-bath momenta + window projection 16^4: {res}")
+    return res
+
+
 def run_extras(api, inputs, torch, np, dev, L, U_aos, Ud, Pd):
     out = {}
     cp = copy_bandwidth(torch, dev)
@@ -501,6 +520,7 @@ def run_extras(api, inputs, torch, np, dev, L, U_aos, Ud, Pd):
     out["D6_power_spectrum_bwd_16x16x16x16"] = d6_spectrum_bwd(api, inputs, torch, np, dev)
     out["D7_gauge_force_spectrum"] = d7_gauge_force_spectrum(api, inputs, torch, dev)
     out["D8_leapfrog_step_16x16x16x16"] = d8_leapfrog(api, inputs, torch, dev)
+    out["D9_heatbath_projection_16x16x16x16"] = d9_heatbath(api, inputs, torch, dev)
     return out
 
 
