@@ -248,3 +248,25 @@ def test_leapfrog_validation():
     assert call(ok, ws_bytes=need - 8) == 3                      # workspace too small
     assert call(ok, u1=U0) == 1                                  # U1 aliases U0
     assert call(ok, p1=P0 + 64) == 1                             # P1 overlaps P0
+
+
+def test_product_path_does_not_use_the_oracle():
+    """Nothing in the package (Python binding, HIP and C++ sources) imports or reads the oracle;
+    bench.py touches it only in its CPU-baseline leg."""
+    import glob
+    import os
+    import re
+    root = os.path.join(os.path.dirname(os.path.abspath(__file__)), "..")
+    pkg = os.path.join(root, "paper_2112_04556_amd")
+    files = [f for ext in ("py", "hip", "h", "cpp") for f in glob.glob(os.path.join(pkg, "**", f"*.{ext}"), recursive=True)]
+    assert files
+    pat = re.compile(r"^\s*(from\s+oracle\b|import\s+oracle\b)|[\"']oracle/", re.M)
+    for f in files:
+        with open(f) as fh:
+            assert not pat.search(fh.read()), f
+    with open(os.path.join(root, "bench.py")) as fh:
+        src = fh.read()
+    uses = [m.start() for m in re.finditer(r"from oracle|import oracle", src)]
+    leg = src.index("def cpu_baseline")
+    end = src.index("\ndef ", leg + 1)
+    assert uses and all(leg < u < end for u in uses)
