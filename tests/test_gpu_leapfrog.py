@@ -93,3 +93,20 @@ def test_leapfrog_energy_error_8():
     ratio = abs(dH[0]) / abs(dH[1])
     assert ratio > 6.0, (dH, ratio)
     assert abs(dH[0]) < 1e-6 * abs(H0)
+
+
+def test_leapfrog_step_mixed_solver_vs_oracle():
+    """The step with mixed-precision solves (FP32 iterations, FP64 reliable updates, every shift to
+    an FP64 true residual of 1e-11) against the oracle's FP64 step: the solve tolerance moves forces
+    and velocities by about 1e-11 relative, so links agree to 1e-9 and momenta to 1e-8 max |P|."""
+    L = (4, 2, 2, 3)
+    announce("leapfrog parity, mixed-precision solves")
+    U, P, Ud, Pd = _state(L, 4)
+    c, r, s = rational.kappa_poles(0.5, 4)
+    r, s = np.asarray(r, np.float64), np.asarray(s, np.float64)
+    U1, P1, st = api.leapfrog_step(L, Ud, Pd, api.Rational(c, r, s), 0.1, 5.0, api.Solver(tol=1e-11, mode=1),
+                                   fp_tol=1e-12)
+    Uo, Po, _, _ = leapfrog.glf_step(U.numpy(), P.numpy(), L, c, r, s, 5.0, 0.1, fp_tol=1e-12)
+    assert np.abs(_links_complex(L, U1) - Uo).max() <= 1e-9
+    assert np.abs(P1.cpu().numpy() - Po).max() <= 1e-8 * np.abs(Po).max()
+    assert st["solver"]["true_relres_max"] <= 1e-11
