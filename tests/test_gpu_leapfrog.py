@@ -13,6 +13,7 @@ import torch
 from gpu_helpers import announce, dev
 from oracle import leapfrog, rational
 from paper_2112_04556_amd import api, inputs
+from paper_2112_04556_amd._lib import RmhError
 
 pytestmark = pytest.mark.gpu
 
@@ -110,3 +111,21 @@ def test_leapfrog_step_mixed_solver_vs_oracle():
     assert np.abs(_links_complex(L, U1) - Uo).max() <= 1e-9
     assert np.abs(P1.cpu().numpy() - Po).max() <= 1e-8 * np.abs(Po).max()
     assert st["solver"]["true_relres_max"] <= 1e-11
+
+
+def test_leapfrog_single_pole_and_noconv():
+    """A one-pole mass term (single-shift solves, no residual ring) against the oracle, and a fixed
+    point cut off after one iteration: RMH_E_NOCONV, raised after the step has run."""
+    L = (2, 2, 2, 4)
+    announce("leapfrog single pole, fixed-point limit")
+    U, P, Ud, Pd = _state(L, 9)
+    c, r, s = 0.5, np.array([1.5]), np.array([2.0])
+    U1, P1, st = api.leapfrog_step(L, Ud, Pd, api.Rational(c, r, s), 0.1, 5.0, api.Solver(tol=1e-12),
+                                   fp_tol=1e-12)
+    Uo, Po, ip, iu = leapfrog.glf_step(U.numpy(), P.numpy(), L, c, r, s, 5.0, 0.1, fp_tol=1e-12)
+    assert np.abs(_links_complex(L, U1) - Uo).max() <= 1e-10
+    assert np.abs(P1.cpu().numpy() - Po).max() <= 1e-9 * np.abs(Po).max()
+    with pytest.raises(RmhError) as ei:
+        api.leapfrog_step(L, Ud, Pd, api.Rational(c, r, s), 0.1, 5.0, api.Solver(tol=1e-12), fp_tol=1e-14,
+                          fp_maxiter=1)
+    assert ei.value.status == 5   # RMH_E_NOCONV
