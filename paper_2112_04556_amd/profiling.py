@@ -6,6 +6,9 @@ Workloads (run under ``rocprofv3``; each prints what it launched):
         a 1 GiB device-to-device copy (calibration: read and written bytes are known)
     python -m paper_2112_04556_amd.profiling stencil --L 32 32 32 64 --dtype f64 --reps 3
         the Laplacian on one link field, autotuned first, then ``reps`` timed launches
+    python -m paper_2112_04556_amd.profiling kinetic --L 32 32 32 64 --n 2 --poles 16 --mode 1 --reps 1
+        kinetic-force evaluations (kappa = 0.9 pole set, solves to 1e-10) of n momentum fields,
+        after one warm-up evaluation
     python -m paper_2112_04556_amd.profiling leapfrog --L 16 16 16 16 --reps 2
         implicit leapfrog steps (12-pole kappa = 0.9 mass term, beta = 5.5, eps = 0.02) on one
         momentum field, after one warm-up step
@@ -122,6 +125,23 @@ def run_stencil(L, dtype_name: str, reps: int):
     print(f"stencil {L} {dtype_name}: config {cfg} (autotune {ms:.4f} ms), {reps} launches", flush=True)
 
 
+def run_kinetic(L, n: int, poles: int, mode: int, reps: int):
+    import torch
+    from . import api, inputs
+    U = api.pack_links(L, inputs.random_links(L, "eps", 0.4, seed=5).to("cuda"))
+    P = inputs.gaussian_fields(L, n, seed=5).to("cuda")
+    rat = api.rational_kappa(0.9, poles)
+    sv = api.Solver(tol=1e-10, mode=mode)
+    ws = torch.empty(api.workspace_bytes(api.L_.OP_KINETIC_FORCE, L, api.RMH_F64, n, poles, 0, mode),
+                     dtype=torch.uint8, device="cuda")
+    out = None
+    for _ in range(reps + 1):
+        out = api.kinetic_force(L, U, P, rat, sv, per_rhs=True, ws=ws)
+    torch.cuda.synchronize()
+    print(f"kinetic {L} n={n} poles={poles} mode={mode}: {reps + 1} evaluations, "
+          f"{out['stats']['iters']} solver iterations", flush=True)
+
+
 def run_leapfrog(L, reps: int):
     import torch
     from . import api, inputs
@@ -147,6 +167,12 @@ def main(argv=None):
     p.add_argument("--L", type=int, nargs=4, default=[32, 32, 32, 64])
     p.add_argument("--dtype", choices=["f64", "f32"], default="f64")
     p.add_argument("--reps", type=int, default=3)
+    p = sub.add_parser("kinetic")
+    p.add_argument("--L", type=int, nargs=4, default=[32, 32, 32, 64])
+    p.add_argument("--n", type=int, default=2)
+    p.add_argument("--poles", type=int, default=16)
+    p.add_argument("--mode", type=int, default=1)
+    p.add_argument("--reps", type=int, default=1)
     p = sub.add_parser("leapfrog")
     p.add_argument("--L", type=int, nargs=4, default=[16, 16, 16, 16])
     p.add_argument("--reps", type=int, default=2)
@@ -168,6 +194,8 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.cmd == "copy":
         run_copy()
+    elif a.cmd == "kinetic":
+        run_kinetic(tuple(a.L), a.n, a.poles, a.mode, a.reps)
     elif a.cmd == "leapfrog":
         run_leapfrog(tuple(a.L), a.reps)
     elif a.cmd == "stencil":
