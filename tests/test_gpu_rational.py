@@ -116,6 +116,29 @@ def test_mixed_switch_points(switch, basis):
             assert res <= 1.01 * tol, (i, j, res)
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_rational_apply_single_pole(mode):
+    """One pole: the single-shift engine (no residual ring; the segment index grows with every
+    iteration, past the engine's 4 coefficient slots, in mixed mode through the FP32 ring as well)
+    against the oracle."""
+    L = (4, 4, 4, 6)
+    announce(f"rational_apply single pole mode={mode}")
+    U, P, Ud, Pd = setup(L, "eps", 0.6, 13, n=2)
+    c, r, s = 0.2, np.array([1.7]), np.array([0.05])   # a small shift: ~30 iterations
+    rat = api.Rational(c, r, s)
+    tol = 1e-10
+    out = api.rational_apply(L, Ud, Pd, rat, api.Solver(tol=tol, mode=mode), want_poles=True)
+    yref, _ = orat.rational_apply(U, P, L, c, r, s, tol=1e-13)
+    y = out["y"].cpu().numpy()
+    xp = out["x_poles"].cpu().numpy()
+    assert out["stats"]["iters"] > 16
+    for i in range(2):
+        bn = np.linalg.norm(P[i])
+        assert np.linalg.norm(y[i] - yref[i]) <= _y_bound(rat, tol, 1e-13, bn)
+        res = np.linalg.norm(P[i] - olap.laplacian(U, xp[i, 0], L, s[0])) / bn
+        assert res <= 1.01 * tol, (i, res)
+
+
 @pytest.mark.parametrize("kappa", [0.5, 0.9])
 @pytest.mark.parametrize("mode", [0, 1])
 def test_rational_apply_16_true_residuals(kappa, mode):
