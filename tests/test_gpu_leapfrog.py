@@ -129,3 +129,14 @@ def test_leapfrog_single_pole_and_noconv():
         api.leapfrog_step(L, Ud, Pd, api.Rational(c, r, s), 0.1, 5.0, api.Solver(tol=1e-12), fp_tol=1e-14,
                           fp_maxiter=1)
     assert ei.value.status == 5   # RMH_E_NOCONV
+
+
+def test_leapfrog_zero_step_is_identity():
+    """eps = 0: the exponential of a zero generator is the identity and every update adds h F = 0,
+    so the step returns its input bitwise."""
+    L = (4, 2, 2, 3)
+    announce("leapfrog eps = 0")
+    _, _, Ud, Pd = _state(L, 2)
+    U1, P1, st = api.leapfrog_step(L, Ud, Pd, api.rational_kappa(0.5, 4), 0.0, 5.0, api.Solver(tol=1e-10))
+    assert torch.equal(U1, Ud) and torch.equal(P1, Pd)
+    assert st["p_iters"] == 1 and st["u_iters"] == 1
