@@ -140,3 +140,29 @@ def test_leapfrog_zero_step_is_identity():
     U1, P1, st = api.leapfrog_step(L, Ud, Pd, api.rational_kappa(0.5, 4), 0.0, 5.0, api.Solver(tol=1e-10))
     assert torch.equal(U1, Ud) and torch.equal(P1, Pd)
     assert st["p_iters"] == 1 and st["u_iters"] == 1
+
+
+def test_leapfrog_trajectory_reversible_and_conserving_8():
+    """Five steps forward, momentum flipped, five steps back: the trajectory returns to its start,
+    and the energy change over the five steps (O(eps^2) along a trajectory, where one step's is
+    O(eps^3)) stays below 1e-6 of H."""
+    L = (8, 8, 8, 8)
+    announce("leapfrog trajectory 8^4")
+    _, _, Ud, Pd = _state(L, 7)
+    rat = api.rational_kappa(0.9, 12)
+    sv = api.Solver(tol=1e-12)
+    beta, eps = 5.5, 0.02
+    H0 = _hamiltonian(L, Ud, Pd, rat, beta, sv)
+    U, P = Ud, Pd
+    for _ in range(5):
+        U, P, _ = api.leapfrog_step(L, U, P, rat, eps, beta, sv, fp_tol=1e-12)
+    dH5 = _hamiltonian(L, U, P, rat, beta, sv) - H0
+    U1, P1, _ = api.leapfrog_step(L, Ud, Pd, rat, eps, beta, sv, fp_tol=1e-12)
+    dH1 = _hamiltonian(L, U1, P1, rat, beta, sv) - H0
+    announce(f"  dH after 1 and 5 steps: {dH1:.3e} {dH5:.3e}")
+    assert abs(dH1) < abs(dH5) < 1e-6 * abs(H0)
+    P = -P
+    for _ in range(5):
+        U, P, _ = api.leapfrog_step(L, U, P, rat, eps, beta, sv, fp_tol=1e-12)
+    assert (U - Ud).abs().max().item() <= 1e-8
+    assert (P + Pd).abs().max().item() <= 1e-8 * Pd.abs().max().item()
