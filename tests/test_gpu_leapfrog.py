@@ -166,3 +166,21 @@ def test_leapfrog_trajectory_reversible_and_conserving_8():
         U, P, _ = api.leapfrog_step(L, U, P, rat, eps, beta, sv, fp_tol=1e-12)
     assert (U - Ud).abs().max().item() <= 1e-8
     assert (P + Pd).abs().max().item() <= 1e-8 * Pd.abs().max().item()
+
+
+@pytest.mark.parametrize("eps", [1.5, 3.0])
+def test_leapfrog_large_generator_link_exponential(eps):
+    """A constant mass term with a large step: U' = exp(i eps P_h) U with generators of Frobenius
+    norm up to about 26, so the link exponential scales by 2^-q (q up to 7) and squares q times.
+    Against the oracle's step, whose exponential is scipy's Pade-based expm: links to 1e-12."""
+    L = (4, 2, 2, 3)
+    announce(f"leapfrog large generator eps={eps}")
+    U, P, Ud, Pd = _state(L, 11)
+    c, r, s = 1.0, np.array([0.0]), np.array([1.0])
+    U1, P1, st = api.leapfrog_step(L, Ud, Pd, api.Rational(c, r, s), eps, 5.0, api.Solver(tol=1e-12),
+                                   fp_tol=1e-12)
+    Uo, Po, _, _ = leapfrog.glf_step(U.numpy(), P.numpy(), L, c, r, s, 5.0, eps, fp_tol=1e-12)
+    Ug = _links_complex(L, U1)
+    assert np.abs(Ug - Uo).max() <= 1e-12
+    assert np.abs(P1.cpu().numpy() - Po).max() <= 1e-11 * np.abs(Po).max()
+    assert np.abs(Ug @ np.conj(np.swapaxes(Ug, -1, -2)) - np.eye(3)).max() <= 1e-13
