@@ -85,7 +85,8 @@ typedef struct {
 } rmh_cheb;
 
 /* R(Delta) = c + sum_j r_j (Delta + sigma_j)^{-1} (section 3, Eq. 6 in partial fractions,
- * Delta units).  r, sigma: host arrays of n_poles values, sigma_j > 0. */
+ * Delta units).  r, sigma: host arrays of n_poles values, sigma_j > 0; 1 <= n_poles <= 64
+ * (RMH_E_ARG outside). */
 typedef struct {
   double c;
   int32_t n_poles;

@@ -129,6 +129,13 @@ def test_validation_rational():
     st = _lib.lib().rmh_rational_apply(L, FAKE, FAKE + 2**20, 1, ctypes.byref(rat), ctypes.byref(sv_bad),
                                        FAKE + 2**21, None, None, None, FAKE + 2**22, 1 << 30, None)
     assert st == 1
+    # pole count outside [1, 64]
+    r65, s65 = np.ones(65), np.linspace(0.5, 10.0, 65)
+    for n in (0, 65):
+        rat_n = _lib.RmhRational(0.0, n, r65.ctypes.data_as(_lib.P_f64), s65.ctypes.data_as(_lib.P_f64))
+        st = _lib.lib().rmh_rational_apply(L, FAKE, FAKE + 2**20, 1, ctypes.byref(rat_n), ctypes.byref(sv),
+                                           FAKE + 2**21, None, None, None, FAKE + 2**22, 1 << 30, None)
+        assert st == 1, n                                                         # RMH_E_ARG
     # workspace too small
     st = _lib.lib().rmh_rational_apply(L, FAKE, FAKE + 2**20, 1, ctypes.byref(rat), ctypes.byref(sv),
                                        FAKE + 2**21, None, None, None, FAKE + 2**22, 1024, None)

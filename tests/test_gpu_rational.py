@@ -139,6 +139,32 @@ def test_rational_apply_single_pole(mode):
         assert res <= 1.01 * tol, (i, res)
 
 
+_MAX_POLES_REF = {}
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_rational_apply_max_poles(mode):
+    """The largest pole set the library takes, 64 shifts (sigma from 0.11 to 8.9e3), against the
+    oracle's per-shift solves, with every shift's FP64 true residual recomputed."""
+    L = (4, 4, 4, 4)
+    announce(f"rational_apply 64 poles mode={mode}")
+    U, P, Ud, Pd = setup(L, "eps", 0.5, 4, n=1)
+    rat = _rat_kappa(0.9, 64)
+    tol = 1e-10
+    out = api.rational_apply(L, Ud, Pd, rat, api.Solver(tol=tol, mode=mode), want_poles=True)
+    if "y" not in _MAX_POLES_REF:
+        _MAX_POLES_REF["y"] = orat.rational_apply(U, P, L, rat.c, rat.r, rat.sigma, tol=1e-13)[0]
+    yref = _MAX_POLES_REF["y"]
+    y = out["y"].cpu().numpy()
+    xp = out["x_poles"].cpu().numpy()
+    bn = np.linalg.norm(P[0])
+    assert np.linalg.norm(y[0] - yref[0]) <= _y_bound(rat, tol, 1e-13, bn)
+    for j, sj in enumerate(rat.sigma):
+        res = np.linalg.norm(P[0] - olap.laplacian(U, xp[0, j], L, sj)) / bn
+        assert res <= 1.01 * tol, (j, res)
+    assert out["stats"]["true_relres_max"] <= tol
+
+
 @pytest.mark.parametrize("kappa", [0.5, 0.9])
 @pytest.mark.parametrize("mode", [0, 1])
 def test_rational_apply_16_true_residuals(kappa, mode):
