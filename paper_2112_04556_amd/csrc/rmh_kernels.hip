@@ -1237,6 +1237,7 @@ template hipError_t launch_cheb_fold<float>(const float*, const float*, int32_t,
 
 hipError_t launch_force(const ForceArgs& a, hipStream_t s) {
   const int32_t n_out = a.per_rhs ? a.n_rhs : 1;
+  if (a.n_pair < 0 || a.n_pair > (int32_t)(sizeof(a.w) / sizeof(a.w[0]))) return hipErrorInvalidValue;
   if (n_out == 0) return hipSuccess;
   dim3 grid((a.g.V + 63) / 64, n_out);
   hipLaunchKernelGGL(k_force, grid, dim3(256), 0, s, a, 1);

@@ -207,6 +207,21 @@ def test_kinetic_force_vs_oracle(mode):
     assert np.allclose(out["K"], Kref, rtol=1e-8)
 
 
+def test_kinetic_force_max_poles_vs_oracle():
+    """The force with the largest pole set, 64 pairs in one force launch, against the oracle."""
+    L = (2, 2, 2, 4)
+    announce("kinetic_force 64 poles")
+    U, P, Ud, Pd = setup(L, "eps", 0.4, 6, n=1)
+    rat = _rat_kappa(0.9, 64)
+    tol = 1e-12
+    out = api.kinetic_force(L, Ud, Pd, rat, api.Solver(tol=tol), want_Y=True)
+    dK = out["dK"][0].cpu().numpy()
+    ref = oforce.kinetic_force_grad(U, P, L, rat.c, rat.r, rat.sigma, tol=1e-13)
+    bound = _force_bound(rat, tol, 1e-13, np.linalg.norm(P), np.linalg.norm(out["Y"].cpu().numpy()))
+    assert np.linalg.norm(dK - ref) <= bound
+    assert np.linalg.norm(ref) > 1e3 * bound
+
+
 def test_rational_apply_bwd_vs_oracle():
     L = (2, 2, 2, 4)
     announce("rational_apply_bwd")
