@@ -76,7 +76,8 @@ typedef enum { RMH_F64 = 0, RMH_F32 = 1 } rmh_dtype;
 /* Chebyshev bandpass windows (section 2): B_w(Delta) = sum_{k=0}^{degree} g_k c^w_k T_k(Delta/8 - 1),
  * c^w_k the Chebyshev coefficients of the indicator of window w, g_k the Jackson kernel
  * (kernel = 1) or 1 (kernel = 0).  edges: host, n_windows + 1 ascending values in [0, 16],
- * or NULL for n_windows equal windows. */
+ * or NULL for n_windows equal windows.  The device calls take 1 <= degree <= 100000 and
+ * 1 <= n_windows <= 4096 (64 for rmh_cheb_filter); RMH_E_ARG outside. */
 typedef struct {
   int32_t degree;
   int32_t n_windows;

@@ -1394,6 +1394,16 @@ rmh_status rmh_laplacian_apply_bwd(const int32_t L[4], const void* U, int32_t dt
   return RMH_OK;
 }
 
+// degree and window count, checked before any host buffer is sized by them
+static rmh_status check_cheb_dims(const rmh_cheb* cheb, int32_t min_degree, int32_t max_windows) {
+  if (!cheb) return fail(RMH_E_ARG, "cheb is NULL");
+  if (cheb->degree < min_degree || cheb->degree > kMaxChebDegree)
+    return fail(RMH_E_ARG, "degree = %d must be in [%d, %d]", cheb->degree, min_degree, kMaxChebDegree);
+  if (cheb->n_windows < 1 || cheb->n_windows > max_windows)
+    return fail(RMH_E_ARG, "n_windows = %d must be in [1, %d]", cheb->n_windows, max_windows);
+  return RMH_OK;
+}
+
 rmh_status rmh_cheb_coefficients(const rmh_cheb* cheb, double* coef) {
   if (!cheb || !coef) return fail(RMH_E_ARG, "cheb or coef is NULL");
   if (cheb->degree < 0 || cheb->n_windows < 1) return fail(RMH_E_ARG, "degree < 0 or n_windows < 1");
@@ -1406,6 +1416,7 @@ rmh_status rmh_cheb_coefficients(const rmh_cheb* cheb, double* coef) {
 rmh_status rmh_power_ratio(const rmh_cheb* cheb, const double* trace_moments, const double* power, int32_t n_rhs,
                            double* ratio) {
   if (!cheb || !trace_moments || !power || !ratio) return fail(RMH_E_ARG, "NULL argument");
+  RMH_TRY(check_cheb_dims(cheb, 0, kMaxSpectrumWindows));
   const int32_t D = cheb->degree, nw = cheb->n_windows;
   std::vector<double> coef((size_t)nw * (D + 1));
   RMH_TRY(rmh_cheb_coefficients(cheb, coef.data()));
@@ -1431,10 +1442,9 @@ rmh_status rmh_power_spectrum(const int32_t L[4], const void* U, int32_t dtype, 
   Geom g;
   RMH_TRY(make_geom(L, &g));
   RMH_TRY(check_dtype(dtype));
-  if (!cheb) return fail(RMH_E_ARG, "cheb is NULL");
+  RMH_TRY(check_cheb_dims(cheb, 1, kMaxSpectrumWindows));
   if (n_rhs < 0) return fail(RMH_E_ARG, "n_rhs < 0");
   const int32_t D = cheb->degree, nw = cheb->n_windows;
-  if (D < 1 || D > 100000) return fail(RMH_E_ARG, "degree = %d must be in [1, 100000]", D);
   std::vector<double> coef((size_t)nw * (D + 1));
   RMH_TRY(rmh_cheb_coefficients(cheb, coef.data()));
   if (n_rhs == 0) return RMH_OK;
@@ -1486,11 +1496,9 @@ rmh_status rmh_cheb_filter(const int32_t L[4], const void* U, int32_t dtype, con
   Geom g;
   RMH_TRY(make_geom(L, &g));
   RMH_TRY(check_dtype(dtype));
-  if (!cheb) return fail(RMH_E_ARG, "cheb is NULL");
+  RMH_TRY(check_cheb_dims(cheb, 1, kMaxFilterWindows));
   if (n_rhs < 0) return fail(RMH_E_ARG, "n_rhs < 0");
   const int32_t D = cheb->degree, nw = cheb->n_windows;
-  if (D < 1 || D > 100000) return fail(RMH_E_ARG, "degree = %d must be in [1, 100000]", D);
-  if (nw > kMaxFilterWindows) return fail(RMH_E_ARG, "n_windows = %d exceeds %d", nw, kMaxFilterWindows);
   std::vector<double> coef((size_t)nw * (D + 1));
   RMH_TRY(rmh_cheb_coefficients(cheb, coef.data()));
   if (n_rhs == 0) return RMH_OK;
@@ -1514,10 +1522,9 @@ static rmh_status cheb_bwd_common(const int32_t L[4], const double* U, const dou
                                   const rmh_cheb* cheb, const void* grad_x, const double* grad_omega, Geom* g,
                                   std::vector<double>* coef) {
   RMH_TRY(make_geom(L, g));
-  if (!cheb) return fail(RMH_E_ARG, "cheb is NULL");
+  RMH_TRY(check_cheb_dims(cheb, 1, kMaxSpectrumWindows));
   if (n_rhs < 0) return fail(RMH_E_ARG, "n_rhs < 0");
   const int32_t D = cheb->degree, nw = cheb->n_windows;
-  if (D < 1 || D > 100000) return fail(RMH_E_ARG, "degree = %d must be in [1, 100000]", D);
   coef->resize((size_t)nw * (D + 1));
   RMH_TRY(rmh_cheb_coefficients(cheb, coef->data()));
   if (!grad_x && !grad_omega) return fail(RMH_E_ARG, "neither grad_x nor grad_omega requested");

@@ -16,6 +16,8 @@ constexpr int kRedBlock = 256;     // threads of the per-rhs scalar kernels
 constexpr int kCgBlock = 512;      // threads of the CG alpha and beta kernels: one (shift, coefficient)
                                    // pair each for 12 shifts over segments of up to 40 iterations
 constexpr int kMaxFilterWindows = 64;
+constexpr int kMaxSpectrumWindows = 4096;   // windows of a power spectrum (host-side sums only)
+constexpr int kMaxChebDegree = 100000;
 constexpr int kMaxShifts = 64;      // poles of one rational (shifts of one multi-shift solve)
 
 // Stencil variants chosen by the tuner.

@@ -277,3 +277,36 @@ def test_product_path_does_not_use_the_oracle():
     leg = src.index("def cpu_baseline")
     end = src.index("\ndef ", leg + 1)
     assert uses and all(leg < u < end for u in uses)
+
+
+@pytest.mark.parametrize("nw", [0, -1, -7, 100000])
+def test_window_count_rejected_before_allocation(nw):
+    """A window count outside the range is an argument error in every Chebyshev call, caught before
+    any buffer is sized by it (a negative count must not become a huge allocation)."""
+    L = _lib.lattice_arg((4, 4, 4, 4))
+    ch = _lib.RmhCheb(8, nw, None, 1)
+    mom = np.zeros(9)
+    lib = _lib.lib()
+    assert lib.rmh_power_spectrum(L, FAKE, 0, FAKE + 2**20, 1, ctypes.byref(ch), None, None, FAKE + 2**22, 1 << 30,
+                                  None) == 1
+    assert lib.rmh_cheb_filter(L, FAKE, 0, FAKE + 2**20, 1, ctypes.byref(ch), FAKE + 2**21, FAKE + 2**22, 1 << 30,
+                               None) == 1
+    assert lib.rmh_cheb_filter_bwd(L, FAKE, FAKE + 2**20, FAKE + 2**21, 1, ctypes.byref(ch), FAKE + 2**23, None, 0,
+                                   FAKE + 2**22, 1 << 30, None) == 1
+    p = mom.ctypes.data_as(_lib.P_f64)
+    assert lib.rmh_power_ratio(ctypes.byref(ch), p, p, 1, p) == 1
+
+
+def test_degree_out_of_range_rejected():
+    L = _lib.lattice_arg((4, 4, 4, 4))
+    mom = np.zeros(4)
+    p = mom.ctypes.data_as(_lib.P_f64)
+    lib = _lib.lib()
+    for D in (-3, 100001):
+        ch = _lib.RmhCheb(D, 2, None, 1)
+        assert lib.rmh_power_spectrum(L, FAKE, 0, FAKE + 2**20, 1, ctypes.byref(ch), None, None, FAKE + 2**22,
+                                      1 << 30, None) == 1
+        assert lib.rmh_power_ratio(ctypes.byref(ch), p, p, 1, p) == 1
+    ch0 = _lib.RmhCheb(0, 2, None, 1)        # degree 0 is a valid host-side ratio (T_0 only)
+    mom[:] = 1.0
+    assert lib.rmh_power_ratio(ctypes.byref(ch0), p, p, 1, p) == 0
