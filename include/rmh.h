@@ -76,8 +76,8 @@ typedef enum { RMH_F64 = 0, RMH_F32 = 1 } rmh_dtype;
 /* Chebyshev bandpass windows (section 2): B_w(Delta) = sum_{k=0}^{degree} g_k c^w_k T_k(Delta/8 - 1),
  * c^w_k the Chebyshev coefficients of the indicator of window w, g_k the Jackson kernel
  * (kernel = 1) or 1 (kernel = 0).  edges: host, n_windows + 1 ascending values in [0, 16],
- * or NULL for n_windows equal windows.  The device calls take 1 <= degree <= 100000 and
- * 1 <= n_windows <= 4096 (64 for rmh_cheb_filter); RMH_E_ARG outside. */
+ * or NULL for n_windows equal windows.  degree <= 100000 and 1 <= n_windows <= 4096 (64 for
+ * rmh_cheb_filter); the device calls need degree >= 1; RMH_E_ARG outside. */
 typedef struct {
   int32_t degree;
   int32_t n_windows;
@@ -197,7 +197,8 @@ rmh_status rmh_laplacian_apply_bwd(const int32_t L[4], const void* U, int32_t dt
 /* ---------------------------------------------------------------------------------------- */
 /* Chebyshev bandpass filters and power spectra (section 2, Eq. 4) */
 
-/* Host: coef[w][k] = g_k c^w_k, n_windows x (degree + 1). */
+/* Host: coef[w][k] = g_k c^w_k, n_windows x (degree + 1); 0 <= degree <= 100000,
+ * 1 <= n_windows <= 4096 (RMH_E_ARG outside). */
 rmh_status rmh_cheb_coefficients(const rmh_cheb* cheb, double* coef);
 
 /* Moments mu[n][k] = <F_n, T_k(A) F_n>, A = Delta/8 - 1, k = 0..degree, summed over nu, and
@@ -216,7 +217,7 @@ rmh_status rmh_power_spectrum(const int32_t L[4], const void* U, int32_t dtype, 
 rmh_status rmh_power_ratio(const rmh_cheb* cheb, const double* trace_moments, const double* power,
                            int32_t n_rhs, double* ratio);
 
-/* Host: exact Tr T_k(A), k = 0..degree, over the link-field space (32 V) at U = 1, where the
+/* Host: exact Tr T_k(A), k = 0..degree (0 <= degree <= 100000), over the link-field space (32 V) at U = 1, where the
  * eigenvalues of Delta are 4 sum_mu sin^2(p_mu/2), p_mu = 2 pi n_mu / L_mu. */
 rmh_status rmh_trace_moments_free(const int32_t L[4], int32_t degree, double* trace_moments);
 

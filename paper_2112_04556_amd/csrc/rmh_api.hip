@@ -1406,7 +1406,7 @@ static rmh_status check_cheb_dims(const rmh_cheb* cheb, int32_t min_degree, int3
 
 rmh_status rmh_cheb_coefficients(const rmh_cheb* cheb, double* coef) {
   if (!cheb || !coef) return fail(RMH_E_ARG, "cheb or coef is NULL");
-  if (cheb->degree < 0 || cheb->n_windows < 1) return fail(RMH_E_ARG, "degree < 0 or n_windows < 1");
+  RMH_TRY(check_cheb_dims(cheb, 0, kMaxSpectrumWindows));
   if (cheb->kernel != 0 && cheb->kernel != 1) return fail(RMH_E_ARG, "kernel must be 0 or 1");
   if (cheb_window_coefficients(cheb->degree, cheb->n_windows, cheb->edges, cheb->kernel, coef) != 0)
     return fail(RMH_E_ARG, "window edges must ascend strictly within [0, 16]");
@@ -1431,7 +1431,8 @@ rmh_status rmh_power_ratio(const rmh_cheb* cheb, const double* trace_moments, co
 rmh_status rmh_trace_moments_free(const int32_t L[4], int32_t degree, double* trace_moments) {
   Geom g;
   RMH_TRY(make_geom(L, &g));
-  if (degree < 0 || !trace_moments) return fail(RMH_E_ARG, "degree < 0 or NULL output");
+  if (degree < 0 || degree > kMaxChebDegree || !trace_moments)
+    return fail(RMH_E_ARG, "degree = %d outside [0, %d] or NULL output", degree, kMaxChebDegree);
   trace_moments_free(L, degree, trace_moments);
   return RMH_OK;
 }

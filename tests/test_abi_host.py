@@ -307,6 +307,9 @@ def test_degree_out_of_range_rejected():
         assert lib.rmh_power_spectrum(L, FAKE, 0, FAKE + 2**20, 1, ctypes.byref(ch), None, None, FAKE + 2**22,
                                       1 << 30, None) == 1
         assert lib.rmh_power_ratio(ctypes.byref(ch), p, p, 1, p) == 1
+    ch = _lib.RmhCheb(2**31 - 1, 2, None, 1)
+    assert lib.rmh_cheb_coefficients(ctypes.byref(ch), p) == 1
+    assert lib.rmh_trace_moments_free(L, 2**31 - 1, p) == 1
     ch0 = _lib.RmhCheb(0, 2, None, 1)        # degree 0 is a valid host-side ratio (T_0 only)
     mom[:] = 1.0
     assert lib.rmh_power_ratio(ctypes.byref(ch0), p, p, 1, p) == 0
