@@ -313,3 +313,24 @@ def test_degree_out_of_range_rejected():
     ch0 = _lib.RmhCheb(0, 2, None, 1)        # degree 0 is a valid host-side ratio (T_0 only)
     mom[:] = 1.0
     assert lib.rmh_power_ratio(ctypes.byref(ch0), p, p, 1, p) == 0
+
+
+def test_empty_batch_is_a_no_op():
+    """n_rhs = 0 returns RMH_OK after argument checks, before any pointer is used or any GPU call
+    (the pointers here are never mapped)."""
+    L = _lib.lattice_arg((4, 4, 4, 4))
+    lib = _lib.lib()
+    r, s = np.array([1.0, 2.0]), np.array([0.5, 1.0])
+    rat = _lib.RmhRational(0.0, 2, r.ctypes.data_as(_lib.P_f64), s.ctypes.data_as(_lib.P_f64))
+    sv = _lib.RmhSolver(1e-10, 100, 0, 0.1, 8, 0.0, 0)
+    ch = _lib.RmhCheb(8, 2, None, 1)
+    st = _lib.RmhStats()
+    assert lib.rmh_laplacian_apply(L, FAKE, 0, FAKE + 2**20, FAKE + 2**21, 0, 0.0, None) == 0
+    assert lib.rmh_power_spectrum(L, FAKE, 0, FAKE + 2**20, 0, ctypes.byref(ch), None, None, FAKE + 2**22, 1 << 30,
+                                  None) == 0
+    assert lib.rmh_cheb_filter(L, FAKE, 0, FAKE + 2**20, 0, ctypes.byref(ch), FAKE + 2**21, FAKE + 2**22, 1 << 30,
+                               None) == 0
+    assert lib.rmh_rational_apply(L, FAKE, FAKE + 2**20, 0, ctypes.byref(rat), ctypes.byref(sv), FAKE + 2**21, None,
+                                  None, ctypes.byref(st), FAKE + 2**22, 1 << 30, None) == 0
+    assert lib.rmh_kinetic_force(L, FAKE, FAKE + 2**20, 0, ctypes.byref(rat), ctypes.byref(sv), None, None,
+                                 FAKE + 2**23, 0, ctypes.byref(st), FAKE + 2**22, 1 << 30, None) == 0
