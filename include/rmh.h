@@ -68,7 +68,8 @@ typedef enum {
   RMH_E_NOCONV = 5,        /* solver hit maxiter; outputs hold the last iterate */
   RMH_E_BREAKDOWN = 6,     /* non-finite or non-positive CG scalar (e.g. NaN source) */
   RMH_E_HIP = 7,           /* a HIP runtime call failed */
-  RMH_E_UNIMPLEMENTED = 8
+  RMH_E_UNIMPLEMENTED = 8,
+  RMH_E_HOST = 9           /* host-side failure (e.g. out of host memory); nothing is thrown */
 } rmh_status;
 
 typedef enum { RMH_F64 = 0, RMH_F32 = 1 } rmh_dtype;

@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "librmh.so")
 RMH_OK = 0
 STATUS_NAMES = {
     0: "RMH_OK", 1: "RMH_E_ARG", 2: "RMH_E_SHAPE", 3: "RMH_E_WORKSPACE", 4: "RMH_E_POLES",
-    5: "RMH_E_NOCONV", 6: "RMH_E_BREAKDOWN", 7: "RMH_E_HIP", 8: "RMH_E_UNIMPLEMENTED",
+    5: "RMH_E_NOCONV", 6: "RMH_E_BREAKDOWN", 7: "RMH_E_HIP", 8: "RMH_E_UNIMPLEMENTED", 9: "RMH_E_HOST",
 }
 
 RMH_F64, RMH_F32 = 0, 1

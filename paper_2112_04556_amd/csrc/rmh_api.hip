@@ -1188,7 +1188,7 @@ const char* rmh_last_error(void) { return g_err.c_str(); }
 int32_t rmh_version(void) { return 100; }
 
 size_t rmh_workspace_bytes(int32_t op, const int32_t L[4], int32_t dtype, int32_t n_rhs, int32_t aux,
-                           int32_t degree, int32_t mode) {
+                           int32_t degree, int32_t mode) try {
   Geom g;
   if (make_geom(L, &g) != RMH_OK) return 0;
   if (check_dtype(dtype) != RMH_OK) return 0;
@@ -1244,9 +1244,11 @@ size_t rmh_workspace_bytes(int32_t op, const int32_t L[4], int32_t dtype, int32_
       return 0;
   }
   return c.off;
+} catch (...) {   // no C++ exception crosses the C ABI
+  return 0;
 }
 
-rmh_status rmh_pack_links(const int32_t L[4], const double* U_aos, void* U_soa, int32_t dtype, rmh_stream stream) {
+rmh_status rmh_pack_links(const int32_t L[4], const double* U_aos, void* U_soa, int32_t dtype, rmh_stream stream) try {
   Geom g;
   RMH_TRY(make_geom(L, &g));
   RMH_TRY(check_dtype(dtype));
@@ -1256,9 +1258,11 @@ rmh_status rmh_pack_links(const int32_t L[4], const double* U_aos, void* U_soa, 
     return fail(RMH_E_ARG, "U_soa overlaps U_aos");
   HIP_TRY(launch_pack_links(g, U_aos, U_soa, dtype, (hipStream_t)stream));
   return RMH_OK;
+} catch (...) {   // no C++ exception crosses the C ABI
+  return fail(RMH_E_HOST, "host-side failure (out of host memory?)");
 }
 
-rmh_status rmh_unpack_links(const int32_t L[4], const double* U_soa, double* U_aos, rmh_stream stream) {
+rmh_status rmh_unpack_links(const int32_t L[4], const double* U_soa, double* U_aos, rmh_stream stream) try {
   Geom g;
   RMH_TRY(make_geom(L, &g));
   RMH_TRY(check_ptr(U_aos, "U_aos"));
@@ -1266,10 +1270,12 @@ rmh_status rmh_unpack_links(const int32_t L[4], const double* U_soa, double* U_a
   if (overlap(U_aos, (size_t)72 * g.V * 8, U_soa, (size_t)72 * g.V * 8)) return fail(RMH_E_ARG, "U_aos overlaps U_soa");
   HIP_TRY(launch_unpack_links(g, U_soa, U_aos, (hipStream_t)stream));
   return RMH_OK;
+} catch (...) {   // no C++ exception crosses the C ABI
+  return fail(RMH_E_HOST, "host-side failure (out of host memory?)");
 }
 
 rmh_status rmh_pack_fields(const int32_t L[4], int32_t n, const double* F_aos, void* F_soa, int32_t dtype,
-                           rmh_stream stream) {
+                           rmh_stream stream) try {
   Geom g;
   RMH_TRY(make_geom(L, &g));
   RMH_TRY(check_dtype(dtype));
@@ -1281,10 +1287,12 @@ rmh_status rmh_pack_fields(const int32_t L[4], int32_t n, const double* F_aos, v
     return fail(RMH_E_ARG, "F_soa overlaps F_aos");
   HIP_TRY(launch_fields_aos_to_soa(g, n, F_aos, F_soa, dtype, (hipStream_t)stream));
   return RMH_OK;
+} catch (...) {   // no C++ exception crosses the C ABI
+  return fail(RMH_E_HOST, "host-side failure (out of host memory?)");
 }
 
 rmh_status rmh_unpack_fields(const int32_t L[4], int32_t n, const void* F_soa, int32_t dtype, double* F_aos,
-                             rmh_stream stream) {
+                             rmh_stream stream) try {
   Geom g;
   RMH_TRY(make_geom(L, &g));
   RMH_TRY(check_dtype(dtype));
@@ -1296,9 +1304,11 @@ rmh_status rmh_unpack_fields(const int32_t L[4], int32_t n, const void* F_soa, i
     return fail(RMH_E_ARG, "F_aos overlaps F_soa");
   HIP_TRY(launch_fields_soa_to_aos(g, n, F_soa, dtype, F_aos, (hipStream_t)stream));
   return RMH_OK;
+} catch (...) {   // no C++ exception crosses the C ABI
+  return fail(RMH_E_HOST, "host-side failure (out of host memory?)");
 }
 
-rmh_status rmh_convert_f64_f32(const double* in, float* out, int64_t n, rmh_stream stream) {
+rmh_status rmh_convert_f64_f32(const double* in, float* out, int64_t n, rmh_stream stream) try {
   if (n < 0) return fail(RMH_E_ARG, "n < 0");
   if (n == 0) return RMH_OK;
   RMH_TRY(check_ptr(in, "in"));
@@ -1306,10 +1316,12 @@ rmh_status rmh_convert_f64_f32(const double* in, float* out, int64_t n, rmh_stre
   if (overlap(in, n * 8, out, n * 4)) return fail(RMH_E_ARG, "out overlaps in");
   HIP_TRY(launch_f64_to_f32(in, out, n, (hipStream_t)stream));
   return RMH_OK;
+} catch (...) {   // no C++ exception crosses the C ABI
+  return fail(RMH_E_HOST, "host-side failure (out of host memory?)");
 }
 
 rmh_status rmh_laplacian_apply(const int32_t L[4], const void* U, int32_t dtype, const void* x, void* y,
-                               int32_t n_rhs, double shift, rmh_stream stream) {
+                               int32_t n_rhs, double shift, rmh_stream stream) try {
   Geom g;
   RMH_TRY(make_geom(L, &g));
   RMH_TRY(check_dtype(dtype));
@@ -1352,11 +1364,13 @@ rmh_status rmh_laplacian_apply(const int32_t L[4], const void* U, int32_t dtype,
     HIP_TRY(launch_hop<float>(h, cfg, (hipStream_t)stream));
   }
   return RMH_OK;
+} catch (...) {   // no C++ exception crosses the C ABI
+  return fail(RMH_E_HOST, "host-side failure (out of host memory?)");
 }
 
 rmh_status rmh_laplacian_apply_bwd(const int32_t L[4], const void* U, int32_t dtype, const void* x, const void* g_,
                                    int32_t n_rhs, double shift, void* grad_x, double* grad_omega, int32_t per_rhs,
-                                   rmh_stream stream) {
+                                   rmh_stream stream) try {
   Geom g;
   RMH_TRY(make_geom(L, &g));
   RMH_TRY(check_dtype(dtype));
@@ -1392,6 +1406,8 @@ rmh_status rmh_laplacian_apply_bwd(const int32_t L[4], const void* U, int32_t dt
     HIP_TRY(launch_force(fa, (hipStream_t)stream));
   }
   return RMH_OK;
+} catch (...) {   // no C++ exception crosses the C ABI
+  return fail(RMH_E_HOST, "host-side failure (out of host memory?)");
 }
 
 // degree and window count, checked before any host buffer is sized by them
@@ -1404,17 +1420,19 @@ static rmh_status check_cheb_dims(const rmh_cheb* cheb, int32_t min_degree, int3
   return RMH_OK;
 }
 
-rmh_status rmh_cheb_coefficients(const rmh_cheb* cheb, double* coef) {
+rmh_status rmh_cheb_coefficients(const rmh_cheb* cheb, double* coef) try {
   if (!cheb || !coef) return fail(RMH_E_ARG, "cheb or coef is NULL");
   RMH_TRY(check_cheb_dims(cheb, 0, kMaxSpectrumWindows));
   if (cheb->kernel != 0 && cheb->kernel != 1) return fail(RMH_E_ARG, "kernel must be 0 or 1");
   if (cheb_window_coefficients(cheb->degree, cheb->n_windows, cheb->edges, cheb->kernel, coef) != 0)
     return fail(RMH_E_ARG, "window edges must ascend strictly within [0, 16]");
   return RMH_OK;
+} catch (...) {   // no C++ exception crosses the C ABI
+  return fail(RMH_E_HOST, "host-side failure (out of host memory?)");
 }
 
 rmh_status rmh_power_ratio(const rmh_cheb* cheb, const double* trace_moments, const double* power, int32_t n_rhs,
-                           double* ratio) {
+                           double* ratio) try {
   if (!cheb || !trace_moments || !power || !ratio) return fail(RMH_E_ARG, "NULL argument");
   RMH_TRY(check_cheb_dims(cheb, 0, kMaxSpectrumWindows));
   const int32_t D = cheb->degree, nw = cheb->n_windows;
@@ -1426,20 +1444,24 @@ rmh_status rmh_power_ratio(const rmh_cheb* cheb, const double* trace_moments, co
     for (int32_t n = 0; n < n_rhs; ++n) ratio[(size_t)n * nw + w] = power[(size_t)n * nw + w] / den;
   }
   return RMH_OK;
+} catch (...) {   // no C++ exception crosses the C ABI
+  return fail(RMH_E_HOST, "host-side failure (out of host memory?)");
 }
 
-rmh_status rmh_trace_moments_free(const int32_t L[4], int32_t degree, double* trace_moments) {
+rmh_status rmh_trace_moments_free(const int32_t L[4], int32_t degree, double* trace_moments) try {
   Geom g;
   RMH_TRY(make_geom(L, &g));
   if (degree < 0 || degree > kMaxChebDegree || !trace_moments)
     return fail(RMH_E_ARG, "degree = %d outside [0, %d] or NULL output", degree, kMaxChebDegree);
   trace_moments_free(L, degree, trace_moments);
   return RMH_OK;
+} catch (...) {   // no C++ exception crosses the C ABI
+  return fail(RMH_E_HOST, "host-side failure (out of host memory?)");
 }
 
 rmh_status rmh_power_spectrum(const int32_t L[4], const void* U, int32_t dtype, const void* F, int32_t n_rhs,
                               const rmh_cheb* cheb, double* moments, double* power, void* ws, size_t ws_bytes,
-                              rmh_stream stream) {
+                              rmh_stream stream) try {
   Geom g;
   RMH_TRY(make_geom(L, &g));
   RMH_TRY(check_dtype(dtype));
@@ -1490,10 +1512,12 @@ rmh_status rmh_power_spectrum(const int32_t L[4], const void* U, int32_t dtype, 
       }
   }
   return RMH_OK;
+} catch (...) {   // no C++ exception crosses the C ABI
+  return fail(RMH_E_HOST, "host-side failure (out of host memory?)");
 }
 
 rmh_status rmh_cheb_filter(const int32_t L[4], const void* U, int32_t dtype, const void* x, int32_t n_rhs,
-                           const rmh_cheb* cheb, void* y, void* ws, size_t ws_bytes, rmh_stream stream) {
+                           const rmh_cheb* cheb, void* y, void* ws, size_t ws_bytes, rmh_stream stream) try {
   Geom g;
   RMH_TRY(make_geom(L, &g));
   RMH_TRY(check_dtype(dtype));
@@ -1517,6 +1541,8 @@ rmh_status rmh_cheb_filter(const int32_t L[4], const void* U, int32_t dtype, con
   if (dtype == RMH_F64)
     return cheb_filter_t<double>(g, (const double*)U, (const double*)x, n_rhs, D, nw, coef, fp, (double*)y, s);
   return cheb_filter_t<float>(g, (const float*)U, (const float*)x, n_rhs, D, nw, coef, fp, (float*)y, s);
+} catch (...) {   // no C++ exception crosses the C ABI
+  return fail(RMH_E_HOST, "host-side failure (out of host memory?)");
 }
 
 static rmh_status cheb_bwd_common(const int32_t L[4], const double* U, const double* x, int32_t n_rhs,
@@ -1539,7 +1565,7 @@ static rmh_status cheb_bwd_common(const int32_t L[4], const double* U, const dou
 
 rmh_status rmh_cheb_filter_bwd(const int32_t L[4], const double* U, const double* x, const double* gy, int32_t n_rhs,
                                const rmh_cheb* cheb, double* grad_x, double* grad_omega, int32_t per_rhs, void* ws,
-                               size_t ws_bytes, rmh_stream stream) {
+                               size_t ws_bytes, rmh_stream stream) try {
   Geom g;
   std::vector<double> coef;
   RMH_TRY(cheb_bwd_common(L, U, x, n_rhs, cheb, grad_x, grad_omega, &g, &coef));
@@ -1565,11 +1591,13 @@ rmh_status rmh_cheb_filter_bwd(const int32_t L[4], const double* U, const double
     for (int32_t w = 0; w < nw; ++w)
       for (int32_t k = 0; k <= D; ++k) ch[((size_t)v * nw + w) * (D + 1) + k] = coef[(size_t)w * (D + 1) + k];
   return cheb_bwd(g, U, x, n_rhs, D, gy, nw, ch, p, grad_x, 1.0, grad_omega, per_rhs, (hipStream_t)stream);
+} catch (...) {   // no C++ exception crosses the C ABI
+  return fail(RMH_E_HOST, "host-side failure (out of host memory?)");
 }
 
 rmh_status rmh_power_spectrum_bwd(const int32_t L[4], const double* U, const double* F, int32_t n_rhs,
                                   const rmh_cheb* cheb, const double* gamma, double* grad_F, double* grad_omega,
-                                  int32_t per_rhs, void* ws, size_t ws_bytes, rmh_stream stream) {
+                                  int32_t per_rhs, void* ws, size_t ws_bytes, rmh_stream stream) try {
   Geom g;
   std::vector<double> coef;
   RMH_TRY(cheb_bwd_common(L, U, F, n_rhs, cheb, grad_F, grad_omega, &g, &coef));
@@ -1599,10 +1627,12 @@ rmh_status rmh_power_spectrum_bwd(const int32_t L[4], const double* U, const dou
         ch[(size_t)v * (D + 1) + k] += gamma[(size_t)v * nw + w] * coef[(size_t)w * (D + 1) + k];
   // F enters both slots of <F, p(A) F>: grad_F = tb_0 + p(A) F = 2 tb_0 (p(A) symmetric)
   return cheb_bwd(g, U, F, n_rhs, D, F, 1, ch, p, grad_F, 2.0, grad_omega, per_rhs, (hipStream_t)stream);
+} catch (...) {   // no C++ exception crosses the C ABI
+  return fail(RMH_E_HOST, "host-side failure (out of host memory?)");
 }
 
 rmh_status rmh_wilson_gauge_force(const int32_t L[4], const double* U, double beta, double* F, double* S, void* ws,
-                                  size_t ws_bytes, rmh_stream stream) {
+                                  size_t ws_bytes, rmh_stream stream) try {
   Geom g;
   RMH_TRY(make_geom(L, &g));
   if (!isfinite(beta)) return fail(RMH_E_ARG, "beta is not finite");
@@ -1633,20 +1663,26 @@ rmh_status rmh_wilson_gauge_force(const int32_t L[4], const double* U, double be
     *S = beta * (6.0 * g.V - tr / 12.0);
   }
   return RMH_OK;
+} catch (...) {   // no C++ exception crosses the C ABI
+  return fail(RMH_E_HOST, "host-side failure (out of host memory?)");
 }
 
 rmh_status rmh_rational_from_quadratics(int32_t n_terms, const double* a0, const double* a1, const double* b0,
-                                        const double* b1, double* r, double* sigma) {
+                                        const double* b1, double* r, double* sigma) try {
   if (n_terms < 1 || !a0 || !a1 || !b0 || !b1 || !r || !sigma) return fail(RMH_E_ARG, "bad arguments");
   if (rational_from_quadratics(n_terms, a0, a1, b0, b1, r, sigma) != 0)
     return fail(RMH_E_POLES, "a quadratic term has no two distinct real roots with positive shifts");
   return RMH_OK;
+} catch (...) {   // no C++ exception crosses the C ABI
+  return fail(RMH_E_HOST, "host-side failure (out of host memory?)");
 }
 
-rmh_status rmh_rational_kappa(double kappa, int32_t n, double* c, double* r, double* sigma) {
+rmh_status rmh_rational_kappa(double kappa, int32_t n, double* c, double* r, double* sigma) try {
   if (!c || !r || !sigma) return fail(RMH_E_ARG, "NULL output");
   if (rational_kappa(kappa, n, c, r, sigma) != 0) return fail(RMH_E_ARG, "need 0 < kappa < 1 and n >= 1");
   return RMH_OK;
+} catch (...) {   // no C++ exception crosses the C ABI
+  return fail(RMH_E_HOST, "host-side failure (out of host memory?)");
 }
 
 static rmh_status rational_common(const int32_t L[4], const double* U, int32_t n_rhs, const rmh_rational* rat,
@@ -1661,7 +1697,7 @@ static rmh_status rational_common(const int32_t L[4], const double* U, int32_t n
 
 rmh_status rmh_rational_apply(const int32_t L[4], const double* U, const double* x, int32_t n_rhs,
                               const rmh_rational* rat, const rmh_solver* solver, double* y, double* x_poles,
-                              double* K, rmh_stats* stats, void* ws, size_t ws_bytes, rmh_stream stream) {
+                              double* K, rmh_stats* stats, void* ws, size_t ws_bytes, rmh_stream stream) try {
   const double t0 = now_s();
   Geom g;
   RMH_TRY(rational_common(L, U, n_rhs, rat, solver, &g));
@@ -1702,11 +1738,13 @@ rmh_status rmh_rational_apply(const int32_t L[4], const double* U, const double*
   }
   fill_stats(stats, &res, 1, now_s() - t0);
   return status_of(res, "rational_apply");
+} catch (...) {   // no C++ exception crosses the C ABI
+  return fail(RMH_E_HOST, "host-side failure (out of host memory?)");
 }
 
 rmh_status rmh_heatbath_momenta(const int32_t L[4], const double* U, const double* xi, int32_t n_rhs, double kappa,
                                 const rmh_rational* rat, const rmh_solver* solver, double* P, rmh_stats* stats,
-                                void* ws, size_t ws_bytes, rmh_stream stream) {
+                                void* ws, size_t ws_bytes, rmh_stream stream) try {
   const double t0 = now_s();
   Geom g;
   RMH_TRY(rational_common(L, U, n_rhs, rat, solver, &g));
@@ -1753,6 +1791,8 @@ rmh_status rmh_heatbath_momenta(const int32_t L[4], const double* U, const doubl
   HIP_TRY(hipStreamSynchronize(s));
   fill_stats(stats, &res, 1, now_s() - t0);
   return status_of(res, "heatbath_momenta");
+} catch (...) {   // no C++ exception crosses the C ABI
+  return fail(RMH_E_HOST, "host-side failure (out of host memory?)");
 }
 
 // second solve (source g) and the force; X holds the pole solutions of the first solve
@@ -1786,7 +1826,7 @@ static rmh_status force_from_solves(RationalPlan& rp, const Geom& g, const doubl
 rmh_status rmh_rational_apply_bwd(const int32_t L[4], const double* U, const double* x, const double* g_,
                                   int32_t n_rhs, const rmh_rational* rat, const rmh_solver* solver, double* grad_x,
                                   double* grad_omega, int32_t per_rhs, rmh_stats* stats, void* ws, size_t ws_bytes,
-                                  rmh_stream stream) {
+                                  rmh_stream stream) try {
   const double t0 = now_s();
   Geom g;
   RMH_TRY(rational_common(L, U, n_rhs, rat, solver, &g));
@@ -1820,12 +1860,14 @@ rmh_status rmh_rational_apply_bwd(const int32_t L[4], const double* U, const dou
   fill_stats(stats, res, 2, now_s() - t0);
   RMH_TRY(status_of(res[0], "rational_apply_bwd (solve of x)"));
   return status_of(res[1], "rational_apply_bwd (solve of g)");
+} catch (...) {   // no C++ exception crosses the C ABI
+  return fail(RMH_E_HOST, "host-side failure (out of host memory?)");
 }
 
 rmh_status rmh_kinetic_force(const int32_t L[4], const double* U, const double* P, int32_t n_rhs,
                              const rmh_rational* rat, const rmh_solver* solver, double* Y, double* K,
                              double* dK_domega, int32_t per_rhs, rmh_stats* stats, void* ws, size_t ws_bytes,
-                             rmh_stream stream) {
+                             rmh_stream stream) try {
   const double t0 = now_s();
   Geom g;
   RMH_TRY(rational_common(L, U, n_rhs, rat, solver, &g));
@@ -1864,6 +1906,8 @@ rmh_status rmh_kinetic_force(const int32_t L[4], const double* U, const double* 
   fill_stats(stats, res, 2, now_s() - t0);
   RMH_TRY(status_of(res[0], "kinetic_force (solve of P)"));
   return status_of(res[1], "kinetic_force (solve of Y)");
+} catch (...) {   // no C++ exception crosses the C ABI
+  return fail(RMH_E_HOST, "host-side failure (out of host memory?)");
 }
 
 // dK/d omega at (U, P) into lp.dK: the kinetic force's two solves and its link derivative
@@ -1931,7 +1975,7 @@ static rmh_status lf_update(LeapfrogPlan& lp, const double* x, const double* y, 
 
 rmh_status rmh_leapfrog_step(const int32_t L[4], const double* U0, const double* P0, const rmh_rational* rat,
                              const rmh_solver* solver, const rmh_leapfrog* lf, double* U1, double* P1,
-                             rmh_leapfrog_stats* stats, void* ws, size_t ws_bytes, rmh_stream stream) {
+                             rmh_leapfrog_stats* stats, void* ws, size_t ws_bytes, rmh_stream stream) try {
   const double t0 = now_s();
   Geom g;
   RMH_TRY(rational_common(L, U0, 1, rat, solver, &g));
@@ -2019,10 +2063,12 @@ rmh_status rmh_leapfrog_step(const int32_t L[4], const double* U0, const double*
     return fail(RMH_E_NOCONV, "leapfrog_step: a fixed point did not reach fp_tol = %g in %d iterations (%d, %d)",
                 tol, lf->fp_maxiter, ip, iu);
   return RMH_OK;
+} catch (...) {   // no C++ exception crosses the C ABI
+  return fail(RMH_E_HOST, "host-side failure (out of host memory?)");
 }
 
 rmh_status rmh_tune_set(const int32_t L[4], int32_t dtype, int32_t n_rhs, int32_t form, int32_t block,
-                        int32_t xcd_remap, int32_t nv, int32_t order, int32_t walk) {
+                        int32_t xcd_remap, int32_t nv, int32_t order, int32_t walk) try {
   Geom g;
   RMH_TRY(make_geom(L, &g));
   RMH_TRY(check_dtype(dtype));
@@ -2042,15 +2088,19 @@ rmh_status rmh_tune_set(const int32_t L[4], int32_t dtype, int32_t n_rhs, int32_
   c.walk = walk;
   tune_store(g, dtype, n_rhs, c);
   return RMH_OK;
+} catch (...) {   // no C++ exception crosses the C ABI
+  return fail(RMH_E_HOST, "host-side failure (out of host memory?)");
 }
 
-rmh_status rmh_tune_clear(void) {
+rmh_status rmh_tune_clear(void) try {
   tune_clear();
   return RMH_OK;
+} catch (...) {   // no C++ exception crosses the C ABI
+  return fail(RMH_E_HOST, "host-side failure (out of host memory?)");
 }
 
 rmh_status rmh_autotune_laplacian(const int32_t L[4], const void* U, int32_t dtype, const void* x, void* y,
-                                  int32_t n_rhs, int32_t reps, int32_t* best, double* best_ms, rmh_stream stream) {
+                                  int32_t n_rhs, int32_t reps, int32_t* best, double* best_ms, rmh_stream stream) try {
   Geom g;
   RMH_TRY(make_geom(L, &g));
   RMH_TRY(check_dtype(dtype));
@@ -2128,9 +2178,11 @@ rmh_status rmh_autotune_laplacian(const int32_t L[4], const void* U, int32_t dty
   }
   if (best_ms) *best_ms = bt;
   return RMH_OK;
+} catch (...) {   // no C++ exception crosses the C ABI
+  return fail(RMH_E_HOST, "host-side failure (out of host memory?)");
 }
 
-rmh_status rmh_profile_enable(int32_t enable) {
+rmh_status rmh_profile_enable(int32_t enable) try {
   std::lock_guard<std::mutex> lk(g_prof.mu);
   prof_flush_locked();
   g_prof.on = enable != 0;
@@ -2141,10 +2193,12 @@ rmh_status rmh_profile_enable(int32_t enable) {
     g_prof.items[c] = 0.0;
   }
   return RMH_OK;
+} catch (...) {   // no C++ exception crosses the C ABI
+  return fail(RMH_E_HOST, "host-side failure (out of host memory?)");
 }
 
 rmh_status rmh_profile_read(int32_t cls, int64_t* launches, double* total_ms, double* total_bytes,
-                            double* total_items) {
+                            double* total_items) try {
   if (cls < 0 || cls >= RMH_PROF_N) return fail(RMH_E_ARG, "profile class %d out of range", cls);
   std::lock_guard<std::mutex> lk(g_prof.mu);
   prof_flush_locked();
@@ -2153,6 +2207,8 @@ rmh_status rmh_profile_read(int32_t cls, int64_t* launches, double* total_ms, do
   if (total_bytes) *total_bytes = g_prof.bytes[cls];
   if (total_items) *total_items = g_prof.items[cls];
   return RMH_OK;
+} catch (...) {   // no C++ exception crosses the C ABI
+  return fail(RMH_E_HOST, "host-side failure (out of host memory?)");
 }
 
 }  // extern "C"
