@@ -334,3 +334,13 @@ def test_empty_batch_is_a_no_op():
                                   None, ctypes.byref(st), FAKE + 2**22, 1 << 30, None) == 0
     assert lib.rmh_kinetic_force(L, FAKE, FAKE + 2**20, 0, ctypes.byref(rat), ctypes.byref(sv), None, None,
                                  FAKE + 2**23, 0, ctypes.byref(st), FAKE + 2**22, 1 << 30, None) == 0
+
+
+def test_every_entry_point_catches_host_exceptions():
+    """Each exported definition is a function-try-block, so no C++ exception crosses the C ABI."""
+    src = open(os.path.join(ROOT, "paper_2112_04556_amd", "csrc", "rmh_api.hip")).read()
+    body = src[src.index('extern "C" {'):src.index('}  // extern "C"')]
+    defs = re.findall(r"^(?:rmh_status|size_t) (rmh_[a-z0-9_]+)\((.*?)\)\s*(try )?\{", body, flags=re.M | re.S)
+    assert len(defs) >= 25
+    missing = [name for name, _, t in defs if not t]
+    assert not missing, missing
