@@ -107,7 +107,10 @@ typedef struct {
  * folded into their FP64 vectors once per segment, so the workspace holds basis + 1 extra link
  * fields per source
  * (mode 1: plus min(2 (basis + 1), 33) FP32 residuals, where the FP32 phase, and the segment open
- * at the switch of precision, go on). */
+ * at the switch of precision, go on).  multishift_target: the multi-shift recursion stops once every
+ * shift's recursive residual is below multishift_target * tol (0 = default 0.5); every pair whose
+ * FP64 true residual is then above tol is refined by its own correction solve (targets above 1
+ * leave pairs for that refinement on purpose; range [0, 1e6] with multishift_target * tol < 1). */
 typedef struct {
   double tol;
   int32_t maxiter;
@@ -116,6 +119,7 @@ typedef struct {
   int32_t check_every;
   double mixed_switch;
   int32_t basis;
+  double multishift_target;
 } rmh_solver;
 
 /* Per-call solver statistics (host). */

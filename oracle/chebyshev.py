@@ -150,9 +150,10 @@ def free_moments_fft(F, L, degree: int) -> np.ndarray:
     ks = np.meshgrid(*[2.0 * np.pi * np.fft.fftfreq(m) for m in shp], indexing="ij")
     lam = sum(4.0 * np.sin(k / 2.0) ** 2 for k in ks)
     th = np.arccos(np.clip(lam / 8.0 - 1.0, -1.0, 1.0)).ravel()
+    Tk = np.cos(np.outer(np.arange(degree + 1), th))      # T_k(lambda_p/8 - 1), shared by every field
     mu = np.empty((F.shape[0], degree + 1))
     for i in range(F.shape[0]):
         Fh = np.fft.fftn(F[i].reshape((4, 8) + shp), axes=(2, 3, 4, 5))
         pw = ((np.abs(Fh) ** 2).sum(axis=(0, 1)) / V).ravel()
-        mu[i] = np.cos(np.outer(np.arange(degree + 1), th)) @ pw
+        mu[i] = Tk @ pw
     return mu

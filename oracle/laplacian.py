@@ -121,3 +121,27 @@ def laplacian_at(U: np.ndarray, P: np.ndarray, L, sites, shift_: float = 0.0) ->
     if shift_ != 0.0:
         res = res + shift_ * P[..., sites]
     return res
+
+
+def bilinear_link_derivative_local(U_links: np.ndarray, a_x: np.ndarray, a_xp: np.ndarray, b_x: np.ndarray,
+                                   b_xp: np.ndarray) -> np.ndarray:
+    """The same derivative for a set of single links, from values next to each link only.
+
+    For m links U_mu(x) (U_links of shape (m, 3, 3)) the derivative d <a, Delta b> / d omega^c_mu(x)
+    involves a and b only at x and x + mu (section 2 derivative, the two hops through the link):
+    a_x, b_x are the component values at x and a_xp, b_xp those at x + mu, each of shape
+    (..., 8, m) with the leading axes (fields, directions nu) summed.  Returns (8, m).
+    This is the per-link form of ``bilinear_link_derivative`` for lattices too large for it.
+    """
+    def mats(p):
+        return su3.to_matrix(np.moveaxis(np.asarray(p, np.float64), -2, -1))   # (..., m, 3, 3)
+
+    Um = np.asarray(U_links)
+    Ud = su3.dagger(Um)
+    A, Ap, B, Bp = mats(a_x), mats(a_xp), mats(b_x), mats(b_xp)
+    Bf = Um @ Bp @ Ud
+    Af = Um @ Ap @ Ud
+    comm = (Bf @ A - A @ Bf) + (Af @ B - B @ Af)
+    comm = comm.reshape((-1,) + comm.shape[-3:]).sum(axis=0)                     # (m, 3, 3)
+    tr = np.einsum("cij,mji->cm", su3.T, comm)
+    return (-2j * tr).real

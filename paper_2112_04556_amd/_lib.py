@@ -36,7 +36,7 @@ class RmhRational(ctypes.Structure):
 
 class RmhSolver(ctypes.Structure):
     _fields_ = [("tol", c_f64), ("maxiter", c_i32), ("mode", c_i32), ("delta", c_f64), ("check_every", c_i32),
-                ("mixed_switch", c_f64), ("basis", c_i32)]
+                ("mixed_switch", c_f64), ("basis", c_i32), ("multishift_target", c_f64)]
 
 
 class RmhStats(ctypes.Structure):

@@ -77,11 +77,12 @@ class Solver:
     delta: float = 0.1
     check_every: int = 8
     mixed_switch: float = 0.0   # 0: library default (1e-4); < 0: FP32 from the first iteration
-    basis: int = 0              # iterations per shift-solution segment (0: library default, 16)
+    basis: int = 0              # iterations per shift-solution segment (0: library default)
+    multishift_target: float = 0.0   # multi-shift stop at this multiple of tol (0: 0.5); > 1 forces refinement
 
     def c_struct(self):
         return L_.RmhSolver(self.tol, self.maxiter, self.mode, self.delta, self.check_every, self.mixed_switch,
-                            self.basis)
+                            self.basis, self.multishift_target)
 
 
 def workspace_bytes(op: int, L, dtype: int, n_rhs: int, aux: int = 0, degree: int = 0, mode: int = 0) -> int:
@@ -198,6 +199,7 @@ def power_spectrum(L, U, F, degree: int, n_windows: int, edges=None, kernel: int
                                    _f64p(mom), _f64p(pw), ws.data_ptr(), ws.numel(), _stream(F.device)),
           "rmh_power_spectrum")
     return mom, pw
+
 
 
 def power_ratio(degree: int, n_windows: int, trace_moments, power, edges=None, kernel: int = 1) -> np.ndarray:

@@ -758,10 +758,12 @@ rmh_status solve_all(SolvePlan& sp, const double* U64, const double* b, double* 
   std::vector<double> sigma((size_t)nr * ns);
   for (int v = 0; v < nr; ++v)
     for (int j = 0; j < ns; ++j) sigma[(size_t)v * ns + j] = sig[j];
-  // the recursive residual is driven below the target so the true residual lands under it
+  // the recursive residual is driven below the target so the true residual lands under it; the
+  // correction solves of the refinement aim at half of tol whatever the multi-shift target
   const double target = 0.5 * sv.tol;
+  const double ms_target = (sv.multishift_target > 0.0 ? sv.multishift_target : 0.5) * sv.tol;
   const double sw = sv.mixed_switch > 0.0 ? sv.mixed_switch : (sv.mixed_switch < 0.0 ? 0.0 : 1e-4);
-  std::vector<double> tol_rel(nr, target);
+  std::vector<double> tol_rel(nr, ms_target);
   SolveInfo info;
   RMH_TRY(engine_solve(e, U64, sp.U32, b, x_hi, sigma, tol_rel, sv.maxiter, sv.delta, sv.check_every, sw, s,
                        &info));
@@ -865,6 +867,9 @@ rmh_status check_solver(const rmh_solver* sv) {
     return fail(RMH_E_ARG, "solver mixed_switch = %g must be < 1", sv->mixed_switch);
   if (sv->basis < 0 || sv->basis > kMaxSlots - 1)
     return fail(RMH_E_ARG, "solver basis = %d outside [0, %d]", sv->basis, kMaxSlots - 1);
+  if (!(sv->multishift_target >= 0.0 && sv->multishift_target <= 1e6) || !(sv->multishift_target * sv->tol < 1.0))
+    return fail(RMH_E_ARG, "solver multishift_target = %g must lie in [0, 1e6] with multishift_target * tol < 1",
+                sv->multishift_target);
   return RMH_OK;
 }
 
@@ -945,7 +950,7 @@ void plan_leapfrog(Carver& c, LeapfrogPlan& lp, const Geom& g, int32_t n_poles, 
 
 template <typename T>
 rmh_status power_spectrum_t(const Geom& g, const T* U, const T* F, int32_t n_rhs, int32_t D,
-                                   const ChebPlan& cp, std::vector<double>* sums_h, hipStream_t s) {
+                                   const ChebPlan& cp, std::vector<double>* sums_h, bool direct_copy, hipStream_t s) {
   const int32_t K = std::max(1, (D + 1) / 2);
   const HopConfig cfg = hop_config(g, sizeof(T) == 8 ? RMH_F64 : RMH_F32, n_rhs, 3);
   const int32_t nblk = hop_num_blocks(g, cfg);
@@ -986,7 +991,12 @@ rmh_status power_spectrum_t(const Geom& g, const T* U, const T* F, int32_t n_rhs
   }
   HIP_TRY(launch_reduce_rows(cp.partials, nblk, K * n_rhs * 3, cp.sums, s));
   sums_h->resize((size_t)K * n_rhs * 3);
-  RMH_TRY(d2h(sums_h->data(), cp.sums, sums_h->size() * 8, s));
+  if (direct_copy) {
+    HIP_TRY(hipMemcpyAsync(sums_h->data(), cp.sums, sums_h->size() * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  } else {
+    RMH_TRY(d2h(sums_h->data(), cp.sums, sums_h->size() * 8, s));
+  }
   return RMH_OK;
 }
 
@@ -1179,6 +1189,73 @@ static hipError_t tune_unit(const Geom& g, const T* U, const T* x, T* y, int32_t
   h.c = -1.0;
   h.z = x;
   return launch_hop<T>(h, cfg, s);
+}
+
+// degree and window count, checked before any host buffer is sized by them
+static rmh_status check_cheb_dims(const rmh_cheb* cheb, int32_t min_degree, int32_t max_windows) {
+  if (!cheb) return fail(RMH_E_ARG, "cheb is NULL");
+  if (cheb->degree < min_degree || cheb->degree > kMaxChebDegree)
+    return fail(RMH_E_ARG, "degree = %d must be in [%d, %d]", cheb->degree, min_degree, kMaxChebDegree);
+  if (cheb->n_windows < 1 || cheb->n_windows > max_windows)
+    return fail(RMH_E_ARG, "n_windows = %d must be in [1, %d]", cheb->n_windows, max_windows);
+  return RMH_OK;
+}
+
+// The power spectrum on a given workspace.  static_ws: nothing is allocated (the sums come back by a
+// plain copy into host memory instead of the pinned stage).
+static rmh_status power_spectrum_impl(const int32_t L[4], const void* U, int32_t dtype, const void* F,
+                                      int32_t n_rhs, const rmh_cheb* cheb, double* moments, double* power,
+                                      void* ws, size_t ws_bytes, bool static_ws, rmh_stream stream) {
+  Geom g;
+  RMH_TRY(make_geom(L, &g));
+  RMH_TRY(check_dtype(dtype));
+  RMH_TRY(check_cheb_dims(cheb, 1, kMaxSpectrumWindows));
+  if (n_rhs < 0) return fail(RMH_E_ARG, "n_rhs < 0");
+  const int32_t D = cheb->degree, nw = cheb->n_windows;
+  std::vector<double> coef((size_t)nw * (D + 1));
+  RMH_TRY(rmh_cheb_coefficients(cheb, coef.data()));
+  if (n_rhs == 0) return RMH_OK;
+  RMH_TRY(check_ptr(U, "U"));
+  RMH_TRY(check_ptr(F, "F"));
+  const int32_t K = std::max(1, (D + 1) / 2);
+  RMH_TRY(check_ptr(ws, "ws"));
+  Carver c(ws);
+  ChebPlan cp = plan_cheb(c, g, dtype, n_rhs, K, true);
+  if (c.off > ws_bytes) return fail(RMH_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, c.off);
+  const size_t fb = (size_t)n_rhs * 32 * g.V * dsize(dtype);
+  if (overlap(ws, c.off, F, fb) || overlap(ws, c.off, U, (size_t)72 * g.V * dsize(dtype)))
+    return fail(RMH_E_ARG, "workspace overlaps an input");
+  std::vector<double> sums;
+  hipStream_t s = (hipStream_t)stream;
+  if (dtype == RMH_F64)
+    RMH_TRY(power_spectrum_t<double>(g, (const double*)U, (const double*)F, n_rhs, D, cp, &sums, static_ws, s));
+  else
+    RMH_TRY(power_spectrum_t<float>(g, (const float*)U, (const float*)F, n_rhs, D, cp, &sums, static_ws, s));
+  // moments from the doubling identities
+  std::vector<double> mu((size_t)n_rhs * (2 * K + 1));
+  for (int32_t n = 0; n < n_rhs; ++n) {
+    double* m = mu.data() + (size_t)n * (2 * K + 1);
+    auto S = [&](int k, int q) { return sums[((size_t)k * n_rhs + n) * 3 + q]; };
+    m[0] = S(0, 0);
+    m[1] = S(0, 1);
+    m[2] = 2.0 * S(0, 2) - m[0];
+    for (int32_t k = 1; k < K; ++k) {
+      m[2 * k + 1] = 2.0 * S(k, 1) - m[1];
+      m[2 * k + 2] = 2.0 * S(k, 2) - m[0];
+    }
+  }
+  for (int32_t n = 0; n < n_rhs; ++n) {
+    const double* m = mu.data() + (size_t)n * (2 * K + 1);
+    if (moments)
+      for (int32_t k = 0; k <= D; ++k) moments[(size_t)n * (D + 1) + k] = m[k];
+    if (power)
+      for (int32_t w = 0; w < nw; ++w) {
+        double acc = 0.0;
+        for (int32_t k = 0; k <= D; ++k) acc += coef[(size_t)w * (D + 1) + k] * m[k];
+        power[(size_t)n * nw + w] = acc;
+      }
+  }
+  return RMH_OK;
 }
 
 extern "C" {
@@ -1410,15 +1487,6 @@ rmh_status rmh_laplacian_apply_bwd(const int32_t L[4], const void* U, int32_t dt
   return fail(RMH_E_HOST, "host-side failure (out of host memory?)");
 }
 
-// degree and window count, checked before any host buffer is sized by them
-static rmh_status check_cheb_dims(const rmh_cheb* cheb, int32_t min_degree, int32_t max_windows) {
-  if (!cheb) return fail(RMH_E_ARG, "cheb is NULL");
-  if (cheb->degree < min_degree || cheb->degree > kMaxChebDegree)
-    return fail(RMH_E_ARG, "degree = %d must be in [%d, %d]", cheb->degree, min_degree, kMaxChebDegree);
-  if (cheb->n_windows < 1 || cheb->n_windows > max_windows)
-    return fail(RMH_E_ARG, "n_windows = %d must be in [1, %d]", cheb->n_windows, max_windows);
-  return RMH_OK;
-}
 
 rmh_status rmh_cheb_coefficients(const rmh_cheb* cheb, double* coef) try {
   if (!cheb || !coef) return fail(RMH_E_ARG, "cheb or coef is NULL");
@@ -1462,56 +1530,7 @@ rmh_status rmh_trace_moments_free(const int32_t L[4], int32_t degree, double* tr
 rmh_status rmh_power_spectrum(const int32_t L[4], const void* U, int32_t dtype, const void* F, int32_t n_rhs,
                               const rmh_cheb* cheb, double* moments, double* power, void* ws, size_t ws_bytes,
                               rmh_stream stream) try {
-  Geom g;
-  RMH_TRY(make_geom(L, &g));
-  RMH_TRY(check_dtype(dtype));
-  RMH_TRY(check_cheb_dims(cheb, 1, kMaxSpectrumWindows));
-  if (n_rhs < 0) return fail(RMH_E_ARG, "n_rhs < 0");
-  const int32_t D = cheb->degree, nw = cheb->n_windows;
-  std::vector<double> coef((size_t)nw * (D + 1));
-  RMH_TRY(rmh_cheb_coefficients(cheb, coef.data()));
-  if (n_rhs == 0) return RMH_OK;
-  RMH_TRY(check_ptr(U, "U"));
-  RMH_TRY(check_ptr(F, "F"));
-  RMH_TRY(check_ptr(ws, "ws"));
-  const int32_t K = std::max(1, (D + 1) / 2);
-  Carver c(ws);
-  ChebPlan cp = plan_cheb(c, g, dtype, n_rhs, K, true);
-  if (c.off > ws_bytes) return fail(RMH_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, c.off);
-  const size_t fb = (size_t)n_rhs * 32 * g.V * dsize(dtype);
-  if (overlap(ws, c.off, F, fb) || overlap(ws, c.off, U, (size_t)72 * g.V * dsize(dtype)))
-    return fail(RMH_E_ARG, "workspace overlaps an input");
-  std::vector<double> sums;
-  hipStream_t s = (hipStream_t)stream;
-  if (dtype == RMH_F64)
-    RMH_TRY(power_spectrum_t<double>(g, (const double*)U, (const double*)F, n_rhs, D, cp, &sums, s));
-  else
-    RMH_TRY(power_spectrum_t<float>(g, (const float*)U, (const float*)F, n_rhs, D, cp, &sums, s));
-  // moments from the doubling identities
-  std::vector<double> mu((size_t)n_rhs * (2 * K + 1));
-  for (int32_t n = 0; n < n_rhs; ++n) {
-    double* m = mu.data() + (size_t)n * (2 * K + 1);
-    auto S = [&](int k, int q) { return sums[((size_t)k * n_rhs + n) * 3 + q]; };
-    m[0] = S(0, 0);
-    m[1] = S(0, 1);
-    m[2] = 2.0 * S(0, 2) - m[0];
-    for (int32_t k = 1; k < K; ++k) {
-      m[2 * k + 1] = 2.0 * S(k, 1) - m[1];
-      m[2 * k + 2] = 2.0 * S(k, 2) - m[0];
-    }
-  }
-  for (int32_t n = 0; n < n_rhs; ++n) {
-    const double* m = mu.data() + (size_t)n * (2 * K + 1);
-    if (moments)
-      for (int32_t k = 0; k <= D; ++k) moments[(size_t)n * (D + 1) + k] = m[k];
-    if (power)
-      for (int32_t w = 0; w < nw; ++w) {
-        double acc = 0.0;
-        for (int32_t k = 0; k <= D; ++k) acc += coef[(size_t)w * (D + 1) + k] * m[k];
-        power[(size_t)n * nw + w] = acc;
-      }
-  }
-  return RMH_OK;
+  return power_spectrum_impl(L, U, dtype, F, n_rhs, cheb, moments, power, ws, ws_bytes, false, stream);
 } catch (...) {   // no C++ exception crosses the C ABI
   return fail(RMH_E_HOST, "host-side failure (out of host memory?)");
 }

@@ -129,6 +129,12 @@ def test_validation_rational():
     st = _lib.lib().rmh_rational_apply(L, FAKE, FAKE + 2**20, 1, ctypes.byref(rat), ctypes.byref(sv_bad),
                                        FAKE + 2**21, None, None, None, FAKE + 2**22, 1 << 30, None)
     assert st == 1
+    # multi-shift target outside [0, 1e6], or its product with tol not below 1
+    for mt, tol in ((-1.0, 1e-10), (2e6, 1e-10), (2.0, 0.5), (float("nan"), 1e-10)):
+        sv_mt = _lib.RmhSolver(tol, 100, 0, 0.1, 8, 0.0, 0, mt)
+        st = _lib.lib().rmh_rational_apply(L, FAKE, FAKE + 2**20, 1, ctypes.byref(rat), ctypes.byref(sv_mt),
+                                           FAKE + 2**21, None, None, None, FAKE + 2**22, 1 << 30, None)
+        assert st == 1, (mt, tol)
     # pole count outside [1, 64]
     r65, s65 = np.ones(65), np.linspace(0.5, 10.0, 65)
     for n in (0, 65):
@@ -344,3 +350,4 @@ def test_every_entry_point_catches_host_exceptions():
     assert len(defs) >= 25
     missing = [name for name, _, t in defs if not t]
     assert not missing, missing
+

@@ -117,6 +117,42 @@ def test_mixed_switch_points(switch, basis):
 
 
 @pytest.mark.parametrize("mode", [0, 1])
+def test_forced_per_shift_refinement(mode):
+    """The multi-shift phase is stopped far above tol (multishift_target = 1e4, i.e. at 1e-6), so
+    every (source, shift) pair leaves it with a true residual above tol and goes through the
+    per-shift correction solves (gather, residual stencil, single-shift solve, scatter-add), in
+    batches of four pairs: 3 sources x 12 poles = 36 pairs, nine batches a round.  Every pair must
+    end at its FP64 true residual <= tol (checked by the oracle's Laplacian) and within the
+    tolerance bound of the unforced FP64 solve."""
+    L = (4, 4, 4, 6)
+    announce(f"forced refinement mode={mode}")
+    U, P, Ud, Pd = setup(L, "eps", 0.6, 14, n=3)
+    rat = _rat_kappa(0.9, 12)
+    tol = 1e-10
+    ref = api.rational_apply(L, Ud, Pd, rat, api.Solver(tol=tol, mode=0), want_poles=True)
+    assert ref["stats"]["refine_iters"] == 0
+    xr = ref["x_poles"].cpu().numpy()
+    out = api.rational_apply(L, Ud, Pd, rat, api.Solver(tol=tol, mode=mode, multishift_target=1e4),
+                             want_poles=True)
+    st = out["stats"]
+    announce(f"  stats {st}")
+    assert st["refine_iters"] > 0 and st["refine_rounds"] >= 1
+    assert st["iters"] < ref["stats"]["iters"]
+    assert st["true_relres_max"] <= tol
+    xp = out["x_poles"].cpu().numpy()
+    for i in range(3):
+        bn = np.linalg.norm(P[i])
+        for j, sj in enumerate(rat.sigma):
+            res = np.linalg.norm(P[i] - olap.laplacian(U, xp[i, j], L, sj)) / bn
+            assert res <= 1.01 * tol, (i, j, res)
+            assert np.linalg.norm(xp[i, j] - xr[i, j]) <= 2 * tol * bn / sj, (i, j)
+    y = out["y"].cpu().numpy()
+    yref, _ = orat.rational_apply(U, P, L, rat.c, rat.r, rat.sigma, tol=1e-13)
+    for i in range(3):
+        assert np.linalg.norm(y[i] - yref[i]) <= _y_bound(rat, tol, 1e-13, np.linalg.norm(P[i]))
+
+
+@pytest.mark.parametrize("mode", [0, 1])
 def test_rational_apply_single_pole(mode):
     """One pole: the single-shift engine (no residual ring; the segment index grows with every
     iteration, past the engine's 4 coefficient slots, in mixed mode through the FP32 ring as well)

@@ -152,3 +152,43 @@ def test_laplacian_at_sites_matches_whole_field():
     sites = np.array([0, 7, 11, 50, lattice.volume(L) - 1])
     full = lap.laplacian(U, P, L, 0.3)
     assert np.allclose(lap.laplacian_at(U, P, L, sites, 0.3), full[..., sites], atol=1e-13)
+
+
+def _gather_local(U, a, b, L, mu, sites):
+    """Inputs of the per-link derivative for links U_mu(sites): values at x and at x + mu."""
+    tab = lattice.neighbour_table(L)
+    fwd = tab[sites, 2 * mu]
+    return U[mu][sites], a[..., sites], a[..., fwd], b[..., sites], b[..., fwd]
+
+
+def test_link_derivative_local_central_differences():
+    # the per-link form pinned to the definition directly: central differences of <a, Delta[U] b>
+    L = (3, 2, 2, 4)
+    U = inputs.random_links(L, "eps", 0.5, seed=31).numpy()
+    a = inputs.gaussian_fields(L, 2, seed=32).numpy()
+    b = inputs.gaussian_fields(L, 2, seed=33).numpy()
+    rng = np.random.default_rng(5)
+    h = 1e-5
+    for _ in range(8):
+        mu, c, s = int(rng.integers(4)), int(rng.integers(8)), int(rng.integers(lattice.volume(L)))
+        G = lap.bilinear_link_derivative_local(*_gather_local(U, a, b, L, mu, np.array([s])))
+
+        def F(e):
+            U2 = U.copy()
+            U2[mu, s] = expm(1j * e * su3.T[c]) @ U[mu, s]
+            return lap.inner(a, lap.laplacian(U2, b, L))
+
+        fd = (F(h) - F(-h)) / (2 * h)
+        assert abs(fd - G[c, 0]) <= 1e-7 * max(1.0, abs(G[c, 0]))
+
+
+def test_link_derivative_local_matches_whole_field():
+    L = (3, 4, 2, 5)
+    U = inputs.random_links(L, "haar", seed=34).numpy()
+    a = inputs.gaussian_fields(L, 3, seed=35).numpy()
+    b = inputs.gaussian_fields(L, 3, seed=36).numpy()
+    full = lap.bilinear_link_derivative(U, a, b, L)
+    sites = np.arange(lattice.volume(L))
+    for mu in range(4):
+        loc = lap.bilinear_link_derivative_local(*_gather_local(U, a, b, L, mu, sites))
+        assert np.abs(loc - full[mu]).max() <= 1e-12 * np.abs(full).max()
