@@ -19,10 +19,12 @@ One step of size eps, h = eps / 2, in three stages:
     (ii)  U'  = exp(i h [Pi(U, P_h) + Pi(U', P_h)]^a T^a) U   fixed point in U'
     (iii) P'  = P_h + h F(U', P_h)                           explicit
 
-Each fixed point is iterated from the explicit guess and stops at the first iterate whose successor
-differs from it by at most fp_tol relative to the successor; that iterate is kept (stage i: P_h;
-stage ii: U', with the successor of Pi(U', P_h) compared against the Pi that built U').  Pi is
-linear in P, so the step run from (U', -P') returns to (U, -P): the scheme is time reversible.
+Each fixed point x = G(x) is iterated from the explicit guess, x_{k+1} = G(x_k), until successive
+iterates differ by at most fp_tol relative to the new one, and the new iterate x_{k+1} is kept
+(stage ii iterates Pi(U', P_h) and rebuilds U' from the new Pi).  Any other stopping rule within
+fp_tol (for instance keeping x_k) differs from this one by at most fp_tol relative in the fixed
+point.  Pi is linear in P, so the step run from (U', -P') returns to (U, -P): the scheme is time
+reversible.
 
 Everything is written from the definitions with the oracle's own rational solves, kinetic-force
 derivative, gauge force and scipy's matrix exponential.
@@ -74,25 +76,27 @@ def glf_step(U0, P0, L, c, r, sigma, beta: float, eps: float, fp_tol: float = 1e
     while True:
         it_p += 1
         Pn = P0 + h * (fg - kinetic_force_grad(U0, Ph[None], L, c, r, sigma, tol))
-        if np.linalg.norm(Pn - Ph) <= fp_tol * np.linalg.norm(Pn):
+        d = np.linalg.norm(Pn - Ph)
+        Ph = Pn
+        if d <= fp_tol * np.linalg.norm(Pn):
             break
         if it_p >= fp_maxiter:
             raise RuntimeError("stage i did not converge")
-        Ph = Pn
     # (ii) U1 = exp(i h (Pi(U0, P_h) + Pi(U1, P_h))) U0, from the guess Pi(U1) = Pi(U0)
     pi0 = velocity(U0, Ph, L, c, r, sigma, tol)
-    pi = pi0                                    # the Pi that U1 is built from
+    pi = pi0
     U1 = link_update(U0, h * (pi0 + pi))
     it_u = 0
     while True:
         it_u += 1
         pn = velocity(U1, Ph, L, c, r, sigma, tol)
-        if np.linalg.norm(pn - pi) <= fp_tol * np.linalg.norm(pn):
+        d = np.linalg.norm(pn - pi)
+        pi = pn
+        U1 = link_update(U0, h * (pi0 + pi))
+        if d <= fp_tol * np.linalg.norm(pn):
             break
         if it_u >= fp_maxiter:
             raise RuntimeError("stage ii did not converge")
-        pi = pn
-        U1 = link_update(U0, h * (pi0 + pi))
     # (iii) P1 = P_h + h F(U1, P_h)
     P1 = Ph + h * total_force(U1, Ph, L, c, r, sigma, beta, tol)
     return U1, P1, it_p, it_u
