@@ -135,3 +135,30 @@ def heatbath_momenta(U, xi, L, kappa: float, c, r, sigma, tol: float = 1e-13):
     Delta, R^{-1} ~ y^{1/2} = y R, so P = (1 - kappa) R xi + kappa Delta (R xi)."""
     y, _ = rational_apply(U, xi, L, c, r, sigma, tol)
     return (1.0 - kappa) * y + kappa * laplacian(U, y, L)
+
+
+def inverse_apply(U, x, L, c, r, sigma, tol: float = 1e-12, maxiter: int = 1000, inner_tol: float = 1e-14):
+    """P = R(Delta)^{-1} x for one field x of shape (4, 8, V), by plain CG on R(Delta) P = x, each
+    application of R(Delta) being rational_apply (R(lambda) > 0 on the spectrum [0, 16] makes R(Delta)
+    symmetric positive definite).  The heat bath of section 3 with M = R^{-2} is P = R(Delta)^{-1} xi.
+    Stops when the residual ||x - R(Delta) P|| <= tol ||x||; the inner shifted solves run to
+    inner_tol."""
+    x = np.asarray(x, np.float64)
+    bnorm = np.sqrt(inner(x, x))
+    P = np.zeros_like(x)
+    if bnorm == 0.0:
+        return P
+    res = x.copy()
+    p = res.copy()
+    rr = inner(res, res)
+    for _ in range(maxiter):
+        Ap = rational_apply(U, p[None], L, c, r, sigma, inner_tol)[0][0]
+        alpha = rr / inner(p, Ap)
+        P += alpha * p
+        res -= alpha * Ap
+        rr_new = inner(res, res)
+        if np.sqrt(rr_new) <= tol * bnorm:
+            return P
+        p = res + (rr_new / rr) * p
+        rr = rr_new
+    raise RuntimeError("inverse_apply did not converge")

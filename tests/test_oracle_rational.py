@@ -183,3 +183,21 @@ def test_heatbath_momenta_against_exact_square_root(kappa, n):
     assert np.abs(P - exact).max() <= bound * np.abs(exact).max()
     back, _ = ra.rational_apply(U, P, L, c, r, s)
     assert np.abs(back - xi).max() <= bound * np.abs(xi).max()
+
+
+@pytest.mark.parametrize("kappa,n", [(0.9, 8), (0.5, 4)])
+def test_inverse_apply_against_dense(kappa, n):
+    """The exact heat bath P = R(Delta)^{-1} xi (CG on R(Delta) P = xi) against the dense
+    eigen-decomposition Q diag(1 / R(lambda)) Q^T xi of the adjoint-form matrix, to 1e-10, and for a
+    rational with c > 0 (Eq. 6 quadratic terms) as well."""
+    L = (2, 2, 2, 2)
+    U = inputs.random_links(L, "eps", 0.6, seed=83).numpy()
+    xi = inputs.gaussian_fields(L, 1, seed=84).numpy()[0]
+    D = dense.dense_laplacian(U, L)
+    w, Q = dense.eigh(D)
+    for c, r, s in (ra.kappa_poles(kappa, n),
+                    ra.poles_from_quadratics(0.4, [0.3, 0.1], [1.0, 0.2], [0.05, 0.3], [0.6, 1.4])):
+        P = ra.inverse_apply(U, xi, L, c, r, s, tol=1e-12)
+        inv = Q @ np.diag(1.0 / ra.rational_scalar(w, c, r, s)) @ Q.T
+        exact = dense.apply_dense_to_link_field(inv, xi)
+        assert np.abs(P - exact).max() <= 1e-10 * np.abs(exact).max()
