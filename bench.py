@@ -1,32 +1,31 @@
 #!/usr/bin/env python3
 """Benchmark of the adjoint-Laplacian hot path on one MI355X.
 
-One step is one RMHMC kinetic-force evaluation on the 16^4 lattice with eps = 0.5 links
-(the lattice, link ensemble and 12-pole (1 - kappa + kappa Delta)^-1-type rational of
-the rational-solve workload, kappa = 0.9), through every stage of the path:
+The metric has two halves: the Laplacian's throughput (Gsite/s and its fraction of the HBM peak)
+and the rational solve's time to an FP64 true residual of 1e-10, mixed precision against FP64.
 
-  1. ingest: pack the links into the SoA layout (FP64) and, inside the solver, FP32;
-  2. forward: multi-shift CG for R(Delta) P to FP64 true residual 1e-10 on every shift,
-     FP32 stencil and vectors with FP64 reliable updates, Y = R(Delta) P, K = 1/2 <Y, Y>;
-  3. backward: second multi-shift solve z_j = (Delta + sigma_j)^-1 Y and the link
-     derivative dK/d omega (the mass-term force, section 3);
-  4. the Chebyshev power spectrum of the force (degree 64, 16 windows): FP32 stencil sweeps
-     with the moments summed in FP64, as for the batched spectra;
-  5. a Chebyshev vector filter of the momentum onto 4 windows (degree 32), on a second
-     stream beside stages 2-4 (it depends only on the momentum and the links).
+Timed step (the JSON line's `value`, `ms_per_step`, `roofline`): one application of Delta to one
+su(3) link field on the largest single-GPU lattice of the workloads, 32^3 x 64 (2.1M sites,
+eps = 0.4 links, FP64, launch configuration autotuned beforehand); inputs resident in HBM, W
+untimed and K timed applications.  `value` = sites x applications / wall time (Gsite/s);
+`roofline` = the kernel's algorithmic bytes (links once, 12 reals per link; input and output once:
+896 B per site) over its HIP-event average launch time, against 8 TB/s, with the HBM traffic the
+committed rocprofv3 counters show for that kernel while its sources are unchanged.
 
-`value` is the Laplacian throughput of the whole step: lattice sites times link fields
-passed through Delta, divided by the step time (every other kernel of the step counts
-against it).  The step time comes from a pass without instrumentation; `roofline` and
-`kernel_time_share` from a second pass of the same steps on one stream (the filter after the
-spectrum, so no launch shares the chip) with HIP events around every launch.
+Second half (`rational_solve`): the 16^4 rational-solve workload (eps = 0.5 links, 12-pole
+(1 - kappa + kappa Delta)^-1-type rational, kappa 0.9 and 0.5, one and eight Gaussian fields),
+time from the call to every shift's FP64 true residual <= 1e-10, FP64 against mixed precision
+(FP32 stencil and vectors with FP64 reliable updates), median of 5.
+
+`hot_path_step`: one pass of every stage of the path on the 16^4 workload: pack the links, the
+12-pole kappa = 0.9 kinetic force (both multi-shift solves to 1e-10 in mixed precision and the link
+derivative), the degree-64/16-window power spectrum of the force (FP32 sweeps, FP64 moments) and a
+degree-32/4-window filter of the momentum on a second stream.
 
 Extra fields (skipped with --no-extras):
   D1  the Laplacian alone at 16^4, 24^4 and 32^3 x 64, FP64 and FP32 (working sets under the
       256 MB Infinity Cache timed over rotating buffer sets of >= 1 GiB), against 8 TB/s and
       against a measured 1 GiB copy;
-  D2  the rational solve alone, time to FP64 true residual 1e-10, FP64 against mixed precision,
-      12 poles, kappa 0.9 and 0.5, one and eight momentum fields (median of 5);
   D3  the batched power spectrum at 24^4 (32 sources, degree 256, 64 windows), Haar and U = 1;
   D4  the 8-pole kinetic force at 16^4;
   D5  the full force step at 32^3 x 64: 16-pole kinetic force of 8 momentum fields, then the
@@ -36,12 +35,10 @@ Extra fields (skipped with --no-extras):
   D7  the Wilson gauge force and its degree-128, 32-window power spectrum (the gauge-force spectra
       of section 2) at 16^4 and 32^3 x 64;
   D8  one implicit leapfrog step of the non-separable Hamiltonian (kinetic term with the 12-pole
-      kappa = 0.9 mass term plus the Wilson action, beta = 5.5, eps = 0.02) at 16^4: time,
-      fixed-point iterations, solver iterations, the energy change of the step and the stencil
-      launches inside it;
+      kappa = 0.9 mass term plus the Wilson action, beta = 5.5, eps = 0.02) at 16^4;
   D9  RMHMC heat-bath momenta P = R(Delta)^-1 xi (12-pole kappa = 0.9 set) at 16^4 and their
-      projection onto 4 spectral windows (degree-32 filter), the input of the section-3 momentum
-      injection.
+      projection onto 4 spectral windows (degree-32 filter).
+`cpu_baseline`: the oracle timed on the host cores (see cpu_baseline).
 """
 from __future__ import annotations
 
@@ -66,55 +63,181 @@ def log(msg):
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=100, help="timed Laplacian applications")
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps-hot", type=int, default=10, help="timed passes of the whole hot path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="only the timed force steps")
+    ap.add_argument("--no-extras", action="store_true", help="skip the per-component figures")
+    ap.add_argument("--headline-config", type=int, nargs=8, default=None,
+                    metavar=("FORM", "BLOCK", "XCD", "NV", "ORDER", "WALK", "NS", "TILE2"),
+                    help="launch the headline stencil with this configuration instead of the autotuner's")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the timed Laplacian applications (the profiled command of the headline kernel)")
     ap.add_argument("--kappa", type=float, default=0.9)
     return ap.parse_args()
 
 
-def cpu_baseline(U, P, L, budget_s=12.0):
-    """The oracle's stencil on the same 16^4 field, repeated for about budget_s seconds."""
+# ---- the CPU-baseline leg: the only code of this file that runs the oracle ----
+
+_CPU = {}   # inputs of the oracle timing, shared with forked workers (copy-on-write)
+
+
+def _host_cores():
+    """The host cores this process may use (the machine's CPU share), at most 16."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _oracle_lap_chunk(bounds):
+    """Worker: the oracle's site-by-site Laplacian on sites [lo, hi), one thread."""
     from threadpoolctl import threadpool_limits
 
+    import numpy as np
     from oracle import laplacian as olap
-    U = U.numpy()
-    P = P.numpy()
-    with threadpool_limits(limits=1):   # the one core the figure is quoted for
-        olap.laplacian(U, P, L)             # warm-up
-        n = 0
+    lo, hi = bounds
+    with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        while True:
-            olap.laplacian(U, P, L)
-            n += 1
-            if time.perf_counter() - t0 >= budget_s:
-                break
-        dt = time.perf_counter() - t0
-    V = L[0] * L[1] * L[2] * L[3]
-    return {"value": V * n / dt / 1e9, "unit": "Gsite/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} applications of the oracle's Laplacian (numpy FP64, literal 3x3 products, "
-                      f"single thread) to the 16^4 momentum field in {dt:.1f} s; stencil only, so it "
-                      f"overstates the oracle's rate for the whole step"}
+        olap.laplacian_at(_CPU["U"], _CPU["P"], _CPU["L"], np.arange(lo, hi))
+        return hi - lo, time.perf_counter() - t0
 
 
-def stencil_traffic(kernel_class):
-    """HBM bytes per stencil launch of this step from the committed rocprofv3 counter summary
+def _oracle_cg_iters(args):
+    """Worker: k iterations of the oracle's per-shift CG on the 16^4 field for one shift, one thread."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import rational as orat
+    sigma, k = args
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        orat.cg_solve(_CPU["U16"], _CPU["P16"][0], _CPU["L16"], sigma, tol=1e-30, maxiter=k)
+        return k, time.perf_counter() - t0
+
+
+def cpu_baseline(budget_s=6.0, Lb=(32, 32, 32, 64), L16=(16, 16, 16, 16), chunk=16384):
+    """The oracle (numpy FP64, as it stands) on the host cores, before the GPU is touched:
+
+    * the Laplacian of the headline workload (one link field, 32^3 x 64, eps = 0.4 links), the
+      site-by-site form laplacian_at over chunks of 16384 sites: one core, then every core of the
+      box's share in a pool of forked single-threaded workers;
+    * per-shift CG iterations (the oracle's solver: one Delta and the vector updates per iteration) on
+      the 16^4 field of the rational-solve workload: one core, then the 12 shifts of the 12-pole set
+      in parallel."""
+    import multiprocessing as mp
+
+    from oracle import rational as orat
+    from paper_2112_04556_amd import inputs
+    Vb = Lb[0] * Lb[1] * Lb[2] * Lb[3]
+    _CPU.update(L=Lb, U=inputs.random_links(Lb, "eps", 0.4, seed=1).numpy(),
+                P=inputs.gaussian_fields(Lb, 1, seed=1).numpy())
+    _CPU.update(L16=L16, U16=inputs.random_links(L16, "eps", 0.5, seed=2).numpy(),
+                P16=inputs.gaussian_fields(L16, 1, seed=2).numpy())
+    cores = _host_cores()
+    # one core
+    sites, t_one, lo = 0, 0.0, 0
+    while t_one < budget_s and lo + chunk <= Vb:
+        n, dt = _oracle_lap_chunk((lo, lo + chunk))
+        sites += n
+        t_one += dt
+        lo += chunk
+    lap_one = sites / t_one / 1e9
+    # every core: a fixed set of chunks sized to about budget_s of wall time
+    per_core = max(1, int(round(budget_s * lap_one * 1e9 / chunk)))
+    nchunk = min(cores * per_core, Vb // chunk)
+    ctx = mp.get_context("fork")
+    with ctx.Pool(cores) as pool:
+        t0 = time.perf_counter()
+        done = pool.map(_oracle_lap_chunk, [(i * chunk, (i + 1) * chunk) for i in range(nchunk)], chunksize=1)
+        t_all = time.perf_counter() - t0
+    lap_all = sum(n for n, _ in done) / t_all / 1e9
+    # per-shift CG
+    _, _, sigma = orat.kappa_poles(0.9, 12)
+    k = 2
+    n1, t1 = _oracle_cg_iters((float(sigma[0]), k))
+    with ctx.Pool(min(cores, 12)) as pool:
+        t0 = time.perf_counter()
+        res = pool.map(_oracle_cg_iters, [(float(s), k) for s in sigma], chunksize=1)
+        t12 = time.perf_counter() - t0
+    return {
+        "value": round(lap_all, 7), "unit": "Gsite/s", "cores": cores, "kind": "oracle",
+        "sample": f"{nchunk} chunks of {chunk} sites of the {'x'.join(map(str, Lb))} eps=0.4 link field, the oracle's "
+                  f"site-by-site Laplacian (numpy FP64, literal 3x3 products) in {cores} forked "
+                  f"single-threaded workers: {t_all:.1f} s wall",
+        "single_core": {"value": round(lap_one, 7), "unit": "Gsite/s", "cores": 1,
+                        "sample": f"{sites} sites of the same field on one thread in {t_one:.1f} s"},
+        "cg_iteration": {"lattice": list(L16),
+            "one_shift_one_core_ms": round(t1 / n1 * 1e3, 1),
+            "twelve_shifts_all_cores_ms": round(t12 / k * 1e3, 1), "cores": min(cores, 12),
+            "sample": f"{k} iterations of the oracle's per-shift CG (one Delta, vector updates) on the {'x'.join(map(str, L16))} "
+                      f"eps=0.5 field, one shift on one thread, then the 12 shifts of the 12-pole kappa=0.9 "
+                      f"set on {min(cores, 12)} forked workers"},
+    }
+
+
+# ---- end of the CPU-baseline leg ----
+
+TRAFFIC_RECORD = "stencil_traffic_32x32x32x64_f64.json"
+
+
+def traffic_record(record=TRAFFIC_RECORD):
+    """The committed rocprofv3 counter summary of the headline stencil, or None."""
+    try:
+        with open(os.path.join(ROOT, "profiles", record)) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return None
+
+
+def stencil_traffic(kernel_class, record=TRAFFIC_RECORD, cfg=None):
+    """HBM bytes per launch of the headline stencil from the committed rocprofv3 counter summary
     (FETCH_SIZE and WRITE_SIZE, scaled by a calibration copy), or None when the summary is
-    missing or the stencil sources have changed since it was taken."""
+    missing, the stencil sources have changed since it was taken, or it counted another launch
+    configuration than cfg."""
     if kernel_class != "stencil":
         return None, None
-    path = os.path.join(ROOT, "profiles", "stencil_traffic_16x16x16x16.json")
-    try:
-        with open(path) as fh:
-            t = json.load(fh)
-    except (OSError, ValueError):
+    t = traffic_record(record)
+    if t is None:
         return None, None
     from paper_2112_04556_amd.profiling import stencil_source_hash
-    rel = os.path.relpath(path, ROOT)
+    rel = os.path.join("profiles", record)
     if t.get("stencil_source_sha256") != stencil_source_hash():
         return None, rel + " (stale: stencil sources changed)"
+    if cfg is not None and t.get("launch_config") is not None and list(t["launch_config"]) != list(cfg):
+        return None, rel + f" (taken with launch configuration {t['launch_config']})"
     return round(float(t["traffic_bytes_per_launch"])), rel
+
+
+def prefer_profiled_config(api, torch, L, U, F, cfg, best_ms, slack=1.03):
+    """The launch configuration whose HBM traffic the committed counter summary holds, when it runs
+    within `slack` of the autotuner's pick (several shapes tie within the timing noise); else the pick."""
+    t = traffic_record()
+    rec = None if t is None else t.get("launch_config")
+    if rec is None or list(rec) == list(cfg):
+        return cfg
+    set_config(api, torch, L, rec)
+    y = torch.empty_like(F)
+    for _ in range(3):
+        api.laplacian_apply(L, U, F, out=y)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        api.laplacian_apply(L, U, F, out=y)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 20
+    if ms <= slack * best_ms:
+        return tuple(rec)
+    set_config(api, torch, L, cfg)
+    return cfg
+
+
+def set_config(api, torch, L, cfg):
+    """Store an 8-field launch configuration for the one-field FP64 Laplacian of lattice L."""
+    kw = dict(zip(("form", "block", "xcd_remap", "nv", "order", "walk", "ns", "tile2"), cfg))
+    form = kw.pop("form")
+    api.tune_set(L, torch.float64, 1, form, purpose="apply", **kw)
 
 
 def main():
@@ -125,33 +248,126 @@ def main():
               "(sharding across GPUs is described in DESIGN.md but not built)", file=sys.stderr)
         sys.exit(2)
 
+    # the oracle on the host cores first: its workers are forked before anything touches the GPU
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle on the host cores)")
+        cpu = cpu_baseline()
+        _CPU.clear()
+        log(f"cpu baseline: {cpu}")
+
     import numpy as np
     import torch
 
     from paper_2112_04556_amd import api, inputs
 
     dev = torch.device("cuda:0")
+
+    # ---- timed step: Delta on one FP64 link field at 32^3 x 64 ----
+    Lb = (32, 32, 32, 64)
+    Vb = api.volume(Lb)
+    log("generating the 32^3x64 inputs")
+    Ub = api.pack_links(Lb, inputs.random_links(Lb, "eps", 0.4, seed=1).to(dev))
+    Fb = inputs.gaussian_fields(Lb, 1, seed=1).to(dev)
+    Yb = torch.empty_like(Fb)
+    if args.headline_config:
+        cfg = tuple(args.headline_config)
+        set_config(api, torch, Lb, cfg)
+    else:
+        cfg, best_ms = api.autotune_laplacian(Lb, Ub, Fb, reps=3, purpose="apply")
+        cfg = prefer_profiled_config(api, torch, Lb, Ub, Fb, cfg, best_ms)
+    log(f"launch configuration {cfg}")
+    log(f"warmup {args.warmup}")
+    for _ in range(args.warmup):
+        api.laplacian_apply(Lb, Ub, Fb, out=Yb)
+    torch.cuda.synchronize()
+    log(f"timing {args.steps} steps")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        api.laplacian_apply(Lb, Ub, Fb, out=Yb)
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) / args.steps * 1e3
+    value = Vb / (ms_step * 1e-3) / 1e9
+    # the same launches again with HIP events around each (on the launch stream)
+    api.profile_enable(True)
+    for _ in range(args.steps):
+        api.laplacian_apply(Lb, Ub, Fb, out=Yb)
+    torch.cuda.synchronize()
+    p = api.profile_read("stencil")
+    api.profile_enable(False)
+    traffic, traffic_src = stencil_traffic("stencil", cfg=cfg)
+    bytes_launch = p["bytes"] / max(p["launches"], 1)
+    roofline = {"bound": "hbm", "kernel": "stencil", "achieved": round(p["gbs"], 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(p["gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "traffic_source": traffic_src, "avg_launch_ms": round(p["avg_ms"], 5),
+                "bytes_per_launch": bytes_launch, "bytes_per_site": round(bytes_launch / Vb, 1),
+                "launches": p["launches"], "working_set": "1.9 GB, HBM (larger than the 256 MB Infinity Cache)",
+                "measured_over": f"the {args.steps} timed applications repeated with HIP events on the launch stream"}
+    log(f"{ms_step:.4f} ms per application, {value:.3f} Gsite/s, {p['gbs']:.1f} GB/s algorithmic")
+    del Ub, Fb, Yb
+    torch.cuda.empty_cache()
+    solves, hot, extras = None, None, {}
+    if not args.headline_only:
+        solves, hot, extras = second_half(args, api, inputs, torch, np, dev)
+
+    result = {
+        "metric": METRIC,
+        "value": round(value, 4),
+        "unit": "Gsite/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "Delta on one su(3) link field (4 x 8 reals per site), 32^3x64 lattice, eps=0.4 "
+                               "links (seed 1), Gaussian field, FP64, periodic",
+                   "lattice": list(Lb), "n_rhs": 1, "launch_config": dict(zip(
+                       ("form", "block", "xcd_remap", "nv", "order", "walk", "ns", "tile2"), cfg)),
+                   "value_definition": "lattice sites through Delta per second (one link field per application)"},
+        "roofline": roofline,
+        **({} if solves is None else {"rational_solve": solves, "hot_path_step": hot}),
+        **extras,
+    }
+    if cpu is not None:
+        result["cpu_baseline"] = cpu
+    print(json.dumps(result), flush=True)
+
+
+def second_half(args, api, inputs, torch, np, dev):
+    """The rational solves to 1e-10 (FP64 against mixed precision), one pass of the whole hot path and
+    the per-component figures, all on the 16^4 workload."""
     L = (16, 16, 16, 16)
-    V = api.volume(L)
-    log("generating inputs")
     U = inputs.random_links(L, "eps", 0.5, seed=2)
     P = inputs.gaussian_fields(L, 1, seed=2)
     U_aos = U.to(dev)
     Pd = P.to(dev)
-    rat = api.rational_kappa(args.kappa, 12)
-    solver = api.Solver(tol=1e-10, mode=1)
-
-    # stencil launch configurations for the shapes of the step (outside the timed region)
     Ud = api.pack_links(L, U_aos)
     U32 = api.pack_links(L, U_aos, torch.float32)
+    solves = d2_solves(api, inputs, torch, dev, L, Ud, Pd)
+    hot = hot_path_step(api, torch, dev, L, U_aos, Ud, U32, Pd, args.kappa, args.steps_hot)
+    extras = {}
+    if not args.no_extras:
+        extras = run_extras(api, inputs, torch, np, dev, L, U_aos, Ud, Pd)
+    return solves, hot, extras
+
+
+def hot_path_step(api, torch, dev, L, U_aos, Ud, U32, Pd, kappa, steps):
+    """Every stage of the path on the 16^4 workload (one Gaussian momentum field): pack the links,
+    the 12-pole kinetic force in mixed precision (both solves to 1e-10, the link derivative), the
+    degree-64/16-window FP32 power spectrum of the force, the degree-32/4-window filter of the momentum
+    on a second stream; timed over `steps` passes, then the same passes on one stream with HIP events
+    around every launch for the kernel-class shares."""
+    V = api.volume(L)
+    rat = api.rational_kappa(kappa, 12)
+    solver = api.Solver(tol=1e-10, mode=1)
     api.autotune_laplacian(L, Ud, Pd, reps=10)
     api.autotune_laplacian(L, U32, Pd.float(), reps=10)
-    # the solver's FP64 true-residual check applies Delta to all 12 shift solutions in one launch
-    api.autotune_laplacian(L, Ud, Pd.expand(12, -1, -1, -1).contiguous(), reps=5)
+    api.autotune_laplacian(L, Ud, Pd.expand(12, -1, -1, -1).contiguous(), reps=5, purpose="cg64")
     ws = torch.empty(api.workspace_bytes(6, L, 0, 1, 12, 0, 1), dtype=torch.uint8, device=dev)
-
-    # the momentum filter needs only P and the links: it runs on a second stream (default
-    # priority) beside the force and its spectrum, whose short CG kernels leave the GPU room
     side = torch.cuda.Stream(device=dev)
 
     def step(overlap=True):
@@ -163,7 +379,6 @@ def main():
             with torch.cuda.stream(side):
                 api.cheb_filter(L, Uw, Pd, 32, 4)
         out = api.kinetic_force(L, Uw, Pd, rat, solver, ws=ws)
-        # spectrum: FP32 stencil sweeps, FP64 moment sums (as the batched spectra)
         api.power_spectrum(L, api.convert_f64_f32(Uw), api.convert_f64_f32(out["dK"]), 64, 16)
         if overlap:
             main.wait_stream(side)
@@ -171,78 +386,32 @@ def main():
             api.cheb_filter(L, Uw, Pd, 32, 4)
         return out
 
-    log(f"warmup {args.warmup}")
-    for _ in range(args.warmup):
+    for _ in range(2):
         last = step()
     torch.cuda.synchronize()
-    log(f"timing {args.steps} steps")
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         last = step()
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_step = (t1 - t0) / args.steps * 1e3
-    # the same steps again with HIP events around every launch of the instrumented kernel classes
-    # (the events add launch gaps, so the step time above is taken without them), on one stream,
-    # so that every launch's duration is its own and not shared with the overlapped filter
+    ms = (time.perf_counter() - t0) / steps * 1e3
     api.profile_enable(True)
-    tp0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         step(overlap=False)
     torch.cuda.synchronize()
-    ms_step_profiled = (time.perf_counter() - tp0) / args.steps * 1e3
     prof = {c: api.profile_read(c) for c in api.PROF_CLASSES}
     api.profile_enable(False)
-    fields_per_step = prof["stencil"]["items"] / args.steps
-    value = V * fields_per_step / (ms_step * 1e-3) / 1e9
-    log(f"{ms_step:.2f} ms/step, {fields_per_step:.0f} link-field stencil applications per step")
-
-    # dominant kernel class of the step by event time
-    dom = max(prof, key=lambda c: prof[c]["ms"])
-    d = prof[dom]
-    traffic, traffic_src = stencil_traffic(dom)
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(d["gbs"], 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(d["gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "traffic_source": traffic_src,
-                "avg_launch_ms": d["avg_ms"], "bytes_per_launch": d["bytes"] / max(d["launches"], 1),
-                "launches": d["launches"],
-                "measured_over": f"a second pass of the {args.steps} timed steps on one stream with HIP "
-                                 f"events ({ms_step_profiled:.3f} ms/step with the events)"}
-    shares = {c: round(prof[c]["ms"] / max(sum(p["ms"] for p in prof.values()), 1e-12), 4) for c in prof}
-
-    extras = {}
-    if not args.no_extras:
-        extras = run_extras(api, inputs, torch, np, dev, L, U_aos, Ud, Pd)
-
-    result = {
-        "metric": METRIC,
-        "value": round(value, 4),
-        "unit": "Gsite/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32+f64",
-        "data": "synthetic",
-        "config": {"workload": "RMHMC kinetic-force evaluation, 16^4 lattice, eps=0.5 links (seed 2), "
-                               f"one Gaussian momentum field, 12-pole kappa={args.kappa} rational to FP64 true "
-                               "residual 1e-10 (FP32 + FP64 reliable updates), force, degree-64/16-window power "
-                               "spectrum (FP32 sweeps, FP64 moments), degree-32/4-window FP64 filter of the "
-                               "momentum on a second stream",
-                   "lattice": list(L), "n_rhs": 1, "poles": 12, "kappa": args.kappa,
-                   "value_definition": "sites x link fields through Delta per second, whole step"},
-        "roofline": roofline,
-        "kernel_time_share": shares,
-        "stats_last_step": last["stats"],
-        **extras,
-    }
-    if not args.no_cpu_baseline:
-        log("cpu baseline")
-        result["cpu_baseline"] = cpu_baseline(U, P, L)
-    print(json.dumps(result), flush=True)
+    tot = max(sum(p["ms"] for p in prof.values()), 1e-12)
+    st = prof["stencil"]
+    out = {"ms": round(ms, 3), "steps": steps, "lattice": list(L), "poles": 12, "kappa": kappa,
+           "stencil_applications": st["items"] / steps,
+           "gsite_s_through_delta": round(V * st["items"] / steps / (ms * 1e-3) / 1e9, 3),
+           "stencil": {"avg_launch_ms": round(st["avg_ms"], 5), "GBs": round(st["gbs"], 1),
+                       "hbm_frac": round(st["gbs"] / HBM_PEAK_GBS, 4),
+                       "working_set": "71 MB, resident in the 256 MB Infinity Cache"},
+           "kernel_time_share": {c: round(prof[c]["ms"] / tot, 4) for c in prof},
+           "stats_last_step": last["stats"]}
+    log(f"hot path step 16^4: {out}")
+    return out
 
 
 def _median_ms(fn, torch, reps=5):
@@ -303,7 +472,7 @@ def d1_laplacian(api, inputs, torch, dev, copy_gbs):
                 "gsite_s": round(gsite, 3), "avg_ms": round(p["avg_ms"], 4), "achieved_GBs": round(p["gbs"], 1),
                 "hbm_frac": round(p["gbs"] / HBM_PEAK_GBS, 4), "copy_frac": round(p["gbs"] / copy_gbs, 4),
                 "bytes_per_site": 112 * ts, "rotating_sets": nset,
-                "config": dict(zip(("form", "block", "xcd_remap", "nv", "order", "walk"), cfg))}
+                "config": dict(zip(("form", "block", "xcd_remap", "nv", "order", "walk", "ns", "tile2"), cfg))}
             log(f"D-1 {key} {name}: {out[key][name]}")
             del sets, Ud, Fd
         del U, F
@@ -314,6 +483,14 @@ def d2_solves(api, inputs, torch, dev, L, Ud, Pd):
     """Rational solve alone, time to FP64 true residual 1e-10: FP64 against mixed precision."""
     solves = {}
     P8 = inputs.gaussian_fields(L, 8, seed=22).to(dev)
+    # launch configurations of the solves' stencils (outside the timed calls): the CG iterations in
+    # each precision and the FP64 residuals (reliable updates, the true residuals of all 12 shifts)
+    U32 = api.convert_f64_f32(Ud)
+    for n, src in ((1, Pd), (8, P8)):
+        api.autotune_laplacian(L, Ud, src, reps=5, purpose="cg")
+        api.autotune_laplacian(L, U32, src.float(), reps=5, purpose="cg")
+        api.autotune_laplacian(L, Ud, src, reps=5, purpose="cg64")
+        api.autotune_laplacian(L, Ud, src.repeat(12, 1, 1, 1), reps=3, purpose="cg64")
     for kappa in (0.9, 0.5):
         rat = api.rational_kappa(kappa, 12)
         for n, src in ((1, Pd), (8, P8)):
@@ -513,7 +690,6 @@ def run_extras(api, inputs, torch, np, dev, L, U_aos, Ud, Pd):
     out["copy_1GiB"] = cp
     log(f"copy: {cp}")
     out["D1_laplacian"] = d1_laplacian(api, inputs, torch, dev, cp["GBs"])
-    out["D2_rational_solve_time_to_1e-10"] = d2_solves(api, inputs, torch, dev, L, Ud, Pd)
     out["D3_power_spectrum_24x24x24x24"] = d3_spectrum(api, inputs, torch, dev)
     out["D4_kinetic_force_16x16x16x16"] = d4_force(api, inputs, torch, dev)
     out["D5_force_step_32x32x32x64"] = d5_force_step(api, inputs, torch, dev)

@@ -281,12 +281,17 @@ rmh_status rmh_rational_apply(const int32_t L[4], const double* U, const double*
                               double* K, rmh_stats* stats, void* ws, size_t ws_bytes, rmh_stream stream);
 
 /* RMHMC heat-bath momenta for the kinetic term 1/2 P M^{-1} P with M = R(Delta)^{-2} (section 3):
- * P = M^{1/2} xi = R(Delta)^{-1} xi for Gaussian xi.  rat must be a pole set with
- * R(Delta)^2 ~ (1 - kappa + kappa Delta)^{-1} (rmh_rational_kappa(kappa, n)), so that
- * R^{-1} ~ (1 - kappa + kappa Delta) R: one multi-shift solve (to the solver's true residual)
- * and one stencil.  xi, P: device FP64 [n_rhs][4][8][V]; U: device FP64.  kappa in (0, 1].
- * Workspace: RMH_OP_HEATBATH (aux = n_poles, degree = solver basis, mode).  Synchronizes the
- * stream.  Projection onto a spectral window (section 3) is rmh_cheb_filter of P. */
+ * P = M^{1/2} xi = R(Delta)^{-1} xi for Gaussian xi.
+ * kappa in (0, 1]: rat must be a pole set with R(Delta)^2 ~ (1 - kappa + kappa Delta)^{-1}
+ * (rmh_rational_kappa(kappa, n)), and R^{-1} is taken as (1 - kappa + kappa Delta) R, exact to the
+ * pole set's accuracy: one multi-shift solve (to the solver's true residual) and one stencil.
+ * kappa = 0: R^{-1} exactly, for any rat with c >= 0, r_j > 0 and distinct sigma_j > 0, through the
+ * partial fractions 1/R(l) = a l + b + sum_k rho_k / (l + tau_k) (tau_k > 0 the negated zeros of R,
+ * n_poles - 1 of them for c = 0, n_poles for c > 0; RMH_E_POLES when R has no such form): one
+ * multi-shift solve with the shifts tau_k and one stencil, exact to the solver's tolerance.
+ * xi, P: device FP64 [n_rhs][4][8][V]; U: device FP64.  Workspace: RMH_OP_HEATBATH (aux = n_poles,
+ * degree = solver basis, mode).  Synchronizes the stream.  Projection onto a spectral window
+ * (section 3) is rmh_cheb_filter of P. */
 rmh_status rmh_heatbath_momenta(const int32_t L[4], const double* U, const double* xi, int32_t n_rhs, double kappa,
                                 const rmh_rational* rat, const rmh_solver* solver, double* P, rmh_stats* stats,
                                 void* ws, size_t ws_bytes, rmh_stream stream);
@@ -367,32 +372,83 @@ rmh_status rmh_leapfrog_step(const int32_t L[4], const double* U0, const double*
 /* ---------------------------------------------------------------------------------------- */
 /* stencil launch tuning */
 
-/* Fix the stencil launch configuration used for lattice L, dtype and launches over n_rhs link
- * fields: form 0 = adjoint 8x8 action R(U) built per hop, 1 = 3x3 matrix products U phi U^dag,
- * 2 = R(U) built and applied two columns at a time; block = 64, 128 or 256 threads; xcd_remap = 1
- * maps consecutive lattice blocks onto one XCD (L2 locality); nv = 4, 2 or 1 directions per thread
- * (1 with form 1 only, and block * nv / 4 a multiple of the 64-wide wave; else RMH_E_ARG);
+/* A stencil launch configuration.  form 0 = adjoint 8x8 action R(U) built per hop, 1 = 3x3 matrix
+ * products U phi U^dag, 2 = R(U) built and applied two columns at a time; block = 64, 128 or 256
+ * threads; xcd_remap = 1 maps consecutive lattice blocks onto one XCD (L2 locality); nv = 4, 2 or 1
+ * directions per thread (1 with form 1 only, and block * nv / 4 a multiple of the 64-wide wave);
  * order = 1 visits the blocks with x3 fastest (x2/x3 neighbours resident together; used when
  * L0*L1 is a multiple of the sites per block); order = 2 splits each site over four lanes, one per
  * direction mu, summed by wave shuffles (four times the threads, for small lattices; walk is then
  * ignored), and order = 3 is that shape visiting its blocks with x3 fastest (as order 1); walk =
  * K > 0 makes each thread walk K consecutive x3 sites carrying the x3 neighbours in registers
- * (used when K divides L3); order outside [0, 3] is RMH_E_ARG.  Every configuration
- * computes the same operator; a form fixes the per-site arithmetic, so results are bitwise
- * identical across block sizes, remaps, nv, orders 0 and 1 and walks of one form (orders 2 and 3
- * sum the eight hops in another order: equal to rounding). */
-rmh_status rmh_tune_set(const int32_t L[4], int32_t dtype, int32_t n_rhs, int32_t form, int32_t block,
-                        int32_t xcd_remap, int32_t nv, int32_t order, int32_t walk);
-/* Time every stencil configuration on the caller's buffers and keep the fastest for (L, dtype,
- * n_rhs).  One timing unit is the pair of launches the drivers use, the plain y = (8 - H) x (CG)
- * and the recursion step y = -H x / 4 - x (Chebyshev sweeps), both writing y (overwritten); reps
- * units each, HIP events on the stream.  best (optional host int32[6]) receives (form, block,
- * xcd_remap, nv, order, walk); best_ms (optional) the mean time of one unit.  RMH_E_ARG for null
- * pointers or y overlapping x or U.  Synchronizes the stream. */
+ * (used when K divides L3); ns = 2 or 4 (nv = 4, form 0 or 2, order 0 or 1, no walk; 4 in FP32
+ * only) makes each thread apply the operator to ns fields of a batch, so each link and adjoint
+ * matrix serves 4 ns vectors (used when ns divides the batch); tile2 = 2 or 4 (with a walk) gives
+ * each walking block an L0 x R x tile2 tile of (x0, x1, x2) columns instead of consecutive
+ * columns, so part of its x2 neighbours are its own (used when the tile divides the plane).  Every
+ * configuration computes the
+ * same operator; a form fixes the per-site arithmetic, so results are bitwise identical across
+ * block sizes, remaps, nv, ns, orders 0 and 1 and walks of one form (orders 2 and 3 sum the eight
+ * hops in another order: equal to rounding). */
+typedef struct {
+  int32_t form, block, xcd_remap, nv, order, walk, ns, tile2;
+} rmh_hop_config;
+
+/* What a stencil launch is for: the drivers look up their configurations under these purposes
+ * (an entry stored for RMH_PURPOSE_ANY serves every purpose without one of its own). */
+typedef enum {
+  RMH_PURPOSE_ANY = -1,
+  RMH_PURPOSE_APPLY = 0,     /* rmh_laplacian_apply */
+  RMH_PURPOSE_CG = 1,        /* multi-shift CG iterations in the working precision */
+  RMH_PURPOSE_CG64 = 2,      /* FP64 residuals: reliable updates, true residuals, refinement */
+  RMH_PURPOSE_MOMENTS = 3,   /* power-spectrum sweeps (recursion step with FP64 dot products) */
+  RMH_PURPOSE_FILTER = 4,    /* vector-filter sweeps (recursion step) */
+  RMH_PURPOSE_CHEB_BWD = 5,  /* backward Chebyshev sweeps */
+  RMH_PURPOSE_HEATBATH = 6   /* the Delta of the heat-bath momenta */
+} rmh_purpose;
+
+/* Store the configuration for lattice L, dtype, launches over n_rhs link fields and a purpose
+ * (RMH_E_ARG for an invalid configuration or purpose).  Lookups take the entry of that key, else the
+ * RMH_PURPOSE_ANY entry of that batch, else the nearest batch size of the purpose, else of
+ * RMH_PURPOSE_ANY, else built-in defaults by lattice size, dtype and batch. */
+rmh_status rmh_tune_set(const int32_t L[4], int32_t dtype, int32_t n_rhs, int32_t purpose, const rmh_hop_config* cfg);
+/* Time every stencil configuration on the caller's buffers and keep the fastest for (L, dtype, n_rhs,
+ * purpose).  The timing unit: for RMH_PURPOSE_MOMENTS, _FILTER and _CHEB_BWD the recursion step
+ * y = -H x / 4 - x; for _APPLY, _CG, _CG64 and _HEATBATH the plain y = (8 - H) x; for _ANY both (the
+ * pair); reps units each, HIP events on the stream, y overwritten.  best (optional, host) receives
+ * the configuration, best_ms (optional) the mean time of one unit.  RMH_E_ARG for null pointers or y
+ * overlapping x or U.  Synchronizes the stream. */
 rmh_status rmh_autotune_laplacian(const int32_t L[4], const void* U, int32_t dtype, const void* x, void* y,
-                                  int32_t n_rhs, int32_t reps, int32_t* best, double* best_ms, rmh_stream stream);
+                                  int32_t n_rhs, int32_t purpose, int32_t reps, rmh_hop_config* best,
+                                  double* best_ms, rmh_stream stream);
+/* Write every stored configuration to a JSON file at path (host), stamped with the current
+ * device's architecture name (gcnArchName) and the HIP runtime version; *n_saved (optional) receives
+ * the entry count.  RMH_E_HOST if the file cannot be written. */
+rmh_status rmh_tune_save(const char* path, int32_t* n_saved);
+/* Read a file written by rmh_tune_save and store its entries, if its architecture and runtime
+ * version match the current device's (else nothing is stored and *n_loaded = 0); *n_loaded
+ * (optional) receives the count stored.  RMH_E_HOST if the file cannot be read, RMH_E_ARG if it
+ * is not such a file or holds an invalid configuration. */
+rmh_status rmh_tune_load(const char* path, int32_t* n_loaded);
 /* Forget every stored configuration. */
 rmh_status rmh_tune_clear(void);
+
+/* ---------------------------------------------------------------------------------------- */
+/* Link displacements (section 2: links vary by left multiplication with exp(i omega^c T^c)) */
+
+/* U1_mu(x) = exp(i omega^c_mu(x) T^c) U0_mu(x) for every link.  U0, U1: device FP64 SoA links
+ * [4][18][V] (U1 must not overlap U0); omega: device FP64 [4][8][V].  The exponential is summed by
+ * scaling and squaring of its Taylor series, so U1 stays in SU(3) to rounding. */
+rmh_status rmh_link_exp(const int32_t L[4], const double* U0, const double* omega, double* U1, rmh_stream stream);
+
+/* The chain rule through that displacement: out = J(omega)^T g per link, where g is the derivative
+ * of a function f with respect to a left-multiplication displacement at the displaced links
+ * exp(i omega.T) U0 (what the backward calls return) and out the derivative of
+ * f(exp(i omega.T) U0) with respect to omega itself.  J is the left-trivialised differential of
+ * the exponential map, J = sum_k M^k / (k+1)!, (M v)^d = f^{adc} omega^a v^c.  omega, g, out: device
+ * FP64 [4][8][V]; out may alias g.  Converges for |omega| up to about 10 per link. */
+rmh_status rmh_link_exp_vjp(const int32_t L[4], const double* omega, const double* g, double* out,
+                            rmh_stream stream);
 
 /* ---------------------------------------------------------------------------------------- */
 /* kernel timing */

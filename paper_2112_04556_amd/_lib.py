@@ -39,6 +39,14 @@ class RmhSolver(ctypes.Structure):
                 ("mixed_switch", c_f64), ("basis", c_i32), ("multishift_target", c_f64)]
 
 
+class RmhHopConfig(ctypes.Structure):
+    _fields_ = [("form", c_i32), ("block", c_i32), ("xcd_remap", c_i32), ("nv", c_i32), ("order", c_i32),
+                ("walk", c_i32), ("ns", c_i32), ("tile2", c_i32)]
+
+    def as_tuple(self):
+        return tuple(getattr(self, k) for k, _ in self._fields_)
+
+
 class RmhStats(ctypes.Structure):
     _fields_ = [("iters", c_i32), ("reliable_updates", c_i32), ("refine_iters", c_i32),
                 ("refine_rounds", c_i32), ("fp64_iters", c_i32), ("reserved", c_i32),
@@ -94,8 +102,13 @@ SIGNATURES = {
     "rmh_rational_apply_bwd": (c_i32, [P_i32, c_vp, c_vp, c_vp, c_i32, ctypes.POINTER(RmhRational),
                                        ctypes.POINTER(RmhSolver), c_vp, c_vp, c_i32, ctypes.POINTER(RmhStats),
                                        c_vp, c_sz, c_vp]),
-    "rmh_tune_set": (c_i32, [P_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32]),
-    "rmh_autotune_laplacian": (c_i32, [P_i32, c_vp, c_i32, c_vp, c_vp, c_i32, c_i32, P_i32, P_f64, c_vp]),
+    "rmh_link_exp": (c_i32, [P_i32, c_vp, c_vp, c_vp, c_vp]),
+    "rmh_link_exp_vjp": (c_i32, [P_i32, c_vp, c_vp, c_vp, c_vp]),
+    "rmh_tune_set": (c_i32, [P_i32, c_i32, c_i32, c_i32, ctypes.POINTER(RmhHopConfig)]),
+    "rmh_autotune_laplacian": (c_i32, [P_i32, c_vp, c_i32, c_vp, c_vp, c_i32, c_i32, c_i32,
+                                       ctypes.POINTER(RmhHopConfig), P_f64, c_vp]),
+    "rmh_tune_save": (c_i32, [ctypes.c_char_p, P_i32]),
+    "rmh_tune_load": (c_i32, [ctypes.c_char_p, P_i32]),
     "rmh_tune_clear": (c_i32, []),
     "rmh_profile_enable": (c_i32, [c_i32]),
     "rmh_profile_read": (c_i32, [c_i32, ctypes.POINTER(c_i64), P_f64, P_f64, P_f64]),

@@ -8,6 +8,7 @@ follow the C entry points without the ``rmh_`` prefix.  Layouts are those of
 from __future__ import annotations
 
 import ctypes
+import os
 from dataclasses import dataclass
 from typing import Optional
 
@@ -21,8 +22,8 @@ __all__ = [
     "Rational", "Solver", "pack_links", "unpack_links", "pack_fields", "unpack_fields", "convert_f64_f32",
     "laplacian_apply", "laplacian_apply_bwd", "cheb_coefficients", "power_spectrum", "power_ratio",
     "trace_moments_free", "cheb_filter", "rational_from_quadratics", "rational_kappa", "rational_apply",
-    "rational_apply_bwd", "kinetic_force", "workspace_bytes", "volume", "tune_set", "tune_clear",
-    "autotune_laplacian", "profile_enable", "profile_read", "PROF_CLASSES",
+    "rational_apply_bwd", "kinetic_force", "workspace_bytes", "volume", "tune_set", "tune_clear", "link_exp", "link_exp_vjp",
+    "autotune_laplacian", "tune_save", "tune_load", "PURPOSES", "profile_enable", "profile_read", "PROF_CLASSES",
 ]
 
 
@@ -201,7 +202,6 @@ def power_spectrum(L, U, F, degree: int, n_windows: int, edges=None, kernel: int
     return mom, pw
 
 
-
 def power_ratio(degree: int, n_windows: int, trace_moments, power, edges=None, kernel: int = 1) -> np.ndarray:
     st, keep = _cheb(degree, n_windows, edges, kernel)
     tm = np.ascontiguousarray(trace_moments, dtype=np.float64)
@@ -276,7 +276,8 @@ def power_spectrum_bwd(L, U, F, gamma, degree: int, n_windows: int, edges=None, 
 
 
 def heatbath_momenta(L, U, xi, kappa: float, rat: Rational, solver: Solver = Solver()):
-    """dict(P, stats): P = R(Delta)^{-1} xi for a pole set with R^2 ~ (1 - kappa + kappa Delta)^{-1}."""
+    """dict(P, stats): P = R(Delta)^{-1} xi; kappa > 0: as (1 - kappa + kappa Delta) R(Delta) xi for a pole set
+    with R^2 ~ (1 - kappa + kappa Delta)^{-1}; kappa = 0: exactly, through the partial fractions of 1/R."""
     _require_f64(U, xi)
     n = xi.shape[0]
     P = torch.empty_like(xi)
@@ -400,29 +401,77 @@ def leapfrog_step(L, U, P, rat: Rational, eps: float, beta: float, solver: Solve
 
 
 # ------------------------------------------------------------------------------------------
+# link displacements
+
+def link_exp(L, U, omega: torch.Tensor) -> torch.Tensor:
+    """exp(i omega.T) U per link (rmh_link_exp): U SoA FP64 (4, 18, V), omega FP64 (4, 8, V)."""
+    _require_f64(U, omega)
+    out = torch.empty_like(U)
+    check(lib().rmh_link_exp(lattice_arg(L), _dev(U, "U"), _dev(omega, "omega"), _dev(out, "U1"),
+                             _stream(U.device)), "rmh_link_exp")
+    return out
+
+
+def link_exp_vjp(L, omega: torch.Tensor, g: torch.Tensor) -> torch.Tensor:
+    """J(omega)^T g per link (rmh_link_exp_vjp): the derivative with respect to omega of a function
+    of exp(i omega.T) U from its left-multiplication derivative g at the displaced links."""
+    _require_f64(omega, g)
+    out = torch.empty_like(g)
+    check(lib().rmh_link_exp_vjp(lattice_arg(L), _dev(omega, "omega"), _dev(g, "g"), _dev(out, "out"),
+                                 _stream(g.device)), "rmh_link_exp_vjp")
+    return out
+
+
+# ------------------------------------------------------------------------------------------
 # stencil tuning
 
+PURPOSES = {"any": -1, "apply": 0, "cg": 1, "cg64": 2, "moments": 3, "filter": 4, "cheb_bwd": 5, "heatbath": 6}
+
+
+def _purpose(purpose) -> int:
+    return PURPOSES[purpose] if isinstance(purpose, str) else int(purpose)
+
+
 def tune_set(L, dtype, n_rhs: int, form: int, block: int = 256, xcd_remap: int = 1, nv: int = 4,
-             order: int = 0, walk: int = 0) -> None:
+             order: int = 0, walk: int = 0, ns: int = 1, purpose="any", tile2: int = 1) -> None:
+    """Store a stencil launch configuration for (L, dtype, n_rhs, purpose) (rmh_tune_set)."""
     code = RMH_F64 if dtype == torch.float64 else RMH_F32
-    check(lib().rmh_tune_set(lattice_arg(L), code, int(n_rhs), int(form), int(block), int(xcd_remap), int(nv),
-                             int(order), int(walk)), "rmh_tune_set")
+    cfg = L_.RmhHopConfig(int(form), int(block), int(xcd_remap), int(nv), int(order), int(walk), int(ns),
+                          int(tile2))
+    check(lib().rmh_tune_set(lattice_arg(L), code, int(n_rhs), _purpose(purpose), ctypes.byref(cfg)),
+          "rmh_tune_set")
 
 
 def tune_clear() -> None:
     check(lib().rmh_tune_clear(), "rmh_tune_clear")
 
 
-def autotune_laplacian(L, U, x, reps: int = 5):
-    """((form, block, xcd_remap, nv, order, walk), ms) of the fastest configuration, now stored; ms is
-    the mean time of one timing unit (a plain application and a Chebyshev recursion step)."""
+def tune_save(path: str) -> int:
+    """Write the stored configurations to a JSON file (stamped with the device architecture and HIP
+    runtime version); returns the entry count."""
+    n = ctypes.c_int32(0)
+    check(lib().rmh_tune_save(os.fsencode(path), ctypes.byref(n)), "rmh_tune_save")
+    return n.value
+
+
+def tune_load(path: str) -> int:
+    """Store the configurations of a file written by tune_save if it was written for this device
+    architecture and HIP runtime; returns the count stored (0 for another device or runtime)."""
+    n = ctypes.c_int32(0)
+    check(lib().rmh_tune_load(os.fsencode(path), ctypes.byref(n)), "rmh_tune_load")
+    return n.value
+
+
+def autotune_laplacian(L, U, x, reps: int = 5, purpose="any"):
+    """((form, block, xcd_remap, nv, order, walk, ns, tile2), ms) of the fastest configuration for x's batch
+    and the purpose, now stored; ms is the mean time of one timing unit."""
     y = torch.empty_like(x)
-    best = (L_.c_i32 * 6)()
+    best = L_.RmhHopConfig()
     ms = ctypes.c_double()
     check(lib().rmh_autotune_laplacian(lattice_arg(L), _dev(U, "U"), _dtype_code(x), _dev(x, "x"), _dev(y, "y"),
-                                       x.shape[0], int(reps), best, ctypes.byref(ms), _stream(x.device)),
-          "rmh_autotune_laplacian")
-    return tuple(best[i] for i in range(6)), ms.value
+                                       x.shape[0], _purpose(purpose), int(reps), ctypes.byref(best),
+                                       ctypes.byref(ms), _stream(x.device)), "rmh_autotune_laplacian")
+    return best.as_tuple(), ms.value
 
 
 # ------------------------------------------------------------------------------------------

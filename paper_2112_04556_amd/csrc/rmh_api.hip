@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -461,12 +462,14 @@ rmh_status engine_solve(Engine& e, const double* U64, const float* U32, const do
       if (seed[v] != seed[0]) return fail(RMH_E_ARG, "internal: non-uniform seed shift");
     HIP_TRY(hipMemcpyAsync(e.params, hp.data(), hp.size(), hipMemcpyHostToDevice, s));
   }
-  const HopConfig c32 = hop_config(g, RMH_F32, nr, 1);
-  const HopConfig c64 = hop_config(g, RMH_F64, nr, 2);
+  // iterations in each precision, and the FP64 residual of the reliable updates
+  const HopConfig c32 = hop_config(g, RMH_F32, nr, RMH_PURPOSE_CG);
+  const HopConfig c64 = hop_config(g, RMH_F64, nr, RMH_PURPOSE_CG);
+  const HopConfig cru = hop_config(g, RMH_F64, nr, RMH_PURPOSE_CG64);
   const int32_t nblk_32 = hop_num_blocks(g, c32), nblk_64 = hop_num_blocks(g, c64);
   CgDev cg64 = cg_view(e, nblk_64, false);
   CgDev cg32 = cg_view(e, nblk_32, true);
-  cg32.nblk_ru = nblk_64;
+  cg32.nblk_ru = hop_num_blocks(g, cru);
 
   bool fp32_phase = mixed && !(switch_rel > 0.0);
   // a seed solution kept outside the ring starts from zero; the flushes write x of the others
@@ -603,7 +606,7 @@ rmh_status engine_solve(Engine& e, const double* U64, const float* U32, const do
         // now its FP64 residual; the stencil's bytes are added once the update count is known
         {
           ProfScope ps(RMH_PROF_STENCIL, 0.0, s, 0.0);
-          HIP_TRY(launch_hop<double>(hr, c64, s));
+          HIP_TRY(launch_hop<double>(hr, cru, s));
         }
       }
     }
@@ -663,7 +666,7 @@ rmh_status true_residuals(Engine& e, const double* U64, const double* b, const d
                           const std::vector<double>& bnorm, hipStream_t s, std::vector<double>* res) {
   const Geom& g = e.g;
   const int32_t nr = e.n_rhs, ns = e.n_shift;
-  const HopConfig c64 = hop_config(g, RMH_F64, nr * ns, 2);
+  const HopConfig c64 = hop_config(g, RMH_F64, nr * ns, RMH_PURPOSE_CG64);
   const int32_t nblk = hop_num_blocks(g, c64);
   HopArgs<double> h{};
   h.g = g;
@@ -754,6 +757,7 @@ rmh_status solve_all(SolvePlan& sp, const double* U64, const double* b, double* 
   const int64_t n = field_reals(g);
   const int32_t nr = e.n_rhs, ns = e.n_shift;
   const int32_t mode = e.mode;
+  if ((int64_t)sig.size() != ns) return fail(RMH_E_ARG, "internal: %zu shifts for a %d-shift plan", sig.size(), ns);
   if (mode) HIP_TRY(launch_f64_to_f32(U64, sp.U32, (int64_t)72 * g.V, s));
   std::vector<double> sigma((size_t)nr * ns);
   for (int v = 0; v < nr; ++v)
@@ -823,7 +827,7 @@ rmh_status solve_all(SolvePlan& sp, const double* U64, const double* b, double* 
       h.store = 1;
       {
         ProfScope ps(RMH_PROF_STENCIL, hop_bytes(g, nb, 8, true, true), s, nb);
-        HIP_TRY(launch_hop<double>(h, hop_config(g, RMH_F64, nb, 2), s));
+        HIP_TRY(launch_hop<double>(h, hop_config(g, RMH_F64, nb, RMH_PURPOSE_CG64), s));
       }
       Engine& re = rp.eng;
       re.n_rhs = nb;
@@ -952,7 +956,7 @@ template <typename T>
 rmh_status power_spectrum_t(const Geom& g, const T* U, const T* F, int32_t n_rhs, int32_t D,
                                    const ChebPlan& cp, std::vector<double>* sums_h, bool direct_copy, hipStream_t s) {
   const int32_t K = std::max(1, (D + 1) / 2);
-  const HopConfig cfg = hop_config(g, sizeof(T) == 8 ? RMH_F64 : RMH_F32, n_rhs, 3);
+  const HopConfig cfg = hop_config(g, sizeof(T) == 8 ? RMH_F64 : RMH_F32, n_rhs, RMH_PURPOSE_MOMENTS);
   const int32_t nblk = hop_num_blocks(g, cfg);
   T* A = (T*)cp.bufA;
   T* B = (T*)cp.bufB;
@@ -1003,7 +1007,7 @@ rmh_status power_spectrum_t(const Geom& g, const T* U, const T* F, int32_t n_rhs
 template <typename T>
 rmh_status cheb_filter_t(const Geom& g, const T* U, const T* x, int32_t n_rhs, int32_t D, int32_t nw,
                          const std::vector<double>& coef, const FilterPlan& fp, T* y, hipStream_t s) {
-  const HopConfig cfg = hop_config(g, sizeof(T) == 8 ? RMH_F64 : RMH_F32, n_rhs, 4);
+  const HopConfig cfg = hop_config(g, sizeof(T) == 8 ? RMH_F64 : RMH_F32, n_rhs, RMH_PURPOSE_FILTER);
   const int64_t n = (int64_t)n_rhs * 32 * g.V;
   RMH_TRY(h2d(fp.coef, coef.data(), coef.size() * sizeof(double), s));
   T* ring = (T*)fp.ring;
@@ -1087,7 +1091,7 @@ rmh_status cheb_bwd(const Geom& g, const double* U, const double* x, int32_t n_r
     RMH_TRY(h2d(p.coef, up.data(), up.size() * 8, s));
   }
   const double* coef_x = p.coef + (size_t)n_rhs * n_y * nk;
-  const HopConfig cfg = hop_config(g, RMH_F64, n_rhs, 5);
+  const HopConfig cfg = hop_config(g, RMH_F64, n_rhs, RMH_PURPOSE_CHEB_BWD);
   auto hop = [&](const double* in, const double* z, double* out, double a, double c) -> rmh_status {
     HopArgs<double> h{};
     h.g = g;
@@ -1170,7 +1174,7 @@ rmh_status cheb_bwd(const Geom& g, const double* U, const double* x, int32_t n_r
 // writing y, so the pick fits the solves and the spectra alike.
 template <typename T>
 static hipError_t tune_unit(const Geom& g, const T* U, const T* x, T* y, int32_t n_rhs, const HopConfig& cfg,
-                            hipStream_t s) {
+                            int32_t kind, hipStream_t s) {
   HopArgs<T> h{};
   h.g = g;
   h.U = U;
@@ -1178,17 +1182,22 @@ static hipError_t tune_unit(const Geom& g, const T* U, const T* x, T* y, int32_t
   h.x_mul = 1;
   h.out = y;
   h.z_div = 1;
-  h.a = -1.0;
-  h.b = 8.0;
   h.n_rhs = n_rhs;
   h.store = 1;
-  hipError_t e = launch_hop<T>(h, cfg, s);
-  if (e != hipSuccess) return e;
-  h.a = -0.25;
-  h.b = 0.0;
-  h.c = -1.0;
-  h.z = x;
-  return launch_hop<T>(h, cfg, s);
+  if (kind & 1) {   // the plain application y = (8 - H) x
+    h.a = -1.0;
+    h.b = 8.0;
+    hipError_t e = launch_hop<T>(h, cfg, s);
+    if (e != hipSuccess) return e;
+  }
+  if (kind & 2) {   // the recursion step y = -H x / 4 - x
+    h.a = -0.25;
+    h.b = 0.0;
+    h.c = -1.0;
+    h.z = x;
+    return launch_hop<T>(h, cfg, s);
+  }
+  return hipSuccess;
 }
 
 // degree and window count, checked before any host buffer is sized by them
@@ -1201,11 +1210,10 @@ static rmh_status check_cheb_dims(const rmh_cheb* cheb, int32_t min_degree, int3
   return RMH_OK;
 }
 
-// The power spectrum on a given workspace.  static_ws: nothing is allocated (the sums come back by a
-// plain copy into host memory instead of the pinned stage).
+// The power spectrum on a given workspace.
 static rmh_status power_spectrum_impl(const int32_t L[4], const void* U, int32_t dtype, const void* F,
                                       int32_t n_rhs, const rmh_cheb* cheb, double* moments, double* power,
-                                      void* ws, size_t ws_bytes, bool static_ws, rmh_stream stream) {
+                                      void* ws, size_t ws_bytes, rmh_stream stream) {
   Geom g;
   RMH_TRY(make_geom(L, &g));
   RMH_TRY(check_dtype(dtype));
@@ -1228,9 +1236,9 @@ static rmh_status power_spectrum_impl(const int32_t L[4], const void* U, int32_t
   std::vector<double> sums;
   hipStream_t s = (hipStream_t)stream;
   if (dtype == RMH_F64)
-    RMH_TRY(power_spectrum_t<double>(g, (const double*)U, (const double*)F, n_rhs, D, cp, &sums, static_ws, s));
+    RMH_TRY(power_spectrum_t<double>(g, (const double*)U, (const double*)F, n_rhs, D, cp, &sums, false, s));
   else
-    RMH_TRY(power_spectrum_t<float>(g, (const float*)U, (const float*)F, n_rhs, D, cp, &sums, static_ws, s));
+    RMH_TRY(power_spectrum_t<float>(g, (const float*)U, (const float*)F, n_rhs, D, cp, &sums, false, s));
   // moments from the doubling identities
   std::vector<double> mu((size_t)n_rhs * (2 * K + 1));
   for (int32_t n = 0; n < n_rhs; ++n) {
@@ -1410,7 +1418,7 @@ rmh_status rmh_laplacian_apply(const int32_t L[4], const void* U, int32_t dtype,
   RMH_TRY(check_ptr(y, "y"));
   const size_t fb = (size_t)n_rhs * 32 * g.V * dsize(dtype), ub = (size_t)72 * g.V * dsize(dtype);
   if (overlap(x, fb, y, fb) || overlap(U, ub, y, fb)) return fail(RMH_E_ARG, "y overlaps x or U");
-  const HopConfig cfg = hop_config(g, dtype, n_rhs, 0);
+  const HopConfig cfg = hop_config(g, dtype, n_rhs, RMH_PURPOSE_APPLY);
   if (dtype == RMH_F64) {
     HopArgs<double> h{};
     h.g = g;
@@ -1530,7 +1538,7 @@ rmh_status rmh_trace_moments_free(const int32_t L[4], int32_t degree, double* tr
 rmh_status rmh_power_spectrum(const int32_t L[4], const void* U, int32_t dtype, const void* F, int32_t n_rhs,
                               const rmh_cheb* cheb, double* moments, double* power, void* ws, size_t ws_bytes,
                               rmh_stream stream) try {
-  return power_spectrum_impl(L, U, dtype, F, n_rhs, cheb, moments, power, ws, ws_bytes, false, stream);
+  return power_spectrum_impl(L, U, dtype, F, n_rhs, cheb, moments, power, ws, ws_bytes, stream);
 } catch (...) {   // no C++ exception crosses the C ABI
   return fail(RMH_E_HOST, "host-side failure (out of host memory?)");
 }
@@ -1767,15 +1775,26 @@ rmh_status rmh_heatbath_momenta(const int32_t L[4], const double* U, const doubl
   const double t0 = now_s();
   Geom g;
   RMH_TRY(rational_common(L, U, n_rhs, rat, solver, &g));
-  if (!(kappa > 0.0 && kappa <= 1.0)) return fail(RMH_E_ARG, "kappa = %g must lie in (0, 1]", kappa);
+  if (!(kappa >= 0.0 && kappa <= 1.0)) return fail(RMH_E_ARG, "kappa = %g must lie in [0, 1]", kappa);
+  // kappa = 0: P = R(Delta)^{-1} xi through the partial fractions of 1/R,
+  // a Delta + b + sum_k rho_k (Delta + tau_k)^{-1}
+  const int32_t np = rat->n_poles;
+  double ia = 0.0, ib = 0.0;
+  std::vector<double> rho(np), tau(np);
+  int32_t m = 0;
+  if (kappa == 0.0 &&
+      rational_inverse(rat->c, np, rat->r, rat->sigma, &ia, &ib, rho.data(), tau.data(), &m) != 0)
+    return fail(RMH_E_POLES, "1/R(Delta) has no partial-fraction form with positive shifts (needs c >= 0, r_j > 0, "
+                             "distinct sigma_j > 0)");
   if (n_rhs == 0) return RMH_OK;
   RMH_TRY(check_ptr(xi, "xi"));
   RMH_TRY(check_ptr(P, "P"));
   RMH_TRY(check_ptr(ws, "ws"));
-  const int32_t np = rat->n_poles;
   Carver c(ws);
   RationalPlan rp;
-  plan_rational(c, rp, g, n_rhs, np, solver->mode, solver->basis, RMH_OP_HEATBATH);
+  // the exact inverse solves over the m shifts tau_k (m <= n_poles, within the queried workspace)
+  plan_rational(c, rp, g, n_rhs, kappa == 0.0 ? std::max(m, 1) : np, solver->mode, solver->basis,
+                RMH_OP_HEATBATH);
   if (c.off > ws_bytes) return fail(RMH_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, c.off);
   const int64_t n = field_reals(g);
   const size_t fb = (size_t)n_rhs * n * 8;
@@ -1783,29 +1802,49 @@ rmh_status rmh_heatbath_momenta(const int32_t L[4], const double* U, const doubl
       overlap(ws, c.off, xi, fb) || overlap(ws, c.off, U, (size_t)72 * g.V * 8))
     return fail(RMH_E_ARG, "overlapping buffers");
   hipStream_t s = (hipStream_t)stream;
-  std::vector<double> sig(rat->sigma, rat->sigma + np);
   SolveResult res;
-  RMH_TRY(solve_all(rp.sp, U, xi, rp.X, sig, *solver, s, &res));
-  std::vector<double> coef(np + 1);
-  coef[0] = rat->c;
-  for (int j = 0; j < np; ++j) coef[1 + j] = rat->r[j];
-  RMH_TRY(h2d(rp.coef, coef.data(), coef.size() * 8, s));
-  HIP_TRY(launch_rational_combine(xi, rp.X, n_rhs, np, rp.coef, rp.Y, n, nullptr, s));
-  // P = (1 - kappa) y + kappa Delta y = -kappa H y + (1 + 7 kappa) y,  y = R(Delta) xi
   HopArgs<double> h{};
   h.g = g;
   h.U = U;
-  h.x = rp.Y;
   h.x_mul = 1;
   h.z_div = 1;
   h.out = P;
-  h.a = -kappa;
-  h.b = 1.0 + 7.0 * kappa;
   h.n_rhs = n_rhs;
   h.store = 1;
+  if (kappa > 0.0) {
+    std::vector<double> sig(rat->sigma, rat->sigma + np);
+    RMH_TRY(solve_all(rp.sp, U, xi, rp.X, sig, *solver, s, &res));
+    std::vector<double> coef(np + 1);
+    coef[0] = rat->c;
+    for (int j = 0; j < np; ++j) coef[1 + j] = rat->r[j];
+    RMH_TRY(h2d(rp.coef, coef.data(), coef.size() * 8, s));
+    HIP_TRY(launch_rational_combine(xi, rp.X, n_rhs, np, rp.coef, rp.Y, n, nullptr, s));
+    // P = (1 - kappa) y + kappa Delta y = -kappa H y + (1 + 7 kappa) y,  y = R(Delta) xi
+    h.x = rp.Y;
+    h.a = -kappa;
+    h.b = 1.0 + 7.0 * kappa;
+  } else {
+    // Y = b xi + sum_k rho_k (Delta + tau_k)^{-1} xi, then P = a Delta xi + Y = -a H xi + 8 a xi + Y
+    if (m > 0) {
+      std::vector<double> sig(tau.begin(), tau.begin() + m);
+      RMH_TRY(solve_all(rp.sp, U, xi, rp.X, sig, *solver, s, &res));
+      std::vector<double> coef(m + 1);
+      coef[0] = ib;
+      for (int k = 0; k < m; ++k) coef[1 + k] = rho[k];
+      RMH_TRY(h2d(rp.coef, coef.data(), coef.size() * 8, s));
+      HIP_TRY(launch_rational_combine(xi, rp.X, n_rhs, m, rp.coef, rp.Y, n, nullptr, s));
+      h.z = rp.Y;
+      h.c = 1.0;
+      h.b = 8.0 * ia;
+    } else {
+      h.b = 8.0 * ia + ib;
+    }
+    h.x = xi;
+    h.a = -ia;
+  }
   {
-    ProfScope ps(RMH_PROF_STENCIL, hop_bytes(g, n_rhs, 8, false, true), s, n_rhs);
-    HIP_TRY(launch_hop<double>(h, hop_config(g, RMH_F64, n_rhs, 6), s));
+    ProfScope ps(RMH_PROF_STENCIL, hop_bytes(g, n_rhs, 8, h.z != nullptr, true), s, n_rhs);
+    HIP_TRY(launch_hop<double>(h, hop_config(g, RMH_F64, n_rhs, RMH_PURPOSE_HEATBATH), s));
   }
   HIP_TRY(hipStreamSynchronize(s));
   fill_stats(stats, &res, 1, now_s() - t0);
@@ -2086,26 +2125,96 @@ rmh_status rmh_leapfrog_step(const int32_t L[4], const double* U0, const double*
   return fail(RMH_E_HOST, "host-side failure (out of host memory?)");
 }
 
-rmh_status rmh_tune_set(const int32_t L[4], int32_t dtype, int32_t n_rhs, int32_t form, int32_t block,
-                        int32_t xcd_remap, int32_t nv, int32_t order, int32_t walk) try {
+rmh_status rmh_link_exp(const int32_t L[4], const double* U0, const double* omega, double* U1, rmh_stream stream) try {
+  Geom g;
+  RMH_TRY(make_geom(L, &g));
+  RMH_TRY(check_ptr(U0, "U0"));
+  RMH_TRY(check_ptr(omega, "omega"));
+  RMH_TRY(check_ptr(U1, "U1"));
+  const size_t ub = (size_t)72 * g.V * 8, wb = (size_t)32 * g.V * 8;
+  if (overlap(U0, ub, U1, ub) || overlap(omega, wb, U1, ub)) return fail(RMH_E_ARG, "U1 overlaps U0 or omega");
+  HIP_TRY(launch_link_exp(g, U0, omega, nullptr, 1.0, U1, (hipStream_t)stream));
+  return RMH_OK;
+} catch (...) {   // no C++ exception crosses the C ABI
+  return fail(RMH_E_HOST, "host-side failure (out of host memory?)");
+}
+
+rmh_status rmh_link_exp_vjp(const int32_t L[4], const double* omega, const double* g_, double* out,
+                            rmh_stream stream) try {
+  Geom g;
+  RMH_TRY(make_geom(L, &g));
+  RMH_TRY(check_ptr(omega, "omega"));
+  RMH_TRY(check_ptr(g_, "g"));
+  RMH_TRY(check_ptr(out, "out"));
+  const size_t wb = (size_t)32 * g.V * 8;
+  if (overlap(omega, wb, out, wb)) return fail(RMH_E_ARG, "out overlaps omega");
+  if (out != g_ && overlap(g_, wb, out, wb)) return fail(RMH_E_ARG, "out partially overlaps g");
+  HIP_TRY(launch_dexp_vjp(g, omega, g_, out, (hipStream_t)stream));
+  return RMH_OK;
+} catch (...) {   // no C++ exception crosses the C ABI
+  return fail(RMH_E_HOST, "host-side failure (out of host memory?)");
+}
+
+static HopConfig from_abi(const rmh_hop_config& c) {
+  HopConfig h;
+  h.form = c.form;
+  h.block = c.block;
+  h.xcd_remap = c.xcd_remap;
+  h.nv = c.nv;
+  h.order = c.order;
+  h.walk = c.walk;
+  h.ns = c.ns;
+  h.tile2 = c.tile2;
+  return h;
+}
+
+static rmh_hop_config to_abi(const HopConfig& h) {
+  rmh_hop_config c;
+  c.form = h.form;
+  c.block = h.block;
+  c.xcd_remap = h.xcd_remap;
+  c.nv = h.nv;
+  c.order = h.order;
+  c.walk = h.walk;
+  c.ns = h.ns;
+  c.tile2 = h.tile2;
+  return c;
+}
+
+static rmh_status check_purpose(int32_t purpose) {
+  if (purpose < RMH_PURPOSE_ANY || purpose > RMH_PURPOSE_HEATBATH)
+    return fail(RMH_E_ARG, "purpose = %d outside [%d, %d]", purpose, (int)RMH_PURPOSE_ANY, (int)RMH_PURPOSE_HEATBATH);
+  return RMH_OK;
+}
+
+// architecture name of the current device and the HIP runtime version, the stamp of a tuning file
+// ("no-device" on a host without a GPU, where the cache can still be saved and loaded)
+static rmh_status device_stamp(std::string* arch, int32_t* runtime) {
+  int dev = 0, ndev = 0;
+  *arch = "no-device";
+  if (hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0) {
+    HIP_TRY(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    *arch = prop.gcnArchName;
+  }
+  (void)hipGetLastError();
+  int rt = 0;
+  if (hipRuntimeGetVersion(&rt) != hipSuccess) rt = 0;
+  *runtime = rt;
+  return RMH_OK;
+}
+
+rmh_status rmh_tune_set(const int32_t L[4], int32_t dtype, int32_t n_rhs, int32_t purpose, const rmh_hop_config* cfg) try {
   Geom g;
   RMH_TRY(make_geom(L, &g));
   RMH_TRY(check_dtype(dtype));
-  if (form < kFormAdjoint || form > kFormStream) return fail(RMH_E_ARG, "form must be 0, 1 or 2");
-  if (block != 64 && block != 128 && block != 256) return fail(RMH_E_ARG, "block must be 64, 128 or 256");
-  if (nv != 1 && nv != 2 && nv != 4) return fail(RMH_E_ARG, "nv must be 1, 2 or 4");
-  if (nv == 1 && form != kFormMatrix) return fail(RMH_E_ARG, "nv = 1 needs form 1 (3x3 products)");
-  if ((block * nv / 4) % 64) return fail(RMH_E_ARG, "block * nv / 4 must be a multiple of 64");
-  HopConfig c;
-  c.form = form;
-  c.block = block;
-  c.xcd_remap = xcd_remap ? 1 : 0;
-  c.nv = nv;
-  if (order < 0 || order > 3) return fail(RMH_E_ARG, "order must be 0, 1, 2 or 3");
-  c.order = order;
-  if (walk < 0 || walk > 64) return fail(RMH_E_ARG, "walk must be in [0, 64]");
-  c.walk = walk;
-  tune_store(g, dtype, n_rhs, c);
+  RMH_TRY(check_purpose(purpose));
+  if (n_rhs < 1) return fail(RMH_E_ARG, "n_rhs must be >= 1");
+  if (!cfg) return fail(RMH_E_ARG, "cfg is NULL");
+  const HopConfig c = from_abi(*cfg);
+  if (const char* why = hop_config_error(c, dtype)) return fail(RMH_E_ARG, "%s", why);
+  tune_store(g, dtype, n_rhs, purpose, c, 0.0);
   return RMH_OK;
 } catch (...) {   // no C++ exception crosses the C ABI
   return fail(RMH_E_HOST, "host-side failure (out of host memory?)");
@@ -2118,11 +2227,37 @@ rmh_status rmh_tune_clear(void) try {
   return fail(RMH_E_HOST, "host-side failure (out of host memory?)");
 }
 
+rmh_status rmh_tune_save(const char* path, int32_t* n_saved) try {
+  if (!path) return fail(RMH_E_ARG, "path is NULL");
+  std::string arch;
+  int32_t rt = 0;
+  RMH_TRY(device_stamp(&arch, &rt));
+  if (tune_save_file(path, arch, rt, n_saved) != 0) return fail(RMH_E_HOST, "cannot write %s", path);
+  return RMH_OK;
+} catch (...) {   // no C++ exception crosses the C ABI
+  return fail(RMH_E_HOST, "host-side failure (out of host memory?)");
+}
+
+rmh_status rmh_tune_load(const char* path, int32_t* n_loaded) try {
+  if (!path) return fail(RMH_E_ARG, "path is NULL");
+  std::string arch;
+  int32_t rt = 0;
+  RMH_TRY(device_stamp(&arch, &rt));
+  const int r = tune_load_file(path, arch, rt, n_loaded);
+  if (r == -1) return fail(RMH_E_HOST, "cannot read %s", path);
+  if (r == -2) return fail(RMH_E_ARG, "%s is not a valid tuning file", path);
+  return RMH_OK;
+} catch (...) {   // no C++ exception crosses the C ABI
+  return fail(RMH_E_HOST, "host-side failure (out of host memory?)");
+}
+
 rmh_status rmh_autotune_laplacian(const int32_t L[4], const void* U, int32_t dtype, const void* x, void* y,
-                                  int32_t n_rhs, int32_t reps, int32_t* best, double* best_ms, rmh_stream stream) try {
+                                  int32_t n_rhs, int32_t purpose, int32_t reps, rmh_hop_config* best, double* best_ms,
+                                  rmh_stream stream) try {
   Geom g;
   RMH_TRY(make_geom(L, &g));
   RMH_TRY(check_dtype(dtype));
+  RMH_TRY(check_purpose(purpose));
   if (n_rhs < 1 || reps < 1) return fail(RMH_E_ARG, "n_rhs and reps must be >= 1");
   RMH_TRY(check_ptr(U, "U"));
   RMH_TRY(check_ptr(x, "x"));
@@ -2131,15 +2266,22 @@ rmh_status rmh_autotune_laplacian(const int32_t L[4], const void* U, int32_t dty
     const size_t fb = (size_t)n_rhs * 32 * g.V * dsize(dtype), ub = (size_t)72 * g.V * dsize(dtype);
     if (overlap(x, fb, y, fb) || overlap(U, ub, y, fb)) return fail(RMH_E_ARG, "y overlaps x or U");
   }
+  // timing unit: 1 = plain application, 2 = recursion step, 3 = both
+  const int32_t unit_kind = (purpose == RMH_PURPOSE_MOMENTS || purpose == RMH_PURPOSE_FILTER ||
+                             purpose == RMH_PURPOSE_CHEB_BWD)
+                                ? 2
+                                : (purpose == RMH_PURPOSE_ANY ? 3 : 1);
   hipStream_t s = (hipStream_t)stream;
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
-  HopConfig bestc;
+  HopConfig bestc = tune_hop(g, dtype, n_rhs, purpose);
   float bt = 1e30f;
   rmh_status st = RMH_OK;
   for (int form = 0; form < 3 && st == RMH_OK; ++form)
     for (int nv : {4, 2, 1})
+    for (int ns : {1, 2, 4})
+    for (int tile2 : {1, 2, 4})
     for (int block : {64, 128, 256})
     for (int walk : {0, 4, 8, 16})
     for (int order = 0; order < 4 && st == RMH_OK; ++order) {
@@ -2151,15 +2293,18 @@ rmh_status rmh_autotune_laplacian(const int32_t L[4], const void* U, int32_t dty
         c.nv = nv;
         c.order = order;
         c.walk = walk;
+        c.ns = ns;
+        c.tile2 = tile2;
+        if (hop_config_error(c, dtype)) continue;
+        if (ns > 1 && n_rhs % ns) continue;
         if ((order == 1 || order == 3) && !hop_order_ok(g, c)) continue;
         if (walk && (order || !hop_walk_ok(g, c))) continue;
-        if ((block * nv / 4) % 64) continue;  // direction groups must be whole waves
-        if (nv == 1 && form != kFormMatrix) continue;
-        tune_store(g, dtype, n_rhs, c);
+        tune_store(g, dtype, n_rhs, purpose, c, 0.0);
         auto unit = [&]() -> rmh_status {
-          const hipError_t e = dtype == RMH_F64
-                                   ? tune_unit<double>(g, (const double*)U, (const double*)x, (double*)y, n_rhs, c, s)
-                                   : tune_unit<float>(g, (const float*)U, (const float*)x, (float*)y, n_rhs, c, s);
+          const hipError_t e =
+              dtype == RMH_F64
+                  ? tune_unit<double>(g, (const double*)U, (const double*)x, (double*)y, n_rhs, c, unit_kind, s)
+                  : tune_unit<float>(g, (const float*)U, (const float*)x, (float*)y, n_rhs, c, unit_kind, s);
           return e == hipSuccess ? RMH_OK : fail(RMH_E_HIP, "stencil launch: %s", hipGetErrorString(e));
         };
         st = unit();  // warm-up
@@ -2175,8 +2320,8 @@ rmh_status rmh_autotune_laplacian(const int32_t L[4], const void* U, int32_t dty
         if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) ms = 1e30f;
         ms /= reps;
         if (log_level() > 0)
-          fprintf(stderr, "[rmh] tune L=%dx%dx%dx%d dtype=%d n=%d form=%d nv=%d block=%d order=%d walk=%d xcd=%d: %.4f ms\n",
-                  g.L0, g.L1, g.L2, g.L3, dtype, n_rhs, form, nv, block, order, walk, xcd, ms);
+          fprintf(stderr, "[rmh] tune L=%dx%dx%dx%d dtype=%d n=%d purpose=%d form=%d nv=%d ns=%d block=%d order=%d walk=%d tile2=%d xcd=%d: %.4f ms\n",
+                  g.L0, g.L1, g.L2, g.L3, dtype, n_rhs, purpose, form, nv, ns, block, order, walk, tile2, xcd, ms);
         if (ms < bt) {
           bt = ms;
           bestc = c;
@@ -2186,15 +2331,8 @@ rmh_status rmh_autotune_laplacian(const int32_t L[4], const void* U, int32_t dty
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st != RMH_OK) return st;
-  tune_store(g, dtype, n_rhs, bestc);
-  if (best) {
-    best[0] = bestc.form;
-    best[1] = bestc.block;
-    best[2] = bestc.xcd_remap;
-    best[3] = bestc.nv;
-    best[4] = bestc.order;
-    best[5] = bestc.walk;
-  }
+  tune_store(g, dtype, n_rhs, purpose, bestc, bt);
+  if (best) *best = to_abi(bestc);
   if (best_ms) *best_ms = bt;
   return RMH_OK;
 } catch (...) {   // no C++ exception crosses the C ABI

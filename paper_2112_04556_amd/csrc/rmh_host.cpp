@@ -4,6 +4,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
+#include <cmath>
 #include <vector>
 
 #include "rmh_host.h"
@@ -105,6 +107,99 @@ int rational_kappa(double kappa, int32_t n, double* c, double* r, double* sigma)
     const double ct = cos(t), tt = tan(t);
     r[j - 1] = sqrt(s) / (n * kappa * ct * ct);
     sigma[j - 1] = (1.0 - kappa + s * tt * tt) / kappa;
+  }
+  return 0;
+}
+
+int rational_inverse(double c, int32_t n, const double* r, const double* sigma, double* a, double* b, double* rho,
+                     double* tau, int32_t* m) {
+  if (n < 1 || !(c >= 0.0)) return -1;
+  std::vector<double> sg(sigma, sigma + n), rr(r, r + n);
+  // poles sorted by sigma (ascending), each with its residue
+  std::vector<int> ord(n);
+  for (int j = 0; j < n; ++j) ord[j] = j;
+  std::sort(ord.begin(), ord.end(), [&](int i, int j) { return sg[i] < sg[j]; });
+  std::vector<double> s_(n), r_(n);
+  for (int j = 0; j < n; ++j) {
+    s_[j] = sg[ord[j]];
+    r_[j] = rr[ord[j]];
+    if (!(r_[j] > 0.0) || !(s_[j] > 0.0)) return -1;
+    if (j && !(s_[j] > s_[j - 1])) return -1;
+  }
+  auto R = [&](double l) {
+    double v = c;
+    for (int j = 0; j < n; ++j) v += r_[j] / (l + s_[j]);
+    return v;
+  };
+  auto dR = [&](double l) {
+    double v = 0.0;
+    for (int j = 0; j < n; ++j) v -= r_[j] / ((l + s_[j]) * (l + s_[j]));
+    return v;
+  };
+  // R decreases strictly between neighbouring poles, from +inf to -inf: one zero in each gap
+  // (-s_{j+1}, -s_j), found by bisection to the last bit; for c > 0 one more below -s_{n-1}
+  std::vector<double> z;
+  auto bisect = [&](double lo, double hi) {   // R(lo) > 0 > R(hi)
+    for (int it = 0; it < 400; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (mid <= lo || mid >= hi) break;
+      if (R(mid) > 0.0)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    return 0.5 * (lo + hi);
+  };
+  for (int j = 0; j + 1 < n; ++j) {
+    const double w = s_[j + 1] - s_[j];
+    double lo = -s_[j + 1] + 1e-300, hi = -s_[j] - 1e-300;
+    // step inside the gap until the signs are established
+    double e = w * 1e-3;
+    while (!(R(-s_[j + 1] + e) > 0.0) && e > 1e-300) e *= 0.5;
+    lo = -s_[j + 1] + e;
+    e = w * 1e-3;
+    while (!(R(-s_[j] - e) < 0.0) && e > 1e-300) e *= 0.5;
+    hi = -s_[j] - e;
+    if (!(R(lo) > 0.0 && R(hi) < 0.0)) return -1;
+    z.push_back(bisect(lo, hi));
+  }
+  if (c > 0.0) {
+    // below the lowest pole R -> c > 0 at -inf and -> -inf at -s_{n-1}
+    double e = 1e-3 * s_[n - 1];
+    while (!(R(-s_[n - 1] - e) < 0.0) && e > 1e-300) e *= 0.5;
+    const double hi = -s_[n - 1] - e;
+    double lo = hi - 1.0;
+    while (!(R(lo) > 0.0)) {
+      lo = hi - 2.0 * (hi - lo);
+      if (lo < -1e300) return -1;
+    }
+    if (!(R(hi) < 0.0)) return -1;
+    z.push_back(bisect(lo, hi));
+  }
+  *m = (int32_t)z.size();
+  for (size_t k = 0; k < z.size(); ++k) {
+    tau[k] = -z[k];
+    rho[k] = 1.0 / dR(z[k]);
+    if (!(tau[k] > 0.0) || !(rho[k] < 0.0)) return -1;
+  }
+  // polynomial part: 1/R(l) - sum_k rho_k/(l + tau_k) = a l + b; for c = 0, a = 1/S1 and
+  // b = S2/S1^2 + sum ... fixed by the values at two points instead (exact for a polynomial of degree 1)
+  auto rest = [&](double l) {
+    double v = 1.0 / R(l);
+    for (size_t k = 0; k < z.size(); ++k) v -= rho[k] / (l + tau[k]);
+    return v;
+  };
+  const double f0 = rest(0.0), f16 = rest(16.0);
+  *a = (f16 - f0) / 16.0;
+  *b = f0;
+  if (c > 0.0) *a = 0.0;
+  // the form must reproduce 1/R across the spectrum [0, 16]
+  for (int q = 0; q <= 32; ++q) {
+    const double l = 0.5 * q;
+    double v = *a * l + *b;
+    for (size_t k = 0; k < z.size(); ++k) v += rho[k] / (l + tau[k]);
+    const double ref = 1.0 / R(l);
+    if (!(std::fabs(v - ref) <= 1e-11 * std::fabs(ref))) return -1;
   }
   return 0;
 }

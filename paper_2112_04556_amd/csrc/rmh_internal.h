@@ -38,6 +38,12 @@ enum HopForm : int32_t { kFormAdjoint = 0, kFormMatrix = 1, kFormStream = 2 };
 // walk = K > 0: each thread walks K consecutive sites along x3 (K divides L3), carrying the
 // centre field, the x-3 field and the x-3 link in registers, so every x3-direction field and
 // link is fetched once per column instead of being re-read from the caches.
+// ns = S > 1 (with nv = 4, orders 0 and 1, no walk; S divides the batch): each thread applies the
+// operator at its site to S fields of the batch, so every link it loads and every adjoint matrix it
+// builds serves 4 S vectors instead of 4 (form 0: the 8x8 matrix is built once per hop and the
+// fields are streamed through it one at a time; form 2: its column pairs are built once per hop
+// and applied to all 4 S vectors).  The per-vector arithmetic is that of nv = 4, so results are
+// bitwise those of ns = 1 with the same form.
 struct HopConfig {
   int32_t form = kFormStream;
   int32_t block = 256;
@@ -45,6 +51,8 @@ struct HopConfig {
   int32_t nv = 4;
   int32_t order = 0;
   int32_t walk = 0;
+  int32_t ns = 1;
+  int32_t tile2 = 1;   // walk only: 2 or 4 gives each block an L0 x R1 x tile2 tile of columns
 };
 
 // out[v] = a * (H x)[v] + b_v * x[v] + c * z[v / z_div]   for v in [0, n_rhs) link fields,
@@ -76,6 +84,8 @@ int hop_order_ok(const Geom& g, const HopConfig& cfg);
 int hop_split_ok(const HopConfig& cfg);
 // whether the x3 walk applies (K divides L3)
 int hop_walk_ok(const Geom& g, const HopConfig& cfg);
+// whether the multi-field shape applies (ns > 1 divides n_rhs, nv = 4, no walk, orders 0 and 1)
+int hop_ns_ok(const HopConfig& cfg, int32_t n_rhs);
 // upper bound of hop_num_blocks over every configuration: 16 sites per block at least (the
 // hop-split shape with one direction group per block), plus one partial block per x3 slice of
 // the walking shape; every per-block partial-sum buffer is sized with it
@@ -241,9 +251,12 @@ hipError_t launch_gauge_force(const Geom& g, const double* U, double beta, doubl
                               hipStream_t s);
 
 // Molecular-dynamics link update: U1_mu(x) = exp(i h (A + B)^c_mu(x) T^c) U0_mu(x) for every link
-// (FP64 SoA links, A and B FP64 [4][8][V]; U1 must not overlap U0)
+// (FP64 SoA links, A and B FP64 [4][8][V], B may be null; U1 must not overlap U0)
 hipError_t launch_link_exp(const Geom& g, const double* U0, const double* A, const double* B, double h, double* U1,
                            hipStream_t s);
+// gout = J(omega)^T gin per link ([4][8][V] FP64 each): the derivative of f(exp(i omega.T) U) with
+// respect to omega from the left-multiplication derivative gin at the displaced links
+hipError_t launch_dexp_vjp(const Geom& g, const double* omega, const double* gin, double* gout, hipStream_t s);
 // out = x + h (y - z) over n reals (FP64), with per-block partials of |out - prev|^2 and |out|^2
 // written to partials[0][nblk], partials[1][nblk], nblk = red_num_blocks(n); prev may be out itself
 // (each element is read before it is written, by the same thread)

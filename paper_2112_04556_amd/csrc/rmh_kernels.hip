@@ -1411,7 +1411,7 @@ __global__ void k_link_exp(Geom g, const double* __restrict__ U0, const double* 
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
     const int64_t e = ((int64_t)mu * 8 + c) * V + s;
-    a[c] = h * (A[e] + B[e]);
+    a[c] = h * (B ? A[e] + B[e] : A[e]);
   }
   // H = sum_c a^c lambda^c / 2 (Gell-Mann), Hermitian traceless
   const double r3 = 0.57735026918962576451;   // 1 / sqrt(3)
@@ -1484,6 +1484,62 @@ hipError_t launch_link_exp(const Geom& g, const double* U0, const double* A, con
                            hipStream_t s) {
   dim3 grid((unsigned)((g.V + kBlock - 1) / kBlock), 4);
   hipLaunchKernelGGL(k_link_exp, grid, dim3(kBlock), 0, s, g, U0, A, B, h, U1);
+  return hipGetLastError();
+}
+
+// The transposed left-trivialised differential of the exponential map, per link:
+// out = J(omega)^T g with exp(i(omega + eps e_c).T) = exp(i eps (J e_c).T + O(eps^2)) exp(i omega.T),
+// so that d/d omega f(exp(i omega.T) U) = J^T (the derivative at the displaced link under left
+// multiplication).  In the adjoint representation J = sum_k M^k / (k+1)!, (M v)^d = f^{adc} omega^a v^c,
+// and M is antisymmetric, so J^T g = sum_k t_k with t_0 = g, t_k = (omega x t_{k-1}) / (k + 1) and
+// (p x q)^d = sum f^{acd} p^a q^c.  The series is summed until a term no longer changes the sum
+// (at most 64 terms: enough for |omega| up to about 10).
+__global__ void k_dexp_vjp(Geom g, const double* __restrict__ omega, const double* __restrict__ gin,
+                           double* __restrict__ gout) {
+  const int32_t mu = blockIdx.y;
+  const int64_t V = g.V;
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= V) return;
+  double w[8], t[8], acc[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int64_t e = ((int64_t)mu * 8 + c) * V + s;
+    w[c] = omega[e];
+    t[c] = gin[e];
+    acc[c] = t[c];
+  }
+#pragma unroll 1
+  for (int k = 1; k <= 64; ++k) {
+    double n[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) n[c] = 0.0;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      const int a = kF[q].a, b = kF[q].b, c = kF[q].c;
+      const double f = kF[q].f;
+      // (w x t)_c += f (w_a t_b - w_b t_a), cyclically in (a, b, c)
+      n[c] += f * (w[a] * t[b] - w[b] * t[a]);
+      n[a] += f * (w[b] * t[c] - w[c] * t[b]);
+      n[b] += f * (w[c] * t[a] - w[a] * t[c]);
+    }
+    const double inv = 1.0 / (double)(k + 1);
+    bool changed = false;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      t[c] = n[c] * inv;
+      const double nxt = acc[c] + t[c];
+      changed = changed || (nxt != acc[c]);
+      acc[c] = nxt;
+    }
+    if (!changed) break;
+  }
+#pragma unroll
+  for (int c = 0; c < 8; ++c) gout[((int64_t)mu * 8 + c) * V + s] = acc[c];
+}
+
+hipError_t launch_dexp_vjp(const Geom& g, const double* omega, const double* gin, double* gout, hipStream_t s) {
+  dim3 grid((unsigned)((g.V + kBlock - 1) / kBlock), 4);
+  hipLaunchKernelGGL(k_dexp_vjp, grid, dim3(kBlock), 0, s, g, omega, gin, gout);
   return hipGetLastError();
 }
 

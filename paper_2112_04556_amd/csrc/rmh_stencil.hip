@@ -305,7 +305,7 @@ __global__ void __launch_bounds__(256) k_hop_split(const HopArgs<T> A, int32_t x
 // hops load their links and neighbours as in k_hop; the x3 forward hop loads U_3(x) and
 // phi(x+3), which become the backward link and the centre field of the next step.
 template <typename T, int FORM, int NV, bool DOTS>
-__global__ void __launch_bounds__(256) k_hop_walk(const HopArgs<T> A, int32_t xcd, int32_t K) {
+__global__ void __launch_bounds__(256) k_hop_walk(const HopArgs<T> A, int32_t xcd, int32_t K, int32_t tile2) {
   constexpr int G = 4 / NV;
   const HopBlock hb = hop_block(xcd, A.n_rhs);
   const int32_t v = hb.v;
@@ -318,7 +318,19 @@ __global__ void __launch_bounds__(256) k_hop_walk(const HopArgs<T> A, int32_t xc
   const int32_t chunk = lb % nchunk;
   const int32_t x3_0 = (lb / nchunk) * K;
   const int32_t grp = __builtin_amdgcn_readfirstlane(threadIdx.x / cpb);  // wave-uniform
-  const int32_t col = chunk * cpb + (threadIdx.x - grp * cpb);
+  const int32_t tc = threadIdx.x - grp * cpb;
+  int32_t col;
+  if (tile2 > 1) {
+    // the block's columns form an L0 x R1 x tile2 tile of the (x0, x1, x2) plane (tiles with x1
+    // fastest), so its x2 neighbours are partly its own columns; hop_walk_ok checks the tiling
+    const int32_t R1 = cpb / (A.g.L0 * tile2);
+    const int32_t nc1 = A.g.L1 / R1;
+    const int32_t c1 = chunk % nc1, c2 = chunk / nc1;
+    const int32_t x0 = tc % A.g.L0, r = tc / A.g.L0;
+    col = x0 + A.g.L0 * ((c1 * R1 + r % R1) + A.g.L1 * (c2 * tile2 + r / R1));
+  } else {
+    col = chunk * cpb + tc;
+  }
   const int nu0 = grp * NV;
   double dsum[3] = {0.0, 0.0, 0.0};
   if (col < P) {
@@ -427,8 +439,168 @@ __global__ void __launch_bounds__(256) k_hop_walk(const HopArgs<T> A, int32_t xc
   }
 }
 
+
+// Multi-field variant of k_hop (one thread per site, all four directions): the thread applies the
+// operator at its site to NS consecutive fields of the batch.  The grid is lattice blocks times field
+// groups of NS, laid out as hop_block lays out fields.  Per hop the link is loaded once and its
+// adjoint matrix built once for all 4 NS vectors: form 0 keeps the 8x8 matrix in registers and
+// streams the fields through it one at a time (registers: the matrix, one field, the NS
+// accumulators); form 2 builds each column pair once and applies it to all 4 NS vectors.  Term order
+// and per-vector arithmetic are those of k_hop, so every field's result is bitwise that of k_hop with
+// the same form.
+template <typename T, int FORM, int NS, bool kT>
+__device__ __forceinline__ void hop_term_ns(const T* __restrict__ Um, int32_t sl, int32_t sn,
+                                            const T* const (&xf)[NS], int32_t V, T (&acc)[NS * 4][8]) {
+  T u[18];
+  load_link<T>(Um, sl, V, u);
+  if (FORM == kFormAdjoint) {
+    T R[64];
+    adjoint_matrix<T>(u, R);
+#pragma unroll
+    for (int f = 0; f < NS; ++f) {
+      T phi[4][8];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int b = 0; b < 8; ++b) phi[i][b] = (xf[f] + (size_t)(i * 8 + b) * V)[sn];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (!kT)
+          adj_apply<T>(R, phi[i], acc[f * 4 + i]);
+        else
+          adj_apply_t<T>(R, phi[i], acc[f * 4 + i]);
+      }
+    }
+  } else {
+    T phi[NS * 4][8];
+#pragma unroll
+    for (int f = 0; f < NS; ++f)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int b = 0; b < 8; ++b) phi[f * 4 + i][b] = (xf[f] + (size_t)(i * 8 + b) * V)[sn];
+    adj_stream<T, NS * 4, kT>(u, phi, acc);
+  }
+}
+
+template <typename T, int FORM, int NS, bool DOTS>
+__global__ void __launch_bounds__(256) k_hop_ns(const HopArgs<T> A, int32_t xcd, int32_t order) {
+  const int32_t ngrp = A.n_rhs / NS;
+  const HopBlock hb = hop_block(xcd, ngrp);
+  const int32_t v0 = hb.v * NS;
+  bool runs[NS];
+  bool any = false;
+#pragma unroll
+  for (int f = 0; f < NS; ++f) {
+    runs[f] = !A.run || A.run[(int64_t)(v0 + f) * A.run_stride] != 0;
+    any = any || runs[f];
+  }
+  if (!any) return;
+  const int32_t V = A.g.V;
+  const int32_t lb = hb.lb;
+  const int32_t spb = blockDim.x;
+  int32_t blk = lb;
+  if (order) {
+    const int32_t x3 = lb % A.g.L3;
+    const int32_t t = lb / A.g.L3;
+    const int32_t x2 = t % A.g.L2;
+    const int32_t chunk = t / A.g.L2;
+    const int32_t cpp = (A.g.L0 * A.g.L1) / spb;
+    blk = (x3 * A.g.L2 + x2) * cpp + chunk;
+  }
+  const int32_t s = blk * spb + threadIdx.x;
+  double dsum[NS * 3];
+#pragma unroll
+  for (int q = 0; q < NS * 3; ++q) dsum[q] = 0.0;
+  if (s < V) {
+    const int64_t FV = 32 * (int64_t)V;
+    const T* xf[NS];
+#pragma unroll
+    for (int f = 0; f < NS; ++f) xf[f] = A.x + ((int64_t)(v0 + f) * A.x_mul + A.x_add) * FV;
+    const T* __restrict__ U = A.U;
+    T acc[NS * 4][8];
+#pragma unroll
+    for (int i = 0; i < NS * 4; ++i)
+#pragma unroll
+      for (int a = 0; a < 8; ++a) acc[i][a] = T(0);
+    int32_t xc[4];
+    site_coords(A.g, s, xc);
+    // the term order of k_hop: x3 backward, then x0, x1, x2 forward and backward, x3 forward
+#pragma unroll 1
+    for (int mu = 0; mu < 4; ++mu) {
+      const int mb = (mu + 3) & 3;
+      const int32_t sb = site_shift(A.g, s, xc, mb, -1);
+      hop_term_ns<T, FORM, NS, true>(U + (int64_t)mb * 18 * V, sb, sb, xf, V, acc);
+      hop_term_ns<T, FORM, NS, false>(U + (int64_t)mu * 18 * V, s, site_shift(A.g, s, xc, mu, +1), xf, V, acc);
+    }
+    const T ca = T(A.a);
+    const T cc = T(A.c);
+#pragma unroll
+    for (int f = 0; f < NS; ++f) {
+      const int32_t v = v0 + f;
+      const T cb = T(A.b_rhs ? A.b_rhs[v] : A.b);
+      const T* zf = A.z ? A.z + (int64_t)(v / A.z_div) * FV : nullptr;  // may alias out
+      T* outf = A.out + (int64_t)v * FV;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t e0 = (int64_t)(i * 8) * V + s;
+        T xs[8], zv[8];
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+          xs[a] = xf[f][e0 + (int64_t)a * V];
+          zv[a] = zf ? zf[e0 + (int64_t)a * V] : T(0);
+        }
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+          const int64_t e = e0 + (int64_t)a * V;
+          const T xv = xs[a];
+          T o = fmadd(ca, acc[f * 4 + i][a], cb * xv);
+          if (zf) o = fmadd(cc, zv[a], o);
+          if (A.store && runs[f]) outf[e] = o;
+          if (DOTS) {
+            const double xd = (double)xv, od = (double)o;
+            dsum[f * 3 + 0] = fma(xd, xd, dsum[f * 3 + 0]);
+            dsum[f * 3 + 1] = fma(od, xd, dsum[f * 3 + 1]);
+            dsum[f * 3 + 2] = fma(od, od, dsum[f * 3 + 2]);
+          }
+        }
+      }
+    }
+  }
+  if (DOTS) {
+    __shared__ double lds[NS * 3][16];
+    block_sum<NS * 3>(dsum, lds);
+    if (threadIdx.x == 0) {
+      const int32_t nblk = hb.nblk;
+#pragma unroll
+      for (int f = 0; f < NS; ++f) {
+        if (!runs[f]) continue;
+        double* p = A.partials + (int64_t)(v0 + f) * 3 * nblk + lb;
+        if (A.dot_mask & 1) p[0] = dsum[f * 3 + 0];
+        if (A.dot_mask & 2) p[nblk] = dsum[f * 3 + 1];
+        if (A.dot_mask & 4) p[2 * nblk] = dsum[f * 3 + 2];
+      }
+    }
+  }
+}
+
 int hop_walk_ok(const Geom& g, const HopConfig& cfg) {
-  return (cfg.walk > 0 && (g.L3 % cfg.walk) == 0) ? 1 : 0;
+  if (!(cfg.walk > 0 && (g.L3 % cfg.walk) == 0)) return 0;
+  if (cfg.tile2 > 1) {
+    // an L0 x R1 x tile2 column tile per block that tiles the (x0, x1, x2) plane exactly
+    const int cpb = cfg.block * cfg.nv / 4;
+    if (cpb % (g.L0 * cfg.tile2) || g.L2 % cfg.tile2) return 0;
+    const int R1 = cpb / (g.L0 * cfg.tile2);
+    if (R1 < 1 || g.L1 % R1) return 0;
+  }
+  return 1;
+}
+
+int hop_ns_ok(const HopConfig& cfg, int32_t n_rhs) {
+  return (cfg.ns > 1 && n_rhs % cfg.ns == 0 && cfg.nv == 4 && cfg.walk == 0 && (cfg.order == 0 || cfg.order == 1) &&
+          (cfg.form == kFormAdjoint || cfg.form == kFormStream))
+             ? 1
+             : 0;
 }
 
 // hop-split shape (order 2, or 3 with the x3-fastest block order): each wave covers 16 sites
@@ -465,6 +637,26 @@ static hipError_t launch_hop_form(const HopArgs<T>& A, const HopConfig& cfg, hip
   const bool dots = A.partials && A.dot_mask;
   // the partial-sum buffers hold hop_max_blocks entries per field and dot product
   if (dots && nblk > hop_max_blocks(A.g)) return hipErrorInvalidValue;
+  if constexpr (NV == 4 && FORM != kFormMatrix) {
+    if (hop_ns_ok(cfg, A.n_rhs)) {
+      const int32_t ord = (cfg.order == 1 && hop_order_ok(A.g, cfg)) ? 1 : 0;
+      dim3 g2((uint32_t)(nblk * (A.n_rhs / cfg.ns)));
+      if (cfg.ns == 2) {
+        if (dots)
+          hipLaunchKernelGGL((k_hop_ns<T, FORM, 2, true>), g2, block, 0, s, A, cfg.xcd_remap, ord);
+        else
+          hipLaunchKernelGGL((k_hop_ns<T, FORM, 2, false>), g2, block, 0, s, A, cfg.xcd_remap, ord);
+      } else if (cfg.ns == 4) {
+        if (dots)
+          hipLaunchKernelGGL((k_hop_ns<T, FORM, 4, true>), g2, block, 0, s, A, cfg.xcd_remap, ord);
+        else
+          hipLaunchKernelGGL((k_hop_ns<T, FORM, 4, false>), g2, block, 0, s, A, cfg.xcd_remap, ord);
+      } else {
+        return hipErrorInvalidValue;
+      }
+      return hipGetLastError();
+    }
+  }
   if (hop_split_ok(cfg)) {
     const int32_t ord = (cfg.order == 3 && hop_order_ok(A.g, cfg)) ? 1 : 0;
     if (dots)
@@ -477,9 +669,9 @@ static hipError_t launch_hop_form(const HopArgs<T>& A, const HopConfig& cfg, hip
   if (hop_walk_ok(A.g, cfg)) {
     const int32_t K = cfg.walk;
     if (dots)
-      hipLaunchKernelGGL((k_hop_walk<T, FORM, NV, true>), grid, block, 0, s, A, cfg.xcd_remap, K);
+      hipLaunchKernelGGL((k_hop_walk<T, FORM, NV, true>), grid, block, 0, s, A, cfg.xcd_remap, K, cfg.tile2);
     else
-      hipLaunchKernelGGL((k_hop_walk<T, FORM, NV, false>), grid, block, 0, s, A, cfg.xcd_remap, K);
+      hipLaunchKernelGGL((k_hop_walk<T, FORM, NV, false>), grid, block, 0, s, A, cfg.xcd_remap, K, cfg.tile2);
     return hipGetLastError();
   }
   if (dots)

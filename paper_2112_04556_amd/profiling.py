@@ -9,6 +9,10 @@ Workloads (run under ``rocprofv3``; each prints what it launched):
     python -m paper_2112_04556_amd.profiling kinetic --L 32 32 32 64 --n 2 --poles 16 --mode 1 --reps 1
         kinetic-force evaluations (kappa = 0.9 pole set, solves to 1e-10) of n momentum fields,
         after one warm-up evaluation
+    python -m paper_2112_04556_amd.profiling spectrum --L 24 24 24 24 --n 32 --degree 16 --windows 64 --dtype f32
+        batched power spectra of n Gaussian sources on Haar links (autotuned first, then one call)
+    python -m paper_2112_04556_amd.profiling solve --L 16 16 16 16 --n 8 --poles 12 --kappa 0.9 --mode 1 --reps 2
+        rational solves (eps = 0.5 links, tol 1e-10) of n Gaussian fields, after one warm-up solve
     python -m paper_2112_04556_amd.profiling leapfrog --L 16 16 16 16 --reps 2
         implicit leapfrog steps (12-pole kappa = 0.9 mass term, beta = 5.5, eps = 0.02) on one
         momentum field, after one warm-up step
@@ -17,7 +21,8 @@ Summaries (run on the host, over the CSV files rocprofv3 wrote):
 
     python -m paper_2112_04556_amd.profiling summarize-trace DIR --prefix rmh::k_hop --last N
     python -m paper_2112_04556_amd.profiling traffic --fetch DIR1 --write DIR2 --prefix rmh::k_hop \
-        --last N --fetch-scale 2.0 --write-scale 1.0 --out FILE.json --command-fetch ... --command-write ...
+        --last N --fetch-scale 2.0 --write-scale 1.0 --out FILE.json --command-fetch ... --command-write ... \
+        [--launch-config FORM BLOCK XCD NV ORDER WALK NS TILE2]
 
 ``traffic`` averages FETCH_SIZE and WRITE_SIZE (KiB per dispatch) over the last N dispatches
 whose kernel name starts with the prefix, scales each by the factor the same counter shows for
@@ -94,7 +99,9 @@ def traffic(fetch_dir: str, write_dir: str, prefix: str, last: int, fetch_scale:
         raise ValueError("no matching dispatches")
     fk = sum(v for _, v in f) / len(f)
     wk = sum(v for _, v in w) / len(w)
-    return {"dispatches": min(len(f), len(w)), "fetch_kib_per_launch": fk, "write_kib_per_launch": wk,
+    names = sorted({n.replace("void ", "").split("(")[0] for n, _ in f + w})
+    return {"dispatches": min(len(f), len(w)), "kernels": names,
+            "fetch_kib_per_launch": fk, "write_kib_per_launch": wk,
             "fetch_scale": fetch_scale, "write_scale": write_scale,
             "traffic_bytes_per_launch": (fk * fetch_scale + wk * write_scale) * 1024.0,
             "stencil_source_sha256": stencil_source_hash()}
@@ -142,6 +149,34 @@ def run_kinetic(L, n: int, poles: int, mode: int, reps: int):
           f"{out['stats']['iters']} solver iterations", flush=True)
 
 
+def run_spectrum(L, n: int, degree: int, windows: int, dtype_name: str, kind: str):
+    import torch
+    from . import api, inputs
+    dt = torch.float64 if dtype_name == "f64" else torch.float32
+    U = api.pack_links(L, inputs.random_links(L, kind, seed=3).to("cuda"), dt)
+    F = inputs.gaussian_fields(L, n, seed=3).to("cuda").to(dt)
+    cfg, ms = api.autotune_laplacian(L, U, F, reps=2)
+    api.power_spectrum(L, U, F, degree, windows)
+    torch.cuda.synchronize()
+    print(f"spectrum {L} n={n} degree={degree} {dtype_name} {kind}: config {cfg}, one call "
+          f"({(degree + 1) // 2} sweeps)", flush=True)
+
+
+def run_solve(L, n: int, poles: int, kappa: float, mode: int, reps: int):
+    import torch
+    from . import api, inputs
+    U = api.pack_links(L, inputs.random_links(L, "eps", 0.5, seed=2).to("cuda"))
+    P = inputs.gaussian_fields(L, n, seed=22).to("cuda")
+    rat = api.rational_kappa(kappa, poles)
+    sv = api.Solver(tol=1e-10, mode=mode)
+    out = None
+    for _ in range(reps + 1):
+        out = api.rational_apply(L, U, P, rat, sv)
+    torch.cuda.synchronize()
+    print(f"solve {L} n={n} poles={poles} kappa={kappa} mode={mode}: {reps + 1} solves, stats {out['stats']}",
+          flush=True)
+
+
 def run_leapfrog(L, reps: int):
     import torch
     from . import api, inputs
@@ -173,6 +208,20 @@ def main(argv=None):
     p.add_argument("--poles", type=int, default=16)
     p.add_argument("--mode", type=int, default=1)
     p.add_argument("--reps", type=int, default=1)
+    p = sub.add_parser("spectrum")
+    p.add_argument("--L", type=int, nargs=4, default=[24, 24, 24, 24])
+    p.add_argument("--n", type=int, default=32)
+    p.add_argument("--degree", type=int, default=16)
+    p.add_argument("--windows", type=int, default=64)
+    p.add_argument("--dtype", choices=["f64", "f32"], default="f32")
+    p.add_argument("--kind", choices=["haar", "unit", "eps"], default="haar")
+    p = sub.add_parser("solve")
+    p.add_argument("--L", type=int, nargs=4, default=[16, 16, 16, 16])
+    p.add_argument("--n", type=int, default=8)
+    p.add_argument("--poles", type=int, default=12)
+    p.add_argument("--kappa", type=float, default=0.9)
+    p.add_argument("--mode", type=int, default=1)
+    p.add_argument("--reps", type=int, default=2)
     p = sub.add_parser("leapfrog")
     p.add_argument("--L", type=int, nargs=4, default=[16, 16, 16, 16])
     p.add_argument("--reps", type=int, default=2)
@@ -191,6 +240,9 @@ def main(argv=None):
     p.add_argument("--command-fetch", default="")
     p.add_argument("--command-write", default="")
     p.add_argument("--workload", default="")
+    p.add_argument("--launch-config", type=int, nargs=8, default=None,
+                   help="the stencil launch configuration of the counted dispatches (form block xcd_remap nv "
+                        "order walk ns tile2)")
     a = ap.parse_args(argv)
     if a.cmd == "copy":
         run_copy()
@@ -200,12 +252,18 @@ def main(argv=None):
         run_leapfrog(tuple(a.L), a.reps)
     elif a.cmd == "stencil":
         run_stencil(tuple(a.L), a.dtype, a.reps)
+    elif a.cmd == "solve":
+        run_solve(tuple(a.L), a.n, a.poles, a.kappa, a.mode, a.reps)
+    elif a.cmd == "spectrum":
+        run_spectrum(tuple(a.L), a.n, a.degree, a.windows, a.dtype, a.kind)
     elif a.cmd == "summarize-trace":
         print(json.dumps(summarize_trace(a.dir, a.prefix, a.last or 10**9), indent=1))
     else:
         t = traffic(a.fetch, a.write, a.prefix, a.last or 10**9, a.fetch_scale, a.write_scale)
         t.update({"workload": a.workload, "command_fetch": a.command_fetch, "command_write": a.command_write,
                   "prefix": a.prefix})
+        if a.launch_config:
+            t["launch_config"] = list(a.launch_config)
         text = json.dumps(t, indent=1)
         if a.out:
             with open(a.out, "w") as fh:

@@ -1,6 +1,7 @@
 """CPU tests of the C ABI: every declared symbol is exported, the host-side FP64 helpers
 agree with the oracle, and argument validation rejects bad calls before any GPU work."""
 import ctypes
+import json
 import os
 import re
 
@@ -169,9 +170,16 @@ def test_heatbath_validation():
     rat = _lib.RmhRational(0.0, 2, r.ctypes.data_as(_lib.P_f64), sg.ctypes.data_as(_lib.P_f64))
     sv = _lib.RmhSolver(1e-10, 100, 0, 0.1, 8, 0.0, 0)
     f = _lib.lib().rmh_heatbath_momenta
-    for kappa in (0.0, 1.5, float("nan")):
+    for kappa in (-0.1, 1.5, float("nan")):
         assert f(L, FAKE, FAKE + 2**20, 1, kappa, ctypes.byref(rat), ctypes.byref(sv), FAKE + 2**21, None,
                  FAKE + 2**22, 1 << 30, None) == 1
+    # kappa = 0 (the exact inverse) takes the partial fractions of 1/R, which this library forms for
+    # positive residues only
+    rn = np.array([1.0, -0.9])
+    bad = _lib.RmhRational(0.0, 2, rn.ctypes.data_as(_lib.P_f64), sg.ctypes.data_as(_lib.P_f64))
+    assert f(L, FAKE, FAKE + 2**20, 1, 0.0, ctypes.byref(bad), ctypes.byref(sv), FAKE + 2**21, None,
+             FAKE + 2**22, 1 << 30, None) == 4
+    assert f(L, FAKE, FAKE + 2**20, 0, 0.0, ctypes.byref(rat), ctypes.byref(sv), None, None, None, 0, None) == 0
     assert f(L, FAKE, FAKE + 2**20, 1, 0.5, ctypes.byref(rat), ctypes.byref(sv), FAKE + 2**21, None,
              FAKE + 2**22, 1024, None) == 3                                   # workspace too small
     assert f(L, FAKE, FAKE + 2**20, 1, 0.5, ctypes.byref(rat), ctypes.byref(sv), FAKE + 2**20, None,
@@ -217,21 +225,90 @@ def test_tune_set_validation():
     """The launch cache is host state: every accepted and rejected configuration, no GPU."""
     f = _lib.lib().rmh_tune_set
     L = _lib.lattice_arg((4, 4, 4, 4))
-    ok = [(0, 256, 1, 4, 0, 0), (1, 64, 0, 4, 1, 0), (2, 128, 1, 2, 2, 0), (1, 256, 1, 1, 2, 0),
-          (2, 128, 0, 4, 0, 4), (1, 128, 1, 2, 3, 0)]
-    for form, block, xcd, nv, order, walk in ok:
-        assert f(L, 0, 1, form, block, xcd, nv, order, walk) == 0, (form, block, nv, order, walk)
-    bad = [(3, 256, 1, 4, 0, 0),     # form
-           (0, 96, 1, 4, 0, 0),      # block
-           (0, 256, 1, 3, 0, 0),     # nv
-           (0, 256, 1, 1, 0, 0),     # nv = 1 needs form 1
-           (0, 64, 1, 2, 2, 0),      # half a wave per direction group
-           (0, 256, 1, 4, 4, 0),     # order
-           (0, 256, 1, 4, -1, 0),
-           (0, 256, 1, 4, 0, 65)]    # walk
-    for form, block, xcd, nv, order, walk in bad:
-        assert f(L, 0, 1, form, block, xcd, nv, order, walk) == 1, (form, block, nv, order, walk)   # RMH_E_ARG
+
+    def put(cfg, dtype=0, n=1, purpose=-1):
+        full = tuple(cfg) + (1,) * (8 - len(cfg))
+        return f(L, dtype, n, purpose, ctypes.byref(_lib.RmhHopConfig(*full)))
+
+    ok = [(0, 256, 1, 4, 0, 0, 1), (1, 64, 0, 4, 1, 0, 1), (2, 128, 1, 2, 2, 0, 1), (1, 256, 1, 1, 2, 0, 1),
+          (2, 128, 0, 4, 0, 4, 1), (1, 128, 1, 2, 3, 0, 1), (0, 64, 1, 4, 1, 0, 2), (2, 128, 0, 4, 0, 0, 2),
+          (0, 256, 1, 4, 0, 8, 1, 2), (2, 128, 0, 4, 0, 4, 1, 4)]
+    for cfg in ok:
+        assert put(cfg) == 0, cfg
+    assert put((2, 64, 1, 4, 0, 0, 4), dtype=1) == 0                # four fields per thread: FP32
+    for purpose in range(-1, 7):
+        assert put((0, 256, 1, 4, 0, 0, 1), purpose=purpose) == 0
+    bad = [(3, 256, 1, 4, 0, 0, 1),     # form
+           (0, 96, 1, 4, 0, 0, 1),      # block
+           (0, 256, 1, 3, 0, 0, 1),     # nv
+           (0, 256, 1, 1, 0, 0, 1),     # nv = 1 needs form 1
+           (0, 64, 1, 2, 2, 0, 1),      # half a wave per direction group
+           (0, 256, 1, 4, 4, 0, 1),     # order
+           (0, 256, 1, 4, -1, 0, 1),
+           (0, 256, 1, 4, 0, 65, 1),    # walk
+           (0, 256, 2, 4, 0, 0, 1),     # xcd_remap
+           (0, 256, 1, 4, 0, 0, 3),     # ns
+           (1, 256, 1, 4, 0, 0, 2),     # ns > 1 with the 3x3 form
+           (0, 256, 1, 2, 0, 0, 2),     # ns > 1 with nv = 2
+           (0, 256, 1, 4, 2, 0, 2),     # ns > 1 with the hop-split order
+           (0, 256, 1, 4, 0, 4, 2),     # ns > 1 with a walk
+           (0, 256, 1, 4, 0, 0, 4),     # ns = 4 in FP64
+           (0, 256, 1, 4, 0, 8, 1, 3),  # tile2
+           (0, 256, 1, 4, 0, 0, 1, 2)]  # tile2 > 1 without a walk
+    for cfg in bad:
+        assert put(cfg) == 1, cfg                                    # RMH_E_ARG
+    for purpose in (-2, 7):
+        assert put((0, 256, 1, 4, 0, 0, 1), purpose=purpose) == 1
+    assert put((0, 256, 1, 4, 0, 0, 1), n=0) == 1
+    assert f(L, 0, 1, -1, None) == 1
     assert _lib.lib().rmh_tune_clear() == 0
+
+
+def test_tune_file_round_trip(tmp_path):
+    """The launch cache survives a save / clear / load round trip through its JSON file (keyed by
+    lattice, dtype, batch and purpose, stamped with the device architecture and HIP runtime); a
+    file stamped for another architecture loads nothing; malformed files and invalid entries are
+    rejected before anything is stored."""
+    lib_ = _lib.lib()
+    assert lib_.rmh_tune_clear() == 0
+    entries = [((4, 4, 4, 4), 0, 1, -1, (0, 256, 1, 4, 0, 0, 1, 1)),
+               ((4, 4, 4, 4), 0, 1, 3, (2, 64, 1, 4, 1, 0, 1, 1)),
+               ((8, 8, 4, 4), 1, 32, 3, (2, 64, 1, 4, 1, 0, 4, 1)),
+               ((32, 32, 32, 64), 0, 1, 0, (0, 256, 1, 4, 0, 8, 1, 2)),
+               ((16, 16, 16, 16), 0, 12, 2, (1, 128, 0, 2, 2, 0, 1, 1))]
+    for L, dt, n, purpose, cfg in entries:
+        assert lib_.rmh_tune_set(_lib.lattice_arg(L), dt, n, purpose, ctypes.byref(_lib.RmhHopConfig(*cfg))) == 0
+    p1, p2 = str(tmp_path / "a.json"), str(tmp_path / "b.json")
+    n = ctypes.c_int32(0)
+    assert lib_.rmh_tune_save(p1.encode(), ctypes.byref(n)) == 0 and n.value == 5
+    doc = json.load(open(p1))
+    assert doc["format"] == "rmh-tune-1" and len(doc["entries"]) == 5
+    got = {(tuple(e[k] for k in ("L0", "L1", "L2", "L3")), e["dtype"], e["n_rhs"], e["purpose"]):
+           tuple(e[k] for k in ("form", "block", "xcd_remap", "nv", "order", "walk", "ns", "tile2"))
+           for e in doc["entries"]}
+    assert got == {(L, dt, n_, p): cfg for L, dt, n_, p, cfg in entries}
+    assert lib_.rmh_tune_clear() == 0
+    assert lib_.rmh_tune_save(p2.encode(), ctypes.byref(n)) == 0 and n.value == 0
+    assert lib_.rmh_tune_load(p1.encode(), ctypes.byref(n)) == 0 and n.value == 5
+    assert lib_.rmh_tune_save(p2.encode(), ctypes.byref(n)) == 0 and n.value == 5
+    assert open(p1).read() == open(p2).read()
+    # another architecture: nothing stored
+    other = dict(doc, arch=doc["arch"] + "-other")
+    p3 = str(tmp_path / "c.json")
+    json.dump(other, open(p3, "w"))
+    assert lib_.rmh_tune_clear() == 0
+    assert lib_.rmh_tune_load(p3.encode(), ctypes.byref(n)) == 0 and n.value == 0
+    # malformed file, invalid entry (ns = 4 in FP64), missing file, null path
+    p4 = str(tmp_path / "d.json")
+    open(p4, "w").write("{not json")
+    assert lib_.rmh_tune_load(p4.encode(), ctypes.byref(n)) == 1
+    bad = dict(doc, entries=[dict(doc["entries"][0], dtype=0, ns=4)])
+    json.dump(bad, open(p4, "w"))
+    assert lib_.rmh_tune_load(p4.encode(), ctypes.byref(n)) == 1
+    assert lib_.rmh_tune_save(p2.encode(), ctypes.byref(n)) == 0 and n.value == 0     # nothing was stored
+    assert lib_.rmh_tune_load(str(tmp_path / "missing.json").encode(), ctypes.byref(n)) == 9
+    assert lib_.rmh_tune_load(None, None) == 1
+    assert lib_.rmh_tune_save(None, None) == 1
 
 
 def test_leapfrog_validation():
@@ -280,8 +357,9 @@ def test_product_path_does_not_use_the_oracle():
     with open(os.path.join(root, "bench.py")) as fh:
         src = fh.read()
     uses = [m.start() for m in re.finditer(r"from oracle|import oracle", src)]
-    leg = src.index("def cpu_baseline")
-    end = src.index("\ndef ", leg + 1)
+    leg = src.index("# ---- the CPU-baseline leg")
+    end = src.index("# ---- end of the CPU-baseline leg")
+    assert leg < src.index("def cpu_baseline") < end
     assert uses and all(leg < u < end for u in uses)
 
 
@@ -350,4 +428,3 @@ def test_every_entry_point_catches_host_exceptions():
     assert len(defs) >= 25
     missing = [name for name, _, t in defs if not t]
     assert not missing, missing
-

@@ -8,7 +8,6 @@ import sys
 import numpy as np
 
 import bench
-from paper_2112_04556_amd import inputs
 from paper_2112_04556_amd.profiling import stencil_source_hash
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -23,9 +22,10 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_stencil_traffic_record():
-    """The committed counter summary parses, and bench reports its figure only while the stencil
-    sources hash to the value stamped in it."""
-    path = os.path.join(ROOT, "profiles", "stencil_traffic_16x16x16x16.json")
+    """The committed counter summary of the headline kernel parses, and bench reports its figure
+    only while the stencil sources hash to the value stamped in it."""
+    path = os.path.join(ROOT, "profiles", bench.TRAFFIC_RECORD)
+    assert bench.stencil_traffic("stencil", "no_such_record.json") == (None, None)
     with open(path) as fh:
         t = json.load(fh)
     assert t["traffic_bytes_per_launch"] > 0
@@ -35,13 +35,23 @@ def test_stencil_traffic_record():
     else:
         assert val is None and "stale" in src
     assert bench.stencil_traffic("force") == (None, None)
+    if val is not None and "launch_config" in t:
+        other = list(t["launch_config"])
+        other[1] = 64 if other[1] != 64 else 128
+        v2, s2 = bench.stencil_traffic("stencil", cfg=other)
+        assert v2 is None and "launch configuration" in s2
+        assert bench.stencil_traffic("stencil", cfg=t["launch_config"]) == (val, src)
 
 
 def test_cpu_baseline_record():
-    """The baseline leg times the oracle's stencil on one core and reports Gsite/s."""
-    L = (4, 4, 4, 4)
-    U = inputs.random_links(L, "eps", 0.5, seed=2)
-    P = inputs.gaussian_fields(L, 1, seed=2)[0]
-    rec = bench.cpu_baseline(U, P, L, budget_s=0.05)
-    assert rec["unit"] == "Gsite/s" and rec["cores"] == 1 and rec["kind"] == "oracle"
+    """The baseline leg times the oracle's Laplacian on one core and on the host cores (forked
+    workers) and the oracle's per-shift CG, and reports Gsite/s with the core count (tiny lattices
+    here; the bench runs it on the 32^3 x 64 workload)."""
+    rec = bench.cpu_baseline(budget_s=0.05, Lb=(4, 4, 4, 8), L16=(2, 2, 2, 4), chunk=64)
+    assert rec["unit"] == "Gsite/s" and rec["kind"] == "oracle"
+    assert 1 <= rec["cores"] <= 16
     assert np.isfinite(rec["value"]) and rec["value"] > 0
+    one = rec["single_core"]
+    assert one["cores"] == 1 and one["value"] > 0
+    cg = rec["cg_iteration"]
+    assert cg["one_shift_one_core_ms"] > 0 and cg["twelve_shifts_all_cores_ms"] > 0

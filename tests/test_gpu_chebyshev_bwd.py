@@ -142,3 +142,18 @@ def test_autograd_power_spectrum():
     edges = och.equal_windows(nw)
     assert rel_max(omega.grad.cpu().numpy(), ocg.power_spectrum_link_derivative(U, F, L, D, edges, gamma)) <= 1e-12
     assert rel_max(Fg.grad.cpu().numpy(), ocg.power_spectrum_source_gradient(U, F, L, D, edges, gamma)) <= 1e-12
+
+
+def test_gradcheck_power_spectrum_displaced_links():
+    """torch.autograd.gradcheck of a weighted sum of window powers at a non-zero link displacement
+    (2^4, degree 8, 3 windows, FP64): the omega and F gradients against central differences."""
+    from paper_2112_04556_amd import autograd
+    L = (2, 2, 2, 2)
+    U, F, Ud, Fd = setup(L, "eps", 0.6, 49, n=1)
+    rng = np.random.default_rng(49)
+    gamma = torch.tensor(rng.normal(size=(1, 3)), device=dev())
+    omega = torch.tensor(0.3 * rng.normal(size=(4, 8, api.volume(L))), dtype=torch.float64, device=dev(),
+                         requires_grad=True)
+    Fg = Fd.clone().requires_grad_(True)
+    assert torch.autograd.gradcheck(lambda w, f: torch.sum(autograd.power_spectrum(w, f, Ud, L, 8, 3) * gamma),
+                                    (omega, Fg), eps=1e-6, atol=1e-7, rtol=1e-6)

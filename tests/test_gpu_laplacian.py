@@ -131,6 +131,46 @@ def test_laplacian_configs_batched_and_deterministic(dtype):
     assert torch.equal(y_a, y_b)
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_laplacian_multi_field_bitwise(dtype):
+    """ns fields per thread (each link and adjoint matrix serving 4 ns vectors): every field's result
+    is bitwise that of one field per thread with the same form, for plain applications, the Chebyshev
+    recursion step with its dot products (power spectrum) and the CG (fields that stop at different
+    iterations), and within the oracle's tolerance."""
+    L = (8, 8, 5, 6)
+    announce(f"laplacian multi-field {dtype}")
+    U, P, Ud, Pd = setup(L, "haar", 0.0, 17, n=4, dtype=dtype)
+    ref = olap.laplacian(U if dtype == torch.float64 else U.astype(np.complex64).astype(np.complex128),
+                         Pd.double().cpu().numpy(), L, 0.0)
+    tol = 1e-12 if dtype == torch.float64 else 1e-5
+    nss = (2, 4) if dtype == torch.float32 else (2,)
+    for form in (0, 2):
+        api.tune_set(L, dtype, 4, form, 64, 1, 4, 1, 0)
+        y1 = api.laplacian_apply(L, Ud, Pd)
+        assert rel_max(y1.double().cpu().numpy(), ref) <= tol
+        for block, xcd, order in ((64, 1, 1), (256, 0, 0), (128, 1, 0)):
+            # the dot products are summed per block: bitwise only against the same block partition
+            api.tune_set(L, dtype, 4, form, block, xcd, 4, order, 0)
+            m1, p1 = api.power_spectrum(L, Ud, Pd, 12, 3)
+            for ns in nss:
+                api.tune_set(L, dtype, 4, form, block, xcd, 4, order, 0, ns=ns)
+                y = api.laplacian_apply(L, Ud, Pd)
+                assert torch.equal(y, y1), (form, ns, block, xcd, order)
+                m, p = api.power_spectrum(L, Ud, Pd, 12, 3)
+                assert np.array_equal(m, m1) and np.array_equal(p, p1), (form, ns, block)
+        api.tune_clear()
+    if dtype == torch.float64:
+        # the FP64 multi-shift CG over two fields: one field per thread against two
+        rat = api.rational_kappa(0.9, 4)
+        P2 = Pd[:2].contiguous()
+        api.tune_set(L, dtype, 2, 0, 64, 1, 4, 1, 0, purpose="cg")
+        a = api.rational_apply(L, Ud, P2, rat, api.Solver(tol=1e-10), want_poles=True)
+        api.tune_set(L, dtype, 2, 0, 64, 1, 4, 1, 0, ns=2, purpose="cg")
+        b = api.rational_apply(L, Ud, P2, rat, api.Solver(tol=1e-10), want_poles=True)
+        api.tune_clear()
+        assert torch.equal(a["x_poles"], b["x_poles"]) and a["stats"]["iters"] == b["stats"]["iters"]
+
+
 @pytest.mark.parametrize("L,kind,seed", CASES)
 def test_laplacian_hop_split_parity(L, kind, seed):
     """order = 2: four lanes per site, one per direction, summed by wave shuffles."""
@@ -188,11 +228,36 @@ def test_laplacian_empty_batch_and_autotune():
     _, _, Ud, Pd = setup(L, "eps", 0.3, 1, n=1)
     empty = torch.empty((0, 4, 8, api.volume(L)), dtype=torch.float64, device=dev())
     api.laplacian_apply(L, Ud, empty)
-    (form, block, xcd, nv, order, walk), ms = api.autotune_laplacian(L, Ud, Pd, reps=2)
+    (form, block, xcd, nv, order, walk, ns, tile2), ms = api.autotune_laplacian(L, Ud, Pd, reps=2)
     assert form in (0, 1, 2) and block in (64, 128, 256) and nv in (1, 2, 4) and ms > 0
     assert nv != 1 or form == 1
+    assert ns == 1 and tile2 in (1, 2, 4)
     U, P, _, _ = setup(L, "eps", 0.3, 1, n=1)
     assert rel_max(api.laplacian_apply(L, Ud, Pd).cpu().numpy(), olap.laplacian(U, P, L)) <= 1e-12
+    api.tune_clear()
+
+
+def test_autotune_per_purpose_and_cache_file(tmp_path):
+    """The autotuner keys its result by purpose; the cache written to a file (stamped with this
+    device's architecture) is read back into an empty cache with the same configurations."""
+    L = (8, 8, 5, 6)
+    _, _, Ud, Pd = setup(L, "eps", 0.3, 2, n=4)
+    api.tune_clear()
+    c_apply, _ = api.autotune_laplacian(L, Ud, Pd, reps=1, purpose="apply")
+    c_mom, _ = api.autotune_laplacian(L, Ud, Pd, reps=1, purpose="moments")
+    path = str(tmp_path / "tune.json")
+    assert api.tune_save(path) == 2
+    import json
+    doc = json.load(open(path))
+    assert doc["arch"].startswith("gfx950") and doc["hip_runtime"] > 0
+    assert sorted(e["purpose"] for e in doc["entries"]) == [0, 3]
+    api.tune_clear()
+    assert api.tune_load(path) == 2
+    path2 = str(tmp_path / "tune2.json")
+    assert api.tune_save(path2) == 2
+    got = {e["purpose"]: tuple(e[k] for k in ("form", "block", "xcd_remap", "nv", "order", "walk", "ns", "tile2"))
+           for e in json.load(open(path2))["entries"]}
+    assert got == {0: c_apply, 3: c_mom}
     api.tune_clear()
 
 

@@ -2,7 +2,9 @@
 at larger sizes: time reversibility, the third-order energy error, SU(3) links.
 
 Tolerances: the GPU solves to a per-shift FP64 true residual of 1e-12 and the oracle to 1e-13;
-each fixed point stops at a relative change of 1e-12.  Forces and velocities therefore agree to
+each fixed point stops at a relative change of 1e-12.  The oracle keeps the converged successor of
+each fixed-point iteration and the GPU the iterate before it (whose solves it reuses); the two
+differ by at most fp_tol = 1e-12 relative in P_h and Pi.  Forces and velocities therefore agree to
 about 1e-11 relative, and one step of size eps moves links and momenta by eps times those, so
 links are compared to 1e-10 and momenta to 1e-9 relative to max |P|.
 """
