@@ -216,6 +216,20 @@ rmh_status rmh_power_spectrum(const int32_t L[4], const void* U, int32_t dtype, 
                               const rmh_cheb* cheb, double* moments, double* power, void* ws, size_t ws_bytes,
                               rmh_stream stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): rmh_power_spectrum with its recursion vectors and
+ * partial sums in the library's static device scratch instead of a workspace argument.  The
+ * scratch is 64 MiB per device (a file-scope device array, held until the process ends); a call
+ * that needs more (the same amount rmh_workspace_bytes(RMH_OP_POWER_SPECTRUM, ...) reports, e.g.
+ * more than one FP64 source at 16^4) returns RMH_E_WORKSPACE before touching any pointer.  The
+ * call allocates nothing: no hipMalloc, hipFree or pinned host staging (the sums come back by a
+ * plain device-to-host copy).  Every call on one device shares that device's scratch, so calls that
+ * overlap on one device (other threads, other streams) race; successive calls are independent
+ * (nothing in the scratch needs to start at zero).  Results equal rmh_power_spectrum's bit for bit. */
+rmh_status rmh_power_spectrum_noalloc(const int32_t L[4], const void* U, int32_t dtype, const void* F,
+                                      int32_t n_rhs, const rmh_cheb* cheb, double* moments, double* power,
+                                      rmh_stream stream);
+
 /* Host: ratio[n][w] = power[n][w] / Tr B_w with Tr B_w = sum_k g_k c^w_k trace_moments[k]
  * (Eq. 4, power per mode).  trace_moments[k] = Tr T_k(A) over the link-field space
  * (e.g. rmh_trace_moments_free, or the mean moments of Gaussian sources). */

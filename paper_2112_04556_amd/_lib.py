@@ -84,6 +84,8 @@ SIGNATURES = {
     "rmh_cheb_coefficients": (c_i32, [ctypes.POINTER(RmhCheb), P_f64]),
     "rmh_power_spectrum": (c_i32, [P_i32, c_vp, c_i32, c_vp, c_i32, ctypes.POINTER(RmhCheb), P_f64, P_f64,
                                    c_vp, c_sz, c_vp]),
+    "rmh_power_spectrum_noalloc": (c_i32, [P_i32, c_vp, c_i32, c_vp, c_i32, ctypes.POINTER(RmhCheb), P_f64, P_f64,
+                                           c_vp]),
     "rmh_power_ratio": (c_i32, [ctypes.POINTER(RmhCheb), P_f64, P_f64, c_i32, P_f64]),
     "rmh_trace_moments_free": (c_i32, [P_i32, c_i32, P_f64]),
     "rmh_cheb_filter": (c_i32, [P_i32, c_vp, c_i32, c_vp, c_i32, ctypes.POINTER(RmhCheb), c_vp, c_vp, c_sz, c_vp]),

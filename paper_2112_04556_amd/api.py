@@ -21,7 +21,7 @@ from ._lib import RMH_F32, RMH_F64, check, lattice_arg, lib
 __all__ = [
     "Rational", "Solver", "pack_links", "unpack_links", "pack_fields", "unpack_fields", "convert_f64_f32",
     "laplacian_apply", "laplacian_apply_bwd", "cheb_coefficients", "power_spectrum", "power_ratio",
-    "trace_moments_free", "cheb_filter", "rational_from_quadratics", "rational_kappa", "rational_apply",
+    "trace_moments_free", "cheb_filter", "power_spectrum_noalloc", "rational_from_quadratics", "rational_kappa", "rational_apply",
     "rational_apply_bwd", "kinetic_force", "workspace_bytes", "volume", "tune_set", "tune_clear", "link_exp", "link_exp_vjp",
     "autotune_laplacian", "tune_save", "tune_load", "PURPOSES", "profile_enable", "profile_read", "PROF_CLASSES",
 ]
@@ -199,6 +199,19 @@ def power_spectrum(L, U, F, degree: int, n_windows: int, edges=None, kernel: int
     check(lib().rmh_power_spectrum(lattice_arg(L), _dev(U, "U"), code, _dev(F, "F"), n, ctypes.byref(st),
                                    _f64p(mom), _f64p(pw), ws.data_ptr(), ws.numel(), _stream(F.device)),
           "rmh_power_spectrum")
+    return mom, pw
+
+
+def power_spectrum_noalloc(L, U, F, degree: int, n_windows: int, edges=None, kernel: int = 1):
+    """power_spectrum on the library's static device scratch (rmh_power_spectrum_noalloc): no
+    workspace tensor, nothing allocated on the device by the call."""
+    n = F.shape[0]
+    st, keep = _cheb(degree, n_windows, edges, kernel)
+    mom = np.empty((n, degree + 1))
+    pw = np.empty((n, n_windows))
+    check(lib().rmh_power_spectrum_noalloc(lattice_arg(L), _dev(U, "U"), _dtype_code(F), _dev(F, "F"), n,
+                                           ctypes.byref(st), _f64p(mom), _f64p(pw), _stream(F.device)),
+          "rmh_power_spectrum_noalloc")
     return mom, pw
 
 

@@ -146,6 +146,33 @@ rmh_status d2h(void* dst, const void* src, size_t bytes, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------------------------------
+// Static device scratch for the entry point that allocates nothing (rmh_power_spectrum_noalloc).
+// Each device holds its own copy of the array at its own address for the life of the process; host
+// code must never pass the array's name to a kernel (in host code it is a host-side stand-in), only
+// the address hipGetSymbolAddress returns for the current device, kept here per device.  Every call
+// on a device shares its array: calls that overlap on one device race.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+static std::mutex g_scratch_mu;
+static std::map<int, void*> g_scratch_addr;
+
+static rmh_status scratch_ptr(void** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_addr.find(dev);
+  if (it == g_scratch_addr.end()) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return fail(RMH_E_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    it = g_scratch_addr.emplace(dev, p).first;
+  }
+  *out = it->second;
+  return RMH_OK;
+}
+
+// ------------------------------------------------------------------------------------------
 // kernel timing (HIP events around launches of the instrumented classes)
 
 struct ProfRec {
@@ -1210,10 +1237,12 @@ static rmh_status check_cheb_dims(const rmh_cheb* cheb, int32_t min_degree, int3
   return RMH_OK;
 }
 
-// The power spectrum on a given workspace.
+// The power spectrum on a given workspace.  static_ws: the workspace is the library's static
+// scratch (ws == nullptr here; it is looked up once the call is known to fit in it), and nothing is
+// allocated: the sums come back by a plain copy into host memory instead of the pinned stage.
 static rmh_status power_spectrum_impl(const int32_t L[4], const void* U, int32_t dtype, const void* F,
                                       int32_t n_rhs, const rmh_cheb* cheb, double* moments, double* power,
-                                      void* ws, size_t ws_bytes, rmh_stream stream) {
+                                      void* ws, size_t ws_bytes, bool static_ws, rmh_stream stream) {
   Geom g;
   RMH_TRY(make_geom(L, &g));
   RMH_TRY(check_dtype(dtype));
@@ -1226,6 +1255,15 @@ static rmh_status power_spectrum_impl(const int32_t L[4], const void* U, int32_t
   RMH_TRY(check_ptr(U, "U"));
   RMH_TRY(check_ptr(F, "F"));
   const int32_t K = std::max(1, (D + 1) / 2);
+  if (static_ws) {
+    Carver need(nullptr);
+    plan_cheb(need, g, dtype, n_rhs, K, true);
+    if (need.off > kScratchBytes)
+      return fail(RMH_E_WORKSPACE, "the call needs %zu bytes of scratch, more than the %zu of the static scratch",
+                  need.off, kScratchBytes);
+    RMH_TRY(scratch_ptr(&ws));
+    ws_bytes = kScratchBytes;
+  }
   RMH_TRY(check_ptr(ws, "ws"));
   Carver c(ws);
   ChebPlan cp = plan_cheb(c, g, dtype, n_rhs, K, true);
@@ -1236,9 +1274,9 @@ static rmh_status power_spectrum_impl(const int32_t L[4], const void* U, int32_t
   std::vector<double> sums;
   hipStream_t s = (hipStream_t)stream;
   if (dtype == RMH_F64)
-    RMH_TRY(power_spectrum_t<double>(g, (const double*)U, (const double*)F, n_rhs, D, cp, &sums, false, s));
+    RMH_TRY(power_spectrum_t<double>(g, (const double*)U, (const double*)F, n_rhs, D, cp, &sums, static_ws, s));
   else
-    RMH_TRY(power_spectrum_t<float>(g, (const float*)U, (const float*)F, n_rhs, D, cp, &sums, false, s));
+    RMH_TRY(power_spectrum_t<float>(g, (const float*)U, (const float*)F, n_rhs, D, cp, &sums, static_ws, s));
   // moments from the doubling identities
   std::vector<double> mu((size_t)n_rhs * (2 * K + 1));
   for (int32_t n = 0; n < n_rhs; ++n) {
@@ -1538,7 +1576,15 @@ rmh_status rmh_trace_moments_free(const int32_t L[4], int32_t degree, double* tr
 rmh_status rmh_power_spectrum(const int32_t L[4], const void* U, int32_t dtype, const void* F, int32_t n_rhs,
                               const rmh_cheb* cheb, double* moments, double* power, void* ws, size_t ws_bytes,
                               rmh_stream stream) try {
-  return power_spectrum_impl(L, U, dtype, F, n_rhs, cheb, moments, power, ws, ws_bytes, stream);
+  return power_spectrum_impl(L, U, dtype, F, n_rhs, cheb, moments, power, ws, ws_bytes, false, stream);
+} catch (...) {   // no C++ exception crosses the C ABI
+  return fail(RMH_E_HOST, "host-side failure (out of host memory?)");
+}
+
+rmh_status rmh_power_spectrum_noalloc(const int32_t L[4], const void* U, int32_t dtype, const void* F,
+                                      int32_t n_rhs, const rmh_cheb* cheb, double* moments, double* power,
+                                      rmh_stream stream) try {
+  return power_spectrum_impl(L, U, dtype, F, n_rhs, cheb, moments, power, nullptr, 0, true, stream);
 } catch (...) {   // no C++ exception crosses the C ABI
   return fail(RMH_E_HOST, "host-side failure (out of host memory?)");
 }

@@ -428,3 +428,23 @@ def test_every_entry_point_catches_host_exceptions():
     assert len(defs) >= 25
     missing = [name for name, _, t in defs if not t]
     assert not missing, missing
+
+
+def test_power_spectrum_noalloc_limits():
+    """The entry point that allocates nothing rejects a call larger than its 64 MiB static scratch
+    (RMH_E_WORKSPACE) and bad arguments (RMH_E_ARG) before touching any pointer or the device."""
+    f = _lib.lib().rmh_power_spectrum_noalloc
+    cheb = _lib.RmhCheb(64, 16, None, 1)
+    big = _lib.lattice_arg((32, 32, 32, 32))          # two FP64 recursion fields alone: 1 GiB
+    assert f(big, FAKE, 0, FAKE + 2**31, 1, ctypes.byref(cheb), None, None, None) == 3
+    assert b"static scratch" in _lib.lib().rmh_last_error()
+    # 16^4: one FP64 source fits, two do not
+    L16 = _lib.lattice_arg((16, 16, 16, 16))
+    ws1 = _lib.lib().rmh_workspace_bytes(2, L16, 0, 1, 16, 64, 0)
+    ws2 = _lib.lib().rmh_workspace_bytes(2, L16, 0, 2, 16, 64, 0)
+    assert ws1 <= 64 << 20 < ws2
+    assert f(L16, FAKE, 0, FAKE + 2**31, 2, ctypes.byref(cheb), None, None, None) == 3
+    bad = _lib.RmhCheb(0, 16, None, 1)                 # degree 0 on the device path
+    assert f(L16, FAKE, 0, FAKE + 2**31, 1, ctypes.byref(bad), None, None, None) == 1
+    assert f(L16, FAKE, 0, FAKE + 2**31, -1, ctypes.byref(cheb), None, None, None) == 1
+    assert f(L16, FAKE, 0, FAKE + 2**31, 0, ctypes.byref(cheb), None, None, None) == 0   # empty batch: no-op
