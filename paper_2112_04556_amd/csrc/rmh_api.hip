@@ -595,9 +595,20 @@ rmh_status engine_solve(Engine& e, const double* U64, const float* U32, const do
   const int32_t* hfl = (const int32_t*)(st.data() + ((char*)e.flags - (char*)e.sc));
   int32_t it = 0;
   info->fp64_iters = 0;
+  // Iterations until the next host check.  From the second check on, the seed's convergence rate
+  // so far predicts when its relative residual reaches the next threshold (the switch to FP32, then
+  // tol: the seed is the last shift to converge, |zeta_j| <= 1), and the check is placed there, at
+  // most check_every iterations away, so the switch is not held back to a fixed grid of checks and
+  // fewer launches run past convergence.  Only where the checks fall depends on it; the device
+  // decides convergence.
+  int32_t chunk = check_every;
+  double rel_prev = 1.0;   // the worst running seed's relative residual at it_prev (r_0 = b)
+  int32_t it_prev = 0;
+  double tol_min = 1.0;
+  for (int v = 0; v < nr; ++v) tol_min = std::min(tol_min, tol_rel[v]);
   while (true) {
-    if (multi && since + check_every > (fp32_phase ? seg32 : seg64)) RMH_TRY(flush(false));
-    for (int i = 0; i < check_every; ++i) {
+    if (multi && since + chunk > (fp32_phase ? seg32 : seg64)) RMH_TRY(flush(false));
+    for (int i = 0; i < chunk; ++i) {
       if (!fp32_phase) {
         {
           ProfScope ps(RMH_PROF_STENCIL, hop_bytes(g, nr, 8, false, true), s, nr);
@@ -637,16 +648,18 @@ rmh_status engine_solve(Engine& e, const double* U64, const float* U32, const do
         }
       }
     }
-    it += check_every;
-    since += check_every;
+    it += chunk;
+    since += chunk;
     if (!fp32_phase) info->fp64_iters = it;
     RMH_TRY(d2h(st.data(), e.sc, e.state_bytes, s));
     bool running = false, below = true;
+    double rel = 0.0;
     for (int v = 0; v < nr; ++v) {
       if (hfl[(size_t)v * kFlN + kFlRun] == 0) continue;
       running = true;
       const double rr = hsc[(size_t)v * kScN + kScRR], bb = hsc[(size_t)v * kScN + kScBnorm2];
       if (!(sqrt(rr) <= switch_rel * sqrt(bb))) below = false;
+      if (bb > 0.0) rel = std::max(rel, sqrt(rr / bb));
     }
     if (!running) break;
     if (mixed && !fp32_phase && below) {
@@ -660,6 +673,14 @@ rmh_status engine_solve(Engine& e, const double* U64, const float* U32, const do
       HIP_TRY(launch_zero(e.x_lo, (size_t)nr * n * 4, s));
       fp32_phase = true;
     }
+    chunk = check_every;
+    const double target = (mixed && !fp32_phase) ? switch_rel : tol_min;
+    if (it > it_prev && rel > target && target > 0.0 && rel < rel_prev) {
+      const double k = ceil(log(target / rel) / (log(rel / rel_prev) / (it - it_prev)));
+      if (k >= 1.0 && k < (double)check_every) chunk = (int32_t)k;
+    }
+    rel_prev = rel;
+    it_prev = it;
     if (it > maxiter + 2 * check_every) break;  // safety net; the device sets NoConv first
   }
   RMH_TRY(flush(true));

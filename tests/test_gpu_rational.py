@@ -244,6 +244,27 @@ def test_kinetic_force_vs_oracle(mode):
     assert np.allclose(out["K"], Kref, rtol=1e-8)
 
 
+def test_kinetic_force_8_fields_16_poles_mixed():
+    """The large-lattice force workload's shape at 4^4: 8 momentum fields in one call, the 16-pole
+    kappa = 0.9 set, mixed precision to 1e-10, the link derivative per field, each against the oracle's
+    kinetic-force gradient within the solve bound."""
+    L = (4, 4, 4, 4)
+    announce("kinetic_force 4^4 8 fields 16 poles mixed")
+    U, P, Ud, Pd = setup(L, "eps", 0.4, 41, n=8)
+    rat = _rat_kappa(0.9, 16)
+    tol = 1e-10
+    out = api.kinetic_force(L, Ud, Pd, rat, api.Solver(tol=tol, mode=1), per_rhs=True, want_Y=True)
+    dK = out["dK"].cpu().numpy()
+    Y = out["Y"].cpu().numpy()
+    assert dK.shape[0] == 8 and out["stats"]["true_relres_max"] <= tol
+    for i in range(8):
+        ref = oforce.kinetic_force_grad(U, P[i:i + 1], L, rat.c, rat.r, rat.sigma, tol=1e-13)
+        bound = _force_bound(rat, tol, 1e-13, np.linalg.norm(P[i]), np.linalg.norm(Y[i]))
+        err = np.linalg.norm(dK[i] - ref)
+        assert err <= bound, (i, err, bound)
+        assert np.linalg.norm(ref) > 100 * bound
+
+
 def test_kinetic_force_max_poles_vs_oracle():
     """The force with the largest pole set, 64 pairs in one force launch, against the oracle."""
     L = (2, 2, 2, 4)
@@ -284,7 +305,11 @@ def _perturb(Ud, L, mu, s, c, h):
     return torch.from_numpy(Uh).to(dev())
 
 
-def _fd_check(L, eps, seed, n_pert, h, tol, rtol):
+def _fd_check(L, eps, seed, n_pert, h, tol, rtol, order=2):
+    """Central differences of K = |Y|^2 / 2 along one link's generator against dK.  The K differences
+    are formed as sum (Y_a - Y_b)(Y_a + Y_b) / 2, free of cancellation.  order 2: (K(h) - K(-h)) / 2h;
+    order 4: (8 (K(h) - K(-h)) - (K(2h) - K(-2h))) / 12h, whose O(h^4) truncation allows an h large
+    enough that the solves' rounding (~tol |Y|^2 per K) divided by h stays far below the force."""
     U, P, Ud, Pd = setup(L, "eps", eps, seed, n=1)
     rat = _rat_kappa(0.9, 8)
     sv = api.Solver(tol=tol, mode=0)
@@ -292,13 +317,20 @@ def _fd_check(L, eps, seed, n_pert, h, tol, rtol):
     rng = np.random.default_rng(seed)
     scale = np.abs(dK).max()
     worst = 0.0
+
+    def dk(mu, s, c, a):
+        Ya = api.rational_apply(L, _perturb(Ud, L, mu, s, c, a), Pd, rat, sv)["y"].cpu().numpy()
+        Yb = api.rational_apply(L, _perturb(Ud, L, mu, s, c, -a), Pd, rat, sv)["y"].cpu().numpy()
+        return 0.5 * np.sum((Ya - Yb) * (Ya + Yb))
+
     for _ in range(n_pert):
         mu, c, s = int(rng.integers(4)), int(rng.integers(8)), int(rng.integers(api.volume(L)))
-        Yp = api.rational_apply(L, _perturb(Ud, L, mu, s, c, h), Pd, rat, sv)["y"].cpu().numpy()
-        Ym = api.rational_apply(L, _perturb(Ud, L, mu, s, c, -h), Pd, rat, sv)["y"].cpu().numpy()
-        fd = 0.5 * np.sum((Yp - Ym) * (Yp + Ym)) / (2 * h)
+        if order == 2:
+            fd = dk(mu, s, c, h) / (2 * h)
+        else:
+            fd = (8.0 * dk(mu, s, c, h) - dk(mu, s, c, 2 * h)) / (12 * h)
         worst = max(worst, abs(fd - dK[mu, c, s]) / scale)
-    announce(f"  FD worst relative deviation {worst:.3e} (tolerance {rtol:.1e})")
+    announce(f"  FD (order {order}, h = {h:.0e}) worst relative deviation {worst:.3e} (tolerance {rtol:.1e})")
     assert worst <= rtol
 
 
@@ -309,14 +341,16 @@ def test_kinetic_force_finite_differences_4():
 
 
 def test_kinetic_force_finite_differences_16():
-    """The 16^4, eps = 0.4, 8-pole workload: 64 random link perturbations, h = 1e-6.
+    """The 16^4, eps = 0.4, 8-pole workload: 64 random link perturbations, fourth-order central
+    differences with h = 2e-3.
 
-    Error model: the two solves are independent, so the difference of the K values carries
-    rounding noise ~ 1e-15 ||Y||^2 ~ 1e-9, i.e. ~ 5e-4 after division by 2h, against
-    force components of order 1-10.
+    Error model: truncation h^4 |K^(5)| / 30 ~ 1e-11 for force derivatives of order 1-10; the
+    solves (true residual 1e-13) leave K with an error ~ 1e-13 |Y|^2 ~ 1e-7 that need not cancel
+    between the displaced evaluations, ~ 1e-5 after division by 12h, against max |dK| of order 10:
+    a relative deviation ~ 1e-6, asserted at 2e-5.
     """
     announce("force FD 16^4")
-    _fd_check((16, 16, 16, 16), 0.4, 4, 64, 1e-6, 1e-13, 2e-3)
+    _fd_check((16, 16, 16, 16), 0.4, 4, 64, 2e-3, 1e-13, 2e-5, order=4)
 
 
 def test_force_cartan_zero_16():
