@@ -22,7 +22,7 @@ Summaries (run on the host, over the CSV files rocprofv3 wrote):
     python -m paper_2112_04556_amd.profiling summarize-trace DIR --prefix rmh::k_hop --last N
     python -m paper_2112_04556_amd.profiling traffic --fetch DIR1 --write DIR2 --prefix rmh::k_hop \
         --last N --fetch-scale 2.0 --write-scale 1.0 --out FILE.json --command-fetch ... --command-write ... \
-        [--launch-config FORM BLOCK XCD NV ORDER WALK NS TILE2]
+        [--launch-config FORM BLOCK XCD NV ORDER WALK NS TILE2] [--append]
 
 ``traffic`` averages FETCH_SIZE and WRITE_SIZE (KiB per dispatch) over the last N dispatches
 whose kernel name starts with the prefix, scales each by the factor the same counter shows for
@@ -243,6 +243,8 @@ def main(argv=None):
     p.add_argument("--launch-config", type=int, nargs=8, default=None,
                    help="the stencil launch configuration of the counted dispatches (form block xcd_remap nv "
                         "order walk ns tile2)")
+    p.add_argument("--append", action="store_true",
+                   help="add the record to the file's list of records (one per launch configuration)")
     a = ap.parse_args(argv)
     if a.cmd == "copy":
         run_copy()
@@ -264,7 +266,16 @@ def main(argv=None):
                   "prefix": a.prefix})
         if a.launch_config:
             t["launch_config"] = list(a.launch_config)
-        text = json.dumps(t, indent=1)
+        doc = t
+        if a.append and a.out and os.path.exists(a.out):
+            with open(a.out) as fh:
+                old = json.load(fh)
+            recs = old.get("records", [old] if "traffic_bytes_per_launch" in old else [])
+            recs = [r for r in recs if r.get("launch_config") != t.get("launch_config")] + [t]
+            doc = {"records": recs}
+        elif a.append:
+            doc = {"records": [t]}
+        text = json.dumps(doc, indent=1)
         if a.out:
             with open(a.out, "w") as fh:
                 fh.write(text + "\n")

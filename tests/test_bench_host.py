@@ -1,6 +1,5 @@
 """Host-side pieces of bench.py (CPU): the one-GPU guard, the committed HBM-traffic figure and the
 CPU baseline's record."""
-import json
 import os
 import subprocess
 import sys
@@ -22,25 +21,22 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_stencil_traffic_record():
-    """The committed counter summary of the headline kernel parses, and bench reports its figure
-    only while the stencil sources hash to the value stamped in it."""
-    path = os.path.join(ROOT, "profiles", bench.TRAFFIC_RECORD)
+    """The committed counter summaries of the headline kernel parse, and bench reports a figure only
+    for a profiled launch configuration while the stencil sources hash to the value stamped in it."""
     assert bench.stencil_traffic("stencil", "no_such_record.json") == (None, None)
-    with open(path) as fh:
-        t = json.load(fh)
-    assert t["traffic_bytes_per_launch"] > 0
-    val, src = bench.stencil_traffic("stencil")
-    if t["stencil_source_sha256"] == stencil_source_hash():
-        assert val == round(float(t["traffic_bytes_per_launch"])) and src.startswith("profiles")
-    else:
-        assert val is None and "stale" in src
+    recs = bench.traffic_records()
+    assert recs and all(r["traffic_bytes_per_launch"] > 0 and len(r["launch_config"]) == 8 for r in recs)
     assert bench.stencil_traffic("force") == (None, None)
-    if val is not None and "launch_config" in t:
-        other = list(t["launch_config"])
-        other[1] = 64 if other[1] != 64 else 128
-        v2, s2 = bench.stencil_traffic("stencil", cfg=other)
-        assert v2 is None and "launch configuration" in s2
-        assert bench.stencil_traffic("stencil", cfg=t["launch_config"]) == (val, src)
+    for t in recs:
+        val, src = bench.stencil_traffic("stencil", cfg=t["launch_config"])
+        if t["stencil_source_sha256"] == stencil_source_hash():
+            assert val == round(float(t["traffic_bytes_per_launch"])) and src.startswith("profiles")
+        else:
+            assert val is None and "stale" in src
+    other = list(recs[0]["launch_config"])
+    other[1] = 64 if other[1] != 64 else 128
+    v2, s2 = bench.stencil_traffic("stencil", cfg=other)
+    assert v2 is None and "launch configuration" in s2
 
 
 def test_cpu_baseline_record():
