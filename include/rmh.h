@@ -100,8 +100,11 @@ typedef struct {
  * ||x - (Delta + sigma_j) x_j|| / ||x|| that every shift must reach.  mode 0: FP64 multi-shift
  * CG; mode 1: mixed precision -- FP64 iterations while the seed residual is above
  * mixed_switch * ||x|| (0 = default 1e-4, negative = none), then FP32 stencil and vectors with
- * FP64 reliable updates of the seed residual (delta = reliable-update threshold, e.g. 0.1).
- * check_every: iterations between host convergence checks (0 = 8).  basis: iterations per
+ * FP64 reliable updates of the seed residual (delta = reliable-update threshold in (0, 1): an update
+ * once the seed residual fell below delta times its largest value since the last one, e.g. 0.01).
+ * check_every: at most this many iterations between host convergence checks (0 = 8); after the
+ * first, each check is placed where the seed's convergence rate so far predicts the next threshold
+ * (the switch to FP32, then tol).  basis: iterations per
  * segment of the shift solutions (0 = 32 in mode 0, 16 in mode 1; at most 32): the shifts other
  * than the seed are carried as coefficients over the stored seed residuals of a segment and
  * folded into their FP64 vectors once per segment, so the workspace holds basis + 1 extra link

@@ -75,7 +75,7 @@ class Solver:
     tol: float = 1e-10
     maxiter: int = 20000
     mode: int = 0          # 0 = FP64, 1 = FP64 then FP32 with FP64 reliable updates
-    delta: float = 0.1
+    delta: float = 0.01         # reliable update once the seed residual fell 100-fold since the last
     check_every: int = 8
     mixed_switch: float = 0.0   # 0: library default (1e-4); < 0: FP32 from the first iteration
     basis: int = 0              # iterations per shift-solution segment (0: library default)
