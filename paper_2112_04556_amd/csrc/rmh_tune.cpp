@@ -263,7 +263,8 @@ int tune_load_file(const char* path, const std::string& arch, int32_t runtime, i
     c.ns = (int32_t)v[13];
     c.tile2 = (int32_t)v[14];
     const int32_t dtype = (int32_t)v[4];
-    if ((dtype != RMH_F64 && dtype != RMH_F32) || v[5] < 1 || v[6] < RMH_PURPOSE_ANY || v[6] > RMH_PURPOSE_HEATBATH)
+    if ((dtype != RMH_F64 && dtype != RMH_F32) || v[5] < 1 || v[5] > (1L << 24) || v[6] < RMH_PURPOSE_ANY ||
+        v[6] > RMH_PURPOSE_HEATBATH)
       return -2;
     for (int i = 0; i < 4; ++i)
       if (v[i] < 2 || v[i] > (1 << 20)) return -2;
