@@ -154,6 +154,33 @@ def test_stencil_32x64_sampled(dtype):
     api.tune_clear()
 
 
+@pytest.mark.parametrize("walk", [8, 16])
+def test_headline_launch_configurations_32x64(walk):
+    """The launch configurations the headline is timed and profiled in (streamed adjoint columns,
+    block 256, a walk of 8 or 16 x3 slices, x2 tiles of 2): FP64 at 32^3 x 64 against the oracle at
+    sampled sites, and bitwise equal to the one-thread-per-site kernel of the same form."""
+    L = (32, 32, 32, 64)
+    V = api.volume(L)
+    announce(f"32^3x64 headline configuration walk={walk}")
+    U = inputs.random_links(L, "eps", 0.4, seed=1)
+    F = inputs.gaussian_fields(L, 1, seed=1)
+    Ud = api.pack_links(L, U.to(dev()))
+    Fd = F.to(dev())
+    try:
+        api.tune_set(L, torch.float64, 1, form=2, block=256, xcd_remap=0, nv=4, order=0, walk=0, purpose="apply")
+        y0 = api.laplacian_apply(L, Ud, Fd)
+        api.tune_set(L, torch.float64, 1, form=2, block=256, xcd_remap=0, nv=4, order=0, walk=walk, tile2=2,
+                     purpose="apply")
+        y = api.laplacian_apply(L, Ud, Fd)
+        torch.cuda.synchronize()
+        assert torch.equal(y, y0)
+        sites = _sample_sites(V, 64, 11)
+        ref = olap.laplacian_at(U.numpy(), F.numpy(), L, sites)
+        assert np.abs(y.cpu().numpy()[..., sites] - ref).max() <= 1e-12 * np.abs(ref).max()
+    finally:
+        api.tune_clear()
+
+
 def test_rational_32x64_mixed_sampled():
     """16-pole kappa = 0.9 rational on one 32^3 x 64 momentum field, mixed precision to 1e-10."""
     L = (32, 32, 32, 64)
