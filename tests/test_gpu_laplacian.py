@@ -132,6 +132,34 @@ def test_laplacian_configs_batched_and_deterministic(dtype):
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_laplacian_walk_tiles_bitwise(dtype):
+    """The walking kernel with x2-tiled column blocks (tile2 = 2, 4) over walks of 2, 3 and 6 x3 sites,
+    both XCD maps and two block sizes, on a lattice the tiles fit (and, at block 256, one they do not,
+    where the shape falls back to one thread per site): bitwise equal to the untiled kernel of the
+    same form, batched and single, and the FP64 result within 1e-12 of the oracle."""
+    L = (8, 8, 4, 6)
+    announce(f"laplacian walk tiles {dtype}")
+    U, P, Ud, Pd = setup(L, "haar", 0.0, 17, n=3, dtype=dtype)
+    for form in (0, 2):
+        api.tune_set(L, dtype, 3, form, 64, 0, 4, 0, 0)
+        ref = api.laplacian_apply(L, Ud, Pd)
+        for block in (64, 128, 256):
+            for walk in (2, 3, 6):
+                for tile2 in (1, 2, 4):
+                    for xcd in (0, 1):
+                        api.tune_set(L, dtype, 3, form, block, xcd, 4, 0, walk, tile2=tile2)
+                        api.tune_set(L, dtype, 1, form, block, xcd, 4, 0, walk, tile2=tile2)
+                        y = api.laplacian_apply(L, Ud, Pd)
+                        y1 = api.laplacian_apply(L, Ud, Pd[2:3].contiguous())
+                        assert torch.equal(y, ref), (form, block, walk, tile2, xcd)
+                        assert torch.equal(y[2:3], y1), (form, block, walk, tile2, xcd)
+        api.tune_clear()
+        if dtype == torch.float64:
+            yref = olap.laplacian(U, P, L)
+            assert rel_max(ref.cpu().numpy(), yref) <= 1e-12
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_laplacian_multi_field_bitwise(dtype):
     """ns fields per thread (each link and adjoint matrix serving 4 ns vectors): every field's result
     is bitwise that of one field per thread with the same form, for plain applications, the Chebyshev
