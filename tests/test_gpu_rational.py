@@ -340,6 +340,18 @@ def test_kinetic_force_finite_differences_4():
     _fd_check((4, 4, 4, 4), 0.4, 4, 16, 1e-6, 1e-13, 1e-5)
 
 
+def test_kinetic_force_finite_differences_16_h1e6():
+    """The 16^4, eps = 0.4, 8-pole workload with the small step h = 1e-6: 64 random link
+    perturbations, second-order central differences with h = 1e-6 (FP64).
+
+    Error model: the displaced solves (true residual 1e-13) leave K with an error ~ 1e-13 |Y|^2 that
+    need not cancel between the two evaluations, up to ~ 1e-7 / 2h ~ 5e-2 absolute in the worst case,
+    against max |dK| of order 10-50; the truncation h^2 |K'''| / 6 is negligible.  Asserted at 2e-3
+    relative to max |dK|; the fourth-order test below checks the same force to 2e-5."""
+    announce("force FD 16^4 h=1e-6")
+    _fd_check((16, 16, 16, 16), 0.4, 4, 64, 1e-6, 1e-13, 2e-3)
+
+
 def test_kinetic_force_finite_differences_16():
     """The 16^4, eps = 0.4, 8-pole workload: 64 random link perturbations, fourth-order central
     differences with h = 2e-3.
