@@ -2397,8 +2397,10 @@ rmh_status rmh_autotune_laplacian(const int32_t L[4], const void* U, int32_t dty
     }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  // the candidates were stored one by one while they were timed: leave the best one measured (or,
+  // after a failure before any was, the configuration looked up at the start) in the table
+  tune_store(g, dtype, n_rhs, purpose, bestc, bt < 1e30f ? bt : 0.0);
   if (st != RMH_OK) return st;
-  tune_store(g, dtype, n_rhs, purpose, bestc, bt);
   if (best) *best = to_abi(bestc);
   if (best_ms) *best_ms = bt;
   return RMH_OK;
