@@ -325,7 +325,7 @@ RMH_HD void mat_hop(const T* u, const T* phi, T* acc) {
         aim[i][j] = -u[2 * (3 * j + i) + 1];
       }
     }
-  // W = A Phi
+  // W = A Phi (the diagonal of Phi is real: its imaginary terms are left out)
   T wre[3][3], wim[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
@@ -334,21 +334,28 @@ RMH_HD void mat_hop(const T* u, const T* phi, T* acc) {
       T sr = 0, si = 0;
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        sr = fmadd(are[i][k], pre[k][j], fmadd(-aim[i][k], pim[k][j], sr));
-        si = fmadd(are[i][k], pim[k][j], fmadd(aim[i][k], pre[k][j], si));
+        if (k == j) {
+          sr = fmadd(are[i][k], pre[k][j], sr);
+          si = fmadd(aim[i][k], pre[k][j], si);
+        } else {
+          sr = fmadd(are[i][k], pre[k][j], fmadd(-aim[i][k], pim[k][j], sr));
+          si = fmadd(are[i][k], pim[k][j], fmadd(aim[i][k], pre[k][j], si));
+        }
       }
       wre[i][j] = sr;
       wim[i][j] = si;
     }
-  // Y = W A^dag : Y_ij = sum_k W_ik conj(A_jk); only the diagonal (real) and upper part
+  // Y = W A^dag : Y_ij = sum_k W_ik conj(A_jk); only the diagonal (real) and upper part; Y is
+  // traceless with Phi, so Y_22 = -(Y_00 + Y_11)
   T yd[3];
 #pragma unroll
-  for (int i = 0; i < 3; ++i) {
+  for (int i = 0; i < 2; ++i) {
     T sr = 0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) sr = fmadd(wre[i][k], are[i][k], fmadd(wim[i][k], aim[i][k], sr));
     yd[i] = sr;
   }
+  yd[2] = -(yd[0] + yd[1]);
   constexpr int pi_[3] = {0, 0, 1};
   constexpr int pj_[3] = {1, 2, 2};
   constexpr int ps_[3] = {0, 3, 5};
