@@ -492,7 +492,20 @@ rmh_status engine_solve(Engine& e, const double* U64, const float* U32, const do
   // iterations in each precision, and the FP64 residual of the reliable updates
   const HopConfig c32 = hop_config(g, RMH_F32, nr, RMH_PURPOSE_CG);
   const HopConfig c64 = hop_config(g, RMH_F64, nr, RMH_PURPOSE_CG);
-  const HopConfig cru = hop_config(g, RMH_F64, nr, RMH_PURPOSE_CG64);
+  // The reliable-update stencil is launched every FP32 iteration and usually finds nothing pending
+  // (its blocks exit at once); an empty launch costs in proportion to its block count, so where the
+  // FP64 residual shape is the hop-split one (four lanes per site) it runs one thread per site
+  // instead (16^4, one field, 12 poles: the mixed solve 3 % faster).
+  HopConfig cru = hop_config(g, RMH_F64, nr, RMH_PURPOSE_CG64);
+  if (cru.order >= 2) {
+    cru.form = kFormStream;
+    cru.block = 256;
+    cru.nv = 4;
+    cru.order = 0;
+    cru.walk = 0;
+    cru.ns = 1;
+    cru.tile2 = 1;
+  }
   const int32_t nblk_32 = hop_num_blocks(g, c32), nblk_64 = hop_num_blocks(g, c64);
   CgDev cg64 = cg_view(e, nblk_64, false);
   CgDev cg32 = cg_view(e, nblk_32, true);
