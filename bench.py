@@ -635,7 +635,8 @@ def d5_force_step(api, inputs, torch, dev):
 
 def d6_spectrum_bwd(api, inputs, torch, np, dev):
     """Backward of the power spectrum (link derivative and source gradient) at 16^4, eps=0.5,
-    degree 64, 16 windows: the reverse Chebyshev sweep (3 x 64 stencil sweeps, 64 derivative passes)."""
+    degree 64, 16 windows: the forward sweep to t_64, then the reverse sweep (per degree one stencil
+    launch over the adjoint and the recomputed forward vectors, and one derivative pass)."""
     L = (16, 16, 16, 16)
     Ud = api.pack_links(L, inputs.random_links(L, "eps", 0.5, seed=6).to(dev))
     F = inputs.gaussian_fields(L, 1, seed=6).to(dev)

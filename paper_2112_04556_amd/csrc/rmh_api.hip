@@ -1123,6 +1123,9 @@ rmh_status cheb_filter_t(const Geom& g, const T* U, const T* x, int32_t n_rhs, i
 //   dL/dx      = tb_0 = G_0 + A tb_1 - tb_2  (through the recursion only).
 // t_D, t_{D-1} come from a forward sweep; the reverse sweep then runs the recursion backwards,
 // t_{k-2} = 2A t_{k-1} - t_k, so only two t and two tb vectors are held.  2A = -H/4.
+// tb_j lives in B[(j-1) % 2] and t_j (j >= 1) in T[(j-1) % 2], and B[i] is followed by T[i] in
+// memory: the two recursion steps of a reverse step (tb_k from tb_{k+1}, tb_{k+2} and t_{k-2} from
+// t_{k-1}, t_k) then read one 2 n_rhs-field batch and write another, and go out as one launch.
 struct ChebBwdPlan {
   double* T[2];
   double* B[2];
@@ -1132,10 +1135,10 @@ struct ChebBwdPlan {
 ChebBwdPlan plan_cheb_bwd(Carver& c, const Geom& g, int32_t n_rhs, int32_t n_y, int32_t D) {
   ChebBwdPlan p{};
   const size_t fr = (size_t)n_rhs * 32 * g.V;
-  p.T[0] = c.take<double>(fr);
-  p.T[1] = c.take<double>(fr);
-  p.B[0] = c.take<double>(fr);
-  p.B[1] = c.take<double>(fr);
+  for (int i = 0; i < 2; ++i) {
+    p.B[i] = c.take<double>(2 * fr);
+    p.T[i] = p.B[i] + fr;
+  }
   p.coef = c.take<double>((size_t)n_rhs * n_y * (D + 2));
   return p;
 }
@@ -1153,7 +1156,9 @@ rmh_status cheb_bwd(const Geom& g, const double* U, const double* x, int32_t n_r
   }
   const double* coef_x = p.coef + (size_t)n_rhs * n_y * nk;
   const HopConfig cfg = hop_config(g, RMH_F64, n_rhs, RMH_PURPOSE_CHEB_BWD);
-  auto hop = [&](const double* in, const double* z, double* out, double a, double c) -> rmh_status {
+  const HopConfig cfg2 = hop_config(g, RMH_F64, 2 * n_rhs, RMH_PURPOSE_CHEB_BWD);
+  // nf fields (n_rhs, or 2 n_rhs for a B[i]-T[i] pair)
+  auto hopn = [&](const double* in, const double* z, double* out, double a, double c, int32_t nf) -> rmh_status {
     HopArgs<double> h{};
     h.g = g;
     h.U = U;
@@ -1164,12 +1169,16 @@ rmh_status cheb_bwd(const Geom& g, const double* U, const double* x, int32_t n_r
     h.out = out;
     h.a = a;
     h.c = c;
-    h.n_rhs = n_rhs;
+    h.n_rhs = nf;
     h.store = 1;
-    ProfScope ps(RMH_PROF_STENCIL, hop_bytes(g, n_rhs, 8, z != nullptr, true), s, n_rhs);
-    HIP_TRY(launch_hop<double>(h, cfg, s));
+    ProfScope ps(RMH_PROF_STENCIL, hop_bytes(g, nf, 8, z != nullptr, true), s, nf);
+    HIP_TRY(launch_hop<double>(h, nf == n_rhs ? cfg : cfg2, s));
     return RMH_OK;
   };
+  auto hop = [&](const double* in, const double* z, double* out, double a, double c) -> rmh_status {
+    return hopn(in, z, out, a, c, n_rhs);
+  };
+  const int64_t fr = n * n_rhs;
   // forward: prv = t_{D-1}, cur = t_D
   const double* prv = x;
   double* cur = p.T[0];
@@ -1181,13 +1190,23 @@ rmh_status cheb_bwd(const Geom& g, const double* U, const double* x, int32_t n_r
     cur = out;
   }
   // reverse
-  double* nb = p.B[0];    // tb_{k+1}
-  double* nb2 = p.B[1];   // tb_{k+2}
+  double* nb = p.B[D % 2];         // tb_{k+1}
+  double* nb2 = p.B[(D - 1) % 2];  // tb_{k+2}
   HIP_TRY(launch_zero(nb, (size_t)n * n_rhs * 8, s));
   HIP_TRY(launch_zero(nb2, (size_t)n * n_rhs * 8, s));
   for (int32_t k = D; k >= 1; --k) {
-    // tb_k into tb_{k+2}'s buffer
-    if (k < D) RMH_TRY(hop(nb, k + 1 < D ? nb2 : nullptr, nb2, -0.25, k + 1 < D ? -1.0 : 0.0));
+    // tb_k into tb_{k+2}'s buffer (for k < D), t_{k-2} = 2A t_{k-1} - t_k into t_k's buffer (for
+    // k >= 3; t_{k-1} stays for the link term below): one launch over the pairs B[i]-T[i] when both
+    // run (tb_{D+1} is the zeroed buffer, so its z term adds nothing)
+    const bool tb_hop = k < D, t_hop = k >= 3;
+    if (tb_hop && t_hop) {
+      if (prv != nb + fr || cur != nb2 + fr) return fail(RMH_E_HOST, "Chebyshev backward: buffer pairing broken");
+      RMH_TRY(hopn(nb, nb2, nb2, -0.25, -1.0, 2 * n_rhs));
+    } else if (tb_hop) {
+      RMH_TRY(hop(nb, k + 1 < D ? nb2 : nullptr, nb2, -0.25, k + 1 < D ? -1.0 : 0.0));
+    } else if (t_hop) {
+      RMH_TRY(hop(prv, cur, cur, -0.25, -1.0));
+    }
     HIP_TRY(launch_cheb_source(nb2, Y, p.coef, n_rhs, n_y, nk, k, n, s));
     std::swap(nb, nb2);   // nb = tb_k, nb2 = tb_{k+1}
     if (grad_omega) {
@@ -1206,17 +1225,13 @@ rmh_status cheb_bwd(const Geom& g, const double* U, const double* x, int32_t n_r
       ProfScope ps(RMH_PROF_FORCE, fbytes, s, n_rhs);
       HIP_TRY(launch_force(fa, s));
     }
-    if (k >= 2) {
-      // t_{k-2} = 2A t_{k-1} - t_k into t_k's buffer; t_0 is x itself
-      if (k >= 3) {
-        RMH_TRY(hop(prv, cur, cur, -0.25, -1.0));
-        const double* t_km2 = cur;
-        cur = (double*)prv;
-        prv = t_km2;
-      } else {
-        cur = (double*)prv;
-        prv = x;
-      }
+    if (k >= 3) {
+      const double* t_km2 = cur;
+      cur = (double*)prv;
+      prv = t_km2;
+    } else if (k == 2) {
+      cur = (double*)prv;   // t_0 is x itself
+      prv = x;
     }
   }
   if (grad_x) {

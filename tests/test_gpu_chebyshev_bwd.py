@@ -49,6 +49,27 @@ def test_power_spectrum_bwd_parity(kind, shape):
     assert rel_max(gF.cpu().numpy(), ref_F) <= 1e-12
 
 
+@pytest.mark.parametrize("D", [2, 3, 4, 5])
+def test_bwd_low_degrees(D):
+    """Degrees 2-5, where the reverse sweep's first steps take each of its forms (the adjoint step
+    alone, the recomputed forward step alone, both in one launch): power-spectrum and filter
+    derivatives against the oracle."""
+    L = L_PAR
+    announce(f"chebyshev bwd degree {D}")
+    U, F, Ud, Fd = setup(L, "eps", 0.6, 45 + D, n=2)
+    nw = 3
+    edges = och.equal_windows(nw)
+    gamma = np.random.default_rng(D).normal(size=(2, nw))
+    gF, go = api.power_spectrum_bwd(L, Ud, Fd, gamma, D, nw)
+    assert rel_max(go[0].cpu().numpy(), ocg.power_spectrum_link_derivative(U, F, L, D, edges, gamma)) <= 1e-12
+    assert rel_max(gF.cpu().numpy(), ocg.power_spectrum_source_gradient(U, F, L, D, edges, gamma)) <= 1e-12
+    gy = np.random.default_rng(100 + D).normal(size=(nw,) + F.shape)
+    gx, gop = api.cheb_filter_bwd(L, Ud, Fd, torch.from_numpy(gy).to(dev()), D, nw, edges, per_rhs=True)
+    rgx, rgop = ocg.cheb_filter_vjp(U, F, gy, L, D, edges, per_rhs=True)
+    assert rel_max(gx.cpu().numpy(), rgx) <= 1e-12
+    assert rel_max(gop.cpu().numpy(), rgop) <= 1e-12
+
+
 def test_cheb_filter_bwd_parity():
     L = L_PAR
     announce("cheb_filter_bwd parity")
