@@ -304,8 +304,19 @@ __global__ void __launch_bounds__(256) k_hop_split(const HopArgs<T> A, int32_t x
 // lattice; each thread walks K consecutive x3 values of its column.  Per step the x0, x1, x2
 // hops load their links and neighbours as in k_hop; the x3 forward hop loads U_3(x) and
 // phi(x+3), which become the backward link and the centre field of the next step.
+// Waves per SIMD the walking kernel is compiled for.  The FP32 3x3-form walk over all four
+// directions needs 170 registers left to itself (two waves per SIMD); capped at 168 it keeps three
+// waves without spilling, and its batched Chebyshev sweeps run 4-5 % faster (they move fewer bytes
+// than one thread per site but were latency-bound at two waves).  The other walks keep the
+// compiler's choice (FP64 and the 8x8 forms do not fit three waves without spilling).
+template <typename T, int FORM, int NV>
+constexpr int hop_walk_waves() {
+  return (sizeof(T) == 4 && FORM == kFormMatrix && NV == 4) ? 3 : 1;
+}
+
 template <typename T, int FORM, int NV, bool DOTS>
-__global__ void __launch_bounds__(256) k_hop_walk(const HopArgs<T> A, int32_t xcd, int32_t K, int32_t tile2) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(hop_walk_waves<T, FORM, NV>())))
+k_hop_walk(const HopArgs<T> A, int32_t xcd, int32_t K, int32_t tile2) {
   constexpr int G = 4 / NV;
   const HopBlock hb = hop_block(xcd, A.n_rhs);
   const int32_t v = hb.v;
@@ -647,10 +658,15 @@ static hipError_t launch_hop_form(const HopArgs<T>& A, const HopConfig& cfg, hip
         else
           hipLaunchKernelGGL((k_hop_ns<T, FORM, 2, false>), g2, block, 0, s, A, cfg.xcd_remap, ord);
       } else if (cfg.ns == 4) {
-        if (dots)
-          hipLaunchKernelGGL((k_hop_ns<T, FORM, 4, true>), g2, block, 0, s, A, cfg.xcd_remap, ord);
-        else
-          hipLaunchKernelGGL((k_hop_ns<T, FORM, 4, false>), g2, block, 0, s, A, cfg.xcd_remap, ord);
+        // four fields per thread: FP32 only (the FP64 kernel would spill)
+        if constexpr (sizeof(T) == 4) {
+          if (dots)
+            hipLaunchKernelGGL((k_hop_ns<T, FORM, 4, true>), g2, block, 0, s, A, cfg.xcd_remap, ord);
+          else
+            hipLaunchKernelGGL((k_hop_ns<T, FORM, 4, false>), g2, block, 0, s, A, cfg.xcd_remap, ord);
+        } else {
+          return hipErrorInvalidValue;
+        }
       } else {
         return hipErrorInvalidValue;
       }

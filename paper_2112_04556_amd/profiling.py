@@ -149,13 +149,19 @@ def run_kinetic(L, n: int, poles: int, mode: int, reps: int):
           f"{out['stats']['iters']} solver iterations", flush=True)
 
 
-def run_spectrum(L, n: int, degree: int, windows: int, dtype_name: str, kind: str):
+def run_spectrum(L, n: int, degree: int, windows: int, dtype_name: str, kind: str, config=None):
     import torch
     from . import api, inputs
     dt = torch.float64 if dtype_name == "f64" else torch.float32
     U = api.pack_links(L, inputs.random_links(L, kind, seed=3).to("cuda"), dt)
     F = inputs.gaussian_fields(L, n, seed=3).to("cuda").to(dt)
-    cfg, ms = api.autotune_laplacian(L, U, F, reps=2)
+    if config:
+        # a pinned launch configuration, so that separate counter runs count the same kernel
+        cfg = tuple(config)
+        form, block, xcd, nv, order, walk, ns, tile2 = cfg
+        api.tune_set(L, dt, n, form, block, xcd, nv, order, walk, ns=ns, tile2=tile2)
+    else:
+        cfg, ms = api.autotune_laplacian(L, U, F, reps=2)
     api.power_spectrum(L, U, F, degree, windows)
     torch.cuda.synchronize()
     print(f"spectrum {L} n={n} degree={degree} {dtype_name} {kind}: config {cfg}, one call "
@@ -215,6 +221,9 @@ def main(argv=None):
     p.add_argument("--windows", type=int, default=64)
     p.add_argument("--dtype", choices=["f64", "f32"], default="f32")
     p.add_argument("--kind", choices=["haar", "unit", "eps"], default="haar")
+    p.add_argument("--config", type=int, nargs=8, default=None,
+                   help="pin the stencil launch configuration (form block xcd_remap nv order walk ns tile2) "
+                        "instead of autotuning")
     p = sub.add_parser("solve")
     p.add_argument("--L", type=int, nargs=4, default=[16, 16, 16, 16])
     p.add_argument("--n", type=int, default=8)
@@ -257,7 +266,7 @@ def main(argv=None):
     elif a.cmd == "solve":
         run_solve(tuple(a.L), a.n, a.poles, a.kappa, a.mode, a.reps)
     elif a.cmd == "spectrum":
-        run_spectrum(tuple(a.L), a.n, a.degree, a.windows, a.dtype, a.kind)
+        run_spectrum(tuple(a.L), a.n, a.degree, a.windows, a.dtype, a.kind, a.config)
     elif a.cmd == "summarize-trace":
         print(json.dumps(summarize_trace(a.dir, a.prefix, a.last or 10**9), indent=1))
     else:
