@@ -535,7 +535,7 @@ def d3_spectrum(api, inputs, torch, dev):
     F = inputs.gaussian_fields(L, 32, seed=3).to(dev).float()
     for kind in ("haar", "unit"):
         U32 = api.pack_links(L, inputs.random_links(L, kind, seed=3).to(dev), torch.float32)
-        api.autotune_laplacian(L, U32, F, reps=2)
+        api.autotune_laplacian(L, U32, F, reps=5, purpose="moments")
         api.power_spectrum(L, U32, F, 256, 64)
         torch.cuda.synchronize()
         api.profile_enable(True)

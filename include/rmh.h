@@ -431,10 +431,13 @@ typedef enum {
 rmh_status rmh_tune_set(const int32_t L[4], int32_t dtype, int32_t n_rhs, int32_t purpose, const rmh_hop_config* cfg);
 /* Time every stencil configuration on the caller's buffers and keep the fastest for (L, dtype, n_rhs,
  * purpose).  The timing unit: for RMH_PURPOSE_MOMENTS, _FILTER and _CHEB_BWD the recursion step
- * y = -H x / 4 - x; for _APPLY, _CG, _CG64 and _HEATBATH the plain y = (8 - H) x; for _ANY both (the
- * pair); reps units each, HIP events on the stream, y overwritten.  best (optional, host) receives
- * the configuration, best_ms (optional) the mean time of one unit.  RMH_E_ARG for null pointers or y
- * overlapping x or U.  Synchronizes the stream. */
+ * y = -H x / 4 - y (written over its z input, as the sweeps write t_{k+1} over t_{k-1}; y is zeroed
+ * first); for _APPLY, _CG, _CG64 and _HEATBATH the plain y = (8 - H) x; for _ANY both (the
+ * pair); with the per-block FP64 dot products that the purpose's drivers fuse into the launch
+ * (_CG, _CG64: one, _MOMENTS: three; their buffer, n_rhs x 3 x a block bound doubles, is allocated
+ * for the call and freed); reps units each, HIP events on the stream, y overwritten.  best
+ * (optional, host) receives the configuration, best_ms (optional) the mean time of one unit.
+ * RMH_E_ARG for null pointers or y overlapping x or U.  Synchronizes the stream. */
 rmh_status rmh_autotune_laplacian(const int32_t L[4], const void* U, int32_t dtype, const void* x, void* y,
                                   int32_t n_rhs, int32_t purpose, int32_t reps, rmh_hop_config* best,
                                   double* best_ms, rmh_stream stream);

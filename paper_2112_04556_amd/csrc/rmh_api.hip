@@ -1246,11 +1246,13 @@ rmh_status cheb_bwd(const Geom& g, const double* U, const double* x, int32_t n_r
 
 // =============================================================================================
 // One timing unit of the autotuner: the two stencil epilogues the drivers use, the plain
-// y = (8 - H) x of the CG and the Chebyshev recursion step y = -H x / 4 - z (z = x here), both
-// writing y, so the pick fits the solves and the spectra alike.
+// y = (8 - H) x of the CG and the Chebyshev recursion step y = -H x / 4 - z with z = y (the sweeps
+// write t_{k+1} over t_{k-1}), so the pick fits the solves and the spectra alike.
+// partials/dot_mask (optional): the per-block FP64 dot products the drivers of a purpose fuse into
+// the same launch (the CG's <p, Ap>, the moments' three), so the unit runs the kernel they run.
 template <typename T>
 static hipError_t tune_unit(const Geom& g, const T* U, const T* x, T* y, int32_t n_rhs, const HopConfig& cfg,
-                            int32_t kind, hipStream_t s) {
+                            int32_t kind, double* partials, int32_t dot_mask, hipStream_t s) {
   HopArgs<T> h{};
   h.g = g;
   h.U = U;
@@ -1260,17 +1262,19 @@ static hipError_t tune_unit(const Geom& g, const T* U, const T* x, T* y, int32_t
   h.z_div = 1;
   h.n_rhs = n_rhs;
   h.store = 1;
+  h.partials = partials;
+  h.dot_mask = partials ? dot_mask : 0;
   if (kind & 1) {   // the plain application y = (8 - H) x
     h.a = -1.0;
     h.b = 8.0;
     hipError_t e = launch_hop<T>(h, cfg, s);
     if (e != hipSuccess) return e;
   }
-  if (kind & 2) {   // the recursion step y = -H x / 4 - x
+  if (kind & 2) {   // the recursion step y = -H x / 4 - y, written over its z input as the sweeps do
     h.a = -0.25;
     h.b = 0.0;
     h.c = -1.0;
-    h.z = x;
+    h.z = y;
     return launch_hop<T>(h, cfg, s);
   }
   return hipSuccess;
@@ -2366,7 +2370,25 @@ rmh_status rmh_autotune_laplacian(const int32_t L[4], const void* U, int32_t dty
                              purpose == RMH_PURPOSE_CHEB_BWD)
                                 ? 2
                                 : (purpose == RMH_PURPOSE_ANY ? 3 : 1);
+  // the dot products fused into the purpose's launches: <p, Ap> in the CG iterations and the FP64
+  // residuals, the three moment sums in the power-spectrum sweeps
+  const int32_t dot_mask = (purpose == RMH_PURPOSE_CG || purpose == RMH_PURPOSE_CG64) ? 2
+                           : purpose == RMH_PURPOSE_MOMENTS                           ? 7
+                                                                                      : 0;
   hipStream_t s = (hipStream_t)stream;
+  double* partials = nullptr;
+  if (dot_mask) {
+    const size_t pb = (size_t)n_rhs * 3 * hop_max_blocks(g) * sizeof(double);
+    if (hipMalloc((void**)&partials, pb) != hipSuccess) return fail(RMH_E_HIP, "hipMalloc of %zu bytes", pb);
+  }
+  struct FreeOnExit {
+    double* p;
+    ~FreeOnExit() {
+      if (p) (void)hipFree(p);
+    }
+  } free_partials{partials};
+  // y is the recursion unit's z input: start it from zeros (it then stays bounded, y <- A x - y)
+  HIP_TRY(launch_zero(y, (size_t)n_rhs * 32 * g.V * dsize(dtype), s));
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
@@ -2398,8 +2420,10 @@ rmh_status rmh_autotune_laplacian(const int32_t L[4], const void* U, int32_t dty
         auto unit = [&]() -> rmh_status {
           const hipError_t e =
               dtype == RMH_F64
-                  ? tune_unit<double>(g, (const double*)U, (const double*)x, (double*)y, n_rhs, c, unit_kind, s)
-                  : tune_unit<float>(g, (const float*)U, (const float*)x, (float*)y, n_rhs, c, unit_kind, s);
+                  ? tune_unit<double>(g, (const double*)U, (const double*)x, (double*)y, n_rhs, c, unit_kind,
+                                      partials, dot_mask, s)
+                  : tune_unit<float>(g, (const float*)U, (const float*)x, (float*)y, n_rhs, c, unit_kind,
+                                     partials, dot_mask, s);
           return e == hipSuccess ? RMH_OK : fail(RMH_E_HIP, "stencil launch: %s", hipGetErrorString(e));
         };
         st = unit();  // warm-up
