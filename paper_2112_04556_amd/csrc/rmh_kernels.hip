@@ -1256,23 +1256,28 @@ struct M3 {
   double re[9], im[9];
 };
 
+// U_mu(x) at site s: rows 0 and 1 loaded (12 reals), row 2 rebuilt from them (SU(3)).
 __device__ __forceinline__ void load_link(const double* __restrict__ U, int32_t mu, int32_t s, int32_t V, M3& m) {
   const double* Um = U + (int64_t)mu * 18 * V;
+  double u[18];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) u[c] = (Um + (size_t)c * V)[s];
+  su3_row2<double>(u);
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
-    m.re[k] = (Um + (size_t)(2 * k) * V)[s];
-    m.im[k] = (Um + (size_t)(2 * k + 1) * V)[s];
+    m.re[k] = u[2 * k];
+    m.im[k] = u[2 * k + 1];
   }
 }
 
-// C = op(A) op(B), op = identity or Hermitian conjugate
-template <bool kDa, bool kDb>
+// C = op(A) op(B) (kAcc: C += op(A) op(B)), op = identity or Hermitian conjugate
+template <bool kDa, bool kDb, bool kAcc = false>
 __device__ __forceinline__ void mul3(const M3& A, const M3& B, M3& C) {
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      double re = 0.0, im = 0.0;
+      double re = kAcc ? C.re[i * 3 + j] : 0.0, im = kAcc ? C.im[i * 3 + j] : 0.0;
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         const int ia = kDa ? k * 3 + i : i * 3 + k;
@@ -1288,73 +1293,64 @@ __device__ __forceinline__ void mul3(const M3& A, const M3& B, M3& C) {
 }
 
 // F^c_mu(x) = -(beta/3) Im Tr(T^c U_mu(x) A_mu(x)), A the sum of the six staples; partials of
-// sum_mu Re Tr(U_mu A_mu) per block (each plaquette enters four times)
+// sum_mu Re Tr(U_mu A_mu) per block (each plaquette enters four times).  A block is four waves over
+// the same 64 consecutive sites, wave w computing the force on U_w: the direction is wave-uniform,
+// every load is a coalesced 64-site row of one component, and a lattice gives four times as many
+// waves as sites / 64 to hide the staples' dependent loads.
 __global__ void __launch_bounds__(256) k_gauge_force(Geom g, const double* __restrict__ U, double beta,
                                                      double* __restrict__ F, double* __restrict__ partials) {
   const int32_t V = g.V;
-  const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t mu = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int32_t s = blockIdx.x * 64 + (threadIdx.x & 63);
   double tr[1] = {0.0};
   if (s < V) {
     int32_t xc[4];
     site_coords(g, s, xc);
+    const int32_t s_pm = site_shift(g, s, xc, mu, +1);
+    int32_t xm[4];
+    site_coords(g, s_pm, xm);
+    M3 A;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) A.re[k] = A.im[k] = 0.0;
 #pragma unroll 1
-    for (int mu = 0; mu < 4; ++mu) {
-      M3 A;
+    for (int nu = 0; nu < 4; ++nu) {
+      if (nu == mu) continue;
+      const int32_t s_pn = site_shift(g, s, xc, nu, +1);
+      const int32_t s_mn = site_shift(g, s, xc, nu, -1);
+      const int32_t s_pm_mn = site_shift(g, s_pm, xm, nu, -1);
+      M3 a, b, t;
+      // upper staple U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag
+      load_link(U, nu, s_pm, V, a);
+      load_link(U, mu, s_pn, V, b);
+      mul3<false, true>(a, b, t);
+      load_link(U, nu, s, V, a);
+      mul3<false, true, true>(t, a, A);
+      // lower staple U_nu(x+mu-nu)^dag U_mu(x-nu)^dag U_nu(x-nu)
+      load_link(U, nu, s_pm_mn, V, a);
+      load_link(U, mu, s_mn, V, b);
+      mul3<true, true>(a, b, t);
+      load_link(U, nu, s_mn, V, a);
+      mul3<false, false, true>(t, a, A);
+    }
+    M3 u, m;
+    load_link(U, mu, s, V, u);
+    mul3<false, false>(u, A, m);
+    tr[0] = m.re[0] + m.re[4] + m.re[8];
+    // Im Tr(lambda^c M) for the eight Gell-Mann matrices; T^c = lambda^c / 2
+    double q[8];
+    q[0] = m.im[3] + m.im[1];
+    q[1] = m.re[1] - m.re[3];
+    q[2] = m.im[0] - m.im[4];
+    q[3] = m.im[6] + m.im[2];
+    q[4] = m.re[2] - m.re[6];
+    q[5] = m.im[7] + m.im[5];
+    q[6] = m.re[5] - m.re[7];
+    q[7] = (m.im[0] + m.im[4] - 2.0 * m.im[8]) * 0.57735026918962576451;
+    if (F) {
+      double* f = F + (int64_t)mu * 8 * V + s;
+      const double k = -beta / 6.0;
 #pragma unroll
-      for (int k = 0; k < 9; ++k) A.re[k] = A.im[k] = 0.0;
-      const int32_t s_pm = site_shift(g, s, xc, mu, +1);
-#pragma unroll 1
-      for (int nu = 0; nu < 4; ++nu) {
-        if (nu == mu) continue;
-        const int32_t s_pn = site_shift(g, s, xc, nu, +1);
-        const int32_t s_mn = site_shift(g, s, xc, nu, -1);
-        int32_t xm[4];
-        site_coords(g, s_pm, xm);
-        const int32_t s_pm_mn = site_shift(g, s_pm, xm, nu, -1);
-        M3 a, b, c, t, st;
-        // upper staple U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag
-        load_link(U, nu, s_pm, V, a);
-        load_link(U, mu, s_pn, V, b);
-        load_link(U, nu, s, V, c);
-        mul3<false, true>(a, b, t);
-        mul3<false, true>(t, c, st);
-#pragma unroll
-        for (int k = 0; k < 9; ++k) {
-          A.re[k] += st.re[k];
-          A.im[k] += st.im[k];
-        }
-        // lower staple U_nu(x+mu-nu)^dag U_mu(x-nu)^dag U_nu(x-nu)
-        load_link(U, nu, s_pm_mn, V, a);
-        load_link(U, mu, s_mn, V, b);
-        load_link(U, nu, s_mn, V, c);
-        mul3<true, true>(a, b, t);
-        mul3<false, false>(t, c, st);
-#pragma unroll
-        for (int k = 0; k < 9; ++k) {
-          A.re[k] += st.re[k];
-          A.im[k] += st.im[k];
-        }
-      }
-      M3 u, m;
-      load_link(U, mu, s, V, u);
-      mul3<false, false>(u, A, m);
-      tr[0] += m.re[0] + m.re[4] + m.re[8];
-      // Im Tr(lambda^c M) for the eight Gell-Mann matrices; T^c = lambda^c / 2
-      double q[8];
-      q[0] = m.im[3] + m.im[1];
-      q[1] = m.re[1] - m.re[3];
-      q[2] = m.im[0] - m.im[4];
-      q[3] = m.im[6] + m.im[2];
-      q[4] = m.re[2] - m.re[6];
-      q[5] = m.im[7] + m.im[5];
-      q[6] = m.re[5] - m.re[7];
-      q[7] = (m.im[0] + m.im[4] - 2.0 * m.im[8]) * 0.57735026918962576451;
-      if (F) {
-        double* f = F + (int64_t)mu * 8 * V + s;
-        const double k = -beta / 6.0;
-#pragma unroll
-        for (int cc = 0; cc < 8; ++cc) f[(int64_t)cc * V] = k * q[cc];
-      }
+      for (int cc = 0; cc < 8; ++cc) f[(int64_t)cc * V] = k * q[cc];
     }
   }
   if (partials) {
@@ -1364,11 +1360,11 @@ __global__ void __launch_bounds__(256) k_gauge_force(Geom g, const double* __res
   }
 }
 
-int gauge_force_blocks(const Geom& g) { return (g.V + kBlock - 1) / kBlock; }
+int gauge_force_blocks(const Geom& g) { return (g.V + 63) / 64; }
 
 hipError_t launch_gauge_force(const Geom& g, const double* U, double beta, double* F, double* partials,
                               hipStream_t s) {
-  hipLaunchKernelGGL(k_gauge_force, dim3(gauge_force_blocks(g)), dim3(kBlock), 0, s, g, U, beta, F, partials);
+  hipLaunchKernelGGL(k_gauge_force, dim3(gauge_force_blocks(g)), dim3(256), 0, s, g, U, beta, F, partials);
   return hipGetLastError();
 }
 
