@@ -64,28 +64,31 @@ hipError_t launch_reduce_rows(const double* partials, int32_t nblk, int32_t m, d
   return hipGetLastError();
 }
 
+// Fills stride over the grid: a launch holds fewer than 2^32 threads, and buffers of 16 GiB and
+// more (a batch of FP64 link fields at 32^3 x 64) have more 4-byte words than that.
+static unsigned fill_blocks(int64_t n) { return (unsigned)std::min<int64_t>((n + kBlock - 1) / kBlock, 1 << 20); }
+
 __global__ void k_zero(uint32_t* p, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0u;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
 }
 
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
   // every buffer is carved at 256-byte granularity, so bytes is a multiple of 4
   const int64_t n = (int64_t)(bytes / 4);
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_zero, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                     (uint32_t*)p, n);
+  hipLaunchKernelGGL(k_zero, dim3(fill_blocks(n)), dim3(kBlock), 0, s, (uint32_t*)p, n);
   return hipGetLastError();
 }
 
 __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
 }
 
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, p, v, n);
+  hipLaunchKernelGGL(k_fill_i32, dim3(fill_blocks(n)), dim3(kBlock), 0, s, p, v, n);
   return hipGetLastError();
 }
 
