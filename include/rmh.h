@@ -150,7 +150,8 @@ typedef enum {
   RMH_OP_POWER_SPECTRUM_BWD = 8,
   RMH_OP_GAUGE_FORCE = 9,
   RMH_OP_HEATBATH = 10,
-  RMH_OP_LEAPFROG = 11
+  RMH_OP_LEAPFROG = 11,
+  RMH_OP_AUTOTUNE = 12
 } rmh_op;
 
 /* ---------------------------------------------------------------------------------------- */
@@ -434,13 +435,14 @@ rmh_status rmh_tune_set(const int32_t L[4], int32_t dtype, int32_t n_rhs, int32_
  * y = -H x / 4 - y (written over its z input, as the sweeps write t_{k+1} over t_{k-1}; y is zeroed
  * first); for _APPLY, _CG, _CG64 and _HEATBATH the plain y = (8 - H) x; for _ANY both (the
  * pair); with the per-block FP64 dot products that the purpose's drivers fuse into the launch
- * (_CG, _CG64: one, _MOMENTS: three; their buffer, n_rhs x 3 x a block bound doubles, is allocated
- * for the call and freed); reps units each, HIP events on the stream, y overwritten.  best
- * (optional, host) receives the configuration, best_ms (optional) the mean time of one unit.
- * RMH_E_ARG for null pointers or y overlapping x or U.  Synchronizes the stream. */
+ * (_CG, _CG64: one, _MOMENTS: three), written into the workspace ws (device, ws_bytes >=
+ * rmh_workspace_bytes(RMH_OP_AUTOTUNE, L, dtype, n_rhs, 0, 0, 0)); reps units each, HIP events on
+ * the stream, y overwritten.  best (optional, host) receives the configuration, best_ms (optional)
+ * the mean time of one unit.  RMH_E_ARG for null pointers or y or ws overlapping x, U or each
+ * other, RMH_E_WORKSPACE for a short workspace.  Synchronizes the stream. */
 rmh_status rmh_autotune_laplacian(const int32_t L[4], const void* U, int32_t dtype, const void* x, void* y,
                                   int32_t n_rhs, int32_t purpose, int32_t reps, rmh_hop_config* best,
-                                  double* best_ms, rmh_stream stream);
+                                  double* best_ms, void* ws, size_t ws_bytes, rmh_stream stream);
 /* Write every stored configuration to a JSON file at path (host), stamped with the current
  * device's architecture name (gcnArchName) and the HIP runtime version; *n_saved (optional) receives
  * the entry count.  RMH_E_HOST if the file cannot be written. */

@@ -20,6 +20,7 @@ RMH_F64, RMH_F32 = 0, 1
 OP_LAPLACIAN, OP_LAPLACIAN_BWD, OP_POWER_SPECTRUM, OP_CHEB_FILTER = 0, 1, 2, 3
 OP_RATIONAL_APPLY, OP_RATIONAL_APPLY_BWD, OP_KINETIC_FORCE = 4, 5, 6
 OP_CHEB_FILTER_BWD, OP_POWER_SPECTRUM_BWD, OP_GAUGE_FORCE, OP_HEATBATH, OP_LEAPFROG = 7, 8, 9, 10, 11
+OP_AUTOTUNE = 12
 
 c_i32, c_i64, c_f64, c_sz, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t, ctypes.c_void_p
 P_i32 = ctypes.POINTER(c_i32)
@@ -108,7 +109,7 @@ SIGNATURES = {
     "rmh_link_exp_vjp": (c_i32, [P_i32, c_vp, c_vp, c_vp, c_vp]),
     "rmh_tune_set": (c_i32, [P_i32, c_i32, c_i32, c_i32, ctypes.POINTER(RmhHopConfig)]),
     "rmh_autotune_laplacian": (c_i32, [P_i32, c_vp, c_i32, c_vp, c_vp, c_i32, c_i32, c_i32,
-                                       ctypes.POINTER(RmhHopConfig), P_f64, c_vp]),
+                                       ctypes.POINTER(RmhHopConfig), P_f64, c_vp, c_sz, c_vp]),
     "rmh_tune_save": (c_i32, [ctypes.c_char_p, P_i32]),
     "rmh_tune_load": (c_i32, [ctypes.c_char_p, P_i32]),
     "rmh_tune_clear": (c_i32, []),

@@ -481,9 +481,11 @@ def autotune_laplacian(L, U, x, reps: int = 5, purpose="any"):
     y = torch.empty_like(x)
     best = L_.RmhHopConfig()
     ms = ctypes.c_double()
+    ws = _workspace(workspace_bytes(L_.OP_AUTOTUNE, L, _dtype_code(x), x.shape[0]), x.device)
     check(lib().rmh_autotune_laplacian(lattice_arg(L), _dev(U, "U"), _dtype_code(x), _dev(x, "x"), _dev(y, "y"),
                                        x.shape[0], _purpose(purpose), int(reps), ctypes.byref(best),
-                                       ctypes.byref(ms), _stream(x.device)), "rmh_autotune_laplacian")
+                                       ctypes.byref(ms), _dev(ws, "ws"), ws.numel(), _stream(x.device)),
+          "rmh_autotune_laplacian")
     return best.as_tuple(), ms.value
 
 

@@ -1361,7 +1361,12 @@ extern "C" {
 
 const char* rmh_last_error(void) { return g_err.c_str(); }
 
-int32_t rmh_version(void) { return 100; }
+// the autotuner's per-block dot-product partials: n_rhs x 3 rows of the largest block count
+static double* plan_autotune(Carver& c, const Geom& g, int32_t n_rhs) {
+  return c.take<double>((size_t)std::max(n_rhs, 1) * 3 * hop_max_blocks(g));
+}
+
+int32_t rmh_version(void) { return 101; }
 
 size_t rmh_workspace_bytes(int32_t op, const int32_t L[4], int32_t dtype, int32_t n_rhs, int32_t aux,
                            int32_t degree, int32_t mode) try {
@@ -1415,6 +1420,9 @@ size_t rmh_workspace_bytes(int32_t op, const int32_t L[4], int32_t dtype, int32_
       plan_leapfrog(c, lp, g, aux, mode ? 1 : 0, degree);
       break;
     }
+    case RMH_OP_AUTOTUNE:
+      plan_autotune(c, g, n_rhs);
+      break;
     default:
       fail(RMH_E_ARG, "unknown op %d", op);
       return 0;
@@ -2352,7 +2360,7 @@ rmh_status rmh_tune_load(const char* path, int32_t* n_loaded) try {
 
 rmh_status rmh_autotune_laplacian(const int32_t L[4], const void* U, int32_t dtype, const void* x, void* y,
                                   int32_t n_rhs, int32_t purpose, int32_t reps, rmh_hop_config* best, double* best_ms,
-                                  rmh_stream stream) try {
+                                  void* ws, size_t ws_bytes, rmh_stream stream) try {
   Geom g;
   RMH_TRY(make_geom(L, &g));
   RMH_TRY(check_dtype(dtype));
@@ -2361,9 +2369,15 @@ rmh_status rmh_autotune_laplacian(const int32_t L[4], const void* U, int32_t dty
   RMH_TRY(check_ptr(U, "U"));
   RMH_TRY(check_ptr(x, "x"));
   RMH_TRY(check_ptr(y, "y"));
+  RMH_TRY(check_ptr(ws, "ws"));
+  Carver cw(ws);
+  double* partials = plan_autotune(cw, g, n_rhs);
+  if (cw.off > ws_bytes) return fail(RMH_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, cw.off);
   {
     const size_t fb = (size_t)n_rhs * 32 * g.V * dsize(dtype), ub = (size_t)72 * g.V * dsize(dtype);
     if (overlap(x, fb, y, fb) || overlap(U, ub, y, fb)) return fail(RMH_E_ARG, "y overlaps x or U");
+    if (overlap(ws, cw.off, x, fb) || overlap(ws, cw.off, y, fb) || overlap(ws, cw.off, U, ub))
+      return fail(RMH_E_ARG, "ws overlaps x, y or U");
   }
   // timing unit: 1 = plain application, 2 = recursion step, 3 = both
   const int32_t unit_kind = (purpose == RMH_PURPOSE_MOMENTS || purpose == RMH_PURPOSE_FILTER ||
@@ -2376,17 +2390,6 @@ rmh_status rmh_autotune_laplacian(const int32_t L[4], const void* U, int32_t dty
                            : purpose == RMH_PURPOSE_MOMENTS                           ? 7
                                                                                       : 0;
   hipStream_t s = (hipStream_t)stream;
-  double* partials = nullptr;
-  if (dot_mask) {
-    const size_t pb = (size_t)n_rhs * 3 * hop_max_blocks(g) * sizeof(double);
-    if (hipMalloc((void**)&partials, pb) != hipSuccess) return fail(RMH_E_HIP, "hipMalloc of %zu bytes", pb);
-  }
-  struct FreeOnExit {
-    double* p;
-    ~FreeOnExit() {
-      if (p) (void)hipFree(p);
-    }
-  } free_partials{partials};
   // y is the recursion unit's z input: start it from zeros (it then stays bounded, y <- A x - y)
   HIP_TRY(launch_zero(y, (size_t)n_rhs * 32 * g.V * dsize(dtype), s));
   hipEvent_t e0, e1;

@@ -35,7 +35,7 @@ def test_every_declared_symbol_is_exported():
 
 def test_version_and_error_string():
     L = _lib.lib()
-    assert L.rmh_version() == 100
+    assert L.rmh_version() == 101
     assert isinstance(L.rmh_last_error(), bytes)
 
 
@@ -189,6 +189,10 @@ def test_heatbath_validation():
 def test_gauge_force_workspace_and_validation():
     L = _lib.lattice_arg((4, 4, 4, 4))
     assert _lib.lib().rmh_workspace_bytes(9, L, 0, 1, 0, 0, 0) == 512      # block partials + the sum
+    # the autotuner's dot-product partials: 3 rows per field of the largest block count
+    a1 = _lib.lib().rmh_workspace_bytes(_lib.OP_AUTOTUNE, L, 0, 1, 0, 0, 0)
+    a4 = _lib.lib().rmh_workspace_bytes(_lib.OP_AUTOTUNE, L, 0, 4, 0, 0, 0)
+    assert a1 > 0 and a4 >= 4 * a1 - 256
     S = np.zeros(1)
     f = _lib.lib().rmh_wilson_gauge_force
     assert f(L, FAKE, 6.0, None, None, None, 0, None) == 1                  # nothing requested
