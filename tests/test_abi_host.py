@@ -452,3 +452,20 @@ def test_power_spectrum_noalloc_limits():
     assert f(L16, FAKE, 0, FAKE + 2**31, 1, ctypes.byref(bad), None, None, None) == 1
     assert f(L16, FAKE, 0, FAKE + 2**31, -1, ctypes.byref(cheb), None, None, None) == 1
     assert f(L16, FAKE, 0, FAKE + 2**31, 0, ctypes.byref(cheb), None, None, None) == 0   # empty batch: no-op
+
+
+def test_autotune_workspace_validation():
+    """The autotuner's dot-product partials come from the caller's workspace: a missing, short or
+    overlapping one is refused before any device work (fake addresses, never dereferenced)."""
+    L = _lib.lattice_arg((4, 4, 4, 4))
+    f = _lib.lib().rmh_autotune_laplacian
+    need = _lib.lib().rmh_workspace_bytes(_lib.OP_AUTOTUNE, L, 0, 2, 0, 0, 0)
+    U, x, y, ws = FAKE, FAKE + 2**20, FAKE + 2**21, FAKE + 2**22
+
+    def call(ws_ptr, ws_bytes):
+        return f(L, U, 0, x, y, 2, 1, 1, None, None, ws_ptr, ws_bytes, None)
+
+    assert call(None, need) == 1                  # RMH_E_ARG: no workspace
+    assert call(ws, need - 8) == 3                # RMH_E_WORKSPACE
+    assert call(y + 256, need) == 1               # the workspace overlaps y
+    assert call(x, need) == 1                     # ... or x
