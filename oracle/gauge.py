@@ -71,3 +71,36 @@ def action_gradient(U, L, beta: float) -> np.ndarray:
 def gauge_force(U, L, beta: float) -> np.ndarray:
     """F_G = -dS_W / d omega, shape (4, 8, V)."""
     return -action_gradient(U, L, beta)
+
+
+def gauge_force_at(U, L, beta: float, sites) -> np.ndarray:
+    """F_G at the given flat site indices only (the definition of ``gauge_force``, the six staples
+    of each link formed from its neighbours, for lattices too large for the whole-field version).
+
+    U: (4, V, 3, 3).  Returns (4, 8, len(sites)).
+    """
+    U = np.asarray(U)
+    sites = np.asarray(sites, dtype=np.int64)
+    stride = [1, L[0], L[0] * L[1], L[0] * L[1] * L[2]]
+    c = np.stack([(sites // stride[mu]) % L[mu] for mu in range(4)], axis=1)
+
+    def at(steps):                       # flat index of x + sum of (direction, sign) steps
+        d = c.copy()
+        for mu, sign in steps:
+            d[:, mu] = (d[:, mu] + sign) % L[mu]
+        return d[:, 0] + L[0] * (d[:, 1] + L[1] * (d[:, 2] + L[2] * d[:, 3]))
+
+    out = np.zeros((4, 8, len(sites)))
+    for mu in range(4):
+        A = np.zeros((len(sites), 3, 3), dtype=np.complex128)
+        for nu in range(4):
+            if nu == mu:
+                continue
+            up = U[nu][at([(mu, 1)])] @ su3.dagger(U[mu][at([(nu, 1)])]) @ su3.dagger(U[nu][sites])
+            down = (su3.dagger(U[nu][at([(mu, 1), (nu, -1)])]) @ su3.dagger(U[mu][at([(nu, -1)])])
+                    @ U[nu][at([(nu, -1)])])
+            A += up + down
+        M = U[mu][sites] @ A
+        out[mu] = -(beta / 3.0) * np.einsum("cij,xji->cx", su3.T, M).imag
+    return out
+

@@ -7,7 +7,8 @@ properties that hold at any size, plus the batched spectrum's grid at a size the
   workload uses and with the small-lattice default; at 24^4 the first moments of two sources in
   different field groups against the oracle, and the U = 1 control of all 32 sources, whose moments
   the oracle gives exactly through the FFT.
-* 32^3 x 64, eps = 0.4 links: the stencil (FP64 and FP32) at sampled sites, a 16-pole
+* 32^3 x 64, eps = 0.4 links: the stencil (FP64 and FP32) and the Wilson gauge force at sampled
+  sites, a 16-pole
   mixed-precision rational solve checked shift by shift at sampled sites, and the kinetic force of
   two momentum fields (16 poles, mixed precision) at sampled links against the oracle's per-link
   derivative fed the pole solutions (each verified by its residual at sampled sites), then the
@@ -24,6 +25,7 @@ import torch
 
 from gpu_helpers import announce, dev
 from oracle import chebyshev as och
+from oracle import gauge as ogauge
 from oracle import laplacian as olap
 from oracle import rational as orat
 from paper_2112_04556_amd import api, inputs
@@ -152,6 +154,23 @@ def test_stencil_32x64_sampled(dtype):
     ref = olap.laplacian_at(Un, Fn, L, sites)
     assert np.abs(y[..., sites] - ref).max() <= tol * np.abs(ref).max()
     api.tune_clear()
+
+
+def test_gauge_force_32x64_sampled():
+    """The Wilson gauge force (beta = 6.4, the bench's workload: eps = 0.4 links, seed 7) at 32^3 x 64
+    against the oracle's site-local staples at sampled sites, all four directions and eight
+    components (the action is checked against the oracle at the small lattices of the gauge tests)."""
+    L = (32, 32, 32, 64)
+    V = api.volume(L)
+    announce("32^3x64 gauge force sampled")
+    U = inputs.random_links(L, "eps", 0.4, seed=7)
+    Ud = api.pack_links(L, U.to(dev()))
+    F, S = api.wilson_gauge_force(L, Ud, 6.4)
+    assert np.isfinite(S)
+    sites = _sample_sites(V, 64, 7)
+    ref = ogauge.gauge_force_at(U.numpy(), L, 6.4, sites)
+    got = F[..., torch.as_tensor(sites, device=dev())].cpu().numpy()
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
 @pytest.mark.parametrize("walk", [8, 16])

@@ -68,3 +68,12 @@ def test_plaquette_count():
     # every plaquette is seen by the staples of its four links
     lhs = np.einsum("mxii->", np.asarray(U) @ gauge.staples(U, L)).real
     assert np.isclose(lhs, 4 * gauge.plaquette_traces(U, L).sum(), rtol=1e-12)
+
+
+def test_gauge_force_at_sites_matches_whole_field():
+    """The site-local force (used at lattices too large for the whole-field one) equals the whole
+    field's at every site of a 4 x 3 x 2 x 3 lattice with Haar links, and at sampled sites of 6^4."""
+    for L, sites in (((4, 3, 2, 3), np.arange(72)), ((6, 6, 6, 6), np.array([0, 5, 37, 215, 216, 1000, 1295]))):
+        U = inputs.random_links(L, "haar", seed=11).numpy()
+        full = gauge.gauge_force(U, L, 5.5)
+        assert np.allclose(gauge.gauge_force_at(U, L, 5.5, sites), full[..., sites], atol=1e-13, rtol=0)
