@@ -666,7 +666,8 @@ def d7_gauge_force_spectrum(api, inputs, torch, dev):
         Fb = F[None].contiguous()
         s_ms, _ = _median_ms(lambda: api.power_spectrum(L, Ud, Fb, 128, 32), torch, reps=3)
         key = "x".join(map(str, L))
-        out[key] = {"force_ms": round(f_ms, 4), "force_GBs": round(V * 104 * 8 / (f_ms * 1e-3) / 1e9, 1),
+        # links as two rows of 12 reals (the third is rebuilt) and the 32-real force: 80 reals per site
+        out[key] = {"force_ms": round(f_ms, 4), "force_GBs": round(V * 80 * 8 / (f_ms * 1e-3) / 1e9, 1),
                     "spectrum_ms": round(s_ms, 3)}
         log(f"D7 gauge force + spectrum {key}: {out[key]}")
         del Ud, F, Fb

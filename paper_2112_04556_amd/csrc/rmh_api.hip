@@ -1221,7 +1221,7 @@ rmh_status cheb_bwd(const Geom& g, const double* U, const double* x, int32_t n_r
       fa.grad = grad_omega;
       fa.per_rhs = per_rhs ? 1 : 0;
       fa.accumulate = (k == D) ? 0 : 1;
-      const double fbytes = (double)g.V * 8.0 * (72.0 + 64.0 * n_rhs + 32.0 * (per_rhs ? n_rhs : 1) * (k == D ? 1.0 : 2.0));
+      const double fbytes = (double)g.V * 8.0 * (48.0 + 64.0 * n_rhs + 32.0 * (per_rhs ? n_rhs : 1) * (k == D ? 1.0 : 2.0));
       ProfScope ps(RMH_PROF_FORCE, fbytes, s, n_rhs);
       HIP_TRY(launch_force(fa, s));
     }
@@ -1585,7 +1585,7 @@ rmh_status rmh_laplacian_apply_bwd(const int32_t L[4], const void* U, int32_t dt
     fa.w[0] = 1.0;
     fa.grad = grad_omega;
     fa.per_rhs = per_rhs ? 1 : 0;
-    const double fbytes = (double)g.V * 8.0 * (72.0 + 64.0 * n_rhs + 32.0 * (per_rhs ? n_rhs : 1));
+    const double fbytes = (double)g.V * 8.0 * (48.0 + 64.0 * n_rhs + 32.0 * (per_rhs ? n_rhs : 1));
     ProfScope ps(RMH_PROF_FORCE, fbytes, (hipStream_t)stream, n_rhs);
     HIP_TRY(launch_force(fa, (hipStream_t)stream));
   }
@@ -1786,7 +1786,7 @@ rmh_status rmh_wilson_gauge_force(const int32_t L[4], const double* U, double be
     if (F && overlap(F, (size_t)32 * g.V * 8, ws, c.off)) return fail(RMH_E_ARG, "F overlaps the workspace");
   }
   {
-    ProfScope ps(RMH_PROF_FORCE, (double)g.V * 8.0 * (72.0 + (F ? 32.0 : 0.0)), s, 1.0);
+    ProfScope ps(RMH_PROF_FORCE, (double)g.V * 8.0 * (48.0 + (F ? 32.0 : 0.0)), s, 1.0);
     HIP_TRY(launch_gauge_force(g, U, beta, F, part, s));
   }
   if (S) {
@@ -1981,7 +1981,7 @@ static rmh_status force_from_solves(RationalPlan& rp, const Geom& g, const doubl
   fa.grad = grad_omega;
   fa.per_rhs = per_rhs ? 1 : 0;
   {
-    const double fbytes = (double)g.V * 8.0 * (72.0 + 64.0 * n_rhs * np + 32.0 * (per_rhs ? n_rhs : 1));
+    const double fbytes = (double)g.V * 8.0 * (48.0 + 64.0 * n_rhs * np + 32.0 * (per_rhs ? n_rhs : 1));
     ProfScope ps(RMH_PROF_FORCE, fbytes, s, n_rhs);
     HIP_TRY(launch_force(fa, s));
   }
@@ -2120,7 +2120,7 @@ static rmh_status lf_force_from_held(LeapfrogPlan& lp, const Geom& g, const doub
   fa.n_rhs = 1;
   fa.n_pair = rat->n_poles;
   fa.grad = lp.dK;
-  ProfScope ps(RMH_PROF_FORCE, (double)g.V * 8.0 * (72.0 + 64.0 * rat->n_poles + 32.0), s, 1.0);
+  ProfScope ps(RMH_PROF_FORCE, (double)g.V * 8.0 * (48.0 + 64.0 * rat->n_poles + 32.0), s, 1.0);
   HIP_TRY(launch_force(fa, s));
   return RMH_OK;
 }

@@ -1093,10 +1093,12 @@ __global__ void __launch_bounds__(256) k_force(const ForceArgs F, int32_t xcd) {
             for (int e = 0; e < 8; ++e) C[b * 8 + e] = fma(af[b], bx[e], fma(bf[b], ax[e], C[b * 8 + e]));
         }
       }
+    // rows 0 and 1 of U_mu(x) (12 reals), row 2 rebuilt (SU(3))
     double u[18];
     const double* Um = F.U + (int64_t)mu * 18 * V;
 #pragma unroll
-    for (int c = 0; c < 18; ++c) u[c] = (Um + (size_t)c * V)[s];
+    for (int c = 0; c < 12; ++c) u[c] = (Um + (size_t)c * V)[s];
+    su3_row2<double>(u);
     // G = sum_b R[:, b] x C[b, :], x the su(3) product (p x q)_c = sum_{a,e} f^{aec} p_a q_e, with
     // the columns of R(U) formed two at a time (the whole of R is never held)
     double G[8];
