@@ -1,6 +1,8 @@
 // The adjoint-Laplacian stencil for gfx950: one hop per direction and sign, fused epilogues
 // (axpby, dot products), the site-per-thread kernel, the hop-split kernel and the
-// x3-walking kernel, and their launch dispatch.
+// x3-walking kernel, and their launch dispatch.  Every kernel writes its output with
+// non-temporal stores: the output is not read again in the launch, and streaming it past the L2
+// leaves that cache to the neighbour fields and links the blocks share.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -168,7 +170,7 @@ __global__ void __launch_bounds__(256) k_hop(const HopArgs<T> A, int32_t xcd, in
         const T xv = xs[a];
         T o = fmadd(ca, acc[i][a], cb * xv);
         if (zf) o = fmadd(cc, zv[a], o);
-        if (A.store) outf[e] = o;
+        if (A.store) __builtin_nontemporal_store(o, &outf[e]);
         if (DOTS) {
           const double xd = (double)xv, od = (double)o;
           dsum[0] = fma(xd, xd, dsum[0]);
@@ -278,7 +280,7 @@ __global__ void __launch_bounds__(256) k_hop_split(const HopArgs<T> A, int32_t x
       const T xv = xs[q];
       T o = fmadd(ca, h, cb * xv);
       if (zf) o = fmadd(cc, zv[q], o);
-      if (A.store) outf[e] = o;
+      if (A.store) __builtin_nontemporal_store(o, &outf[e]);
       if (DOTS) {
         const double xd = (double)xv, od = (double)o;
         dsum[0] = fma(xd, xd, dsum[0]);
@@ -419,7 +421,7 @@ k_hop_walk(const HopArgs<T> A, int32_t xcd, int32_t K, int32_t tile2) {
           const T xv = cen[i][a];
           T o = fmadd(ca, acc[i][a], cb * xv);
           if (zf) o = fmadd(cc, zv[a], o);
-          if (A.store) outf[e] = o;
+          if (A.store) __builtin_nontemporal_store(o, &outf[e]);
           if (DOTS) {
             const double xd = (double)xv, od = (double)o;
             dsum[0] = fma(xd, xd, dsum[0]);
@@ -567,7 +569,7 @@ __global__ void __launch_bounds__(256) k_hop_ns(const HopArgs<T> A, int32_t xcd,
           const T xv = xs[a];
           T o = fmadd(ca, acc[f * 4 + i][a], cb * xv);
           if (zf) o = fmadd(cc, zv[a], o);
-          if (A.store && runs[f]) outf[e] = o;
+          if (A.store && runs[f]) __builtin_nontemporal_store(o, &outf[e]);
           if (DOTS) {
             const double xd = (double)xv, od = (double)o;
             dsum[f * 3 + 0] = fma(xd, xd, dsum[f * 3 + 0]);
