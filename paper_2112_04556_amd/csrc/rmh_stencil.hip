@@ -1,8 +1,9 @@
 // The adjoint-Laplacian stencil for gfx950: one hop per direction and sign, fused epilogues
 // (axpby, dot products), the site-per-thread kernel, the hop-split kernel and the
 // x3-walking kernel, and their launch dispatch.  Every kernel writes its output with
-// non-temporal stores: the output is not read again in the launch, and streaming it past the L2
-// leaves that cache to the neighbour fields and links the blocks share.
+// non-temporal stores (and reads a per-field z input with non-temporal loads): neither is touched
+// again in the launch, and streaming them past the L2 leaves that cache to the neighbour fields
+// and links the blocks share.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -63,6 +64,14 @@ __device__ __forceinline__ void hop_apply(const T* u, const T (*phi)[8], T (*acc
   } else {
     adj_stream<T, NV, kT>(u, phi, acc);
   }
+}
+
+// An element of the z input: read once when each field has its own z (z_div = 1), so it is loaded
+// non-temporally and does not take L2 space from the neighbour fields; a z shared by several
+// fields (z_div > 1) is loaded normally for the others to hit.
+template <typename T>
+__device__ __forceinline__ T load_z(const T* p, bool once) {
+  return once ? __builtin_nontemporal_load(p) : *p;
 }
 
 // The link at site s (component c at Um[c V + s]): rows 0 and 1 are loaded, row 2 is rebuilt
@@ -162,7 +171,7 @@ __global__ void __launch_bounds__(256) k_hop(const HopArgs<T> A, int32_t xcd, in
 #pragma unroll
       for (int a = 0; a < 8; ++a) {
         xs[a] = xf[e0 + (int64_t)a * V];
-        zv[a] = zf ? zf[e0 + (int64_t)a * V] : T(0);
+        zv[a] = zf ? load_z(&zf[e0 + (int64_t)a * V], A.z_div == 1) : T(0);
       }
 #pragma unroll
       for (int a = 0; a < 8; ++a) {
@@ -271,7 +280,7 @@ __global__ void __launch_bounds__(256) k_hop_split(const HopArgs<T> A, int32_t x
       hs[q] = __builtin_bit_cast(T, hb_);
       const int64_t e = (int64_t)(nu0 * 8 + 4 * q + mu) * V + s;
       xs[q] = xf[e];
-      zv[q] = zf ? zf[e] : T(0);
+      zv[q] = zf ? load_z(&zf[e], A.z_div == 1) : T(0);
     }
 #pragma unroll
     for (int q = 0; q < 2 * NV; ++q) {
@@ -414,7 +423,7 @@ k_hop_walk(const HopArgs<T> A, int32_t xcd, int32_t K, int32_t tile2) {
         const int64_t e0 = (int64_t)((nu0 + i) * 8) * V + s;
         T zv[8];
 #pragma unroll
-        for (int a = 0; a < 8; ++a) zv[a] = zf ? zf[e0 + (int64_t)a * V] : T(0);
+        for (int a = 0; a < 8; ++a) zv[a] = zf ? load_z(&zf[e0 + (int64_t)a * V], A.z_div == 1) : T(0);
 #pragma unroll
         for (int a = 0; a < 8; ++a) {
           const int64_t e = e0 + (int64_t)a * V;
@@ -561,7 +570,7 @@ __global__ void __launch_bounds__(256) k_hop_ns(const HopArgs<T> A, int32_t xcd,
 #pragma unroll
         for (int a = 0; a < 8; ++a) {
           xs[a] = xf[f][e0 + (int64_t)a * V];
-          zv[a] = zf ? zf[e0 + (int64_t)a * V] : T(0);
+          zv[a] = zf ? load_z(&zf[e0 + (int64_t)a * V], A.z_div == 1) : T(0);
         }
 #pragma unroll
         for (int a = 0; a < 8; ++a) {
