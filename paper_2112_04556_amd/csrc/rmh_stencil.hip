@@ -311,10 +311,6 @@ __global__ void __launch_bounds__(256) k_hop_split(const HopArgs<T> A, int32_t x
   }
 }
 
-// Walking variant of k_hop: a block of B threads covers B * NV / 4 columns (x0, x1, x2) of the
-// lattice; each thread walks K consecutive x3 values of its column.  Per step the x0, x1, x2
-// hops load their links and neighbours as in k_hop; the x3 forward hop loads U_3(x) and
-// phi(x+3), which become the backward link and the centre field of the next step.
 // Waves per SIMD the walking kernel is compiled for.  The FP32 3x3-form walk over all four
 // directions needs 170 registers left to itself (two waves per SIMD); capped at 168 it keeps three
 // waves without spilling, and its batched Chebyshev sweeps run 4-5 % faster (they move fewer bytes
@@ -325,9 +321,14 @@ constexpr int hop_walk_waves() {
   return (sizeof(T) == 4 && FORM == kFormMatrix && NV == 4) ? 3 : 1;
 }
 
+// Walking variant of k_hop: a block of B threads covers B * NV / 4 columns (x0, x1, x2) of the
+// lattice; each thread walks K consecutive x3 values of its column.  Per step the x1 and x2 hops
+// load their links and neighbours as in k_hop, the x0 hops too unless lane_x0 (then they take the
+// neighbours from the other lanes of the x0 row); the x3 forward hop loads U_3(x) and phi(x+3),
+// which become the backward link and the centre field of the next step.
 template <typename T, int FORM, int NV, bool DOTS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(hop_walk_waves<T, FORM, NV>())))
-k_hop_walk(const HopArgs<T> A, int32_t xcd, int32_t K, int32_t tile2) {
+k_hop_walk(const HopArgs<T> A, int32_t xcd, int32_t K, int32_t tile2, int32_t lane_x0) {
   constexpr int G = 4 / NV;
   const HopBlock hb = hop_block(xcd, A.n_rhs);
   const int32_t v = hb.v;
@@ -398,8 +399,40 @@ k_hop_walk(const HopArgs<T> A, int32_t xcd, int32_t K, int32_t tile2) {
         load_link<T>(U3, sb, V, u);
         hop_apply<T, FORM, NV, true>(u, bwd, acc);
       }
+      int32_t mu_begin = 0;
+      if (lane_x0) {
+        // x0 hops from the other lanes of this x0 row (a row of L0 lanes lies within the wave):
+        // the field at x +- 0 is that lane's carried centre, and the backward link U_0(x - 0) is
+        // the forward link that lane loads, passed as its 12 loaded reals (row 2 rebuilt here, as
+        // load_link does) -- the same values the loads would give, in the same order of terms
+        const int32_t lane = threadIdx.x & 63;
+        const int32_t x0 = xc[0];
+        const int32_t row = lane - x0;
+        const int32_t lp = row + (x0 + 1 == A.g.L0 ? 0 : x0 + 1);
+        const int32_t lm = row + (x0 == 0 ? A.g.L0 - 1 : x0 - 1);
+        T u[18], u12[12], phi[NV][8];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) u12[c] = (U + (size_t)c * V)[s];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) u[c] = u12[c];
+        su3_row2<T>(u);
+#pragma unroll
+        for (int i = 0; i < NV; ++i)
+#pragma unroll
+          for (int b = 0; b < 8; ++b) phi[i][b] = __shfl(cen[i][b], lp, 64);
+        hop_apply<T, FORM, NV, false>(u, phi, acc);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) u[c] = __shfl(u12[c], lm, 64);
+        su3_row2<T>(u);
+#pragma unroll
+        for (int i = 0; i < NV; ++i)
+#pragma unroll
+          for (int b = 0; b < 8; ++b) phi[i][b] = __shfl(cen[i][b], lm, 64);
+        hop_apply<T, FORM, NV, true>(u, phi, acc);
+        mu_begin = 1;
+      }
 #pragma unroll 1
-      for (int mu = 0; mu < 3; ++mu) {
+      for (int mu = mu_begin; mu < 3; ++mu) {
         const T* __restrict__ Um = U + (int64_t)mu * 18 * V;
         hop_term_fwd<T, FORM, NV>(Um, s, site_shift(A.g, s, xc, mu, +1), xf, nu0, V, acc);
         hop_term<T, FORM, NV, true>(Um, site_shift(A.g, s, xc, mu, -1), xf, nu0, V, acc);
@@ -695,10 +728,15 @@ static hipError_t launch_hop_form(const HopArgs<T>& A, const HopConfig& cfg, hip
   const int32_t order = (cfg.order == 1 && hop_order_ok(A.g, cfg)) ? 1 : 0;
   if (hop_walk_ok(A.g, cfg)) {
     const int32_t K = cfg.walk;
+    // the x0 rows lie whole within a wave (L0 divides 64 and the columns per block): their x0
+    // neighbours come from other lanes instead of the caches
+    const int32_t cpb = cfg.block * cfg.nv / 4;
+    const int32_t lane_x0 = (64 % A.g.L0 == 0 && cpb % A.g.L0 == 0) ? 1 : 0;
     if (dots)
-      hipLaunchKernelGGL((k_hop_walk<T, FORM, NV, true>), grid, block, 0, s, A, cfg.xcd_remap, K, cfg.tile2);
+      hipLaunchKernelGGL((k_hop_walk<T, FORM, NV, true>), grid, block, 0, s, A, cfg.xcd_remap, K, cfg.tile2, lane_x0);
     else
-      hipLaunchKernelGGL((k_hop_walk<T, FORM, NV, false>), grid, block, 0, s, A, cfg.xcd_remap, K, cfg.tile2);
+      hipLaunchKernelGGL((k_hop_walk<T, FORM, NV, false>), grid, block, 0, s, A, cfg.xcd_remap, K, cfg.tile2,
+                         lane_x0);
     return hipGetLastError();
   }
   if (dots)
