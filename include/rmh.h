@@ -46,6 +46,9 @@
  *              gives a thread-local message for the last failing call.
  *              Reductions are deterministic (fixed order): repeated calls give
  *              bitwise-identical results.
+ * Environment  RMH_LOG=1 prints the solver's and the autotuner's diagnostics to stderr;
+ *              nothing else is read from the environment (launch shapes come only from
+ *              rmh_tune_set, rmh_tune_load, rmh_autotune_laplacian or the built-in defaults).
  */
 #ifndef RMH_H
 #define RMH_H
