@@ -325,7 +325,7 @@ constexpr int hop_walk_waves() {
 // lattice; each thread walks K consecutive x3 values of its column.  Per step the x1 and x2 hops
 // load their links and neighbours as in k_hop, the x0 hops too unless lane_x0 (then they take the
 // neighbours from the other lanes of the x0 row); the x3 forward hop loads U_3(x) and phi(x+3),
-// which become the backward link and the centre field of the next step.
+// which stay in registers as the backward link and the centre field of the next step.
 template <typename T, int FORM, int NV, bool DOTS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(hop_walk_waves<T, FORM, NV>())))
 k_hop_walk(const HopArgs<T> A, int32_t xcd, int32_t K, int32_t tile2, int32_t lane_x0) {
@@ -368,12 +368,14 @@ k_hop_walk(const HopArgs<T> A, int32_t xcd, int32_t K, int32_t tile2, int32_t la
     T* outf = A.out + (int64_t)v * FV;
     int32_t xc[4];
     site_coords(A.g, col + x3_0 * P, xc);
-    // carried state: the centre field and the x-3 field (the link U_3(x-3), loaded by this
-    // thread one step earlier, is read again from the cache)
-    T cen[NV][8], bwd[NV][8];
+    // carried state: the centre field, the x-3 field and the 12 loaded reals of the link U_3(x-3)
+    // (this thread's forward x3 link of the step before; row 2 is rebuilt from them each step)
+    T cen[NV][8], bwd[NV][8], l3[12];
     {
       const int32_t s0 = col + x3_0 * P;
       const int32_t sb = (x3_0 == 0) ? s0 + (A.g.L3 - 1) * P : s0 - P;
+#pragma unroll
+      for (int c = 0; c < 12; ++c) l3[c] = (U3 + (size_t)c * V)[sb];
 #pragma unroll
       for (int i = 0; i < NV; ++i)
 #pragma unroll
@@ -394,9 +396,10 @@ k_hop_walk(const HopArgs<T> A, int32_t xcd, int32_t K, int32_t tile2, int32_t la
         for (int a = 0; a < 8; ++a) acc[i][a] = T(0);
       // x3 backward hop: carried field, link U_3(x - 3)
       {
-        const int32_t sb = (x3 == 0) ? s + (A.g.L3 - 1) * P : s - P;
         T u[18];
-        load_link<T>(U3, sb, V, u);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) u[c] = l3[c];
+        su3_row2<T>(u);
         hop_apply<T, FORM, NV, true>(u, bwd, acc);
       }
       int32_t mu_begin = 0;
@@ -442,7 +445,11 @@ k_hop_walk(const HopArgs<T> A, int32_t xcd, int32_t K, int32_t tile2, int32_t la
       {
         const int32_t sf = (x3 == A.g.L3 - 1) ? s - (A.g.L3 - 1) * P : s + P;
         T u[18];
-        load_link<T>(U3, s, V, u);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) l3[c] = (U3 + (size_t)c * V)[s];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) u[c] = l3[c];
+        su3_row2<T>(u);
 #pragma unroll
         for (int i = 0; i < NV; ++i)
 #pragma unroll
