@@ -312,10 +312,12 @@ __global__ void __launch_bounds__(256) k_hop_split(const HopArgs<T> A, int32_t x
 }
 
 // Waves per SIMD the walking kernel is compiled for.  The FP32 3x3-form walk over all four
-// directions needs 170 registers left to itself (two waves per SIMD); capped at 168 it keeps three
-// waves without spilling, and its batched Chebyshev sweeps run 4-5 % faster (they move fewer bytes
-// than one thread per site but were latency-bound at two waves).  The other walks keep the
-// compiler's choice (FP64 and the 8x8 forms do not fit three waves without spilling).
+// directions needs about 170 registers left to itself (two waves per SIMD); capped at 168 it keeps
+// three waves, and its batched Chebyshev sweeps ran 4-5 % faster (they move fewer bytes than one
+// thread per site but were latency-bound at two waves).  Under the cap the variant with the fused
+// dot products (the sweeps, the CG) does not spill; the plain one spills about 130 B per lane since
+// the x0 hops take their neighbours from other lanes.  The other walks keep the compiler's choice
+// (FP64 and the 8x8 forms do not fit three waves without spilling).
 template <typename T, int FORM, int NV>
 constexpr int hop_walk_waves() {
   return (sizeof(T) == 4 && FORM == kFormMatrix && NV == 4) ? 3 : 1;
